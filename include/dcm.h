@@ -1,0 +1,222 @@
+/* dcm.h -- C ABI of libdcm.so, the MI355X (gfx950) dynamic cutoff method (DCM) library.
+ *
+ * The library computes the per-timestep path of the dynamic cutoff method of
+ * P. Springer, "A Scalable, Linear-Time Dynamic Cutoff Algorithm for Molecular
+ * Simulations of Interfacial Systems" (RWTH Aachen, 2014):
+ *   interface detection (Section 4, Fig. 14): binning (Eq. 9-10), smoothing,
+ *   two-means density estimate (Eq. 14), labels (Eq. 11-12), removal of small
+ *   components (Section 4.2), band-limited distance to the interface
+ *   (Eq. 15-19, Section 4.3.2), trilinear interpolation (Alg. 3.1) and the
+ *   exponential cutoff function (Eq. 7-8); then Lennard-Jones forces, energy and
+ *   virial with per-particle cutoffs (Eq. 4, Alg. 3.2) and velocity-Verlet
+ *   integration of Eq. 1-2.
+ *
+ * Conventions for every entry point:
+ *  - Every function returns dcm_status: DCM_OK (0), DCM_PENDING (1) or a negative
+ *    error. No exception crosses the ABI. dcm_last_error() returns a thread-local
+ *    message for the last non-OK status.
+ *  - Pointers named d_* are device (HBM) pointers owned by the caller; h_* are host
+ *    pointers. The library never allocates device memory: all device state lives
+ *    in a caller-provided workspace (sized by dcm_workspace_bytes) that must stay
+ *    valid, untouched, until dcm_destroy.
+ *  - Particle arrays are FP64 structure-of-arrays [3][n] (all x, then all y, then
+ *    all z) in caller (particle id) order. Internally particles are kept sorted by
+ *    cell; outputs are permuted back to caller order.
+ *  - Grid arrays have G = Nx*Ny*Nz entries, x fastest: index (k*Ny + j)*Nx + i.
+ *  - Work is enqueued on the given stream (a hipStream_t; NULL = default stream)
+ *    and the call returns; outputs are valid once the stream reaches that point.
+ *    One stream per system; a handle must not be used from two threads at once.
+ *  - Units are reduced Lennard-Jones units (sigma, epsilon, mass).
+ */
+#ifndef DCM_H
+#define DCM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dcm_status;
+enum {
+    DCM_OK = 0,
+    DCM_PENDING = 1,           /* dcm_poll: request not finished yet                   */
+    DCM_E_INVALID = -1,        /* bad argument or parameter set (see dcm_create)       */
+    DCM_E_WORKSPACE = -2,      /* workspace missing, misaligned or too small           */
+    DCM_E_HIP = -3,            /* a HIP runtime call failed                            */
+    DCM_E_BUDGET = -4,         /* serving: request can never fit the memory budget     */
+    DCM_E_NONFINITE = -5,      /* non-finite input, or non-finite forces were produced */
+    DCM_E_UNKNOWN_TICKET = -6, /* serving: no such request                             */
+    DCM_E_NOT_CONVERGED = -7   /* distance iteration hit its sweep limit               */
+};
+
+enum { DCM_FP64 = 0, DCM_FP32C = 1 };       /* plain FP64 / FP32 pair math, compensated sums */
+enum { DCM_PAIR_I = 0, DCM_PAIR_MAX = 1 };  /* pair (i,j) used iff r < r_c[i] (Alg. 3.2) /
+                                               iff r < max(r_c[i], r_c[j]) (symmetric)     */
+
+typedef void *dcm_stream_t;                 /* a hipStream_t */
+
+/* Method parameters. Defaults in brackets are those of the slab workloads. */
+typedef struct {
+    double box[3];          /* periodic box edges L_x, L_y, L_z                           */
+    double epsilon, sigma;  /* Lennard-Jones parameters of Eq. 4 [1, 1]                   */
+    double mass;            /* particle mass [1]                                          */
+    double rc_min, rc_max;  /* cutoff range of Eq. 7 [2.5, 6.0]                           */
+    double alpha;           /* steepness of Eq. 7 [-0.5]; any non-zero value              */
+    double bin;             /* target box edge of Eq. 10 [1.0]: N_k = max(3, round(L_k/bin)) */
+    int32_t smooth_passes;  /* passes of the periodic [1,2,1] filter per axis, 0..4 [1]   */
+    int32_t min_component;  /* components with fewer boxes are removed (Section 4.2) [27] */
+    int32_t detect_every;   /* force evaluation k re-detects the interface iff
+                               k % detect_every == 0 [2]; 0 = only at creation            */
+    int32_t precision;      /* DCM_FP64 or DCM_FP32C                                      */
+    int32_t pair_rule;      /* DCM_PAIR_I or DCM_PAIR_MAX                                 */
+    int32_t energy_shift;   /* 1: pair energy V(r) - V(r_c) (forces unchanged) [0]        */
+    double dt;              /* velocity-Verlet time step [0.005]                          */
+} dcm_params;
+
+/* One thermodynamic record (all FP64 sums in a fixed reduction order).
+ * ke = m/2 sum |v|^2; pe = sum_i e_i with e_i = 1/2 sum_j V(r_ij) over the pairs i uses;
+ * virial[6] = sum_i 1/2 sum_j r_ij (x) f_ij in the order xx, yy, zz, xy, xz, yz;
+ * pairs = number of ordered pairs (i, j) used; step = force-evaluation index k. */
+typedef struct {
+    double ke, pe, virial[6];
+    int64_t pairs;
+    int64_t step;
+} dcm_thermo;
+
+/* Optional outputs of an interface detection. Each member is a caller device pointer
+ * or NULL (not wanted). Grid arrays have G entries, particle arrays n (caller order). */
+typedef struct {
+    uint32_t *count;   /* particles per box, Eq. 9                                       */
+    uint32_t *smooth;  /* smoothed counts                                                */
+    uint8_t *raw;      /* threshold labels before component removal (0 liquid, 1 vapor)  */
+    uint8_t *label;    /* final labels, Eq. 11-12                                        */
+    double *dist;      /* box-interface distances, Eq. 5, capped at r_c^max + max h_k     */
+    double *rc;        /* per-particle cutoffs r_c[i], Eq. 7                              */
+    double *km;        /* [3] vapor centre, liquid centre, threshold (Eq. 14)             */
+    int64_t *stats;    /* [6] Lloyd iterations, vapor / liquid components removed,
+                          vapor / liquid boxes flipped, distance sweeps                  */
+} dcm_detect_out;
+
+typedef struct dcm_system dcm_system;
+
+/* Library version string (static storage). */
+const char *dcm_version(void);
+
+/* Thread-local message describing the last non-OK status of this thread. */
+const char *dcm_last_error(void);
+
+/* Grid of Eq. 10 for these parameters: dims = {N_x, N_y, N_z}. Host only.
+ * DCM_E_INVALID for a non-positive box or bin. */
+dcm_status dcm_grid_dims(const dcm_params *p, int32_t dims[3]);
+
+/* Bytes of device workspace a system of n particles needs (host only, no GPU use).
+ * DCM_E_INVALID if the parameter set is rejected (same checks as dcm_create). */
+dcm_status dcm_workspace_bytes(const dcm_params *p, int64_t n, size_t *bytes);
+
+/* Create a system from positions d_x and velocities d_v ([3][n], caller order; copied,
+ * the caller keeps ownership). d_ws must be 256-byte aligned and hold ws_bytes >=
+ * dcm_workspace_bytes. Enqueues: periodic wrap, binning, interface detection and the
+ * force evaluation k = 0, so the system is ready for dcm_step. Synchronizes the stream
+ * once to validate inputs.
+ * DCM_E_INVALID: n < 2 or n >= 2^31; box edge <= 0; bin <= 0; rc_min <= 0 or
+ *   rc_min > rc_max; rc_max >= min(L)/2 (minimum image); N_k < 3; N_k < 2 ceil(rc_max/h_k)
+ *   + 2 (a stencil would reach a cell twice); alpha == 0 with rc_min != rc_max;
+ *   smooth_passes outside 0..4; min_component < 0; detect_every < 0; dt, mass or sigma
+ *   <= 0; epsilon < 0; unknown precision or pair_rule.
+ * DCM_E_WORKSPACE: d_ws NULL, misaligned or too small. DCM_E_NONFINITE: a non-finite
+ * coordinate or velocity. DCM_E_HIP: a HIP call failed. *out is set only on DCM_OK. */
+dcm_status dcm_create(const dcm_params *p, int64_t n, void *d_ws, size_t ws_bytes,
+                      const double *d_x, const double *d_v, dcm_stream_t stream,
+                      dcm_system **out);
+
+/* As dcm_create, but resumes a saved state: d_rc [n] holds the cutoffs carried by each
+ * particle and step the index k of the force evaluation that state belongs to. The
+ * interface is re-detected only if k % detect_every == 0 (Section 3: cutoffs are
+ * carried between detections), so a resumed run repeats the original bit for bit. */
+dcm_status dcm_create_from_state(const dcm_params *p, int64_t n, void *d_ws, size_t ws_bytes,
+                                 const double *d_x, const double *d_v, const double *d_rc,
+                                 int64_t step, dcm_stream_t stream, dcm_system **out);
+
+/* Replace every particle's cutoff with d_rc[n] (caller order; each value must lie in
+ * [rc_min, rc_max], DCM_E_INVALID is reported by dcm_check otherwise) and recompute the
+ * forces of the current state. Used to evaluate Alg. 3.2 on given cutoffs. */
+dcm_status dcm_set_cutoffs(dcm_system *s, dcm_stream_t stream, const double *d_rc);
+
+/* Re-run the interface detection of Fig. 14 (Eq. 9-19, Alg. 3.1, Eq. 7) on the current
+ * positions, replace the per-particle cutoffs, and write the requested outputs (out may
+ * be NULL). Does not recompute forces. */
+dcm_status dcm_detect_interface(dcm_system *s, dcm_stream_t stream, const dcm_detect_out *out);
+
+/* Evaluate Alg. 3.2 (Eq. 4 Lennard-Jones, pair used iff r < r_c[i]; only f_i updated) on
+ * the current state and cutoffs. Outputs in caller order, each optional (NULL):
+ * d_f [3][n] forces, d_e [n] per-particle energy e_i, d_w [6][n] per-particle virial
+ * (xx, yy, zz, xy, xz, yz), d_pairs [n] pairs used by each particle, d_th one record
+ * (ke of the current velocities). */
+dcm_status dcm_compute_forces(dcm_system *s, dcm_stream_t stream, double *d_f, double *d_e,
+                              double *d_w, uint32_t *d_pairs, dcm_thermo *d_th);
+
+/* Advance nsteps velocity-Verlet steps (Eq. 1-2): v += dt/(2m) F; x += dt v; wrap;
+ * re-bin; re-detect the interface when k % detect_every == 0; forces (Alg. 3.2);
+ * v += dt/(2m) F. d_th (optional) receives nsteps records, one per step. nsteps >= 0. */
+dcm_status dcm_step(dcm_system *s, int32_t nsteps, dcm_stream_t stream, dcm_thermo *d_th);
+
+/* Copy the current state out (caller order; each pointer optional): d_x, d_v [3][n],
+ * d_rc [n]. *h_step (host, optional) receives the force-evaluation index k. */
+dcm_status dcm_get_state(dcm_system *s, dcm_stream_t stream, double *d_x, double *d_v,
+                         double *d_rc, int64_t *h_step);
+
+/* Synchronize the stream and report sticky device-side conditions raised since the
+ * system was created: DCM_E_NONFINITE (a non-finite force), DCM_E_NOT_CONVERGED (the
+ * distance sweeps hit their limit), DCM_E_INVALID (smoothed counts beyond the histogram
+ * range, or cutoffs outside [rc_min, rc_max]). DCM_OK otherwise. */
+dcm_status dcm_check(dcm_system *s, dcm_stream_t stream);
+
+/* Per-stage timing with HIP events on the system's stream (off by default). Stages:
+ * 0 kick/drift/key, 1 sort and cell ranges, 2 smoothing, 3 two-means, 4 labels and
+ * components, 5 distance, 6 interpolation and cutoffs, 7 pair forces, 8 reductions.
+ * dcm_stage_times synchronizes and returns total milliseconds and launch counts per stage
+ * (arrays of DCM_NSTAGES) accumulated since profiling was switched on. */
+#define DCM_NSTAGES 9
+dcm_status dcm_set_profiling(dcm_system *s, int32_t on);
+dcm_status dcm_stage_times(dcm_system *s, double *h_ms, int64_t *h_counts);
+
+/* Release the handle (host memory only; the caller frees the workspace afterwards).
+ * Waits for nothing: synchronize the stream first if work is still queued. */
+dcm_status dcm_destroy(dcm_system *s);
+
+/* ---- grid stages on caller images (the same kernels the system path runs) ----------
+ * dims = {N_x, N_y, N_z}, each >= 3; d_ws of at least dcm_grid_workspace_bytes. */
+dcm_status dcm_grid_workspace_bytes(const int32_t dims[3], size_t *bytes);
+
+/* Periodic [1,2,1] smoothing along x, then y, then z, repeated `passes` (0..4) times;
+ * integer arithmetic (stands in for the perimeter penalty of Eq. 13). */
+dcm_status dcm_grid_smooth(const int32_t dims[3], int32_t passes, const uint32_t *d_in,
+                           uint32_t *d_out, void *d_ws, size_t ws_bytes, dcm_stream_t stream);
+
+/* Two-means estimate of the vapor and liquid densities (Eq. 14, Lloyd's iteration from
+ * the minimum and maximum): d_km[3] = {rho_v, rho_l, threshold}; d_stats[0] = iterations.
+ * A box is liquid iff its value exceeds the threshold. Values must be < 65536. */
+dcm_status dcm_grid_two_means(const int32_t dims[3], const uint32_t *d_g, double *d_km,
+                              int64_t *d_stats, void *d_ws, size_t ws_bytes, dcm_stream_t stream);
+
+/* Labels of Eq. 11-12 (liquid 0 iff g > d_km[2]) into d_raw, then removal of 6-connected
+ * periodic components with fewer than min_component boxes, vapor first, then liquid on the
+ * updated image (Section 4.2), into d_label. d_stats[4] (optional): vapor / liquid
+ * components removed, vapor / liquid boxes flipped. */
+dcm_status dcm_grid_segment(const int32_t dims[3], const uint32_t *d_g, const double *d_km,
+                            int32_t min_component, uint8_t *d_raw, uint8_t *d_label,
+                            int64_t *d_stats, void *d_ws, size_t ws_bytes, dcm_stream_t stream);
+
+/* Distance of liquid boxes (label 0) to the vapor set (label 1): the fixed point of the
+ * Godunov upwind update (Eq. 16-19) restricted to values <= cap, all other values set to
+ * cap (Section 4.3.2). h = box edges. *d_sweeps (optional, device) = sweeps used. */
+dcm_status dcm_grid_distance(const int32_t dims[3], const double h[3], double cap,
+                             const uint8_t *d_label, double *d_dist, int64_t *d_sweeps,
+                             void *d_ws, size_t ws_bytes, dcm_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DCM_H */

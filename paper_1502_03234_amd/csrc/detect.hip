@@ -1,0 +1,481 @@
+// detect.hip -- interface detection on the box grid (Section 4, Fig. 14).
+//
+//   smoothing        periodic [1,2,1] per axis on the counts of Eq. 9 (integer, exact)
+//   two-means        Eq. 14 with K = 2: histogram of the smoothed values, then Lloyd's
+//                    iteration from (min, max) in one workgroup with exact integer sums
+//   labels           Eq. 11-12: liquid (0) iff value > threshold, else vapor (1)
+//   components       Section 4.2: 6-connected periodic components by lock-free union-find
+//                    (links always point to the smaller index, so each component ends up
+//                    named by its smallest box index); components below the size limit
+//                    flip phase, vapor first, then liquid on the updated image
+//   distance         Eq. 15-19 and Section 4.3.2: in-place Godunov relaxation of the liquid
+//                    boxes, keeping only values inside the band r_c^max + h, repeated until a
+//                    sweep changes nothing
+//   cutoffs          Alg. 3.1 trilinear interpolation of box-centre distances, then Eq. 7-8
+#include "internal.h"
+
+namespace dcm {
+
+namespace {
+
+inline unsigned grid1(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+__device__ __forceinline__ int64_t lin(const Grid &g, int64_t i, int64_t j, int64_t k)
+{
+    return (k * g.n[1] + j) * g.n[0] + i;
+}
+
+__device__ __forceinline__ void coords(const Grid &g, int64_t c, int64_t &i, int64_t &j, int64_t &k)
+{
+    i = c % g.n[0];
+    int64_t r = c / g.n[0];
+    j = r % g.n[1];
+    k = r / g.n[1];
+}
+
+// ---- smoothing ------------------------------------------------------------------------
+__global__ void k_smooth_axis(Grid g, const uint32_t *in, const uint32_t *cell_start, uint32_t *out,
+                              int axis)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.G) return;
+    int64_t i, j, k;
+    coords(g, c, i, j, k);
+    int64_t q[3] = {i, j, k};
+    int64_t lo[3] = {i, j, k}, hi[3] = {i, j, k};
+    lo[axis] = q[axis] == 0 ? g.n[axis] - 1 : q[axis] - 1;
+    hi[axis] = q[axis] == g.n[axis] - 1 ? 0 : q[axis] + 1;
+    int64_t cl = lin(g, lo[0], lo[1], lo[2]), ch = lin(g, hi[0], hi[1], hi[2]);
+    uint32_t a, b, d;
+    if (cell_start) {
+        a = cell_start[cl + 1] - cell_start[cl];
+        b = cell_start[c + 1] - cell_start[c];
+        d = cell_start[ch + 1] - cell_start[ch];
+    } else {
+        a = in[cl];
+        b = in[c];
+        d = in[ch];
+    }
+    out[c] = a + 2u * b + d;
+}
+
+__global__ void k_count_from_ranges(const uint32_t *cell_start, int64_t G, uint32_t *out)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < G) out[c] = cell_start[c + 1] - cell_start[c];
+}
+
+// ---- histogram and two-means ----------------------------------------------------------
+constexpr int kLdsBins = 8192;
+
+__global__ void __launch_bounds__(kBlock) k_hist(const uint32_t *img, int64_t G, uint32_t *hist,
+                                                 uint32_t *flags)
+{
+    __shared__ uint32_t lh[kLdsBins];
+    for (int b = threadIdx.x; b < kLdsBins; b += kBlock) lh[b] = 0;
+    __syncthreads();
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < G;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t v = img[c];
+        if (v < (uint32_t)kLdsBins) atomicAdd(&lh[v], 1u);
+        else if (v < (uint32_t)kHistBins) atomicAdd(&hist[v], 1u);
+        else atomicOr(flags, kFlagHistOverflow);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kLdsBins; b += kBlock)
+        if (lh[b]) atomicAdd(&hist[b], lh[b]);
+}
+
+constexpr int kTmThreads = 1024;
+
+template <typename T>
+__device__ T block_sum_1024(T v, T *lds /*[16]*/)
+{
+    const int tid = threadIdx.x, w = tid >> 6;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((tid & 63) == 0) lds[w] = v;
+    __syncthreads();
+    T s = 0;
+    for (int q = 0; q < kTmThreads / 64; ++q) s += lds[q];
+    __syncthreads();
+    return s;
+}
+
+__global__ void __launch_bounds__(kTmThreads) k_two_means(const uint32_t *hist, double *km,
+                                                          long long *stats_iter)
+{
+    __shared__ long long l64[16];
+    __shared__ int lmn[16], lmx[16];
+    const int tid = threadIdx.x, w = tid >> 6;
+    int mn = kHistBins, mx = -1;
+    for (int b = tid; b < kHistBins; b += kTmThreads)
+        if (hist[b]) { if (b < mn) mn = b; if (b > mx) mx = b; }
+    for (int off = 32; off > 0; off >>= 1) {
+        mn = min(mn, __shfl_xor(mn, off, 64));
+        mx = max(mx, __shfl_xor(mx, off, 64));
+    }
+    if ((tid & 63) == 0) { lmn[w] = mn; lmx[w] = mx; }
+    __syncthreads();
+    mn = kHistBins; mx = -1;
+    for (int q = 0; q < 16; ++q) { mn = min(mn, lmn[q]); mx = max(mx, lmx[q]); }
+    __syncthreads();
+    if (mx < 0) mn = mx = 0;                    // empty histogram (cannot happen for G >= 27)
+    if (mn == mx) {
+        if (tid == 0) {
+            km[0] = (double)mn; km[1] = (double)mx; km[2] = (double)mn - 1.0;
+            if (stats_iter) *stats_iter = 0;
+        }
+        return;
+    }
+    double cv = (double)mn, cl = (double)mx;
+    long long prev = -1;
+    int it;
+    for (it = 1; it <= 1000; ++it) {
+        double m = 0.5 * (cv + cl);
+        long long sv = 0, nv = 0, sl = 0, nl = 0;
+        for (int b = mn + tid; b <= mx; b += kTmThreads) {
+            long long c = hist[b];
+            if ((double)b > m) { sl += c * b; nl += c; }
+            else               { sv += c * b; nv += c; }
+        }
+        sv = block_sum_1024(sv, l64);
+        nv = block_sum_1024(nv, l64);
+        sl = block_sum_1024(sl, l64);
+        nl = block_sum_1024(nl, l64);
+        cv = (double)sv / (double)nv;
+        cl = (double)sl / (double)nl;
+        if (nl == prev) break;
+        prev = nl;
+    }
+    if (tid == 0) {
+        km[0] = cv; km[1] = cl; km[2] = 0.5 * (cv + cl);
+        if (stats_iter) *stats_iter = it;
+    }
+}
+
+// ---- labels and components ------------------------------------------------------------
+__global__ void k_threshold(const uint32_t *img, const double *km, int64_t G, uint8_t *raw, uint8_t *label)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= G) return;
+    uint8_t s = ((double)img[c] > km[2]) ? 0 : 1;
+    raw[c] = s;
+    label[c] = s;
+}
+
+__global__ void k_cc_init(const uint8_t *label, uint8_t phase, int64_t G, uint32_t *parent, uint32_t *csize)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= G) return;
+    parent[c] = label[c] == phase ? (uint32_t)c : kInvalid;
+    csize[c] = 0;
+}
+
+__device__ __forceinline__ uint32_t load_parent(uint32_t *parent, uint32_t x)
+{
+    return __hip_atomic_load(parent + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ uint32_t find_root(uint32_t *parent, uint32_t x)
+{
+    uint32_t p = load_parent(parent, x);
+    while (p != x) {
+        x = p;
+        p = load_parent(parent, x);
+    }
+    return x;
+}
+
+// Join the trees of a and b; the larger root is linked under the smaller one.
+__device__ void unite(uint32_t *parent, uint32_t a, uint32_t b)
+{
+    for (;;) {
+        a = find_root(parent, a);
+        b = find_root(parent, b);
+        if (a == b) return;
+        if (a < b) { uint32_t t = a; a = b; b = t; }
+        uint32_t old = atomicMin(parent + a, b);
+        if (old == a) return;
+        a = old;
+    }
+}
+
+__global__ void k_cc_merge(Grid g, const uint8_t *label, uint8_t phase, uint32_t *parent)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.G || label[c] != phase) return;
+    int64_t i, j, k;
+    coords(g, c, i, j, k);
+    int64_t nb[3] = {lin(g, i + 1 == g.n[0] ? 0 : i + 1, j, k),
+                     lin(g, i, j + 1 == g.n[1] ? 0 : j + 1, k),
+                     lin(g, i, j, k + 1 == g.n[2] ? 0 : k + 1)};
+    for (int q = 0; q < 3; ++q)
+        if (label[nb[q]] == phase) unite(parent, (uint32_t)c, (uint32_t)nb[q]);
+}
+
+__global__ void k_cc_flatten(int64_t G, uint32_t *parent)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= G) return;
+    uint32_t p = parent[c];
+    if (p == kInvalid) return;
+    parent[c] = find_root(parent, (uint32_t)c);
+}
+
+// Component sizes, counted only until they reach `limit` (only "size < limit" matters).
+__global__ void k_cc_size(int64_t G, const uint32_t *parent, uint32_t *csize, uint32_t limit)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t r = c < G ? parent[c] : kInvalid;
+    bool active = r != kInvalid;
+    const unsigned lane = __lane_id();
+    unsigned long long pending = __ballot(active);
+    while (pending) {
+        int leader = __ffsll((long long)pending) - 1;
+        uint32_t rl = __shfl(r, leader, 64);
+        unsigned long long peers = __ballot(active && r == rl);
+        if ((int)lane == leader) {
+            uint32_t cur = __hip_atomic_load(csize + rl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (cur < limit) atomicAdd(csize + rl, (uint32_t)__popcll(peers));
+        }
+        if (peers & (1ull << lane)) active = false;
+        pending &= ~peers;
+    }
+}
+
+__global__ void k_cc_flip(int64_t G, uint8_t *label, uint8_t phase, const uint32_t *parent,
+                          const uint32_t *csize, uint32_t limit, long long *stats, int slot)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool flip = false, root = false;
+    if (c < G && label[c] == phase) {
+        uint32_t r = parent[c];
+        if (csize[r] < limit) {
+            flip = true;
+            root = r == (uint32_t)c;
+            label[c] = (uint8_t)(1 - phase);
+        }
+    }
+    unsigned long long nf = __popcll(__ballot(flip));
+    unsigned long long nr = __popcll(__ballot(root));
+    if (__lane_id() == 0 && stats) {
+        if (nr) atomicAdd((unsigned long long *)(stats + slot), nr);
+        if (nf) atomicAdd((unsigned long long *)(stats + slot + 2), nf);
+    }
+}
+
+// ---- distance (Godunov relaxation) ----------------------------------------------------
+__device__ __forceinline__ void cswap(double &a, double &b, double &ha, double &hb)
+{
+    if (b < a) {
+        double t = a; a = b; b = t;
+        t = ha; ha = hb; hb = t;
+    }
+}
+
+// Larger root of sum_k ((d - a_k)^+ / h_k)^2 = 1 over the axes whose a_k lie below d.
+__device__ double godunov(double a0, double a1, double a2, double h0, double h1, double h2)
+{
+    cswap(a0, a1, h0, h1);
+    cswap(a1, a2, h1, h2);
+    cswap(a0, a1, h0, h1);
+    if (isinf(a0)) return INFINITY;
+    double d = a0 + h0;
+    if (d > a1) {
+        double w0 = 1.0 / (h0 * h0), w1 = 1.0 / (h1 * h1);
+        double sw = w0 + w1;
+        double swa = w0 * a0 + w1 * a1;
+        double dd = a0 - a1;
+        double disc = sw - w0 * w1 * (dd * dd);
+        if (disc < 0.0) disc = 0.0;
+        d = (swa + sqrt(disc)) / sw;
+        if (d > a2) {
+            double w2 = 1.0 / (h2 * h2);
+            sw = w0 + w1 + w2;
+            swa = w0 * a0 + w1 * a1 + w2 * a2;
+            double d01 = a0 - a1, d02 = a0 - a2, d12 = a1 - a2;
+            disc = sw - (w0 * w1 * (d01 * d01) + w0 * w2 * (d02 * d02) + w1 * w2 * (d12 * d12));
+            if (disc < 0.0) disc = 0.0;
+            d = (swa + sqrt(disc)) / sw;
+        }
+    }
+    return d;
+}
+
+__global__ void k_dist_init(const uint8_t *label, int64_t G, double *dist)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < G) dist[c] = label[c] == 1 ? 0.0 : INFINITY;
+}
+
+__global__ void __launch_bounds__(kBlock) k_dist_sweep(Grid g, const uint8_t *label, double *dist,
+                                                       double cap, uint32_t *changed, int it)
+{
+    if (it > 0 && __hip_atomic_load(changed + it - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        return;                                    // the previous sweep changed nothing: converged
+    bool ch = false;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < g.G;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        if (label[c] == 1) continue;
+        int64_t i, j, k;
+        coords(g, c, i, j, k);
+        double ax = fmin(dist[lin(g, i == 0 ? g.n[0] - 1 : i - 1, j, k)],
+                         dist[lin(g, i == g.n[0] - 1 ? 0 : i + 1, j, k)]);
+        double ay = fmin(dist[lin(g, i, j == 0 ? g.n[1] - 1 : j - 1, k)],
+                         dist[lin(g, i, j == g.n[1] - 1 ? 0 : j + 1, k)]);
+        double az = fmin(dist[lin(g, i, j, k == 0 ? g.n[2] - 1 : k - 1)],
+                         dist[lin(g, i, j, k == g.n[2] - 1 ? 0 : k + 1)]);
+        if (isinf(ax) && isinf(ay) && isinf(az)) continue;
+        double db = godunov(ax, ay, az, g.h[0], g.h[1], g.h[2]);
+        if (db <= cap && db < dist[c]) {
+            dist[c] = db;
+            ch = true;
+        }
+    }
+    if (__ballot(ch) && __lane_id() == 0) changed[it] = 1u;
+}
+
+__global__ void k_dist_finish(const uint32_t *changed, int max_sweeps, long long *sweeps, uint32_t *flags)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int used = max_sweeps;
+    for (int s = 0; s < max_sweeps; ++s)
+        if (changed[s] == 0) { used = s + 1; break; }
+    if (sweeps) *sweeps = used;
+    if (changed[max_sweeps - 1] != 0) atomicOr(flags, kFlagNotConverged);
+}
+
+__global__ void k_cap_copy(const double *dist, double cap, double *out, int64_t G)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < G) out[c] = fmin(dist[c], cap);
+}
+
+// ---- per-particle distance and cutoff -------------------------------------------------
+__device__ __forceinline__ double lerp(double a, double b, double t) { return a + t * (b - a); }
+
+__global__ void k_cutoffs(Grid g, PSet s, int64_t n, const double *dist, double cap, double rc_min,
+                          double rc_max, double alpha, double a, double b)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    double4 q = s.pos[p];
+    double x[3] = {q.x, q.y, q.z};
+    int64_t i0[3], i1[3];
+    double t[3];
+    for (int k = 0; k < 3; ++k) {
+        double u = x[k] / g.h[k] - 0.5;
+        if (!isfinite(u)) u = 0.0;                 // keeps the gathers inside the grid
+        double f = floor(u);
+        t[k] = u - f;
+        int64_t fi = (int64_t)f % g.n[k];
+        if (fi < 0) fi += g.n[k];
+        i0[k] = fi;
+        i1[k] = fi + 1 == g.n[k] ? 0 : fi + 1;
+    }
+#define DV(ii, jj, kk) fmin(dist[lin(g, ii, jj, kk)], cap)
+    double c00 = lerp(DV(i0[0], i0[1], i0[2]), DV(i1[0], i0[1], i0[2]), t[0]);
+    double c10 = lerp(DV(i0[0], i1[1], i0[2]), DV(i1[0], i1[1], i0[2]), t[0]);
+    double c01 = lerp(DV(i0[0], i0[1], i1[2]), DV(i1[0], i0[1], i1[2]), t[0]);
+    double c11 = lerp(DV(i0[0], i1[1], i1[2]), DV(i1[0], i1[1], i1[2]), t[0]);
+#undef DV
+    double c0 = lerp(c00, c10, t[1]);
+    double c1 = lerp(c01, c11, t[1]);
+    double d = lerp(c0, c1, t[2]);
+    double rc;
+    if (rc_min == rc_max || d <= 0.0) rc = rc_max;
+    else if (d >= rc_max) rc = rc_min;
+    else rc = a * exp2(alpha * (rc_max - d)) + b;
+    q.w = rc;
+    s.pos[p] = q;
+}
+
+}  // namespace
+
+void launch_count_from_ranges(const uint32_t *cell_start, int64_t G, uint32_t *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_count_from_ranges, dim3(grid1(G)), dim3(kBlock), 0, st, cell_start, G, out);
+}
+
+// `passes` rounds of x, y, z [1,2,1] passes; the first reads counts from cell ranges when
+// cell_start is given (else from `in`); the result always ends in `out`.
+void launch_smooth(const Grid &g, int passes, const uint32_t *cell_start, const uint32_t *in,
+                   uint32_t *out, uint32_t *tmp, hipStream_t st)
+{
+    if (passes == 0) {
+        if (cell_start) launch_count_from_ranges(cell_start, g.G, out, st);
+        else launch_copy_bytes(out, in, sizeof(uint32_t) * (size_t)g.G, st);
+        return;
+    }
+    int total = 3 * passes;
+    const uint32_t *src = in;
+    const uint32_t *cs = cell_start;
+    for (int s = 0; s < total; ++s) {
+        uint32_t *dst = ((total - 1 - s) % 2 == 0) ? out : tmp;
+        hipLaunchKernelGGL(k_smooth_axis, dim3(grid1(g.G)), dim3(kBlock), 0, st, g, src, cs, dst, s % 3);
+        src = dst;
+        cs = nullptr;
+    }
+}
+
+void launch_two_means(const Grid &g, const uint32_t *img, GridWork w, long long *stats_out,
+                      hipStream_t st)
+{
+    launch_fill_u32(w.hist, 0u, kHistBins, st);
+    unsigned nb = (unsigned)std::min<int64_t>((g.G + kBlock - 1) / kBlock, 1024);
+    hipLaunchKernelGGL(k_hist, dim3(nb), dim3(kBlock), 0, st, img, g.G, w.hist, w.flags);
+    hipLaunchKernelGGL(k_two_means, dim3(1), dim3(kTmThreads), 0, st, w.hist, w.km, stats_out);
+}
+
+void launch_segment(const Grid &g, const uint32_t *img, const double *km, int32_t min_component,
+                    GridWork w, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_threshold, dim3(grid1(g.G)), dim3(kBlock), 0, st, img, km, g.G, w.raw, w.label);
+    if (min_component <= 1) return;                 // no component can be smaller
+    for (int pass = 0; pass < 2; ++pass) {
+        uint8_t phase = pass == 0 ? 1 : 0;
+        hipLaunchKernelGGL(k_cc_init, dim3(grid1(g.G)), dim3(kBlock), 0, st, w.label, phase, g.G,
+                           w.parent, w.csize);
+        hipLaunchKernelGGL(k_cc_merge, dim3(grid1(g.G)), dim3(kBlock), 0, st, g, w.label, phase, w.parent);
+        hipLaunchKernelGGL(k_cc_flatten, dim3(grid1(g.G)), dim3(kBlock), 0, st, g.G, w.parent);
+        hipLaunchKernelGGL(k_cc_size, dim3(grid1(g.G)), dim3(kBlock), 0, st, g.G, w.parent, w.csize,
+                           (uint32_t)min_component);
+        hipLaunchKernelGGL(k_cc_flip, dim3(grid1(g.G)), dim3(kBlock), 0, st, g.G, w.label, phase,
+                           w.parent, w.csize, (uint32_t)min_component, w.stats, 1 + pass);
+    }
+}
+
+// In-place relaxation converges within a few sweeps per box of band depth; the bound leaves
+// a wide margin and is reported as non-convergence if ever reached.
+int max_distance_sweeps(const Grid &g, double cap)
+{
+    double hmin = std::min(g.h[0], std::min(g.h[1], g.h[2]));
+    int depth = (int)std::ceil(cap / hmin);
+    return 4 * depth + 16;
+}
+
+void launch_distance(const Grid &g, double cap, const uint8_t *label, double *dist, GridWork w,
+                     hipStream_t st)
+{
+    int ms = max_distance_sweeps(g, cap);
+    launch_fill_u32(w.changed, 0u, ms + 1, st);
+    hipLaunchKernelGGL(k_dist_init, dim3(grid1(g.G)), dim3(kBlock), 0, st, label, g.G, dist);
+    unsigned nb = (unsigned)std::min<int64_t>((g.G + kBlock - 1) / kBlock, 4096);
+    for (int it = 0; it < ms; ++it)
+        hipLaunchKernelGGL(k_dist_sweep, dim3(nb), dim3(kBlock), 0, st, g, label, dist, cap, w.changed, it);
+    hipLaunchKernelGGL(k_dist_finish, dim3(1), dim3(64), 0, st, w.changed, ms, w.stats + 5, w.flags);
+}
+
+void launch_cap_copy(const double *dist, double cap, double *out, int64_t G, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cap_copy, dim3(grid1(G)), dim3(kBlock), 0, st, dist, cap, out, G);
+}
+
+void launch_cutoffs(const Grid &g, PSet s, int64_t n, const double *dist, double cap, double rc_min,
+                    double rc_max, double alpha, double a, double b, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cutoffs, dim3(grid1(n)), dim3(kBlock), 0, st, g, s, n, dist, cap, rc_min,
+                       rc_max, alpha, a, b);
+}
+
+}  // namespace dcm

@@ -1,0 +1,282 @@
+// integrate.hip -- velocity-Verlet integration of Eq. 1-2 and the fixed-order reductions.
+//
+// A step is: v += dt/(2m) F, x += dt v, periodic wrap, re-binning, (detection), forces,
+// v += dt/(2m) F. The closing half-kick of one step and the opening half-kick and drift of the
+// next read the same forces, so inside a multi-step call they run as one streaming kernel
+// (the kinetic energy of the completed step is taken between the two kicks); the arithmetic is
+// the same sequence of operations as two separate kernels. Thermodynamic sums are formed per
+// workgroup and then over workgroups in a fixed order, so every run gives the same bits.
+#include "internal.h"
+
+namespace dcm {
+
+namespace {
+
+inline unsigned grid1(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+__device__ __forceinline__ double wrap1(double x, double L)
+{
+    double t = x - L * floor(x / L);
+    if (t < 0.0) t += L;
+    if (t >= L) t = 0.0;
+    return t;
+}
+
+__device__ __forceinline__ int32_t box_of(double x, double h, int32_t N)
+{
+    double f = floor(x / h);
+    int32_t i = (int32_t)f;
+    if (f > (double)(N - 1)) i = N - 1;
+    if (i < 0) i = 0;
+    return i;
+}
+
+__device__ double block_sum(double v)
+{
+    __shared__ double lds[kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int q = 0; q < kBlock / 64; ++q) s += lds[q];
+    return s;
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t count)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+__global__ void k_copy_bytes(uint8_t *dst, const uint8_t *src, size_t bytes)
+{
+    size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 16;
+    if (i + 16 <= bytes && (((uintptr_t)dst | (uintptr_t)src) & 15) == 0) {
+        *(uint4 *)(dst + i) = *(const uint4 *)(src + i);
+    } else {
+        for (size_t q = i; q < i + 16 && q < bytes; ++q) dst[q] = src[q];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_kick_drift_key(Grid g, PSet s, const double *fx,
+                                                           const double *fy, const double *fz,
+                                                           int64_t n, double hdt, double dt,
+                                                           int second_kick, uint32_t *key,
+                                                           uint32_t *val, Partial *ke_partials)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double ke = 0.0;
+    if (i < n) {
+        double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
+        const double f0 = fx[i], f1 = fy[i], f2 = fz[i];
+        if (second_kick) {            // close the previous step
+            vx = vx + hdt * f0;
+            vy = vy + hdt * f1;
+            vz = vz + hdt * f2;
+            ke = vx * vx + vy * vy + vz * vz;
+        }
+        vx = vx + hdt * f0;
+        vy = vy + hdt * f1;
+        vz = vz + hdt * f2;
+        double4 p = s.pos[i];
+        p.x = wrap1(p.x + dt * vx, g.L[0]);
+        p.y = wrap1(p.y + dt * vy, g.L[1]);
+        p.z = wrap1(p.z + dt * vz, g.L[2]);
+        s.pos[i] = p;
+        s.vx[i] = vx;
+        s.vy[i] = vy;
+        s.vz[i] = vz;
+        int32_t a = box_of(p.x, g.h[0], g.n[0]);
+        int32_t b = box_of(p.y, g.h[1], g.n[1]);
+        int32_t c = box_of(p.z, g.h[2], g.n[2]);
+        key[i] = (uint32_t)(((int64_t)c * g.n[1] + b) * g.n[0] + a);
+        val[i] = (uint32_t)i;
+    }
+    if (second_kick) {
+        double t = block_sum(ke);
+        if (threadIdx.x == 0) ke_partials[blockIdx.x].ke = t;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_kick(PSet s, const double *fx, const double *fy,
+                                                 const double *fz, int64_t n, double hdt,
+                                                 int apply, Partial *ke_partials)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double ke = 0.0;
+    if (i < n) {
+        double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
+        if (apply) {
+            vx = vx + hdt * fx[i];
+            vy = vy + hdt * fy[i];
+            vz = vz + hdt * fz[i];
+            s.vx[i] = vx;
+            s.vy[i] = vy;
+            s.vz[i] = vz;
+        }
+        ke = vx * vx + vy * vy + vz * vz;
+    }
+    double t = block_sum(ke);
+    if (threadIdx.x == 0) ke_partials[blockIdx.x].ke = t;
+}
+
+constexpr int kRedThreads = 1024;
+
+// Sums of the force-workgroup partials (e, W, pairs) and kick-workgroup partials (sum v^2) in
+// a fixed order: thread t adds partials t, t + 1024, ...; then a fixed tree.
+__global__ void __launch_bounds__(kRedThreads) k_reduce_thermo(const Partial *fp, int nf,
+                                                               const Partial *kp, int nk,
+                                                               double mass, long long step,
+                                                               dcm_thermo *out)
+{
+    __shared__ double lds[kRedThreads / 64][8];
+    __shared__ long long ldp[kRedThreads / 64];
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    long long pc = 0;
+    for (int q = threadIdx.x; q < nf; q += kRedThreads) {
+        v[0] += fp[q].e;
+        for (int r = 0; r < 6; ++r) v[1 + r] += fp[q].w[r];
+        pc += fp[q].pairs;
+    }
+    for (int q = threadIdx.x; q < nk; q += kRedThreads) v[7] += kp[q].ke;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+        for (int off = 32; off > 0; off >>= 1) v[r] += __shfl_xor(v[r], off, 64);
+    for (int off = 32; off > 0; off >>= 1) pc += __shfl_xor(pc, off, 64);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        for (int r = 0; r < 8; ++r) lds[w][r] = v[r];
+        ldp[w] = pc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        dcm_thermo t = {};
+        double ke = 0.0;
+        for (int q = 0; q < kRedThreads / 64; ++q) {
+            t.pe += lds[q][0];
+            for (int r = 0; r < 6; ++r) t.virial[r] += lds[q][1 + r];
+            ke += lds[q][7];
+            t.pairs += ldp[q];
+        }
+        t.ke = 0.5 * mass * ke;
+        t.step = step;
+        *out = t;
+    }
+}
+
+__global__ void k_unsort(PSet s, const double *fx, const double *fy, const double *fz, int64_t n,
+                         double *x_out, double *v_out, double *rc_out, double *f_out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t id = s.id[i];
+    if (x_out || rc_out) {
+        double4 p = s.pos[i];
+        if (x_out) { x_out[id] = p.x; x_out[n + id] = p.y; x_out[2 * n + id] = p.z; }
+        if (rc_out) rc_out[id] = p.w;
+    }
+    if (v_out) { v_out[id] = s.vx[i]; v_out[n + id] = s.vy[i]; v_out[2 * n + id] = s.vz[i]; }
+    if (f_out) { f_out[id] = fx[i]; f_out[n + id] = fy[i]; f_out[2 * n + id] = fz[i]; }
+}
+
+__global__ void k_load_state(PSet s, const double *x, const double *v, const double *rc, int64_t n,
+                             double rc_fill)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    s.pos[i] = make_double4(x[i], x[n + i], x[2 * n + i], rc ? rc[i] : rc_fill);
+    s.vx[i] = v[i];
+    s.vy[i] = v[n + i];
+    s.vz[i] = v[2 * n + i];
+    s.id[i] = (uint32_t)i;
+}
+
+__global__ void k_scatter_rc(PSet s, const double *rc_in, int64_t n, double rc_min, double rc_max,
+                             uint32_t *flags)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double r = rc_in[s.id[i]];
+    if (!(r >= rc_min && r <= rc_max)) atomicOr(flags, kFlagBadCutoff);
+    s.pos[i].w = r;
+}
+
+__global__ void k_check_finite(const double *a, int64_t count, uint32_t *flags)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = i < count && !isfinite(a[i]);
+    if (__ballot(bad) && __lane_id() == 0) atomicOr(flags, kFlagNonFinite);
+}
+
+}  // namespace
+
+int stream_blocks(int64_t n) { return (int)grid1(n); }
+
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t st)
+{
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid1(count)), dim3(kBlock), 0, st, p, v, count);
+}
+
+void launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t st)
+{
+    if (bytes == 0) return;
+    size_t chunks = (bytes + 15) / 16;
+    hipLaunchKernelGGL(k_copy_bytes, dim3(grid1((int64_t)chunks)), dim3(kBlock), 0, st,
+                       (uint8_t *)dst, (const uint8_t *)src, bytes);
+}
+
+void launch_kick_drift_key(const Grid &g, PSet s, const double *fx, const double *fy,
+                           const double *fz, int64_t n, double hdt, double dt, int second_kick,
+                           uint32_t *key, uint32_t *val, Partial *ke_partials, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_kick_drift_key, dim3(grid1(n)), dim3(kBlock), 0, st, g, s, fx, fy, fz, n,
+                       hdt, dt, second_kick, key, val, ke_partials);
+}
+
+void launch_kick(PSet s, const double *fx, const double *fy, const double *fz, int64_t n,
+                 double hdt, Partial *ke_partials, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_kick, dim3(grid1(n)), dim3(kBlock), 0, st, s, fx, fy, fz, n, hdt, 1,
+                       ke_partials);
+}
+
+void launch_ke_only(PSet s, int64_t n, Partial *ke_partials, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_kick, dim3(grid1(n)), dim3(kBlock), 0, st, s, (const double *)nullptr,
+                       (const double *)nullptr, (const double *)nullptr, n, 0.0, 0, ke_partials);
+}
+
+void launch_reduce_thermo(const Partial *force_parts, int nforce, const Partial *ke_parts, int nke,
+                          double mass, long long step, dcm_thermo *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce_thermo, dim3(1), dim3(kRedThreads), 0, st, force_parts, nforce,
+                       ke_parts, nke, mass, step, out);
+}
+
+void launch_unsort(PSet s, const double *fx, const double *fy, const double *fz, int64_t n,
+                   double *x_out, double *v_out, double *rc_out, double *f_out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_unsort, dim3(grid1(n)), dim3(kBlock), 0, st, s, fx, fy, fz, n, x_out, v_out,
+                       rc_out, f_out);
+}
+
+void launch_load_state(PSet s, const double *x, const double *v, const double *rc, int64_t n,
+                       double rc_fill, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_load_state, dim3(grid1(n)), dim3(kBlock), 0, st, s, x, v, rc, n, rc_fill);
+}
+
+void launch_scatter_rc(PSet s, const double *rc_in, int64_t n, double rc_min, double rc_max,
+                       uint32_t *flags, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scatter_rc, dim3(grid1(n)), dim3(kBlock), 0, st, s, rc_in, n, rc_min, rc_max,
+                       flags);
+}
+
+void launch_check_finite(const double *a, int64_t count, uint32_t *flags, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_check_finite, dim3(grid1(count)), dim3(kBlock), 0, st, a, count, flags);
+}
+
+}  // namespace dcm

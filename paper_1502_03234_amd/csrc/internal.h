@@ -1,0 +1,134 @@
+// internal.h -- shared declarations of libdcm's HIP translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/dcm.h"
+
+namespace dcm {
+
+constexpr int kBlock = 256;               // threads per workgroup for streaming kernels
+constexpr int kHistBins = 65536;          // capacity of the smoothed-value histogram
+constexpr uint32_t kInvalid = 0xFFFFFFFFu;
+
+// sticky device condition bits (dcm_check)
+constexpr uint32_t kFlagNonFinite = 1u;
+constexpr uint32_t kFlagHistOverflow = 2u;
+constexpr uint32_t kFlagNotConverged = 4u;
+constexpr uint32_t kFlagBadCutoff = 8u;
+
+// Grid geometry shared by every kernel that maps positions to boxes (Eq. 10).
+struct Grid {
+    int32_t n[3];       // N_x, N_y, N_z
+    double h[3];        // box edges L_k / N_k
+    double L[3];        // periodic box
+    int64_t G;          // N_x N_y N_z
+};
+
+// One copy of the per-particle state in cell-sorted order.
+struct PSet {
+    double4 *pos;       // x, y, z, r_c
+    double *vx, *vy, *vz;
+    uint32_t *id;       // caller index of the particle in this slot
+};
+
+// Per-block partial sums written by the force and kick kernels, reduced in fixed order.
+struct Partial {
+    double e, w[6], ke;
+    long long pairs;
+    long long pad;
+};
+
+// Scratch of the grid pipeline (interface detection), G entries each unless noted.
+struct GridWork {
+    uint32_t *cell_start;   // [G + 1] first sorted slot of each box (Eq. 9 counts = differences)
+    uint32_t *g;            // smoothed image
+    uint32_t *gtmp;         // smoothing ping-pong
+    uint8_t *raw;           // threshold labels
+    uint8_t *label;         // labels after component removal
+    uint32_t *parent;       // union-find parents (component = smallest member index)
+    uint32_t *csize;        // component sizes (saturating at min_component)
+    double *dist;           // box-interface distances
+    uint32_t *hist;         // [kHistBins]
+    double *km;             // [3] rho_v, rho_l, threshold
+    long long *stats;       // [8] detection statistics
+    uint32_t *changed;      // [max sweeps + 1] per-sweep change counters
+    uint32_t *flags;        // [1] sticky device conditions
+};
+
+// ---- launchers (each enqueues on `st`; no synchronization) ------------------------------
+// sort.hip
+size_t sort_scratch_bytes(int64_t n);
+void launch_wrap_key(const Grid &g, PSet s, int64_t n, uint32_t *key, uint32_t *val, hipStream_t st);
+void launch_init_ids(PSet s, int64_t n, hipStream_t st);
+void launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key_alt, uint32_t *val_alt,
+                       void *scratch, int64_t n, int bits, hipStream_t st);
+void launch_cell_ranges(const uint32_t *key_sorted, int64_t n, int64_t G, uint32_t *cell_start,
+                        hipStream_t st);
+void launch_cell_fixup(const uint32_t *cell_start, int64_t G, uint32_t *val, const uint32_t *id_old,
+                       hipStream_t st);
+void launch_gather(PSet from, PSet to, const uint32_t *perm, int64_t n, hipStream_t st);
+
+// detect.hip
+void launch_smooth(const Grid &g, int passes, const uint32_t *cell_start, const uint32_t *in,
+                   uint32_t *out, uint32_t *tmp, hipStream_t st);
+void launch_two_means(const Grid &g, const uint32_t *img, GridWork w, long long *stats_out,
+                      hipStream_t st);
+void launch_segment(const Grid &g, const uint32_t *img, const double *km, int32_t min_component,
+                    GridWork w, hipStream_t st);
+int max_distance_sweeps(const Grid &g, double cap);
+void launch_distance(const Grid &g, double cap, const uint8_t *label, double *dist, GridWork w,
+                     hipStream_t st);
+void launch_cutoffs(const Grid &g, PSet s, int64_t n, const double *dist, double cap,
+                    double rc_min, double rc_max, double alpha, double a, double b, hipStream_t st);
+void launch_cap_copy(const double *dist, double cap, double *out, int64_t G, hipStream_t st);
+void launch_count_from_ranges(const uint32_t *cell_start, int64_t G, uint32_t *out, hipStream_t st);
+
+// force.hip
+struct ForceArgs {
+    Grid grid;
+    const double4 *pos;
+    const uint32_t *cell_start;
+    const uint32_t *id;
+    int64_t n;
+    double eps24, eps4, sigma2;
+    double rc_max;          // largest cutoff (search radius of the symmetric rule)
+    int pair_rule;
+    int energy_shift;
+    int precision;
+    double *fx, *fy, *fz;
+    double *e_out;          // per-atom energy in caller order (optional)
+    double *w_out;          // per-atom virial [6][n] in caller order (optional)
+    uint32_t *pairs_out;    // per-atom pair count in caller order (optional)
+    Partial *partials;      // [force_blocks(n)]
+    uint32_t *flags;
+};
+int force_blocks(int64_t n);
+void launch_forces(const ForceArgs &a, hipStream_t st);
+
+// integrate.hip
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t st);
+void launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t st);
+int stream_blocks(int64_t n);
+void launch_kick_drift_key(const Grid &g, PSet s, const double *fx, const double *fy,
+                           const double *fz, int64_t n, double hdt, double dt, int second_kick,
+                           uint32_t *key, uint32_t *val, Partial *ke_partials, hipStream_t st);
+void launch_kick(PSet s, const double *fx, const double *fy, const double *fz, int64_t n,
+                 double hdt, Partial *ke_partials, hipStream_t st);
+void launch_ke_only(PSet s, int64_t n, Partial *ke_partials, hipStream_t st);
+void launch_reduce_thermo(const Partial *force_parts, int nforce, const Partial *ke_parts, int nke,
+                          double mass, long long step, dcm_thermo *out, hipStream_t st);
+void launch_unsort(PSet s, const double *fx, const double *fy, const double *fz, int64_t n,
+                   double *x_out, double *v_out, double *rc_out, double *f_out, hipStream_t st);
+void launch_load_state(PSet s, const double *x, const double *v, const double *rc, int64_t n,
+                       double rc_fill, hipStream_t st);
+void launch_scatter_rc(PSet s, const double *rc_in, int64_t n, double rc_min, double rc_max,
+                       uint32_t *flags, hipStream_t st);
+void launch_check_finite(const double *a, int64_t count, uint32_t *flags, hipStream_t st);
+
+}  // namespace dcm

@@ -1,0 +1,315 @@
+// sort.hip -- binning of particles into boxes by sort-and-segment (Section 4, Eq. 9-10).
+//
+// Each particle gets the linear index of the box containing it (x fastest). The particles
+// are then sorted by that key with a stable LSD radix sort whose per-tile ranks come from
+// wavefront ballots (no atomics anywhere), the first slot of every box is found where the
+// sorted key changes, and slots inside a box are ordered by particle id so that the
+// internal order -- and with it every summation order -- is a function of the state alone.
+// The box counts b_ijk of Eq. 9 are differences of consecutive box starts.
+#include "internal.h"
+
+namespace dcm {
+
+namespace {
+
+constexpr int kRadixBits = 8;
+constexpr int kDigits = 1 << kRadixBits;
+constexpr int kItems = 8;                          // keys per thread per tile
+constexpr int kWaves = kBlock / 64;
+constexpr int kTile = kBlock * kItems;             // 2048 keys per tile
+
+__device__ __forceinline__ double wrap1(double x, double L)
+{
+    double t = x - L * floor(x / L);
+    if (t < 0.0) t += L;
+    if (t >= L) t = 0.0;
+    return t;
+}
+
+__device__ __forceinline__ int32_t box_of(double x, double h, int32_t N)
+{
+    double f = floor(x / h);
+    int32_t i = (int32_t)f;
+    if (f > (double)(N - 1)) i = N - 1;
+    if (i < 0) i = 0;
+    return i;
+}
+
+__global__ void k_wrap_key(Grid g, PSet s, int64_t n, uint32_t *key, uint32_t *val)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double4 p = s.pos[i];
+    p.x = wrap1(p.x, g.L[0]);
+    p.y = wrap1(p.y, g.L[1]);
+    p.z = wrap1(p.z, g.L[2]);
+    s.pos[i] = p;
+    int32_t a = box_of(p.x, g.h[0], g.n[0]);
+    int32_t b = box_of(p.y, g.h[1], g.n[1]);
+    int32_t c = box_of(p.z, g.h[2], g.n[2]);
+    key[i] = (uint32_t)(((int64_t)c * g.n[1] + b) * g.n[0] + a);
+    val[i] = (uint32_t)i;
+}
+
+__global__ void k_init_ids(PSet s, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) s.id[i] = (uint32_t)i;
+}
+
+__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+
+// Lanes of the current wave (among `valid` ones) whose digit equals this lane's.
+__device__ __forceinline__ unsigned long long peer_mask(uint32_t digit, bool valid)
+{
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        bool bit = (digit >> b) & 1u;
+        unsigned long long bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+    }
+    return peers;
+}
+
+// Per-tile digit counts: tile_counts[d * ntiles + t].
+__global__ void __launch_bounds__(kBlock) k_radix_count(const uint32_t *key, int64_t n, int shift,
+                                                        uint32_t *tile_counts, int64_t ntiles)
+{
+    __shared__ uint32_t whist[kWaves][kDigits];
+    const int tid = threadIdx.x, w = tid >> 6;
+    const unsigned lane = lane_id();
+    for (int d = tid; d < kWaves * kDigits; d += kBlock) (&whist[0][0])[d] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)w * 64 * kItems;
+    for (int r = 0; r < kItems; ++r) {
+        int64_t i = base + r * 64 + lane;
+        bool valid = i < n;
+        uint32_t digit = valid ? (key[i] >> shift) & (kDigits - 1) : 0u;
+        unsigned long long peers = peer_mask(digit, valid);
+        unsigned long long lower = peers & ((1ull << lane) - 1ull);
+        if (valid && lower == 0ull) whist[w][digit] += (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    for (int d = tid; d < kDigits; d += kBlock) {
+        uint32_t c = 0;
+        for (int q = 0; q < kWaves; ++q) c += whist[q][d];
+        tile_counts[(int64_t)d * ntiles + blockIdx.x] = c;
+    }
+}
+
+// Exclusive scan of 256 values held one per thread (blockDim == 256); returns the total.
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *out_excl, uint32_t *lds /*[kWaves]*/)
+{
+    const int tid = threadIdx.x, w = tid >> 6;
+    const unsigned lane = lane_id();
+    uint32_t incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t t = __shfl_up(incl, off, 64);
+        if (lane >= (unsigned)off) incl += t;
+    }
+    if (lane == 63) lds[w] = incl;
+    __syncthreads();
+    uint32_t wbase = 0, total = 0;
+    for (int q = 0; q < kWaves; ++q) {
+        if (q < w) wbase += lds[q];
+        total += lds[q];
+    }
+    *out_excl = wbase + incl - v;
+    __syncthreads();
+    return total;
+}
+
+// One block per digit: exclusive scan of its per-tile counts (in place) and the digit total.
+__global__ void __launch_bounds__(kBlock) k_digit_scan(uint32_t *tile_counts, int64_t ntiles,
+                                                       uint32_t *digit_total)
+{
+    __shared__ uint32_t lds[kWaves];
+    uint32_t *row = tile_counts + (int64_t)blockIdx.x * ntiles;
+    uint32_t carry = 0;
+    for (int64_t start = 0; start < ntiles; start += kBlock * 4) {
+        uint32_t v[4], s = 0;
+        for (int q = 0; q < 4; ++q) {
+            int64_t t = start + (int64_t)threadIdx.x * 4 + q;
+            v[q] = t < ntiles ? row[t] : 0u;
+            s += v[q];
+        }
+        uint32_t excl;
+        uint32_t total = block_exclusive_scan(s, &excl, lds);
+        uint32_t run = carry + excl;
+        for (int q = 0; q < 4; ++q) {
+            int64_t t = start + (int64_t)threadIdx.x * 4 + q;
+            if (t < ntiles) row[t] = run;
+            run += v[q];
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
+}
+
+// Stable scatter of one radix pass.
+__global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t *key, const uint32_t *val,
+                                                          uint32_t *key_out, uint32_t *val_out,
+                                                          int64_t n, int shift,
+                                                          const uint32_t *tile_prefix, int64_t ntiles,
+                                                          const uint32_t *digit_total)
+{
+    __shared__ uint32_t whist[kWaves][kDigits];
+    __shared__ uint32_t gbase[kDigits];
+    __shared__ uint32_t lds[kWaves];
+    const int tid = threadIdx.x, w = tid >> 6;
+    const unsigned lane = lane_id();
+    for (int d = tid; d < kWaves * kDigits; d += kBlock) (&whist[0][0])[d] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)w * 64 * kItems;
+    uint32_t k[kItems], v[kItems], dg[kItems], rk[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        int64_t i = base + r * 64 + lane;
+        bool valid = i < n;
+        k[r] = valid ? key[i] : 0u;
+        v[r] = valid ? val[i] : 0u;
+        uint32_t digit = (k[r] >> shift) & (kDigits - 1);
+        dg[r] = digit;
+        unsigned long long peers = peer_mask(digit, valid);
+        unsigned long long lower = peers & ((1ull << lane) - 1ull);
+        rk[r] = whist[w][digit] + (uint32_t)__popcll(lower);
+        if (valid && lower == 0ull) whist[w][digit] += (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    {
+        // digit base = exclusive scan over digit totals + this tile's prefix for the digit;
+        // per-wave bases = exclusive scan over the waves of the tile
+        uint32_t excl;
+        block_exclusive_scan(digit_total[tid], &excl, lds);
+        uint32_t acc = 0;
+        for (int q = 0; q < kWaves; ++q) {
+            uint32_t c = whist[q][tid];
+            whist[q][tid] = acc;
+            acc += c;
+        }
+        gbase[tid] = excl + tile_prefix[(int64_t)tid * ntiles + blockIdx.x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        int64_t i = base + r * 64 + lane;
+        if (i < n) {
+            uint32_t dst = gbase[dg[r]] + whist[w][dg[r]] + rk[r];
+            key_out[dst] = k[r];
+            val_out[dst] = v[r];
+        }
+    }
+}
+
+// Box starts from sorted keys: the slot where key changes from a to b is the start of every
+// box in (a, b]; boxes before the first key start at 0, after the last at n.
+__global__ void k_cell_ranges(const uint32_t *key, int64_t n, int64_t G, uint32_t *cell_start)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    int64_t lo = (i == 0) ? 0 : (int64_t)key[i - 1] + 1;
+    int64_t hi = (i == n) ? G : (int64_t)key[i];
+    for (int64_t c = lo; c <= hi; ++c) cell_start[c] = (uint32_t)i;
+}
+
+// Inside each box, order slots by particle id (insertion sort; boxes hold a few particles).
+__global__ void k_cell_fixup(const uint32_t *cell_start, int64_t G, uint32_t *val, const uint32_t *id)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= G) return;
+    uint32_t s = cell_start[c], e = cell_start[c + 1];
+    if (e - s < 2) return;
+    for (uint32_t q = s + 1; q < e; ++q) {
+        uint32_t vq = val[q];
+        uint32_t iq = id[vq];
+        uint32_t j = q;
+        while (j > s) {
+            uint32_t vp = val[j - 1];
+            if (id[vp] <= iq) break;
+            val[j] = vp;
+            --j;
+        }
+        val[j] = vq;
+    }
+}
+
+__global__ void k_gather(PSet from, PSet to, const uint32_t *perm, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t o = perm[i];
+    to.pos[i] = from.pos[o];
+    to.vx[i] = from.vx[o];
+    to.vy[i] = from.vy[o];
+    to.vz[i] = from.vz[o];
+    to.id[i] = from.id[o];
+}
+
+inline unsigned grid1(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+size_t sort_scratch_bytes(int64_t n)
+{
+    int64_t ntiles = (n + kTile - 1) / kTile;
+    return sizeof(uint32_t) * ((size_t)kDigits * (size_t)ntiles + kDigits);
+}
+
+void launch_wrap_key(const Grid &g, PSet s, int64_t n, uint32_t *key, uint32_t *val, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_wrap_key, dim3(grid1(n)), dim3(kBlock), 0, st, g, s, n, key, val);
+}
+
+void launch_init_ids(PSet s, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_init_ids, dim3(grid1(n)), dim3(kBlock), 0, st, s, n);
+}
+
+// Sorts (key, val) by key over the low `bits` bits. The result ends in (key, val): an odd
+// number of passes finishes with a copy back from the alternate buffers.
+void launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key_alt, uint32_t *val_alt,
+                       void *scratch, int64_t n, int bits, hipStream_t st)
+{
+    int64_t ntiles = (n + kTile - 1) / kTile;
+    uint32_t *tile_counts = (uint32_t *)scratch;
+    uint32_t *digit_total = tile_counts + (size_t)kDigits * ntiles;
+    uint32_t *ki = key, *vi = val, *ko = key_alt, *vo = val_alt;
+    int passes = (bits + kRadixBits - 1) / kRadixBits;
+    for (int p = 0; p < passes; ++p) {
+        int shift = p * kRadixBits;
+        hipLaunchKernelGGL(k_radix_count, dim3((unsigned)ntiles), dim3(kBlock), 0, st, ki, n, shift,
+                           tile_counts, ntiles);
+        hipLaunchKernelGGL(k_digit_scan, dim3(kDigits), dim3(kBlock), 0, st, tile_counts, ntiles,
+                           digit_total);
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(kBlock), 0, st, ki, vi, ko,
+                           vo, n, shift, tile_counts, ntiles, digit_total);
+        uint32_t *t = ki; ki = ko; ko = t;
+        t = vi; vi = vo; vo = t;
+    }
+    if (ki != key) {
+        launch_copy_bytes(key, ki, sizeof(uint32_t) * (size_t)n, st);
+        launch_copy_bytes(val, vi, sizeof(uint32_t) * (size_t)n, st);
+    }
+}
+
+void launch_cell_ranges(const uint32_t *key_sorted, int64_t n, int64_t G, uint32_t *cell_start,
+                        hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cell_ranges, dim3(grid1(n + 1)), dim3(kBlock), 0, st, key_sorted, n, G,
+                       cell_start);
+}
+
+void launch_cell_fixup(const uint32_t *cell_start, int64_t G, uint32_t *val, const uint32_t *id_old,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cell_fixup, dim3(grid1(G)), dim3(kBlock), 0, st, cell_start, G, val, id_old);
+}
+
+void launch_gather(PSet from, PSet to, const uint32_t *perm, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gather, dim3(grid1(n)), dim3(kBlock), 0, st, from, to, perm, n);
+}
+
+}  // namespace dcm

@@ -1,0 +1,101 @@
+"""The C-ABI library: it loads, exports every entry point include/dcm.h declares, and its
+host-only calls (grid dims, workspace sizes, parameter validation) behave. CPU only."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dcm.h")
+LIB = os.path.join(ROOT, "paper_1502_03234_amd", "libdcm.so")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dcm_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def dcm():
+    if not os.path.exists(LIB):
+        from paper_1502_03234_amd import build
+        build.build()
+    from paper_1502_03234_amd import dcm as mod
+    return mod
+
+
+def test_header_declares_entry_points():
+    syms = declared_symbols()
+    for required in ("dcm_create", "dcm_detect_interface", "dcm_compute_forces", "dcm_step",
+                     "dcm_get_state", "dcm_destroy", "dcm_workspace_bytes"):
+        assert required in syms
+
+
+def test_library_exports_every_declared_symbol(dcm):
+    lib = C.CDLL(LIB)
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (dcm_[a-z_0-9]+)$", out, flags=re.M))
+    assert set(declared_symbols()) <= exported
+
+
+def test_binding_covers_header(dcm):
+    for s in declared_symbols():
+        assert hasattr(dcm, s), s
+
+
+def test_grid_dims_and_workspace(dcm):
+    p = dcm.params((320.0, 320.0, 60.0))
+    assert dcm.dcm_grid_dims(p) == (320, 320, 60)
+    b = dcm.dcm_workspace_bytes(p, 2_048_000)
+    assert 400e6 < b < 2e9
+    p2 = dcm.params((28.0, 28.0, 60.0))
+    assert dcm.dcm_workspace_bytes(p2, 16000) < b
+    assert dcm.dcm_version().startswith("dcm-mi355x")
+
+
+@pytest.mark.parametrize("bad", [
+    dict(rc_max=7.0, box=(14.0, 14.0, 60.0)),          # rc_max >= L/2
+    dict(rc_min=3.0, rc_max=2.5),                      # rc_min > rc_max
+    dict(alpha=0.0),                                   # flat cutoff function
+    dict(smooth_passes=5),
+    dict(box=(13.0, 28.0, 60.0)),                      # 13 boxes < 2 ceil(6/1) + 2
+    dict(dt=0.0),
+    dict(precision=7),
+    dict(pair_rule=3),
+    dict(min_component=-1),
+])
+def test_invalid_parameters_rejected(dcm, bad):
+    kw = dict(box=(28.0, 28.0, 60.0))
+    kw.update(bad)
+    box = kw.pop("box")
+    p = dcm.params(box, **kw)
+    with pytest.raises(dcm.DcmError) as e:
+        dcm.dcm_workspace_bytes(p, 1000)
+    assert e.value.status == dcm.DCM_E_INVALID
+    assert dcm.dcm_last_error()
+
+
+def test_invalid_n_and_workspace(dcm):
+    p = dcm.params((28.0, 28.0, 60.0))
+    with pytest.raises(dcm.DcmError) as e:
+        dcm.dcm_workspace_bytes(p, 1)
+    assert e.value.status == dcm.DCM_E_INVALID
+    # a missing workspace is rejected before any device work
+    h = C.c_void_p()
+    st = dcm._lib.dcm_create(C.byref(p), 1000, None, 0, None, None, None, C.byref(h))
+    assert st in (dcm.DCM_E_INVALID, dcm.DCM_E_WORKSPACE)
+    x = C.c_void_p(256)
+    st = dcm._lib.dcm_create(C.byref(p), 1000, x, 10, x, x, None, C.byref(h))
+    assert st == dcm.DCM_E_WORKSPACE and h.value is None
+
+
+def test_grid_stage_argument_checks(dcm):
+    with pytest.raises(dcm.DcmError) as e:
+        dcm.dcm_grid_workspace_bytes((2, 5, 5))
+    assert e.value.status == dcm.DCM_E_INVALID
+    assert dcm.dcm_grid_workspace_bytes((5, 5, 5)) > 0

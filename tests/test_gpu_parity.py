@@ -1,0 +1,305 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars: integer stages (box counts, smoothed values, labels, components, pair counts) bit-exact;
+two-means centres bit-exact (exact integer sums, same FP64 operation sequence); distances and
+cutoffs within 4 ulp; forces per atom |dF_i| / max(|F_i|, F_rms) <= 1e-12; energy and virial
+sums within 1e-12 of the sum of absolute per-atom terms (the conditioning of a sum whose terms
+cancel). The oracle is run on the GPU's own wrapped positions and cutoffs where a stage is
+tested in isolation.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle as O  # noqa: E402
+from paper_1502_03234_amd import dcm, synth  # noqa: E402
+
+FORCE_TOL = 1e-12
+ULP_TOL = 4
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+def ulp_close(a, b, k=ULP_TOL):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return np.all(np.abs(a - b) <= k * np.spacing(np.maximum(np.abs(a), np.abs(b))))
+
+
+def force_err(f, ref):
+    frms = np.sqrt(np.mean(np.sum(ref ** 2, axis=0)))
+    return np.linalg.norm(f - ref, axis=0) / np.maximum(np.linalg.norm(ref, axis=0), frms)
+
+
+def sum_close(got, terms, tol=1e-12):
+    ref = np.sum(terms)
+    return abs(got - ref) <= tol * np.sum(np.abs(terms)) + 1e-300
+
+
+def make(state, **kw):
+    p = dcm.params(state.box, **kw)
+    po = O.params(state.box, **{k: v for k, v in kw.items() if k != "precision"})
+    return p, po
+
+
+def check_system(state, p, po, name):
+    say(f"{name}: n={state.n} box={state.box}")
+    s = dcm.System(p, state.x, state.v)
+    det = s.detect()
+    fo = s.forces()
+    x, v, rc, k = s.state()
+    torch.cuda.synchronize()
+    s.check()
+    xw = x.cpu().numpy()
+    # positions were wrapped, not changed
+    assert np.array_equal(xw, O.wrap(po, state.x))
+    od = O.detect(po, xw)
+    assert np.array_equal(det["count"].cpu().numpy().astype(np.uint32), od.count), "counts"
+    assert np.array_equal(det["smooth"].cpu().numpy().astype(np.uint32), od.smooth), "smoothing"
+    assert np.array_equal(det["km"].cpu().numpy(), od.km), (det["km"].cpu().numpy(), od.km)
+    assert np.array_equal(det["raw"].cpu().numpy(), od.raw), "threshold labels"
+    assert np.array_equal(det["label"].cpu().numpy(), od.label), "labels after removal"
+    st = det["stats"].cpu().numpy()
+    assert st[0] == od.stats[0] and np.array_equal(st[1:5], od.stats[1:5]), (st, od.stats)
+    assert ulp_close(det["dist"].cpu().numpy(), od.dist), "distances"
+    rc_gpu = rc.cpu().numpy()
+    assert ulp_close(rc_gpu, od.rc), "cutoffs"
+    assert ulp_close(det["rc"].cpu().numpy(), rc_gpu, 0)
+    ref = O.forces(po, xw, rc_gpu)
+    err = force_err(fo["f"].cpu().numpy(), ref.f)
+    say(f"{name}: max force error {err.max():.2e}, pairs {int(ref.pairs.sum())}")
+    assert err.max() <= FORCE_TOL
+    assert np.array_equal(fo["pairs"].cpu().numpy().astype(np.int64), ref.pairs), "pair counts"
+    e = fo["e"].cpu().numpy()
+    assert np.all(np.abs(e - ref.e) <= 1e-12 * np.maximum(np.abs(ref.e), 1.0))
+    w = fo["w"].cpu().numpy()
+    wscale = np.maximum(np.abs(ref.w).max(axis=0, keepdims=True), 1.0)
+    assert np.all(np.abs(w - ref.w) <= 1e-12 * wscale)
+    th = dcm.thermo_records(fo["thermo"])[0]
+    assert th["pairs"] == int(ref.pairs.sum())
+    assert sum_close(th["pe"], ref.e)
+    for c in range(6):
+        assert sum_close(th["virial"][c], ref.w[c])
+    assert sum_close(th["ke"], 0.5 * state.v ** 2)
+    return s
+
+
+def test_slab16k_full_parity(slab16k):
+    p, po = make(slab16k)
+    s = check_system(slab16k, p, po, "slab16k")
+    s.close()
+
+
+@pytest.mark.parametrize("n,box,seed", [
+    (3000, (16.0, 16.0, 28.0), 1),       # small, a ragged last workgroup
+    (5617, (14.0, 14.0, 60.0), 2),       # smallest serving box (stencil spans the whole x row)
+    (40000, (41.0, 37.0, 52.0), 3),      # non-square, odd sizes
+])
+def test_ragged_slabs(n, box, seed):
+    st = synth.small_slab(n, box, seed)
+    p, po = make(st)
+    check_system(st, p, po, f"slab n={n}").close()
+
+
+def test_static_limit_and_symmetric_rule(slab16k):
+    # r_c^min = r_c^max: plain truncated LJ, Newton's third law holds to rounding
+    for kw in (dict(rc_min=3.0, rc_max=3.0), dict(pair_rule=dcm.DCM_PAIR_MAX),
+               dict(rc_min=4.0, rc_max=4.0, energy_shift=1),
+               dict(pair_rule=dcm.DCM_PAIR_MAX, energy_shift=1)):
+        p, po = make(slab16k, **kw)
+        s = check_system(slab16k, p, po, f"slab16k {kw}")
+        f = s.forces()["f"].cpu().numpy()
+        assert np.max(np.abs(f.sum(axis=1))) < 1e-9
+        s.close()
+
+
+def test_one_step_matches_oracle(slab16k):
+    p, po = make(slab16k)
+    s = dcm.System(p, slab16k.x, slab16k.v)
+    x0, v0, rc0, _ = s.state()
+    f0 = s.forces()["f"]
+    torch.cuda.synchronize()
+    st = O.RunState(x0.cpu().numpy(), v0.cpu().numpy(), rc0.cpu().numpy(), f0.cpu().numpy(), 0)
+    th = dcm.thermo_records(s.step(1))
+    x1, v1, rc1, k1 = s.state()
+    torch.cuda.synchronize()
+    ot = O.run(po, st, 1)
+    assert k1 == 1
+    # positions/velocities after one step: identical up to the rounding of the forces
+    assert np.max(np.abs(x1.cpu().numpy() - st.x)) < 1e-13
+    assert np.max(np.abs(v1.cpu().numpy() - st.v)) < 1e-11
+    assert np.array_equal(rc1.cpu().numpy(), st.rc)      # step 1 does not re-detect
+    assert abs(th[0]["ke"] - ot[0]["ke"]) < 1e-12 * abs(ot[0]["ke"])
+    assert abs(th[0]["pe"] - ot[0]["pe"]) < 1e-11 * abs(ot[0]["pe"])
+    assert th[0]["pairs"] == ot[0]["pairs"]
+    s.close()
+
+
+def test_detect_schedule_and_determinism(slab16k):
+    """Re-detection happens on even force evaluations; two runs give the same bits."""
+    p, _ = make(slab16k)
+    outs = []
+    for _ in range(2):
+        s = dcm.System(p, slab16k.x, slab16k.v)
+        th = s.step(6)
+        x, v, rc, k = s.state()
+        torch.cuda.synchronize()
+        outs.append((x.cpu().numpy(), v.cpu().numpy(), rc.cpu().numpy(), th.cpu().numpy()))
+        assert k == 6
+        s.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
+
+def test_checkpoint_resume_bitwise(slab16k):
+    p, _ = make(slab16k)
+    a = dcm.System(p, slab16k.x, slab16k.v)
+    a.step(7)
+    xa, va, rca, ka = a.state()
+    b0 = dcm.System(p, slab16k.x, slab16k.v)
+    b0.step(3)
+    x, v, rc, k = b0.state()
+    b = dcm.System(p, x, v, rc=rc, step=k)
+    b.step(4)
+    xb, vb, rcb, kb = b.state()
+    torch.cuda.synchronize()
+    assert ka == kb == 7
+    assert torch.equal(xa, xb) and torch.equal(va, vb) and torch.equal(rca, rcb)
+    for s in (a, b0, b):
+        s.close()
+
+
+def test_set_cutoffs_matches_oracle(slab16k):
+    p, po = make(slab16k)
+    s = dcm.System(p, slab16k.x, slab16k.v)
+    rng = np.random.default_rng(0)
+    rc = rng.uniform(2.5, 6.0, slab16k.n)
+    s.set_cutoffs(rc)
+    fo = s.forces()
+    x, _, rcg, _ = s.state()
+    torch.cuda.synchronize()
+    assert np.array_equal(rcg.cpu().numpy(), rc)
+    ref = O.forces(po, x.cpu().numpy(), rc)
+    assert force_err(fo["f"].cpu().numpy(), ref.f).max() <= FORCE_TOL
+    assert np.array_equal(fo["pairs"].cpu().numpy().astype(np.int64), ref.pairs)
+    s.close()
+
+
+def test_nonfinite_input_rejected(slab16k):
+    p, _ = make(slab16k)
+    x = slab16k.x.copy()
+    x[1, 5] = np.nan
+    with pytest.raises(dcm.DcmError) as e:
+        dcm.System(p, x, slab16k.v)
+    assert e.value.status == dcm.DCM_E_NONFINITE
+
+
+# ---- grid stages on synthetic images ----------------------------------------------------
+def _grid_ws(dims):
+    return dcm.workspace(dcm.dcm_grid_workspace_bytes(dims))
+
+
+@pytest.mark.parametrize("dims,passes", [((7, 5, 6), 1), ((33, 17, 9), 2), ((3, 3, 3), 1)])
+def test_grid_smooth(dims, passes):
+    rng = np.random.default_rng(sum(dims))
+    img = rng.integers(0, 9, size=int(np.prod(dims))).astype(np.uint32)
+    out = torch.empty(img.size, dtype=torch.int32, device="cuda")
+    dcm.dcm_grid_smooth(dims, passes, torch.from_numpy(img.view(np.int32)).cuda(), out, _grid_ws(dims))
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), O.smooth(dims, passes, img))
+
+
+def test_grid_two_means_and_segment():
+    rng = np.random.default_rng(4)
+    for trial in range(6):
+        dims = tuple(int(v) for v in rng.integers(4, 20, size=3))
+        G = int(np.prod(dims))
+        img = np.where(rng.random(G) < 0.4, rng.poisson(3, G), rng.poisson(40, G)).astype(np.uint32)
+        ws = _grid_ws(dims)
+        km = torch.empty(3, dtype=torch.float64, device="cuda")
+        it = torch.empty(1, dtype=torch.int64, device="cuda")
+        g = torch.from_numpy(img.view(np.int32)).cuda()
+        dcm.dcm_grid_two_means(dims, g, km, it, ws)
+        raw = torch.empty(G, dtype=torch.uint8, device="cuda")
+        lab = torch.empty(G, dtype=torch.uint8, device="cuda")
+        stats = torch.empty(4, dtype=torch.int64, device="cuda")
+        mc = int(rng.integers(2, 12))
+        dcm.dcm_grid_segment(dims, g, km, mc, raw, lab, stats, ws)
+        torch.cuda.synchronize()
+        okm, oit = O.two_means(img)
+        assert np.array_equal(km.cpu().numpy(), okm) and it.item() == oit
+        oraw, olab, ost = O.segment(dims, img, okm[2], mc)
+        assert np.array_equal(raw.cpu().numpy(), oraw)
+        assert np.array_equal(lab.cpu().numpy(), olab), (dims, mc)
+        assert np.array_equal(stats.cpu().numpy(), ost)
+
+
+def test_grid_distance_half_space_sphere_and_random():
+    cases = []
+    s = np.zeros((30, 5, 6), np.uint8)
+    s[:4] = 1
+    s[20:] = 1
+    cases.append(((6, 5, 30), (1.0, 1.0, 1.0), 7.0, s.ravel()))
+    cases.append(((6, 5, 30), (1.0, 1.0, 0.5), 7.0, s.ravel()))
+    n, R = 40, 8.0
+    k, j, i = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    r = np.sqrt((k - 19.5) ** 2 + (j - 19.5) ** 2 + (i - 19.5) ** 2)
+    cases.append(((n, n, n), (1.0, 1.0, 1.0), 7.0, (r < R).astype(np.uint8).ravel()))
+    rng = np.random.default_rng(3)
+    cases.append(((23, 19, 31), (1.0, 0.8, 1.3), 6.0, (rng.random(23 * 19 * 31) < 0.02).astype(np.uint8)))
+    for dims, h, cap, lab in cases:
+        say(f"distance dims={dims} h={h}")
+        d = torch.empty(lab.size, dtype=torch.float64, device="cuda")
+        sw = torch.empty(1, dtype=torch.int64, device="cuda")
+        dcm.dcm_grid_distance(dims, h, cap, torch.from_numpy(lab).cuda(), d, sw, _grid_ws(dims))
+        torch.cuda.synchronize()
+        od, _ = O.distance(dims, h, cap, lab)
+        assert ulp_close(d.cpu().numpy(), od), dims
+        assert 1 <= sw.item() < 100
+
+
+# ---- full size: sampled parity at the 2M-particle slab ---------------------------------------
+@pytest.mark.slow
+def test_slab2m_sampled_parity():
+    st = synth.named("slab2m")
+    p, po = make(st)
+    say("slab2m: create + detect")
+    s = dcm.System(p, st.x, st.v)
+    det = s.detect()
+    fo = s.forces(per_atom=True, thermo=True)
+    x, v, rc, k = s.state()
+    torch.cuda.synchronize()
+    s.check()
+    xw = x.cpu().numpy()
+    say("slab2m: oracle detect")
+    od = O.detect(po, xw)
+    assert np.array_equal(det["count"].cpu().numpy().astype(np.uint32), od.count)
+    assert np.array_equal(det["label"].cpu().numpy(), od.label)
+    assert np.array_equal(det["km"].cpu().numpy(), od.km)
+    rc_gpu = rc.cpu().numpy()
+    assert ulp_close(rc_gpu, od.rc)
+    idx = np.random.default_rng(9).choice(st.n, 3000, replace=False)
+    # every particle within 7 sigma of a periodic face is among the sampled too
+    edge = np.nonzero((xw[0] < 7) | (xw[0] > st.box[0] - 7))[0][:500]
+    idx = np.unique(np.concatenate([idx, edge]))
+    say(f"slab2m: oracle forces on {idx.size} particles")
+    ref = O.forces(po, xw, rc_gpu, subset=idx)
+    f = fo["f"].cpu().numpy()[:, idx]
+    frms = np.sqrt(np.mean(np.sum(f ** 2, axis=0)))
+    err = np.linalg.norm(f - ref.f, axis=0) / np.maximum(np.linalg.norm(ref.f, axis=0), frms)
+    say(f"slab2m: max sampled force error {err.max():.2e}")
+    assert err.max() <= FORCE_TOL
+    assert np.array_equal(fo["pairs"].cpu().numpy()[idx].astype(np.int64), ref.pairs)
+    th = dcm.thermo_records(fo["thermo"])[0]
+    e = fo["e"].cpu().numpy()
+    assert abs(th["pe"] - e.sum()) <= 1e-12 * np.abs(e).sum()
+    assert th["pairs"] == int(fo["pairs"].cpu().numpy().astype(np.int64).sum())
+    s.step(4)
+    s.check()
+    s.close()
