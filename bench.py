@@ -1,0 +1,205 @@
+"""Benchmark of the DCM per-timestep hot path on one MI355X.
+
+Workload: the 2,048,000-particle Lennard-Jones liquid/vapor slab (box 320 x 320 x 60 sigma,
+98 % liquid at density 0.8, 2 % vapor, T* = 0.7), cutoffs 2.5..6 sigma from the exponential
+cutoff function, interface re-detected every other step, FP64, energy/virial/kinetic thermo
+every step. One step = velocity-Verlet kicks and drift, binning (sort-and-segment),
+interface detection on even steps, forces.
+
+Prints ONE JSON line: metric, value (atom-steps/s), roofline of the pair-force kernel (FP64
+vector ALU), the oracle's CPU baseline on a bounded sample, and a per-stage breakdown.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VALU_PEAK_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+FLOPS_PER_PAIR = 41              # algorithmic FP64 flops per in-range ordered pair
+WORKLOAD = "slab2m"
+# HBM-side bytes per k_forces launch from FETCH_SIZE/WRITE_SIZE counter runs, scaled by a plain
+# 1 GiB copy (profiles/k_forces_slab2m_traffic.md). Valid only for the kernel source it was
+# taken on: reported as null once csrc/force.hip no longer hashes to this value.
+FORCE_TRAFFIC_BYTES = 4.82e9
+FORCE_TRAFFIC_SRC = "87f90f904ea59053"
+
+
+def force_traffic():
+    import hashlib
+    path = os.path.join(ROOT, "paper_1502_03234_amd", "csrc", "force.hip")
+    with open(path, "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()[:16]
+    return FORCE_TRAFFIC_BYTES if h == FORCE_TRAFFIC_SRC else None
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(state, sample: int, seed: int = 12345):
+    """Time the CPU oracle on a bounded sample of the same workload: one interface detection
+    on the full state (charged at 1/2 per step: detection every other step), forces for a
+    seeded random sample of particles (per-particle cost scaled to all particles), and one
+    full velocity-Verlet position/velocity update."""
+    import numpy as np
+    import oracle as O
+
+    p = O.params(state.box)
+    x = O.wrap(p, state.x)
+    t0 = time.perf_counter()
+    det = O.detect(p, x)
+    t_det = time.perf_counter() - t0
+    idx = np.sort(np.random.default_rng(seed).choice(state.n, sample, replace=False))
+    t0 = time.perf_counter()
+    O.forces(p, x, det.rc, subset=idx)
+    t_f = (time.perf_counter() - t0) / sample * state.n
+    v = state.v.copy()
+    f = np.zeros_like(v)
+    t0 = time.perf_counter()
+    v += 0.0025 * f
+    x2 = x + 0.005 * v
+    O.wrap(p, x2)
+    v += 0.0025 * f
+    t_int = time.perf_counter() - t0
+    per_step = t_f + 0.5 * t_det + t_int
+    return dict(value=state.n / per_step, unit="atom-steps/s", cores=1, kind="oracle",
+                sample=(f"slab2m: detection on all {state.n} particles (x1/2 per step), forces "
+                        f"for {sample} seeded random particles scaled to {state.n}, one full "
+                        f"integration update; {per_step:.1f} s per step"),
+                seconds=dict(detect=t_det, forces_scaled=t_f, integrate=t_int))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--precision", choices=["fp64", "fp32c"], default="fp64")
+    ap.add_argument("--cpu-sample", type=int, default=60000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--compare-static", action="store_true",
+                    help="also time the same system with a static cutoff r_c = r_c^max")
+    ap.add_argument("--forces-only", type=int, default=0, metavar="K",
+                    help="only create the system and run K force evaluations (counter passes)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run one plain device copy of BYTES (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build shards nothing across GPUs "
+              "(see DESIGN.md for how the path would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1502_03234_amd import dcm, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {src.numel() * 8} bytes")
+        return
+    log(f"generating {WORKLOAD}")
+    state = synth.named(WORKLOAD)
+    prec = dcm.DCM_FP64 if args.precision == "fp64" else dcm.DCM_FP32C
+    p = dcm.params(state.box, precision=prec)
+    stream = torch.cuda.current_stream()
+    sysm = dcm.System(p, state.x, state.v)
+    if args.forces_only:
+        for _ in range(args.forces_only):
+            dcm.dcm_compute_forces(sysm.h, stream)
+        torch.cuda.synchronize()
+        log(f"{args.forces_only} force evaluations done")
+        return
+    th = torch.empty(max(args.steps, args.warmup, 1) * dcm.THERMO_DOUBLES, dtype=torch.float64, device=dev)
+    log(f"n={state.n} grid={sysm.dims} warmup={args.warmup}")
+    if args.warmup:
+        dcm.dcm_step(sysm.h, args.warmup, stream, th)
+    torch.cuda.synchronize()
+    sysm.check()
+    dcm.dcm_set_profiling(sysm.h, True)
+    base = dcm.dcm_stage_times(sysm.h)                   # cumulative timers, zero here
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dcm.dcm_step(sysm.h, args.steps, stream, th)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = dcm.dcm_stage_times(sysm.h)
+    sysm.check()
+    rec = dcm.thermo_records(th[: args.steps * dcm.THERMO_DOUBLES])
+    pairs = sum(r["pairs"] for r in rec) / len(rec)
+    ms_step = elapsed / args.steps * 1e3
+    value = state.n * args.steps / elapsed
+    f_ms, f_cnt = stages["forces"][0] - base["forces"][0], stages["forces"][1] - base["forces"][1]
+    f_avg_s = f_ms / f_cnt * 1e-3
+    achieved = FLOPS_PER_PAIR * pairs / f_avg_s / 1e12
+    breakdown = {k: round((v[0] - base[k][0]) / args.steps, 5) for k, v in stages.items()}
+    log(f"{ms_step:.4f} ms/step, force kernel {f_avg_s * 1e3:.4f} ms, pairs/step {pairs:.4e}, "
+        f"breakdown ms/step {breakdown}")
+    e0 = rec[0]["ke"] + rec[0]["pe"]
+    e1 = rec[-1]["ke"] + rec[-1]["pe"]
+
+    static = None
+    if args.compare_static:
+        sysm.close()
+        ps = dcm.params(state.box, rc_min=6.0, rc_max=6.0, precision=prec)
+        ss = dcm.System(ps, state.x, state.v)
+        dcm.dcm_step(ss.h, 3, stream, th)
+        torch.cuda.synchronize()
+        ks = max(10, args.steps // 10)
+        t0 = time.perf_counter()
+        dcm.dcm_step(ss.h, ks, stream, th)
+        torch.cuda.synchronize()
+        st_ms = (time.perf_counter() - t0) / ks * 1e3
+        static = dict(ms_per_step=round(st_ms, 4), dcm_speedup=round(st_ms / ms_step, 3))
+        ss.close()
+    else:
+        sysm.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle on a sample of {args.cpu_sample} particles")
+        cpu = cpu_baseline(state, args.cpu_sample)
+
+    out = {
+        "metric": "atom-steps/s/GPU at 2M-atom LJ slab",
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == dcm.DCM_FP64 else "f32-compensated",
+        "data": "synthetic",
+        "config": {"workload": "LJ liquid/vapor slab, 2,048,000 particles, box 320x320x60, "
+                               "r_c 2.5..6 (exponential), detect every 2nd step, dt 0.005, NVE",
+                   "n_particles": state.n, "grid": list(sysm.dims), "detect_every": 2,
+                   "thermo_every_step": True},
+        "roofline": {"bound": "alu", "kernel": "k_forces (FP64 pair forces, energy, virial)",
+                     "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": force_traffic(),
+                     "avg_launch_ms": f_avg_s * 1e3, "pairs_per_launch": pairs,
+                     "flops_per_pair": FLOPS_PER_PAIR},
+        "cpu_baseline": cpu and {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
+        "breakdown_ms_per_step": breakdown,
+        "energy_drift_per_atom": (e1 - e0) / state.n,
+        "static_cutoff_6": static,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

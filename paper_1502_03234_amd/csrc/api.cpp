@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -90,7 +91,7 @@ dcm_status validate(const dcm_params *p, int64_t n, Grid &g)
     if (p->detect_every < 0) return fail(DCM_E_INVALID, "detect_every must be >= 0");
     if (!(p->dt > 0.0) || !(p->mass > 0.0) || !(p->sigma > 0.0) || !(p->epsilon >= 0.0))
         return fail(DCM_E_INVALID, "dt, mass and sigma must be positive, epsilon non-negative");
-    if (p->precision != DCM_FP64 && p->precision != DCM_FP32C) return fail(DCM_E_INVALID, "unknown precision");
+    if (p->precision != DCM_FP64) return fail(DCM_E_INVALID, "precision: only DCM_FP64 is available");
     if (p->pair_rule != DCM_PAIR_I && p->pair_rule != DCM_PAIR_MAX) return fail(DCM_E_INVALID, "unknown pair_rule");
     return DCM_OK;
 }
@@ -165,6 +166,9 @@ size_t layout(dcm_system *s, void *ws)
     s->gw.stats = b.take<long long>(8);
     s->gw.changed = b.take<uint32_t>(max_distance_sweeps(s->grid, s->cap) + 1);
     s->gw.flags = b.take<uint32_t>(1);
+    s->gw.tdirty = b.take<uint32_t>(2 * distance_tiles(s->grid));
+    s->gw.tcur = b.take<uint32_t>(2 * distance_tiles(s->grid));
+    s->gw.dist2 = b.take<double>(G);
     s->nfb = force_blocks(n);
     s->nkb = stream_blocks(n);
     s->fparts = b.take<Partial>(s->nfb);
@@ -526,6 +530,9 @@ static size_t grid_layout(const Grid &g, GridWork &w, void *ws, double cap)
     w.stats = b.take<long long>(8);
     w.changed = b.take<uint32_t>(max_distance_sweeps(g, cap) + 1);
     w.flags = b.take<uint32_t>(1);
+    w.tdirty = b.take<uint32_t>(2 * distance_tiles(g));
+    w.tcur = b.take<uint32_t>(2 * distance_tiles(g));
+    w.dist2 = b.take<double>(G);
     return b.off + 256;
 }
 

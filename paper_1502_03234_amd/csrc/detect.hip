@@ -163,25 +163,27 @@ __global__ void k_threshold(const uint32_t *img, const double *km, int64_t G, ui
     label[c] = s;
 }
 
-__global__ void k_cc_init(const uint8_t *label, uint8_t phase, int64_t G, uint32_t *parent, uint32_t *csize)
-{
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= G) return;
-    parent[c] = label[c] == phase ? (uint32_t)c : kInvalid;
-    csize[c] = 0;
-}
-
 __device__ __forceinline__ uint32_t load_parent(uint32_t *parent, uint32_t x)
 {
     return __hip_atomic_load(parent + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ __forceinline__ void store_parent(uint32_t *parent, uint32_t x, uint32_t v)
+{
+    __hip_atomic_store(parent + x, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of x's tree with path halving: every visited box is re-pointed at its grandparent.
+// Parents only ever decrease along a tree path, so the plain stores keep the forest valid
+// whatever other threads do concurrently.
 __device__ uint32_t find_root(uint32_t *parent, uint32_t x)
 {
     uint32_t p = load_parent(parent, x);
     while (p != x) {
+        uint32_t gp = load_parent(parent, p);
+        if (gp != p) store_parent(parent, x, gp);
         x = p;
-        p = load_parent(parent, x);
+        p = gp;
     }
     return x;
 }
@@ -200,17 +202,101 @@ __device__ void unite(uint32_t *parent, uint32_t a, uint32_t b)
     }
 }
 
-__global__ void k_cc_merge(Grid g, const uint8_t *label, uint8_t phase, uint32_t *parent)
+// Block-local labelling: each workgroup owns a CT^3 tile of boxes, joins same-phase face
+// neighbours inside the tile with a union-find in LDS, and writes for every box of the phase
+// the global index of its tile-local root (the smallest member of its tile-local piece: local
+// and global linear orders agree inside a tile). csize is cleared on the way.
+constexpr int CT = 8;
+constexpr int kCtBoxes = CT * CT * CT;
+
+__device__ __forceinline__ uint32_t lfind(uint32_t *lp, uint32_t x)
+{
+    uint32_t p = lp[x];
+    while (p != x) {
+        uint32_t gp = lp[p];
+        if (gp != p) lp[x] = gp;
+        x = p;
+        p = gp;
+    }
+    return x;
+}
+
+__device__ __forceinline__ void lunite(uint32_t *lp, uint32_t a, uint32_t b)
+{
+    for (;;) {
+        a = lfind(lp, a);
+        b = lfind(lp, b);
+        if (a == b) return;
+        if (a < b) { uint32_t t = a; a = b; b = t; }
+        uint32_t old = atomicMin(lp + a, b);
+        if (old == a) return;
+        a = old;
+    }
+}
+
+__global__ void __launch_bounds__(kCtBoxes) k_cc_local(Grid g, const uint8_t *label, uint8_t phase,
+                                                      uint32_t *parent, uint32_t *csize, uint32_t *psize)
+{
+    __shared__ uint32_t lp[kCtBoxes];
+    __shared__ uint32_t lc[kCtBoxes];
+    const int ntx = (g.n[0] + CT - 1) / CT, nty = (g.n[1] + CT - 1) / CT;
+    const int b = blockIdx.x;
+    const int x0 = (b % ntx) * CT, y0 = ((b / ntx) % nty) * CT, z0 = (b / (ntx * nty)) * CT;
+    const int l = threadIdx.x;
+    const int lx = l % CT, ly = (l / CT) % CT, lz = l / (CT * CT);
+    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+    const bool in = gx < g.n[0] && gy < g.n[1] && gz < g.n[2];
+    const int64_t c = in ? lin(g, gx, gy, gz) : 0;
+    const bool mine = in && label[c] == phase;
+    lp[l] = mine ? (uint32_t)l : kInvalid;
+    lc[l] = 0;
+    __syncthreads();
+    if (mine) {
+        if (lx + 1 < CT && gx + 1 < g.n[0] && lp[l + 1] != kInvalid) lunite(lp, l, l + 1);
+        if (ly + 1 < CT && gy + 1 < g.n[1] && lp[l + CT] != kInvalid) lunite(lp, l, l + CT);
+        if (lz + 1 < CT && gz + 1 < g.n[2] && lp[l + CT * CT] != kInvalid) lunite(lp, l, l + CT * CT);
+    }
+    __syncthreads();
+    uint32_t r = mine ? lfind(lp, l) : 0u;
+    if (mine) atomicAdd(lc + r, 1u);
+    __syncthreads();
+    if (in) {
+        csize[c] = 0;
+        if (mine) {
+            int rx = r % CT, ry = (r / CT) % CT, rz = r / (CT * CT);
+            parent[c] = (uint32_t)lin(g, x0 + rx, y0 + ry, z0 + rz);
+            psize[c] = lc[r];
+        } else {
+            parent[c] = kInvalid;
+        }
+    }
+}
+
+// Joins across tile faces (and the periodic faces of the grid): only boxes on a tile's upper
+// faces look at their +x / +y / +z neighbour. Only "fewer than `limit` boxes" matters, and a
+// piece that already has `limit` boxes inside its tile is large whatever it joins, so a face
+// is joined only when at least one of its two pieces is small; a small piece still ends in
+// the same tree as every piece it touches, and the size count below is exact below `limit`.
+__global__ void k_cc_merge(Grid g, const uint8_t *label, uint8_t phase, uint32_t *parent,
+                           const uint32_t *psize, uint32_t limit)
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.G || label[c] != phase) return;
     int64_t i, j, k;
     coords(g, c, i, j, k);
-    int64_t nb[3] = {lin(g, i + 1 == g.n[0] ? 0 : i + 1, j, k),
-                     lin(g, i, j + 1 == g.n[1] ? 0 : j + 1, k),
-                     lin(g, i, j, k + 1 == g.n[2] ? 0 : k + 1)};
-    for (int q = 0; q < 3; ++q)
-        if (label[nb[q]] == phase) unite(parent, (uint32_t)c, (uint32_t)nb[q]);
+    const bool fx = (i % CT) == CT - 1 || i + 1 == g.n[0];
+    const bool fy = (j % CT) == CT - 1 || j + 1 == g.n[1];
+    const bool fz = (k % CT) == CT - 1 || k + 1 == g.n[2];
+    if (!(fx || fy || fz)) return;
+    int64_t nb[3] = {fx ? lin(g, i + 1 == g.n[0] ? 0 : i + 1, j, k) : -1,
+                     fy ? lin(g, i, j + 1 == g.n[1] ? 0 : j + 1, k) : -1,
+                     fz ? lin(g, i, j, k + 1 == g.n[2] ? 0 : k + 1) : -1};
+    const bool small = psize[c] < limit;
+    for (int q = 0; q < 3; ++q) {
+        if (nb[q] < 0 || label[nb[q]] != phase) continue;
+        if (!small && psize[nb[q]] >= limit) continue;
+        unite(parent, (uint32_t)c, (uint32_t)nb[q]);
+    }
 }
 
 __global__ void k_cc_flatten(int64_t G, uint32_t *parent)
@@ -308,31 +394,160 @@ __global__ void k_dist_init(const uint8_t *label, int64_t G, double *dist)
     if (c < G) dist[c] = label[c] == 1 ? 0.0 : INFINITY;
 }
 
-__global__ void __launch_bounds__(kBlock) k_dist_sweep(Grid g, const uint8_t *label, double *dist,
-                                                       double cap, uint32_t *changed, int it)
+// One global relaxation pass over LDS tiles. Two copies of the distance grid alternate;
+// cur[t] says which copy holds tile t's values as of the end of the previous pass. A tile
+// marked dirty loads its boxes and a one-box halo (each from the copy current for the tile that
+// owns it), relaxes its liquid boxes with synchronous (Jacobi) updates in double-buffered LDS
+// until nothing changes (halo held fixed), and writes the result into its other copy. Every
+// read of a pass sees the previous pass's state, so the outcome does not depend on the order
+// in which tiles run. A tile that lowers a value on a face marks the tile across that face
+// dirty for the next pass. Passes repeat until one changes nothing.
+constexpr int TX = 16, TY = 8, TZ = 8;
+constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
+constexpr int kTileThreads = 256;
+constexpr int kPerThread = TX * TY * TZ / kTileThreads;
+constexpr int kLocalMax = 128;
+
+__global__ void __launch_bounds__(kTileThreads) k_dist_tiles(Grid g, const uint8_t *label, double *d0,
+                                                             double *d1, double cap, uint32_t *changed,
+                                                             uint32_t *dirty, uint32_t *cur, int it)
 {
-    if (it > 0 && __hip_atomic_load(changed + it - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-        return;                                    // the previous sweep changed nothing: converged
-    bool ch = false;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < g.G;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        if (label[c] == 1) continue;
-        int64_t i, j, k;
-        coords(g, c, i, j, k);
-        double ax = fmin(dist[lin(g, i == 0 ? g.n[0] - 1 : i - 1, j, k)],
-                         dist[lin(g, i == g.n[0] - 1 ? 0 : i + 1, j, k)]);
-        double ay = fmin(dist[lin(g, i, j == 0 ? g.n[1] - 1 : j - 1, k)],
-                         dist[lin(g, i, j == g.n[1] - 1 ? 0 : j + 1, k)]);
-        double az = fmin(dist[lin(g, i, j, k == 0 ? g.n[2] - 1 : k - 1)],
-                         dist[lin(g, i, j, k == g.n[2] - 1 ? 0 : k + 1)]);
-        if (isinf(ax) && isinf(ay) && isinf(az)) continue;
-        double db = godunov(ax, ay, az, g.h[0], g.h[1], g.h[2]);
-        if (db <= cap && db < dist[c]) {
-            dist[c] = db;
-            ch = true;
+    const int b = blockIdx.x;
+    const int ntiles = gridDim.x;
+    uint32_t *dflag = dirty + (it & 1) * ntiles, *dnext = dirty + ((it + 1) & 1) * ntiles;
+    const uint32_t *cprev = cur + (it & 1) * ntiles;
+    uint32_t *cnext = cur + ((it + 1) & 1) * ntiles;
+    const bool converged = it > 0 &&
+        __hip_atomic_load(changed + it - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    const uint32_t mycur = cprev[b];
+    if (converged || dflag[b] == 0) {
+        if (threadIdx.x == 0) { cnext[b] = mycur; dflag[b] = 0u; }
+        return;
+    }
+    __shared__ double t[2][HZ][HY][HX];
+    __shared__ int any;
+    __shared__ int faces[6];
+    const int ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY, ntz = (g.n[2] + TZ - 1) / TZ;
+    const int bx = b % ntx, by = (b / ntx) % nty, bz = b / (ntx * nty);
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+    if (threadIdx.x < 6) faces[threadIdx.x] = 0;
+    // positions one box outside the grid hold the periodic neighbour (the only outside
+    // positions a grid box reads); positions further out (partial tiles) hold infinity
+    for (int q = threadIdx.x; q < HX * HY * HZ; q += kTileThreads) {
+        int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
+        int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+        double v = INFINITY;
+        if (gx <= g.n[0] && gy <= g.n[1] && gz <= g.n[2]) {
+            int cx = gx < 0 ? gx + g.n[0] : (gx == g.n[0] ? 0 : gx);
+            int cy = gy < 0 ? gy + g.n[1] : (gy == g.n[1] ? 0 : gy);
+            int cz = gz < 0 ? gz + g.n[2] : (gz == g.n[2] ? 0 : gz);
+            int owner = ((cz / TZ) * nty + cy / TY) * ntx + cx / TX;
+            const double *src = cprev[owner] ? d1 : d0;
+            v = src[lin(g, cx, cy, cz)];
+        }
+        t[0][hz][hy][hx] = v;
+        t[1][hz][hy][hx] = v;
+    }
+    int own[kPerThread];
+    bool liq[kPerThread];
+    for (int r = 0; r < kPerThread; ++r) {
+        int q = threadIdx.x + r * kTileThreads;
+        int lx = q % TX, ly = (q / TX) % TY, lz = q / (TX * TY);
+        own[r] = q;
+        int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+        liq[r] = gx < g.n[0] && gy < g.n[1] && gz < g.n[2] && label[lin(g, gx, gy, gz)] != 1;
+    }
+    __syncthreads();
+    int src = 0;
+    for (int sweep = 0; sweep < kLocalMax; ++sweep) {
+        if (threadIdx.x == 0) any = 0;
+        __syncthreads();
+        bool ch = false;
+        for (int r = 0; r < kPerThread; ++r) {
+            int q = own[r];
+            int hx = q % TX + 1, hy = (q / TX) % TY + 1, hz = q / (TX * TY) + 1;
+            double old = t[src][hz][hy][hx];
+            double nv = old;
+            if (liq[r]) {
+                double ax = fmin(t[src][hz][hy][hx - 1], t[src][hz][hy][hx + 1]);
+                double ay = fmin(t[src][hz][hy - 1][hx], t[src][hz][hy + 1][hx]);
+                double az = fmin(t[src][hz - 1][hy][hx], t[src][hz + 1][hy][hx]);
+                if (!(isinf(ax) && isinf(ay) && isinf(az))) {
+                    double db = godunov(ax, ay, az, g.h[0], g.h[1], g.h[2]);
+                    if (db <= cap && db < old) { nv = db; ch = true; }
+                }
+            }
+            t[src ^ 1][hz][hy][hx] = nv;
+        }
+        if (ch) any = 1;
+        __syncthreads();
+        const int stop = any == 0;
+        src ^= 1;
+        __syncthreads();
+        if (stop) break;
+    }
+    // write back into the tile's other copy (only if something changed)
+    bool wrote = false;
+    for (int r = 0; r < kPerThread; ++r) {
+        int q = own[r];
+        int lx = q % TX, ly = (q / TX) % TY, lz = q / (TX * TY);
+        int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+        if (gx >= g.n[0] || gy >= g.n[1] || gz >= g.n[2]) continue;
+        double v = t[src][lz + 1][ly + 1][lx + 1];
+        // the loaded value (the tile's own copy): compare to detect a change
+        double was = (mycur ? d1 : d0)[lin(g, gx, gy, gz)];
+        if (v < was) {
+            wrote = true;
+            if (lx == 0) faces[0] = 1;
+            if (lx == TX - 1 || gx == g.n[0] - 1) faces[1] = 1;
+            if (ly == 0) faces[2] = 1;
+            if (ly == TY - 1 || gy == g.n[1] - 1) faces[3] = 1;
+            if (lz == 0) faces[4] = 1;
+            if (lz == TZ - 1 || gz == g.n[2] - 1) faces[5] = 1;
         }
     }
-    if (__ballot(ch) && __lane_id() == 0) changed[it] = 1u;
+    __shared__ int tile_wrote;
+    if (threadIdx.x == 0) tile_wrote = 0;
+    __syncthreads();
+    if (wrote) tile_wrote = 1;
+    __syncthreads();
+    if (tile_wrote) {
+        double *dst = mycur ? d0 : d1;
+        for (int r = 0; r < kPerThread; ++r) {
+            int q = own[r];
+            int lx = q % TX, ly = (q / TX) % TY, lz = q / (TX * TY);
+            int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+            if (gx >= g.n[0] || gy >= g.n[1] || gz >= g.n[2]) continue;
+            dst[lin(g, gx, gy, gz)] = t[src][lz + 1][ly + 1][lx + 1];
+        }
+    }
+    if (threadIdx.x == 0) {
+        cnext[b] = tile_wrote ? 1u - mycur : mycur;
+        dflag[b] = 0u;
+        if (tile_wrote) {
+            changed[it] = 1u;
+            const int nbx[2] = {bx == 0 ? ntx - 1 : bx - 1, bx == ntx - 1 ? 0 : bx + 1};
+            const int nby[2] = {by == 0 ? nty - 1 : by - 1, by == nty - 1 ? 0 : by + 1};
+            const int nbz[2] = {bz == 0 ? ntz - 1 : bz - 1, bz == ntz - 1 ? 0 : bz + 1};
+            for (int f = 0; f < 2; ++f) {
+                if (faces[f]) dnext[(bz * nty + by) * ntx + nbx[f]] = 1u;
+                if (faces[2 + f]) dnext[(bz * nty + nby[f]) * ntx + bx] = 1u;
+                if (faces[4 + f]) dnext[(nbz[f] * nty + by) * ntx + bx] = 1u;
+            }
+        }
+    }
+}
+
+// Final values into d0: boxes whose tile ended with the second copy current are copied.
+__global__ void k_dist_gather(Grid g, double *d0, const double *d1, const uint32_t *cur_final)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.G) return;
+    int64_t i, j, k;
+    coords(g, c, i, j, k);
+    const int ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY;
+    const int owner = (int)(((k / TZ) * nty + j / TY) * ntx + i / TX);
+    if (cur_final[owner]) d0[c] = d1[c];
 }
 
 __global__ void k_dist_finish(const uint32_t *changed, int max_sweeps, long long *sweeps, uint32_t *flags)
@@ -434,9 +649,11 @@ void launch_segment(const Grid &g, const uint32_t *img, const double *km, int32_
     if (min_component <= 1) return;                 // no component can be smaller
     for (int pass = 0; pass < 2; ++pass) {
         uint8_t phase = pass == 0 ? 1 : 0;
-        hipLaunchKernelGGL(k_cc_init, dim3(grid1(g.G)), dim3(kBlock), 0, st, w.label, phase, g.G,
-                           w.parent, w.csize);
-        hipLaunchKernelGGL(k_cc_merge, dim3(grid1(g.G)), dim3(kBlock), 0, st, g, w.label, phase, w.parent);
+        unsigned nct = (unsigned)(((g.n[0] + CT - 1) / CT) * ((g.n[1] + CT - 1) / CT) * ((g.n[2] + CT - 1) / CT));
+        hipLaunchKernelGGL(k_cc_local, dim3(nct), dim3(kCtBoxes), 0, st, g, w.label, phase, w.parent, w.csize,
+                           w.gtmp);
+        hipLaunchKernelGGL(k_cc_merge, dim3(grid1(g.G)), dim3(kBlock), 0, st, g, w.label, phase, w.parent,
+                           (const uint32_t *)w.gtmp, (uint32_t)min_component);
         hipLaunchKernelGGL(k_cc_flatten, dim3(grid1(g.G)), dim3(kBlock), 0, st, g.G, w.parent);
         hipLaunchKernelGGL(k_cc_size, dim3(grid1(g.G)), dim3(kBlock), 0, st, g.G, w.parent, w.csize,
                            (uint32_t)min_component);
@@ -445,13 +662,17 @@ void launch_segment(const Grid &g, const uint32_t *img, const double *km, int32_
     }
 }
 
-// In-place relaxation converges within a few sweeps per box of band depth; the bound leaves
-// a wide margin and is reported as non-convergence if ever reached.
+int64_t distance_tiles(const Grid &g)
+{
+    return (int64_t)((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY) * ((g.n[2] + TZ - 1) / TZ);
+}
+
+// Global passes needed: the band depth in tiles plus slack; reaching the bound is reported.
 int max_distance_sweeps(const Grid &g, double cap)
 {
     double hmin = std::min(g.h[0], std::min(g.h[1], g.h[2]));
     int depth = (int)std::ceil(cap / hmin);
-    return 4 * depth + 16;
+    return depth / std::min(TX, std::min(TY, TZ)) + 12;
 }
 
 void launch_distance(const Grid &g, double cap, const uint8_t *label, double *dist, GridWork w,
@@ -460,9 +681,15 @@ void launch_distance(const Grid &g, double cap, const uint8_t *label, double *di
     int ms = max_distance_sweeps(g, cap);
     launch_fill_u32(w.changed, 0u, ms + 1, st);
     hipLaunchKernelGGL(k_dist_init, dim3(grid1(g.G)), dim3(kBlock), 0, st, label, g.G, dist);
-    unsigned nb = (unsigned)std::min<int64_t>((g.G + kBlock - 1) / kBlock, 4096);
+    const unsigned ntiles = (unsigned)distance_tiles(g);
+    launch_fill_u32(w.tdirty, 1u, ntiles, st);
+    launch_fill_u32(w.tdirty + ntiles, 0u, ntiles, st);
+    launch_fill_u32(w.tcur, 0u, 2 * (int64_t)ntiles, st);
     for (int it = 0; it < ms; ++it)
-        hipLaunchKernelGGL(k_dist_sweep, dim3(nb), dim3(kBlock), 0, st, g, label, dist, cap, w.changed, it);
+        hipLaunchKernelGGL(k_dist_tiles, dim3(ntiles), dim3(kTileThreads), 0, st, g, label, dist, w.dist2, cap,
+                           w.changed, w.tdirty, w.tcur, it);
+    hipLaunchKernelGGL(k_dist_gather, dim3(grid1(g.G)), dim3(kBlock), 0, st, g, dist, (const double *)w.dist2,
+                       (const uint32_t *)(w.tcur + (ms & 1) * ntiles));
     hipLaunchKernelGGL(k_dist_finish, dim3(1), dim3(64), 0, st, w.changed, ms, w.stats + 5, w.flags);
 }
 

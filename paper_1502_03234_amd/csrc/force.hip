@@ -3,7 +3,9 @@
 // f_i is updated, so every ordered pair is visited from its own side -- a full list).
 //
 // One lane per particle, particles in cell-sorted order so that a wavefront holds a run of
-// neighbouring boxes along x. Lane i walks the box rows (fixed y, z) whose rectangle comes
+// neighbouring boxes along x. Each candidate interval is scanned four slots at a time with all
+// four loads issued before use (the loop is bound by memory latency otherwise; staging the
+// rows through LDS measured slower). Lane i walks the box rows (fixed y, z) whose rectangle comes
 // within r_c[i] of it; inside a row the candidate boxes are the x-interval that the sphere
 // cuts, so the traversed volume follows the sphere at box resolution in y and z and exactly
 // in x (the small-bin stencil idea of Fig. 13b taken to single boxes). Each candidate interval
@@ -22,16 +24,6 @@ namespace {
 
 constexpr int kForceBlock = 256;
 
-// Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous range of
-// logical blocks so that neighbouring particles share one L2.
-__device__ __forceinline__ int64_t xcd_remap(int64_t p, int64_t nblk)
-{
-    constexpr int64_t kXcd = 8;
-    int64_t q = nblk / kXcd, r = nblk % kXcd;
-    int64_t xcd = p % kXcd, local = p / kXcd;
-    return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
-}
-
 __device__ __forceinline__ double rcp_refined(double a)
 {
     double y = __builtin_amdgcn_rcp(a);
@@ -41,28 +33,33 @@ __device__ __forceinline__ double rcp_refined(double a)
     return fma(y, e, y);
 }
 
-__device__ __forceinline__ int floor_div(double v, double h) { return (int)floor(v / h); }
+__device__ __forceinline__ int floor_mul(double v, double inv_h) { return (int)floor(v * inv_h); }
+
+// Conservative square root for box bounds: the hardware estimate, enlarged well past its error.
+__device__ __forceinline__ double sqrt_up(double v) { return __builtin_amdgcn_sqrt(v) * (1.0 + 1e-6) + 1e-9; }
 
 struct Acc {
     double fx, fy, fz, e, wxx, wyy, wzz, wxy, wxz, wyz, eshift;
     uint32_t pairs;
 };
 
-template <int PAIR, bool SHIFT>
-__device__ __forceinline__ void interact(const ForceArgs &a, const double4 pj, int64_t i, int64_t j,
+template <int PAIR, bool SHIFT, bool IMAGE>
+__device__ __forceinline__ void interact(const ForceArgs &a, const double4 pj, bool valid,
                                          double xi, double yi, double zi, double rci, double rc2,
                                          double sx, double sy, double sz, Acc &c)
 {
-    double dx = xi - (pj.x + sx);
-    double dy = yi - (pj.y + sy);
-    double dz = zi - (pj.z + sz);
+    // x_j moved to the periodic image of its interval (adding 0 is exact, so the no-image
+    // variant gives the same bits without the three additions)
+    double dx = IMAGE ? xi - (pj.x + sx) : xi - pj.x;
+    double dy = IMAGE ? yi - (pj.y + sy) : yi - pj.y;
+    double dz = IMAGE ? zi - (pj.z + sz) : zi - pj.z;
     double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
     double lim2 = rc2;
     if (PAIR == DCM_PAIR_MAX) {
         double rcp = pj.w > rci ? pj.w : rci;
         lim2 = rcp * rcp;
     }
-    if (r2 < lim2 && j != i) {
+    if (valid && r2 < lim2) {
         double inv = rcp_refined(r2);
         double sr2 = a.sigma2 * inv;
         double sr6 = sr2 * sr2 * sr2;
@@ -87,11 +84,46 @@ __device__ __forceinline__ void interact(const ForceArgs &a, const double4 pj, i
     }
 }
 
-template <int PAIR, bool SHIFT>
+// All candidates of one slot interval [jb, je), U loads in flight at a time; the particle
+// itself (slot i) is skipped.
+template <int PAIR, bool SHIFT, bool IMAGE, int U>
+__device__ __forceinline__ void scan(const ForceArgs &a, uint32_t jb, uint32_t je, int64_t i,
+                                     double xi, double yi, double zi, double rci, double rc2,
+                                     double sx, double sy, double sz, Acc &c)
+{
+    for (uint32_t j0 = jb; j0 < je; j0 += U) {
+        const uint32_t last = je - 1;
+        double4 p[U];
+        uint32_t jj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            jj[u] = j0 + u < je ? j0 + u : last;
+            p[u] = a.pos[jj[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            interact<PAIR, SHIFT, IMAGE>(a, p[u], j0 + u < je && jj[u] != i, xi, yi, zi, rci, rc2, sx, sy, sz, c);
+    }
+}
+
+template <int PAIR, bool SHIFT, int U>
+__device__ __forceinline__ void scan_interval(const ForceArgs &a, uint32_t jb, uint32_t je, int64_t i,
+                                              double xi, double yi, double zi, double rci, double rc2,
+                                              double sx, double sy, double sz, Acc &c)
+{
+    const bool image = sx != 0.0 || sy != 0.0 || sz != 0.0;
+    if (__any(image))
+        scan<PAIR, SHIFT, true, U>(a, jb, je, i, xi, yi, zi, rci, rc2, sx, sy, sz, c);
+    else
+        scan<PAIR, SHIFT, false, U>(a, jb, je, i, xi, yi, zi, rci, rc2, sx, sy, sz, c);
+}
+
+template <int PAIR, bool SHIFT, int U>
 __global__ void __launch_bounds__(kForceBlock) k_forces(ForceArgs a, double rc_max)
 {
-    const int64_t nblk = gridDim.x;
-    const int64_t b = xcd_remap(blockIdx.x, nblk);
+    // hardware (round-robin over XCDs) block order: the cost per particle varies strongly
+    // with z through the cutoffs, and interleaving keeps every XCD's share of it even
+    const int64_t b = blockIdx.x;
     const int64_t i = b * kForceBlock + threadIdx.x;
     const Grid &g = a.grid;
     Acc c = {};
@@ -108,8 +140,9 @@ __global__ void __launch_bounds__(kForceBlock) k_forces(ForceArgs a, double rc_m
         double rs = PAIR == DCM_PAIR_MAX ? rc_max : rci;
         rs = rs * (1.0 + 1e-12) + 1e-9;
         const double rs2 = rs * rs;
-        const int izlo = sane ? floor_div(zi - rs, g.h[2]) : 0;
-        const int izhi = sane ? floor_div(zi + rs, g.h[2]) : -1;
+        const double ihx = 1.0 / g.h[0], ihy = 1.0 / g.h[1], ihz = 1.0 / g.h[2];
+        const int izlo = sane ? floor_mul(zi - rs, ihz) : 0;
+        const int izhi = sane ? floor_mul(zi + rs, ihz) : -1;
         for (int iz = izlo; iz <= izhi; ++iz) {
             const double zlo = iz * g.h[2];
             const double dzm = fmax(0.0, fmax(zlo - zi, zi - (zlo + g.h[2])));
@@ -119,8 +152,8 @@ __global__ void __launch_bounds__(kForceBlock) k_forces(ForceArgs a, double rc_m
             double sz = 0.0;
             if (iz < 0) { wz += g.n[2]; sz = -g.L[2]; }
             else if (iz >= g.n[2]) { wz -= g.n[2]; sz = g.L[2]; }
-            const double ry = sqrt(remz);
-            const int iylo = floor_div(yi - ry, g.h[1]), iyhi = floor_div(yi + ry, g.h[1]);
+            const double ry = sqrt_up(remz);
+            const int iylo = floor_mul(yi - ry, ihy), iyhi = floor_mul(yi + ry, ihy);
             for (int iy = iylo; iy <= iyhi; ++iy) {
                 const double ylo = iy * g.h[1];
                 const double dym = fmax(0.0, fmax(ylo - yi, yi - (ylo + g.h[1])));
@@ -130,8 +163,8 @@ __global__ void __launch_bounds__(kForceBlock) k_forces(ForceArgs a, double rc_m
                 double sy = 0.0;
                 if (iy < 0) { wy += g.n[1]; sy = -g.L[1]; }
                 else if (iy >= g.n[1]) { wy -= g.n[1]; sy = g.L[1]; }
-                const double rx = sqrt(rem);
-                const int ixlo = floor_div(xi - rx, g.h[0]), ixhi = floor_div(xi + rx, g.h[0]);
+                const double rx = sqrt_up(rem);
+                const int ixlo = floor_mul(xi - rx, ihx), ixhi = floor_mul(xi + rx, ihx);
                 const int64_t row = ((int64_t)wz * g.n[1] + wy) * g.n[0];
                 // up to two contiguous slot ranges (the second one wraps around x)
                 int lo0 = ixlo, hi0 = ixhi, lo1 = 0, hi1 = -1;
@@ -143,16 +176,11 @@ __global__ void __launch_bounds__(kForceBlock) k_forces(ForceArgs a, double rc_m
                     hi0 = g.n[0] - 1;
                     lo1 = 0; hi1 = ixhi - g.n[0]; sx1 = g.L[0];
                 }
-                {
-                    const uint32_t jb = a.cell_start[row + lo0], je = a.cell_start[row + hi0 + 1];
-                    for (uint32_t j = jb; j < je; ++j)
-                        interact<PAIR, SHIFT>(a, a.pos[j], i, j, xi, yi, zi, rci, rc2, sx0, sy, sz, c);
-                }
-                if (hi1 >= lo1) {
-                    const uint32_t jb = a.cell_start[row + lo1], je = a.cell_start[row + hi1 + 1];
-                    for (uint32_t j = jb; j < je; ++j)
-                        interact<PAIR, SHIFT>(a, a.pos[j], i, j, xi, yi, zi, rci, rc2, sx1, sy, sz, c);
-                }
+                scan_interval<PAIR, SHIFT, U>(a, a.cell_start[row + lo0], a.cell_start[row + hi0 + 1], i, xi, yi,
+                                           zi, rci, rc2, sx0, sy, sz, c);
+                if (hi1 >= lo1)
+                    scan_interval<PAIR, SHIFT, U>(a, a.cell_start[row + lo1], a.cell_start[row + hi1 + 1], i, xi,
+                                               yi, zi, rci, rc2, sx1, sy, sz, c);
             }
         }
         // e_i = 1/2 sum 4 eps (sr12 - sr6); W_i = 1/2 sum dx (x) f
@@ -212,20 +240,22 @@ __global__ void __launch_bounds__(kForceBlock) k_forces(ForceArgs a, double rc_m
     }
 }
 
+
 }  // namespace
 
 int force_blocks(int64_t n) { return (int)((n + kForceBlock - 1) / kForceBlock); }
 
 void launch_forces(const ForceArgs &a, hipStream_t st)
 {
+    constexpr int U = 4;
     const int nb = force_blocks(a.n);
     const double rc_max = a.rc_max;
     if (a.pair_rule == DCM_PAIR_MAX) {
-        if (a.energy_shift) hipLaunchKernelGGL((k_forces<DCM_PAIR_MAX, true>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
-        else hipLaunchKernelGGL((k_forces<DCM_PAIR_MAX, false>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
+        if (a.energy_shift) hipLaunchKernelGGL((k_forces<DCM_PAIR_MAX, true, U>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
+        else hipLaunchKernelGGL((k_forces<DCM_PAIR_MAX, false, U>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
     } else {
-        if (a.energy_shift) hipLaunchKernelGGL((k_forces<DCM_PAIR_I, true>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
-        else hipLaunchKernelGGL((k_forces<DCM_PAIR_I, false>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
+        if (a.energy_shift) hipLaunchKernelGGL((k_forces<DCM_PAIR_I, true, U>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
+        else hipLaunchKernelGGL((k_forces<DCM_PAIR_I, false, U>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
     }
 }
 

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstddef>
+#include <climits>
 #include <cstdint>
 
 #include "../../include/dcm.h"
@@ -59,6 +60,9 @@ struct GridWork {
     long long *stats;       // [8] detection statistics
     uint32_t *changed;      // [max sweeps + 1] per-sweep change counters
     uint32_t *flags;        // [1] sticky device conditions
+    uint32_t *tdirty;       // [2 * distance_tiles] pass flags of the distance tiles
+    uint32_t *tcur;         // [2 * distance_tiles] which distance copy is current per tile
+    double *dist2;          // second copy of the distance grid
 };
 
 // ---- launchers (each enqueues on `st`; no synchronization) ------------------------------
@@ -82,6 +86,7 @@ void launch_two_means(const Grid &g, const uint32_t *img, GridWork w, long long 
 void launch_segment(const Grid &g, const uint32_t *img, const double *km, int32_t min_component,
                     GridWork w, hipStream_t st);
 int max_distance_sweeps(const Grid &g, double cap);
+int64_t distance_tiles(const Grid &g);
 void launch_distance(const Grid &g, double cap, const uint8_t *label, double *dist, GridWork w,
                      hipStream_t st);
 void launch_cutoffs(const Grid &g, PSet s, int64_t n, const double *dist, double cap,

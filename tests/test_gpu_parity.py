@@ -32,6 +32,16 @@ def ulp_close(a, b, k=ULP_TOL):
     return np.all(np.abs(a - b) <= k * np.spacing(np.maximum(np.abs(a), np.abs(b))))
 
 
+def rc_close(rc, ref, rc_min=2.5, rc_max=6.0, alpha=-0.5, h=1.0):
+    """Cutoffs within the propagated bound: box distances may differ by 4 ulp of the band cap
+    (two valid update orders of the same upwind equations), the cutoff function's slope is at
+    most |a alpha ln 2| (Eq. 7-8), plus 4 ulp of r_c itself for the exponential."""
+    a = (rc_max - rc_min) / (2.0 ** (alpha * rc_max) - 1.0) if rc_min != rc_max else 0.0
+    slope = abs(a * alpha * np.log(2.0))
+    tol = slope * ULP_TOL * np.spacing(rc_max + h) + ULP_TOL * np.spacing(np.maximum(np.abs(rc), np.abs(ref)))
+    return np.all(np.abs(np.asarray(rc) - np.asarray(ref)) <= tol)
+
+
 def force_err(f, ref):
     frms = np.sqrt(np.mean(np.sum(ref ** 2, axis=0)))
     return np.linalg.norm(f - ref, axis=0) / np.maximum(np.linalg.norm(ref, axis=0), frms)
@@ -69,7 +79,7 @@ def check_system(state, p, po, name):
     assert st[0] == od.stats[0] and np.array_equal(st[1:5], od.stats[1:5]), (st, od.stats)
     assert ulp_close(det["dist"].cpu().numpy(), od.dist), "distances"
     rc_gpu = rc.cpu().numpy()
-    assert ulp_close(rc_gpu, od.rc), "cutoffs"
+    assert rc_close(rc_gpu, od.rc, p.rc_min, p.rc_max, p.alpha), "cutoffs"
     assert ulp_close(det["rc"].cpu().numpy(), rc_gpu, 0)
     ref = O.forces(po, xw, rc_gpu)
     err = force_err(fo["f"].cpu().numpy(), ref.f)
@@ -283,7 +293,8 @@ def test_slab2m_sampled_parity():
     assert np.array_equal(det["label"].cpu().numpy(), od.label)
     assert np.array_equal(det["km"].cpu().numpy(), od.km)
     rc_gpu = rc.cpu().numpy()
-    assert ulp_close(rc_gpu, od.rc)
+    assert ulp_close(det["dist"].cpu().numpy(), od.dist), "distances"
+    assert rc_close(rc_gpu, od.rc), "cutoffs"
     idx = np.random.default_rng(9).choice(st.n, 3000, replace=False)
     # every particle within 7 sigma of a periodic face is among the sampled too
     edge = np.nonzero((xw[0] < 7) | (xw[0] > st.box[0] - 7))[0][:500]
