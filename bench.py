@@ -76,6 +76,52 @@ def cpu_baseline(state, sample: int, seed: int = 12345):
                 seconds=dict(detect=t_det, forces_scaled=t_f, integrate=t_int))
 
 
+def precision_study(nsteps: int, sample: int = 2000):
+    """Both forms on the 256,000-particle slab with shifted pair energies: total-energy drift
+    per particle over nsteps, and the per-atom force error |dF_i| / max(|F_i|, F_rms) of each
+    form against the FP64 oracle on sampled particles of that form's own state (checkpoints at
+    0, nsteps/2 and nsteps)."""
+    import numpy as np
+    import torch
+    import oracle as O
+    from paper_1502_03234_amd import dcm, synth
+
+    st = synth.named("slab256k")
+    po = O.params(st.box, energy_shift=1)
+    idx = np.sort(np.random.default_rng(7).choice(st.n, sample, replace=False))
+    out = {"study": "precision", "workload": "LJ slab 256,000 particles, box 112x112x60, shifted pair "
+           "energies, detect every 2nd step", "steps": nsteps, "forms": {}}
+    for name, prec in (("f64", dcm.DCM_FP64), ("f32c", dcm.DCM_FP32C)):
+        p = dcm.params(st.box, precision=prec, energy_shift=1)
+        s = dcm.System(p, st.x, st.v)
+        errs, energies = [], []
+        half = nsteps // 2
+        for leg in (0, half, nsteps - half):
+            if leg:
+                th = dcm.thermo_records(s.step(leg))
+                energies += [r["ke"] + r["pe"] for r in th]
+            fo = s.forces(per_atom=False, thermo=(not energies))
+            if not energies:
+                t0 = dcm.thermo_records(fo["thermo"])[0]
+                energies.append(t0["ke"] + t0["pe"])
+            x, v, rc, k = s.state()
+            torch.cuda.synchronize()
+            ref = O.forces(po, x.cpu().numpy(), rc.cpu().numpy(), subset=idx)
+            f = fo["f"].cpu().numpy()[:, idx]
+            frms = np.sqrt(np.mean(np.sum(ref.f ** 2, axis=0)))
+            e = np.linalg.norm(f - ref.f, axis=0) / np.maximum(np.linalg.norm(ref.f, axis=0), frms)
+            errs.append({"step": k, "max": float(e.max()), "rms": float(np.sqrt(np.mean(e ** 2)))})
+            log(f"{name} step {k}: force error max {e.max():.3e}")
+        s.check()
+        en = np.array(energies) / st.n
+        out["forms"][name] = {"energy_per_particle_start": float(en[0]),
+                              "drift_per_particle": float(en[-1] - en[0]),
+                              "max_excursion_per_particle": float(np.max(np.abs(en - en[0]))),
+                              "force_error": errs}
+        s.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +134,8 @@ def main():
                     help="also time the same system with a static cutoff r_c = r_c^max")
     ap.add_argument("--forces-only", type=int, default=0, metavar="K",
                     help="only create the system and run K force evaluations (counter passes)")
+    ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
+                    help="256k slab: NVE drift and force error vs the oracle for both forms")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -108,6 +156,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copied {src.numel() * 8} bytes")
+        return
+    if args.precision_study:
+        precision_study(args.precision_study)
         return
     log(f"generating {WORKLOAD}")
     state = synth.named(WORKLOAD)

@@ -91,7 +91,7 @@ dcm_status validate(const dcm_params *p, int64_t n, Grid &g)
     if (p->detect_every < 0) return fail(DCM_E_INVALID, "detect_every must be >= 0");
     if (!(p->dt > 0.0) || !(p->mass > 0.0) || !(p->sigma > 0.0) || !(p->epsilon >= 0.0))
         return fail(DCM_E_INVALID, "dt, mass and sigma must be positive, epsilon non-negative");
-    if (p->precision != DCM_FP64) return fail(DCM_E_INVALID, "precision: only DCM_FP64 is available");
+    if (p->precision != DCM_FP64 && p->precision != DCM_FP32C) return fail(DCM_E_INVALID, "unknown precision");
     if (p->pair_rule != DCM_PAIR_I && p->pair_rule != DCM_PAIR_MAX) return fail(DCM_E_INVALID, "unknown pair_rule");
     return DCM_OK;
 }
@@ -255,6 +255,8 @@ void forces(dcm_system *s, hipStream_t st, double *e_out, double *w_out, uint32_
     a.eps24 = 24.0 * s->p.epsilon;
     a.eps4 = 4.0 * s->p.epsilon;
     a.sigma2 = s->p.sigma * s->p.sigma;
+    a.eps24f = (float)a.eps24;
+    a.sigma2f = (float)a.sigma2;
     a.rc_max = s->p.rc_max;
     a.pair_rule = s->p.pair_rule;
     a.energy_shift = s->p.energy_shift;

@@ -43,6 +43,30 @@ struct Acc {
     uint32_t pairs;
 };
 
+// Precision form: FP32 running sums with their TwoSum error terms (force, energy), plain FP32
+// virial sums.
+struct Acc32 {
+    float fx, fy, fz, e, cfx, cfy, cfz, ce, wxx, wyy, wzz, wxy, wxz, wyz, eshift;
+    uint32_t pairs;
+};
+
+// s + x with the rounding error of the addition collected in c (Knuth's TwoSum: exact for any
+// magnitudes, no branch).
+__device__ __forceinline__ void two_sum_add(float &s, float &c, float x)
+{
+    const float t = s + x;
+    const float bp = t - s;
+    const float ap = t - bp;
+    c += (s - ap) + (x - bp);
+    s = t;
+}
+
+__device__ __forceinline__ float rcp_f32(float a)
+{
+    float y = __builtin_amdgcn_rcpf(a);
+    return fmaf(y, fmaf(-a, y, 1.0f), y);
+}
+
 template <int PAIR, bool SHIFT, bool IMAGE>
 __device__ __forceinline__ void interact(const ForceArgs &a, const double4 pj, bool valid,
                                          double xi, double yi, double zi, double rci, double rc2,
@@ -84,12 +108,53 @@ __device__ __forceinline__ void interact(const ForceArgs &a, const double4 pj, b
     }
 }
 
+template <int PAIR, bool SHIFT, bool IMAGE>
+__device__ __forceinline__ void interact(const ForceArgs &a, const double4 pj, bool valid,
+                                         double xi, double yi, double zi, double rci, double rc2,
+                                         double sx, double sy, double sz, Acc32 &c)
+{
+    // displacement, r^2 and the cutoff test stay FP64: the pair set is the FP64 one
+    double dx = IMAGE ? xi - (pj.x + sx) : xi - pj.x;
+    double dy = IMAGE ? yi - (pj.y + sy) : yi - pj.y;
+    double dz = IMAGE ? zi - (pj.z + sz) : zi - pj.z;
+    double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    double lim2 = rc2;
+    if (PAIR == DCM_PAIR_MAX) {
+        double rcp = pj.w > rci ? pj.w : rci;
+        lim2 = rcp * rcp;
+    }
+    if (valid && r2 < lim2) {
+        const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
+        const float inv = rcp_f32((float)r2);
+        const float sr2 = a.sigma2f * inv;
+        const float sr6 = sr2 * sr2 * sr2;
+        const float fr = a.eps24f * sr6 * fmaf(2.0f, sr6, -1.0f) * inv;
+        const float fxp = fr * fdx, fyp = fr * fdy, fzp = fr * fdz;
+        two_sum_add(c.fx, c.cfx, fxp);
+        two_sum_add(c.fy, c.cfy, fyp);
+        two_sum_add(c.fz, c.cfz, fzp);
+        two_sum_add(c.e, c.ce, fmaf(sr6, sr6, -sr6));
+        c.wxx = fmaf(fdx, fxp, c.wxx);
+        c.wyy = fmaf(fdy, fyp, c.wyy);
+        c.wzz = fmaf(fdz, fzp, c.wzz);
+        c.wxy = fmaf(fdx, fyp, c.wxy);
+        c.wxz = fmaf(fdx, fzp, c.wxz);
+        c.wyz = fmaf(fdy, fzp, c.wyz);
+        c.pairs += 1;
+        if (SHIFT && PAIR == DCM_PAIR_MAX) {
+            const float s2 = a.sigma2f / (float)lim2;
+            const float s6 = s2 * s2 * s2;
+            c.eshift += fmaf(s6, s6, -s6);
+        }
+    }
+}
+
 // All candidates of one slot interval [jb, je), U loads in flight at a time; the particle
 // itself (slot i) is skipped.
-template <int PAIR, bool SHIFT, bool IMAGE, int U>
+template <int PAIR, bool SHIFT, bool IMAGE, int U, typename A>
 __device__ __forceinline__ void scan(const ForceArgs &a, uint32_t jb, uint32_t je, int64_t i,
                                      double xi, double yi, double zi, double rci, double rc2,
-                                     double sx, double sy, double sz, Acc &c)
+                                     double sx, double sy, double sz, A &c)
 {
     for (uint32_t j0 = jb; j0 < je; j0 += U) {
         const uint32_t last = je - 1;
@@ -106,26 +171,80 @@ __device__ __forceinline__ void scan(const ForceArgs &a, uint32_t jb, uint32_t j
     }
 }
 
-template <int PAIR, bool SHIFT, int U>
+template <int PAIR, bool SHIFT, int U, typename A>
 __device__ __forceinline__ void scan_interval(const ForceArgs &a, uint32_t jb, uint32_t je, int64_t i,
                                               double xi, double yi, double zi, double rci, double rc2,
-                                              double sx, double sy, double sz, Acc &c)
+                                              double sx, double sy, double sz, A &c)
 {
     const bool image = sx != 0.0 || sy != 0.0 || sz != 0.0;
     if (__any(image))
-        scan<PAIR, SHIFT, true, U>(a, jb, je, i, xi, yi, zi, rci, rc2, sx, sy, sz, c);
+        scan<PAIR, SHIFT, true, U, A>(a, jb, je, i, xi, yi, zi, rci, rc2, sx, sy, sz, c);
     else
-        scan<PAIR, SHIFT, false, U>(a, jb, je, i, xi, yi, zi, rci, rc2, sx, sy, sz, c);
+        scan<PAIR, SHIFT, false, U, A>(a, jb, je, i, xi, yi, zi, rci, rc2, sx, sy, sz, c);
 }
 
-template <int PAIR, bool SHIFT, int U>
+// Walks the box rows within particle i's search radius and scans each row's x-interval.
+template <int PAIR, bool SHIFT, int U, typename A>
+__device__ __forceinline__ void traverse(const ForceArgs &a, int64_t i, double xi, double yi, double zi,
+                                         double rci, double rc2, double rc_max, A &c)
+{
+    const Grid &g = a.grid;
+    // search radius (slightly enlarged so that rounding in the box bounds never drops a box
+    // that holds an in-range particle; the pair test itself is exact)
+    double rs = PAIR == DCM_PAIR_MAX ? rc_max : rci;
+    rs = rs * (1.0 + 1e-12) + 1e-9;
+    const double rs2 = rs * rs;
+    const double ihx = 1.0 / g.h[0], ihy = 1.0 / g.h[1], ihz = 1.0 / g.h[2];
+    const int izlo = floor_mul(zi - rs, ihz), izhi = floor_mul(zi + rs, ihz);
+    for (int iz = izlo; iz <= izhi; ++iz) {
+        const double zlo = iz * g.h[2];
+        const double dzm = fmax(0.0, fmax(zlo - zi, zi - (zlo + g.h[2])));
+        const double remz = rs2 - dzm * dzm;
+        if (remz < 0.0) continue;
+        int wz = iz;
+        double sz = 0.0;
+        if (iz < 0) { wz += g.n[2]; sz = -g.L[2]; }
+        else if (iz >= g.n[2]) { wz -= g.n[2]; sz = g.L[2]; }
+        const double ry = sqrt_up(remz);
+        const int iylo = floor_mul(yi - ry, ihy), iyhi = floor_mul(yi + ry, ihy);
+        for (int iy = iylo; iy <= iyhi; ++iy) {
+            const double ylo = iy * g.h[1];
+            const double dym = fmax(0.0, fmax(ylo - yi, yi - (ylo + g.h[1])));
+            const double rem = remz - dym * dym;
+            if (rem < 0.0) continue;
+            int wy = iy;
+            double sy = 0.0;
+            if (iy < 0) { wy += g.n[1]; sy = -g.L[1]; }
+            else if (iy >= g.n[1]) { wy -= g.n[1]; sy = g.L[1]; }
+            const double rx = sqrt_up(rem);
+            const int ixlo = floor_mul(xi - rx, ihx), ixhi = floor_mul(xi + rx, ihx);
+            const int64_t row = ((int64_t)wz * g.n[1] + wy) * g.n[0];
+            // up to two contiguous slot ranges (the second one wraps around x)
+            int lo0 = ixlo, hi0 = ixhi, lo1 = 0, hi1 = -1;
+            double sx0 = 0.0, sx1 = 0.0;
+            if (ixlo < 0) {
+                lo0 = ixlo + g.n[0]; hi0 = g.n[0] - 1; sx0 = -g.L[0];
+                lo1 = 0; hi1 = ixhi;
+            } else if (ixhi >= g.n[0]) {
+                hi0 = g.n[0] - 1;
+                lo1 = 0; hi1 = ixhi - g.n[0]; sx1 = g.L[0];
+            }
+            scan_interval<PAIR, SHIFT, U, A>(a, a.cell_start[row + lo0], a.cell_start[row + hi0 + 1], i, xi, yi,
+                                             zi, rci, rc2, sx0, sy, sz, c);
+            if (hi1 >= lo1)
+                scan_interval<PAIR, SHIFT, U, A>(a, a.cell_start[row + lo1], a.cell_start[row + hi1 + 1], i, xi,
+                                                 yi, zi, rci, rc2, sx1, sy, sz, c);
+        }
+    }
+}
+
+template <int PAIR, bool SHIFT, int U, int PREC>
 __global__ void __launch_bounds__(kForceBlock) k_forces(ForceArgs a, double rc_max)
 {
     // hardware (round-robin over XCDs) block order: the cost per particle varies strongly
     // with z through the cutoffs, and interleaving keeps every XCD's share of it even
     const int64_t b = blockIdx.x;
     const int64_t i = b * kForceBlock + threadIdx.x;
-    const Grid &g = a.grid;
     Acc c = {};
     if (i < a.n) {
         const double4 pi = a.pos[i];
@@ -134,55 +253,22 @@ __global__ void __launch_bounds__(kForceBlock) k_forces(ForceArgs a, double rc_m
         // a non-finite position or a cutoff outside (0, rc_max] would send the box loops out
         // of the grid: such a particle gets no traversal and a NaN force (flagged below)
         const bool sane = isfinite(xi) && isfinite(yi) && isfinite(zi) && rci > 0.0 && rci <= rc_max;
-        if (!sane) c.fx = NAN;
-        // search radius (slightly enlarged so that rounding in the box bounds never drops a
-        // box that holds an in-range particle; the pair test itself is exact)
-        double rs = PAIR == DCM_PAIR_MAX ? rc_max : rci;
-        rs = rs * (1.0 + 1e-12) + 1e-9;
-        const double rs2 = rs * rs;
-        const double ihx = 1.0 / g.h[0], ihy = 1.0 / g.h[1], ihz = 1.0 / g.h[2];
-        const int izlo = sane ? floor_mul(zi - rs, ihz) : 0;
-        const int izhi = sane ? floor_mul(zi + rs, ihz) : -1;
-        for (int iz = izlo; iz <= izhi; ++iz) {
-            const double zlo = iz * g.h[2];
-            const double dzm = fmax(0.0, fmax(zlo - zi, zi - (zlo + g.h[2])));
-            const double remz = rs2 - dzm * dzm;
-            if (remz < 0.0) continue;
-            int wz = iz;
-            double sz = 0.0;
-            if (iz < 0) { wz += g.n[2]; sz = -g.L[2]; }
-            else if (iz >= g.n[2]) { wz -= g.n[2]; sz = g.L[2]; }
-            const double ry = sqrt_up(remz);
-            const int iylo = floor_mul(yi - ry, ihy), iyhi = floor_mul(yi + ry, ihy);
-            for (int iy = iylo; iy <= iyhi; ++iy) {
-                const double ylo = iy * g.h[1];
-                const double dym = fmax(0.0, fmax(ylo - yi, yi - (ylo + g.h[1])));
-                const double rem = remz - dym * dym;
-                if (rem < 0.0) continue;
-                int wy = iy;
-                double sy = 0.0;
-                if (iy < 0) { wy += g.n[1]; sy = -g.L[1]; }
-                else if (iy >= g.n[1]) { wy -= g.n[1]; sy = g.L[1]; }
-                const double rx = sqrt_up(rem);
-                const int ixlo = floor_mul(xi - rx, ihx), ixhi = floor_mul(xi + rx, ihx);
-                const int64_t row = ((int64_t)wz * g.n[1] + wy) * g.n[0];
-                // up to two contiguous slot ranges (the second one wraps around x)
-                int lo0 = ixlo, hi0 = ixhi, lo1 = 0, hi1 = -1;
-                double sx0 = 0.0, sx1 = 0.0;
-                if (ixlo < 0) {
-                    lo0 = ixlo + g.n[0]; hi0 = g.n[0] - 1; sx0 = -g.L[0];
-                    lo1 = 0; hi1 = ixhi;
-                } else if (ixhi >= g.n[0]) {
-                    hi0 = g.n[0] - 1;
-                    lo1 = 0; hi1 = ixhi - g.n[0]; sx1 = g.L[0];
-                }
-                scan_interval<PAIR, SHIFT, U>(a, a.cell_start[row + lo0], a.cell_start[row + hi0 + 1], i, xi, yi,
-                                           zi, rci, rc2, sx0, sy, sz, c);
-                if (hi1 >= lo1)
-                    scan_interval<PAIR, SHIFT, U>(a, a.cell_start[row + lo1], a.cell_start[row + hi1 + 1], i, xi,
-                                               yi, zi, rci, rc2, sx1, sy, sz, c);
-            }
+        if (PREC == DCM_FP64) {
+            if (sane) traverse<PAIR, SHIFT, U, Acc>(a, i, xi, yi, zi, rci, rc2, rc_max, c);
+        } else {
+            Acc32 c32 = {};
+            if (sane) traverse<PAIR, SHIFT, U, Acc32>(a, i, xi, yi, zi, rci, rc2, rc_max, c32);
+            // FP32 sums and their compensation terms, combined in FP64
+            c.fx = (double)c32.fx + (double)c32.cfx;
+            c.fy = (double)c32.fy + (double)c32.cfy;
+            c.fz = (double)c32.fz + (double)c32.cfz;
+            c.e = (double)c32.e + (double)c32.ce;
+            c.wxx = c32.wxx; c.wyy = c32.wyy; c.wzz = c32.wzz;
+            c.wxy = c32.wxy; c.wxz = c32.wxz; c.wyz = c32.wyz;
+            c.eshift = c32.eshift;
+            c.pairs = c32.pairs;
         }
+        if (!sane) c.fx = NAN;
         // e_i = 1/2 sum 4 eps (sr12 - sr6); W_i = 1/2 sum dx (x) f
         double e = 0.5 * a.eps4 * c.e;
         if (SHIFT) {
@@ -240,23 +326,29 @@ __global__ void __launch_bounds__(kForceBlock) k_forces(ForceArgs a, double rc_m
     }
 }
 
-
 }  // namespace
 
 int force_blocks(int64_t n) { return (int)((n + kForceBlock - 1) / kForceBlock); }
 
-void launch_forces(const ForceArgs &a, hipStream_t st)
+template <int PREC>
+static void launch_prec(const ForceArgs &a, int nb, hipStream_t st)
 {
     constexpr int U = 4;
-    const int nb = force_blocks(a.n);
     const double rc_max = a.rc_max;
     if (a.pair_rule == DCM_PAIR_MAX) {
-        if (a.energy_shift) hipLaunchKernelGGL((k_forces<DCM_PAIR_MAX, true, U>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
-        else hipLaunchKernelGGL((k_forces<DCM_PAIR_MAX, false, U>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
+        if (a.energy_shift) hipLaunchKernelGGL((k_forces<DCM_PAIR_MAX, true, U, PREC>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
+        else hipLaunchKernelGGL((k_forces<DCM_PAIR_MAX, false, U, PREC>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
     } else {
-        if (a.energy_shift) hipLaunchKernelGGL((k_forces<DCM_PAIR_I, true, U>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
-        else hipLaunchKernelGGL((k_forces<DCM_PAIR_I, false, U>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
+        if (a.energy_shift) hipLaunchKernelGGL((k_forces<DCM_PAIR_I, true, U, PREC>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
+        else hipLaunchKernelGGL((k_forces<DCM_PAIR_I, false, U, PREC>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
     }
+}
+
+void launch_forces(const ForceArgs &a, hipStream_t st)
+{
+    const int nb = force_blocks(a.n);
+    if (a.precision == DCM_FP32C) launch_prec<DCM_FP32C>(a, nb, st);
+    else launch_prec<DCM_FP64>(a, nb, st);
 }
 
 }  // namespace dcm

@@ -102,6 +102,7 @@ struct ForceArgs {
     const uint32_t *id;
     int64_t n;
     double eps24, eps4, sigma2;
+    float eps24f, sigma2f;  // the same constants for the FP32 precision form
     double rc_max;          // largest cutoff (search radius of the symmetric rule)
     int pair_rule;
     int energy_shift;

@@ -314,3 +314,55 @@ def test_slab2m_sampled_parity():
     s.step(4)
     s.check()
     s.close()
+
+
+# ---- precision form: FP32 pair math, compensated FP32 per-particle sums --------------------
+FP32_FORCE_TOL = 1e-5
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(pair_rule=dcm.DCM_PAIR_MAX), dict(energy_shift=1),
+                                dict(rc_min=3.0, rc_max=3.0)])
+def test_precision_form_against_fp64_oracle(slab16k, kw):
+    p = dcm.params(slab16k.box, precision=dcm.DCM_FP32C, **kw)
+    po = O.params(slab16k.box, **kw)
+    s = dcm.System(p, slab16k.x, slab16k.v)
+    fo = s.forces()
+    x, v, rc, k = s.state()
+    torch.cuda.synchronize()
+    s.check()
+    xw, rcg = x.cpu().numpy(), rc.cpu().numpy()
+    ref = O.forces(po, xw, rcg)
+    err = force_err(fo["f"].cpu().numpy(), ref.f)
+    say(f"fp32c {kw}: max per-atom force error {err.max():.2e}")
+    assert err.max() <= FP32_FORCE_TOL
+    # the cutoff test runs in FP64: the pair set is exactly the FP64 one
+    assert np.array_equal(fo["pairs"].cpu().numpy().astype(np.int64), ref.pairs)
+    e = fo["e"].cpu().numpy()
+    assert np.max(np.abs(e - ref.e) / np.maximum(np.abs(ref.e), 1.0)) < 1e-5
+    w = fo["w"].cpu().numpy()
+    wscale = np.maximum(np.abs(ref.w).max(axis=0, keepdims=True), 1.0)
+    assert np.max(np.abs(w - ref.w) / wscale) < 1e-4
+    th = dcm.thermo_records(fo["thermo"])[0]
+    assert abs(th["pe"] - ref.e.sum()) <= 1e-6 * np.abs(ref.e).sum()
+    s.close()
+
+
+def test_precision_form_steps_and_schedule(slab16k):
+    """The precision form runs the same step sequence (detection schedule, integration)."""
+    p = dcm.params(slab16k.box, precision=dcm.DCM_FP32C)
+    a = dcm.System(p, slab16k.x, slab16k.v)
+    th = dcm.thermo_records(a.step(10))
+    a.check()
+    p64 = dcm.params(slab16k.box)
+    b = dcm.System(p64, slab16k.x, slab16k.v)
+    th64 = dcm.thermo_records(b.step(10))
+    xa, _, _, ka = a.state()
+    xb, _, _, kb = b.state()
+    torch.cuda.synchronize()
+    assert ka == kb == 10
+    # trajectories stay close over a few steps (the forces differ by ~1e-7 relative)
+    assert float((xa - xb).abs().max()) < 1e-6
+    for r, q in zip(th, th64):
+        assert abs(r["pe"] - q["pe"]) < 1e-5 * abs(q["pe"]) and r["pairs"] == q["pairs"]
+    a.close()
+    b.close()
