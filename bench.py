@@ -122,6 +122,109 @@ def precision_study(nsteps: int, sample: int = 2000):
     print(json.dumps(out), flush=True)
 
 
+def serving_study(nseeds: int, nsys: int = 64, nsteps: int = 100, load: float = 0.8):
+    """Serving form against one-system-at-a-time solves on the same Poisson traces.
+
+    Systems: 64 slabs, N log-uniform on [4,000, 200,000], T* uniform on [0.65, 0.85], 100 steps
+    each. Sequential: every request is solved alone (H2D copy, create, 100 steps, D2H copy);
+    its wall-clock service time is measured once and the FIFO timeline of each trace follows
+    from the arrival times (exact for a single FIFO server). Capacity = requests / sum of
+    service times; arrivals are Poisson at load x capacity. Server: the same requests are
+    submitted at their arrival times to a dcm_server whose HBM budget is a quarter of the
+    trace's total footprint, so admission queues. Latency = completion - arrival."""
+    import numpy as np
+    import torch
+    from paper_1502_03234_amd import dcm, synth
+
+    trace = synth.serving_trace(1, nsys)
+    systems = [synth.serving_system(j, n, t) for j, (n, t) in enumerate(trace)]
+    params = [dcm.params(s.box) for s in systems]
+    sizes = np.array([s.n for s in systems])
+    log(f"serving: {nsys} systems, {sizes.sum()} particles, sizes {sizes.min()}..{sizes.max()}")
+    # sequential service times
+    svc = np.zeros(nsys)
+    for j, (s, p) in enumerate(zip(systems, params)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = torch.from_numpy(s.x).cuda()
+        v = torch.from_numpy(s.v).cuda()
+        sysm = dcm.System(p, x, v)
+        sysm.step(nsteps, thermo=True)
+        xo, vo, rc, k = sysm.state()
+        xo.cpu(), vo.cpu()
+        torch.cuda.synchronize()
+        svc[j] = time.perf_counter() - t0
+        sysm.close()
+    # warm the sequential path once more for the first (cold) system
+    cap = nsys / svc.sum()
+    rate = load * cap
+    foot = [dcm.dcm_workspace_bytes(p, s.n) + 48 * s.n + 4096 for s, p in zip(systems, params)]
+    budget = max(int(0.25 * sum(foot)), max(foot) + 4096)
+    pool = dcm.workspace(int(1.25 * budget))
+    seq_lat, srv_lat, seq_tp, srv_tp = [], [], [], []
+    atom_steps = float(sizes.sum()) * nsteps
+    for seed in range(1, nseeds + 1):
+        order = np.random.default_rng(seed).permutation(nsys)
+        arr = synth.poisson_arrivals(seed, nsys, rate)
+        # sequential FIFO timeline
+        t, lat = 0.0, []
+        for a, j in zip(arr, order):
+            t = max(t, a) + svc[j]
+            lat.append(t - a)
+        seq_lat += lat
+        seq_tp.append(atom_steps / (t - arr[0]))
+        # server, real time
+        sv = dcm.dcm_server_create(budget, pool)
+        t0 = time.perf_counter()
+        tickets, done = {}, {}
+        nxt = 0
+        while len(done) < nsys:
+            now = time.perf_counter() - t0
+            while nxt < nsys and arr[nxt] <= now:
+                j = order[nxt]
+                tickets[dcm.dcm_submit(sv, params[j], systems[j].x, systems[j].v, nsteps)] = (j, arr[nxt])
+                nxt += 1
+            for tk, (j, a) in list(tickets.items()):
+                st = dcm.dcm_poll(sv, tk, systems[j].n)[0]
+                if st == dcm.DCM_OK:
+                    done[tk] = (time.perf_counter() - t0) - a
+                    del tickets[tk]
+            time.sleep(0.0005)
+        last = time.perf_counter() - t0
+        stats = dcm.dcm_server_query(sv)
+        dcm.dcm_server_destroy(sv)
+        srv_lat += list(done.values())
+        srv_tp.append(atom_steps / (last - arr[0]))
+        log(f"seed {seed}: server p50 {np.percentile(list(done.values()), 50):.3f}s, "
+            f"batches {stats['batches']}, sequential p50 {np.percentile(lat, 50):.3f}s")
+    # saturated: every request arrives at t = 0; makespan against the sum of service times
+    sv = dcm.dcm_server_create(budget, pool)
+    t0 = time.perf_counter()
+    tickets = {dcm.dcm_submit(sv, params[j], systems[j].x, systems[j].v, nsteps): j
+               for j in range(nsys)}
+    while tickets:
+        for tk, j in list(tickets.items()):
+            if dcm.dcm_poll(sv, tk, systems[j].n)[0] == dcm.DCM_OK:
+                del tickets[tk]
+        time.sleep(0.0005)
+    makespan = time.perf_counter() - t0
+    dcm.dcm_server_destroy(sv)
+    log(f"saturated: server makespan {makespan:.3f}s, sequential {svc.sum():.3f}s")
+    out = {"study": "serving", "systems": nsys, "steps_each": nsteps, "seeds": nseeds,
+           "particles_total": int(sizes.sum()), "load": load, "arrival_rate_per_s": rate,
+           "hbm_budget_bytes": budget, "sequential_capacity_req_per_s": cap,
+           "server": {"throughput_atom_steps_per_s": float(np.mean(srv_tp)),
+                      "p50_latency_s": float(np.percentile(srv_lat, 50)),
+                      "p99_latency_s": float(np.percentile(srv_lat, 99))},
+           "sequential": {"throughput_atom_steps_per_s": float(np.mean(seq_tp)),
+                          "p50_latency_s": float(np.percentile(seq_lat, 50)),
+                          "p99_latency_s": float(np.percentile(seq_lat, 99))},
+           "saturated": {"server_atom_steps_per_s": atom_steps / makespan,
+                         "sequential_atom_steps_per_s": atom_steps / float(svc.sum())},
+           "samples": len(srv_lat)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,12 +239,14 @@ def main():
                     help="only create the system and run K force evaluations (counter passes)")
     ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
                     help="256k slab: NVE drift and force error vs the oracle for both forms")
+    ap.add_argument("--serve", type=int, default=0, metavar="SEEDS",
+                    help="serving study: 64 systems, Poisson arrivals, server vs sequential")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build shards nothing across GPUs "
-              "(see DESIGN.md for how the path would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: the DCM path here has no multi-GPU "
+              "decomposition; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -159,6 +264,9 @@ def main():
         return
     if args.precision_study:
         precision_study(args.precision_study)
+        return
+    if args.serve:
+        serving_study(args.serve)
         return
     log(f"generating {WORKLOAD}")
     state = synth.named(WORKLOAD)

@@ -216,6 +216,52 @@ dcm_status dcm_grid_distance(const int32_t dims[3], const double h[3], double ca
                              const uint8_t *d_label, double *d_dist, int64_t *d_sweeps,
                              void *d_ws, size_t ws_bytes, dcm_stream_t stream);
 
+
+/* ---- serving form -------------------------------------------------------------------
+ * A request loop runs many independent systems (each a full system as above) on one GPU.
+ * Not a thesis algorithm: it batches the per-step path of Sections 3-4 across systems.
+ *
+ * A worker thread admits queued requests in arrival order while the front request's device
+ * footprint (its dcm_workspace_bytes plus state staging and thermo records) fits the
+ * remaining HBM budget and a free range of the pool. Admitted systems stay resident, each on
+ * its own stream; the step sequence of one detection period is captured once into a hipGraph
+ * and replayed for all resident systems every batch (remaining steps shorter than a period
+ * run as ordinary launches). Results are copied to host memory on completion.
+ * Thread safety: submit/poll/query may be called from any one thread at a time. */
+typedef struct dcm_server dcm_server;
+
+typedef struct {
+    int64_t submitted, admitted, completed, rejected, queued, running, batches;
+    size_t bytes_in_use;
+} dcm_server_stats;
+
+/* d_pool: caller-owned device memory of pool_bytes (256-byte aligned) the server sub-allocates;
+ * hbm_budget <= pool_bytes caps the bytes resident at once. Work queued on `stream` is waited
+ * for first. DCM_E_INVALID for a NULL/misaligned pool or a budget of 0 or above pool_bytes. */
+dcm_status dcm_server_create(size_t hbm_budget, void *d_pool, size_t pool_bytes, dcm_stream_t stream,
+                             dcm_server **out);
+
+/* Queue one system: parameters as for dcm_create, host arrays h_x, h_v [3][n] (copied; the
+ * caller may free them on return), nsteps >= 0 velocity-Verlet steps. *ticket identifies it.
+ * DCM_E_BUDGET if its footprint exceeds the budget (it could never be admitted); the checks
+ * of dcm_workspace_bytes otherwise. */
+dcm_status dcm_submit(dcm_server *sv, const dcm_params *p, int64_t n, const double *h_x, const double *h_v,
+                      int32_t nsteps, uint64_t *ticket);
+
+/* DCM_PENDING while the request is queued or running. When it has finished: its status
+ * (DCM_OK or the error of its system), and on DCM_OK the final positions and velocities into
+ * h_x_out, h_v_out [3][n] (host, optional) and the last step's thermo record into h_last
+ * (optional); the ticket is then released. DCM_E_UNKNOWN_TICKET for a ticket never issued or
+ * already returned. */
+dcm_status dcm_poll(dcm_server *sv, uint64_t ticket, double *h_x_out, double *h_v_out, dcm_thermo *h_last);
+
+/* Counters of the request loop (host copy). */
+dcm_status dcm_server_query(dcm_server *sv, dcm_server_stats *st);
+
+/* Stop admitting, let resident systems finish their steps, drop still-queued requests, join
+ * the worker and release the handle (the caller frees the pool afterwards). */
+dcm_status dcm_server_destroy(dcm_server *sv);
+
 #ifdef __cplusplus
 }
 #endif

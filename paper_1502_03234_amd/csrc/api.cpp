@@ -103,33 +103,11 @@ int key_bits(int64_t G)
     return b;
 }
 
-struct Event {
-    int stage;
-    hipEvent_t a, b;
-};
+
 
 }  // namespace
 
-struct dcm_system {
-    dcm_params p;
-    int64_t n;
-    Grid grid;
-    int bits;
-    double hdt, cut_a, cut_b, cap;
-    PSet set[2];
-    int cur;
-    double *fx, *fy, *fz;
-    uint32_t *key, *val, *key_alt, *val_alt;
-    void *sort_scratch;
-    GridWork gw;
-    Partial *fparts, *kparts;
-    int nfb, nkb;
-    int64_t k;
-    bool profiling;
-    std::vector<Event> events, spare;
-    double ms[DCM_NSTAGES];
-    int64_t counts[DCM_NSTAGES];
-};
+
 
 namespace {
 

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstddef>
 #include <climits>
+#include <vector>
 #include <cstdint>
 
 #include "../../include/dcm.h"
@@ -138,3 +139,32 @@ void launch_scatter_rc(PSet s, const double *rc_in, int64_t n, double rc_min, do
 void launch_check_finite(const double *a, int64_t count, uint32_t *flags, hipStream_t st);
 
 }  // namespace dcm
+
+// Handle of one system (shared by the C ABI and the serving loop).
+namespace dcm {
+struct Event {
+    int stage;
+    hipEvent_t a, b;
+};
+}  // namespace dcm
+
+struct dcm_system {
+    dcm_params p;
+    int64_t n;
+    dcm::Grid grid;
+    int bits;
+    double hdt, cut_a, cut_b, cap;
+    dcm::PSet set[2];
+    int cur;
+    double *fx, *fy, *fz;
+    uint32_t *key, *val, *key_alt, *val_alt;
+    void *sort_scratch;
+    dcm::GridWork gw;
+    dcm::Partial *fparts, *kparts;
+    int nfb, nkb;
+    int64_t k;
+    bool profiling;
+    std::vector<dcm::Event> events, spare;
+    double ms[DCM_NSTAGES];
+    int64_t counts[DCM_NSTAGES];
+};

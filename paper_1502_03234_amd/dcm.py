@@ -47,6 +47,12 @@ class Thermo(C.Structure):
 THERMO_DOUBLES = C.sizeof(Thermo) // 8     # 10 doubles per record
 
 
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("rejected", C.c_int64), ("queued", C.c_int64), ("running", C.c_int64),
+                ("batches", C.c_int64), ("bytes_in_use", C.c_size_t)]
+
+
 class DetectOut(C.Structure):
     _fields_ = [("count", C.c_void_p), ("smooth", C.c_void_p), ("raw", C.c_void_p),
                 ("label", C.c_void_p), ("dist", C.c_void_p), ("rc", C.c_void_p),
@@ -80,6 +86,11 @@ _SIGS = {
     "dcm_grid_two_means": ([_vp, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
     "dcm_grid_segment": ([_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
     "dcm_grid_distance": ([_vp, _vp, C.c_double, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
+    "dcm_server_create": ([_sz, _vp, _sz, _vp, C.POINTER(_vp)], _i32),
+    "dcm_submit": ([_vp, _PP, _i64, _vp, _vp, _i32, C.POINTER(C.c_uint64)], _i32),
+    "dcm_poll": ([_vp, C.c_uint64, _vp, _vp, C.POINTER(Thermo)], _i32),
+    "dcm_server_query": ([_vp, C.POINTER(ServerStats)], _i32),
+    "dcm_server_destroy": ([_vp], _i32),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -230,6 +241,48 @@ def dcm_grid_distance(dims, h, cap: float, label, dist, sweeps, ws, stream=None)
     hh = (C.c_double * 3)(*h)
     _check(_lib.dcm_grid_distance(d, hh, float(cap), _ptr(label), _ptr(dist), _ptr(sweeps), _ptr(ws),
                                   ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def dcm_server_create(budget: int, pool, stream=None) -> int:
+    h = C.c_void_p()
+    _check(_lib.dcm_server_create(int(budget), _ptr(pool), pool.numel() * pool.element_size(),
+                                  _stream(stream), C.byref(h)))
+    return h.value
+
+
+def dcm_submit(sv: int, p: Params, x, v, nsteps: int) -> int:
+    """x, v: host float64 [3][n] arrays (numpy); copied by the library."""
+    import numpy as np
+    x = np.ascontiguousarray(x, np.float64)
+    v = np.ascontiguousarray(v, np.float64)
+    t = C.c_uint64()
+    _check(_lib.dcm_submit(sv, C.byref(p), x.shape[1], x.ctypes.data, v.ctypes.data, int(nsteps),
+                           C.byref(t)))
+    return t.value
+
+
+def dcm_poll(sv: int, ticket: int, n: int):
+    """(status, x, v, thermo): status DCM_PENDING, or DCM_OK with host results."""
+    import numpy as np
+    x = np.empty((3, n))
+    v = np.empty((3, n))
+    th = Thermo()
+    st = _lib.dcm_poll(sv, int(ticket), x.ctypes.data, v.ctypes.data, C.byref(th))
+    if st == DCM_PENDING:
+        return st, None, None, None
+    _check(st)
+    rec = dict(ke=th.ke, pe=th.pe, virial=list(th.virial), pairs=th.pairs, step=th.step)
+    return st, x, v, rec
+
+
+def dcm_server_query(sv: int) -> dict:
+    s = ServerStats()
+    _check(_lib.dcm_server_query(sv, C.byref(s)))
+    return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+
+def dcm_server_destroy(sv: int):
+    _check(_lib.dcm_server_destroy(sv))
 
 
 # ---- convenience: a system whose workspace and state tensors torch allocates -------------

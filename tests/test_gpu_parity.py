@@ -366,3 +366,77 @@ def test_precision_form_steps_and_schedule(slab16k):
         assert abs(r["pe"] - q["pe"]) < 1e-5 * abs(q["pe"]) and r["pairs"] == q["pairs"]
     a.close()
     b.close()
+
+
+# ---- serving form -------------------------------------------------------------------------
+def _eager(p, st, nsteps):
+    s = dcm.System(p, st.x, st.v)
+    th = dcm.thermo_records(s.step(nsteps)) if nsteps else []
+    x, v, rc, k = s.state()
+    torch.cuda.synchronize()
+    s.close()
+    return x.cpu().numpy(), v.cpu().numpy(), (th[-1] if th else None)
+
+
+def _serve(reqs, budget, pool_bytes):
+    import time
+    pool = dcm.workspace(pool_bytes)
+    sv = dcm.dcm_server_create(budget, pool)
+    tickets = [dcm.dcm_submit(sv, p, st.x, st.v, ns) for p, st, ns in reqs]
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets) and time.time() - t0 < 120:
+        for t, (p, st, ns) in zip(tickets, reqs):
+            if t in out:
+                continue
+            r = dcm.dcm_poll(sv, t, st.n)
+            if r[0] == dcm.DCM_OK:
+                out[t] = r
+        time.sleep(0.002)
+    stats = dcm.dcm_server_query(sv)
+    dcm.dcm_server_destroy(sv)
+    assert len(out) == len(tickets), "server did not finish in time"
+    return [out[t] for t in tickets], stats
+
+
+def test_served_systems_equal_eager_runs_bitwise():
+    """Graph-captured batched steps give the same bits as ordinary dcm_step calls
+    (several replays per system, odd tails, a period of 6 for detect_every = 3)."""
+    reqs = []
+    for j, (n, box, ns, de) in enumerate([(3000, (16.0, 16.0, 28.0), 7, 2), (5617, (14.0, 14.0, 60.0), 10, 2),
+                                          (9000, (20.0, 18.0, 40.0), 1, 2), (4000, (16.0, 16.0, 32.0), 13, 3),
+                                          (4000, (16.0, 16.0, 32.0), 6, 1)]):
+        st = synth.small_slab(n, box, 100 + j)
+        reqs.append((dcm.params(st.box, detect_every=de), st, ns))
+    got, stats = _serve(reqs, budget=1 << 31, pool_bytes=1 << 31)
+    assert stats["completed"] == len(reqs) and stats["rejected"] == 0
+    for (p, st, ns), (status, x, v, th) in zip(reqs, got):
+        ex, ev, eth = _eager(p, st, ns)
+        assert np.array_equal(x, ex) and np.array_equal(v, ev)
+        assert th["step"] == ns
+        if eth:
+            assert th["ke"] == eth["ke"] and th["pe"] == eth["pe"] and th["pairs"] == eth["pairs"]
+
+
+def test_server_budget_queues_and_rejects():
+    sts = [synth.small_slab(3000, (16.0, 16.0, 28.0), 200 + j) for j in range(4)]
+    p = dcm.params(sts[0].box)
+    ws = dcm.dcm_workspace_bytes(p, sts[0].n)
+    budget = int(ws * 1.5)              # one system resident at a time
+    got, stats = _serve([(p, st, 4) for st in sts], budget=budget, pool_bytes=4 * ws)
+    assert stats["completed"] == 4 and stats["admitted"] == 4
+    for st, (status, x, v, th) in zip(sts, got):
+        ex, ev, _ = _eager(p, st, 4)
+        assert np.array_equal(x, ex)
+    # a request that can never fit, an unknown ticket, destroy with work queued
+    pool = dcm.workspace(4 * ws)
+    sv = dcm.dcm_server_create(budget, pool)
+    big = synth.small_slab(20000, (30.0, 30.0, 40.0), 9)
+    with pytest.raises(dcm.DcmError) as e:
+        dcm.dcm_submit(sv, dcm.params(big.box), big.x, big.v, 2)
+    assert e.value.status == dcm.DCM_E_BUDGET
+    assert dcm._lib.dcm_poll(sv, 12345, None, None, None) == dcm.DCM_E_UNKNOWN_TICKET
+    for st in sts:
+        dcm.dcm_submit(sv, p, st.x, st.v, 50)
+    dcm.dcm_server_destroy(sv)           # finishes the resident system, drops the queue
+    torch.cuda.synchronize()
