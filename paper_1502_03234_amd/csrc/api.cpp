@@ -66,6 +66,7 @@ bool grid_of(const dcm_params *p, Grid &g)
         g.L[k] = p->box[k];
     }
     g.G = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    g.sy = g.sz = 0;
     return true;
 }
 
@@ -84,6 +85,10 @@ dcm_status validate(const dcm_params *p, int64_t n, Grid &g)
         if (g.n[k] < need)
             return fail(DCM_E_INVALID, "axis %d has %d boxes; the cutoff stencil needs %d", k, g.n[k], need);
     }
+    // force rows of two boxes in y and in z where the axis has an even box count and room for
+    // the stencil in units of two boxes (a lane's rows then never meet the same storage row twice)
+    g.sy = (g.n[1] % 2 == 0 && g.n[1] >= 2 * (int)std::ceil(p->rc_max / g.h[1]) + 6) ? 1 : 0;
+    g.sz = (g.n[2] % 2 == 0 && g.n[2] >= 2 * (int)std::ceil(p->rc_max / g.h[2]) + 6) ? 1 : 0;
     if (p->alpha == 0.0 && p->rc_min != p->rc_max) return fail(DCM_E_INVALID, "alpha must be non-zero");
     if (!std::isfinite(p->alpha)) return fail(DCM_E_INVALID, "alpha must be finite");
     if (p->smooth_passes < 0 || p->smooth_passes > 4) return fail(DCM_E_INVALID, "smooth_passes must be 0..4");
@@ -370,7 +375,7 @@ dcm_status dcm_detect_interface(dcm_system *s, dcm_stream_t stream, const dcm_de
     detect(s, st);
     if (o) {
         const int64_t G = s->grid.G;
-        if (o->count) launch_count_from_ranges(s->gw.cell_start, G, o->count, st);
+        if (o->count) launch_count_from_ranges(s->grid, s->gw.cell_start, o->count, st);
         if (o->smooth) launch_copy_bytes(o->smooth, s->gw.g, sizeof(uint32_t) * G, st);
         if (o->raw) launch_copy_bytes(o->raw, s->gw.raw, (size_t)G, st);
         if (o->label) launch_copy_bytes(o->label, s->gw.label, (size_t)G, st);

@@ -48,9 +48,12 @@ __global__ void k_smooth_axis(Grid g, const uint32_t *in, const uint32_t *cell_s
     int64_t cl = lin(g, lo[0], lo[1], lo[2]), ch = lin(g, hi[0], hi[1], hi[2]);
     uint32_t a, b, d;
     if (cell_start) {
-        a = cell_start[cl + 1] - cell_start[cl];
-        b = cell_start[c + 1] - cell_start[c];
-        d = cell_start[ch + 1] - cell_start[ch];
+        const uint32_t kl = box_key(g, (int32_t)lo[0], (int32_t)lo[1], (int32_t)lo[2]);
+        const uint32_t kc = box_key(g, (int32_t)i, (int32_t)j, (int32_t)k);
+        const uint32_t kh = box_key(g, (int32_t)hi[0], (int32_t)hi[1], (int32_t)hi[2]);
+        a = cell_start[kl + 1] - cell_start[kl];
+        b = cell_start[kc + 1] - cell_start[kc];
+        d = cell_start[kh + 1] - cell_start[kh];
     } else {
         a = in[cl];
         b = in[c];
@@ -59,10 +62,14 @@ __global__ void k_smooth_axis(Grid g, const uint32_t *in, const uint32_t *cell_s
     out[c] = a + 2u * b + d;
 }
 
-__global__ void k_count_from_ranges(const uint32_t *cell_start, int64_t G, uint32_t *out)
+__global__ void k_count_from_ranges(Grid g, const uint32_t *cell_start, uint32_t *out)
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < G) out[c] = cell_start[c + 1] - cell_start[c];
+    if (c >= g.G) return;
+    int64_t i, j, k;
+    coords(g, c, i, j, k);
+    const uint32_t q = box_key(g, (int32_t)i, (int32_t)j, (int32_t)k);
+    out[c] = cell_start[q + 1] - cell_start[q];
 }
 
 // ---- histogram and two-means ----------------------------------------------------------
@@ -607,9 +614,9 @@ __global__ void k_cutoffs(Grid g, PSet s, int64_t n, const double *dist, double 
 
 }  // namespace
 
-void launch_count_from_ranges(const uint32_t *cell_start, int64_t G, uint32_t *out, hipStream_t st)
+void launch_count_from_ranges(const Grid &g, const uint32_t *cell_start, uint32_t *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_count_from_ranges, dim3(grid1(G)), dim3(kBlock), 0, st, cell_start, G, out);
+    hipLaunchKernelGGL(k_count_from_ranges, dim3(grid1(g.G)), dim3(kBlock), 0, st, g, cell_start, out);
 }
 
 // `passes` rounds of x, y, z [1,2,1] passes; the first reads counts from cell ranges when
@@ -618,7 +625,7 @@ void launch_smooth(const Grid &g, int passes, const uint32_t *cell_start, const 
                    uint32_t *out, uint32_t *tmp, hipStream_t st)
 {
     if (passes == 0) {
-        if (cell_start) launch_count_from_ranges(cell_start, g.G, out, st);
+        if (cell_start) launch_count_from_ranges(g, cell_start, out, st);
         else launch_copy_bytes(out, in, sizeof(uint32_t) * (size_t)g.G, st);
         return;
     }

@@ -2,20 +2,26 @@
 // (Eq. 4; Section 3.2, Alg. 3.2: particle i uses the pair (i, j) iff |r_ij| < r_c[i] and only
 // f_i is updated, so every ordered pair is visited from its own side -- a full list).
 //
-// One lane per particle, particles in cell-sorted order so that a wavefront holds a run of
-// neighbouring boxes along x. Each candidate interval is scanned four slots at a time with all
-// four loads issued before use (the loop is bound by memory latency otherwise; staging the
-// rows through LDS measured slower). Lane i walks the box rows (fixed y, z) whose rectangle comes
-// within r_c[i] of it; inside a row the candidate boxes are the x-interval that the sphere
-// cuts, so the traversed volume follows the sphere at box resolution in y and z and exactly
-// in x (the small-bin stencil idea of Fig. 13b taken to single boxes). Each candidate interval
-// is a contiguous range of sorted slots. Periodic images are handled per interval: a wrapped
-// interval adds the box edge to x_j, so dx = x_i - (x_j + shift) is the same number the
-// minimum-image convention gives.
+// One lane per particle, particles in storage (sort-key) order, so a wavefront holds a run of
+// neighbouring boxes along x inside one force row. A force row is a block of 2 x 2 boxes in y
+// and z (1 x 1 where an axis is too short or odd; see box_key), and storage order keeps the boxes
+// of a force row and any x-interval in one contiguous slot range. Lane i walks the force rows
+// whose y-z rectangle comes within r_c[i] of it and, in each, scans the slot range of the
+// x-interval the sphere cuts: the small-bin stencil of Fig. 13b with single-box resolution in
+// x. Grouping rows in y and z trades some extra candidates for a third of the row steps and far
+// better L2 reuse between neighbouring waves. The row loops are uniform over the wave, in row
+// offsets relative to each lane's own force row, so the lanes of one row scan the same
+// neighbour rows together. Candidates are loaded four at a time with all loads issued before
+// use (the loop is bound by memory latency otherwise). Periodic images are handled per
+// interval: a wrapped interval adds the box edge to x_j, so dx = x_i - (x_j + shift) is the same
+// number the minimum-image convention gives.
 //
-// 1/r^2 uses the hardware reciprocal refined by two Newton steps (error ~1 ulp). Energy and
-// virial are accumulated per particle, reduced per workgroup in a fixed order, and the
-// workgroup partials are summed in a fixed order by the reduction kernel.
+// 1/r^2 uses the hardware reciprocal refined by one Newton step (the estimate carries about half
+// the FP64 bits; one step squares its relative error, leaving a few ulp). Energy and virial are
+// accumulated per particle, reduced per workgroup in a fixed order, and the workgroup partials
+// are summed in a fixed order by the reduction kernel.
+#include <climits>
+
 #include "internal.h"
 
 namespace dcm {
@@ -28,8 +34,6 @@ __device__ __forceinline__ double rcp_refined(double a)
 {
     double y = __builtin_amdgcn_rcp(a);
     double e = fma(-a, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-a, y, 1.0);
     return fma(y, e, y);
 }
 
@@ -149,125 +153,172 @@ __device__ __forceinline__ void interact(const ForceArgs &a, const double4 pj, b
     }
 }
 
-// All candidates of one slot interval [jb, je), U loads in flight at a time; the particle
-// itself (slot i) is skipped.
+// One lane's particle.
+struct Particle {
+    int64_t i;      // sorted slot (a valid slot also for lanes without a particle)
+    double x, y, z, rc, rc2;
+};
+
+// All candidates of one slot interval [jb, je) (empty for lanes without one), U loads in flight
+// at a time; the particle itself is skipped. The loop runs until the wave's longest interval is
+// done.
 template <int PAIR, bool SHIFT, bool IMAGE, int U, typename A>
-__device__ __forceinline__ void scan(const ForceArgs &a, uint32_t jb, uint32_t je, int64_t i,
-                                     double xi, double yi, double zi, double rci, double rc2,
+__device__ __forceinline__ void scan(const ForceArgs &a, const Particle &q, uint32_t jb, uint32_t je,
                                      double sx, double sy, double sz, A &c)
 {
-    for (uint32_t j0 = jb; j0 < je; j0 += U) {
-        const uint32_t last = je - 1;
+    const uint32_t len = je - jb;
+    for (uint32_t t = 0; __any(t < len); t += U) {
         double4 p[U];
         uint32_t jj[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            jj[u] = j0 + u < je ? j0 + u : last;
+            jj[u] = t + u < len ? jb + t + u : (uint32_t)q.i;
             p[u] = a.pos[jj[u]];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            interact<PAIR, SHIFT, IMAGE>(a, p[u], j0 + u < je && jj[u] != i, xi, yi, zi, rci, rc2, sx, sy, sz, c);
+            interact<PAIR, SHIFT, IMAGE>(a, p[u], jj[u] != (uint32_t)q.i, q.x, q.y, q.z, q.rc, q.rc2, sx, sy, sz, c);
     }
 }
 
+// The image variant runs only for waves in which some lane's interval is a periodic image.
 template <int PAIR, bool SHIFT, int U, typename A>
-__device__ __forceinline__ void scan_interval(const ForceArgs &a, uint32_t jb, uint32_t je, int64_t i,
-                                              double xi, double yi, double zi, double rci, double rc2,
+__device__ __forceinline__ void scan_interval(const ForceArgs &a, const Particle &q, uint32_t jb, uint32_t je,
                                               double sx, double sy, double sz, A &c)
 {
-    const bool image = sx != 0.0 || sy != 0.0 || sz != 0.0;
+    const bool image = jb < je && (sx != 0.0 || sy != 0.0 || sz != 0.0);
     if (__any(image))
-        scan<PAIR, SHIFT, true, U, A>(a, jb, je, i, xi, yi, zi, rci, rc2, sx, sy, sz, c);
+        scan<PAIR, SHIFT, true, U, A>(a, q, jb, je, sx, sy, sz, c);
     else
-        scan<PAIR, SHIFT, false, U, A>(a, jb, je, i, xi, yi, zi, rci, rc2, sx, sy, sz, c);
+        scan<PAIR, SHIFT, false, U, A>(a, q, jb, je, sx, sy, sz, c);
 }
 
-// Walks the box rows within particle i's search radius and scans each row's x-interval.
+__device__ __forceinline__ int wave_min(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Walks the force rows (2^sz x 2^sy boxes in z and y, see box_key) that come within particle
+// i's search radius and scans, in each, the slot range of the x-interval the sphere cuts. The
+// row loops are uniform over the wave: they run over the union of the lanes' row offsets
+// relative to each lane's own force row, so lanes of one row look at the same neighbour rows
+// together and their windows overlap. Each lane visits exactly its own rows, in increasing z,
+// then y, then x.
 template <int PAIR, bool SHIFT, int U, typename A>
-__device__ __forceinline__ void traverse(const ForceArgs &a, int64_t i, double xi, double yi, double zi,
-                                         double rci, double rc2, double rc_max, A &c)
+__device__ __forceinline__ void traverse(const ForceArgs &a, bool live, const Particle &q, double rc_max, A &c)
 {
     const Grid &g = a.grid;
     // search radius (slightly enlarged so that rounding in the box bounds never drops a box
     // that holds an in-range particle; the pair test itself is exact)
-    double rs = PAIR == DCM_PAIR_MAX ? rc_max : rci;
+    double rs = PAIR == DCM_PAIR_MAX ? rc_max : q.rc;
     rs = rs * (1.0 + 1e-12) + 1e-9;
     const double rs2 = rs * rs;
-    const double ihx = 1.0 / g.h[0], ihy = 1.0 / g.h[1], ihz = 1.0 / g.h[2];
-    const int izlo = floor_mul(zi - rs, ihz), izhi = floor_mul(zi + rs, ihz);
-    for (int iz = izlo; iz <= izhi; ++iz) {
-        const double zlo = iz * g.h[2];
-        const double dzm = fmax(0.0, fmax(zlo - zi, zi - (zlo + g.h[2])));
+    const int nY = g.n[1] >> g.sy, nZ = g.n[2] >> g.sz, gs = g.sy + g.sz;
+    const double Hy = g.h[1] * (double)(1 << g.sy), Hz = g.h[2] * (double)(1 << g.sz);
+    const double iHy = 1.0 / Hy, iHz = 1.0 / Hz, ihx = 1.0 / g.h[0];
+    const int Yi = live ? floor_mul(q.y, iHy) : 0, Zi = live ? floor_mul(q.z, iHz) : 0;
+    const int zlo_r = live ? floor_mul(q.z - rs, iHz) - Zi : INT_MAX;
+    const int zhi_r = live ? floor_mul(q.z + rs, iHz) - Zi : INT_MIN;
+    const int zb = wave_min(zlo_r), ze = wave_max(zhi_r);
+    for (int dZ = zb; dZ <= ze; ++dZ) {
+        const int Z = Zi + dZ;
+        const double zlo = Z * Hz;
+        const double dzm = fmax(0.0, fmax(zlo - q.z, q.z - (zlo + Hz)));
         const double remz = rs2 - dzm * dzm;
-        if (remz < 0.0) continue;
-        int wz = iz;
+        const bool zok = dZ >= zlo_r && dZ <= zhi_r && remz >= 0.0;
+        int wZ = Z;
         double sz = 0.0;
-        if (iz < 0) { wz += g.n[2]; sz = -g.L[2]; }
-        else if (iz >= g.n[2]) { wz -= g.n[2]; sz = g.L[2]; }
-        const double ry = sqrt_up(remz);
-        const int iylo = floor_mul(yi - ry, ihy), iyhi = floor_mul(yi + ry, ihy);
-        for (int iy = iylo; iy <= iyhi; ++iy) {
-            const double ylo = iy * g.h[1];
-            const double dym = fmax(0.0, fmax(ylo - yi, yi - (ylo + g.h[1])));
+        if (Z < 0) { wZ += nZ; sz = -g.L[2]; }
+        else if (Z >= nZ) { wZ -= nZ; sz = g.L[2]; }
+        const double ry = sqrt_up(zok ? remz : 0.0);
+        const int ylo_r = zok ? floor_mul(q.y - ry, iHy) - Yi : INT_MAX;
+        const int yhi_r = zok ? floor_mul(q.y + ry, iHy) - Yi : INT_MIN;
+        const int yb = wave_min(ylo_r), ye = wave_max(yhi_r);
+        for (int dY = yb; dY <= ye; ++dY) {
+            const int Y = Yi + dY;
+            const double ylo = Y * Hy;
+            const double dym = fmax(0.0, fmax(ylo - q.y, q.y - (ylo + Hy)));
             const double rem = remz - dym * dym;
-            if (rem < 0.0) continue;
-            int wy = iy;
+            const bool yok = zok && dY >= ylo_r && dY <= yhi_r && rem >= 0.0;
+            int wY = Y;
             double sy = 0.0;
-            if (iy < 0) { wy += g.n[1]; sy = -g.L[1]; }
-            else if (iy >= g.n[1]) { wy -= g.n[1]; sy = g.L[1]; }
-            const double rx = sqrt_up(rem);
-            const int ixlo = floor_mul(xi - rx, ihx), ixhi = floor_mul(xi + rx, ihx);
-            const int64_t row = ((int64_t)wz * g.n[1] + wy) * g.n[0];
+            if (Y < 0) { wY += nY; sy = -g.L[1]; }
+            else if (Y >= nY) { wY -= nY; sy = g.L[1]; }
             // up to two contiguous slot ranges (the second one wraps around x)
-            int lo0 = ixlo, hi0 = ixhi, lo1 = 0, hi1 = -1;
+            uint32_t b0 = 0, e0 = 0, b1 = 0, e1 = 0;
             double sx0 = 0.0, sx1 = 0.0;
-            if (ixlo < 0) {
-                lo0 = ixlo + g.n[0]; hi0 = g.n[0] - 1; sx0 = -g.L[0];
-                lo1 = 0; hi1 = ixhi;
-            } else if (ixhi >= g.n[0]) {
-                hi0 = g.n[0] - 1;
-                lo1 = 0; hi1 = ixhi - g.n[0]; sx1 = g.L[0];
+            if (yok) {
+                const double rx = sqrt_up(rem);
+                const int ixlo = floor_mul(q.x - rx, ihx), ixhi = floor_mul(q.x + rx, ihx);
+                const uint32_t row = (uint32_t)(wZ * nY + wY) * (uint32_t)g.n[0];
+                int lo0 = ixlo, hi0 = ixhi, lo1 = 0, hi1 = -1;
+                if (ixlo < 0) {
+                    lo0 = ixlo + g.n[0]; hi0 = g.n[0] - 1; sx0 = -g.L[0];
+                    lo1 = 0; hi1 = ixhi;
+                } else if (ixhi >= g.n[0]) {
+                    hi0 = g.n[0] - 1;
+                    lo1 = 0; hi1 = ixhi - g.n[0]; sx1 = g.L[0];
+                }
+                b0 = a.cell_start[(row + (uint32_t)lo0) << gs];
+                e0 = a.cell_start[(row + (uint32_t)hi0 + 1u) << gs];
+                if (hi1 >= lo1) {
+                    b1 = a.cell_start[(row + (uint32_t)lo1) << gs];
+                    e1 = a.cell_start[(row + (uint32_t)hi1 + 1u) << gs];
+                }
             }
-            scan_interval<PAIR, SHIFT, U, A>(a, a.cell_start[row + lo0], a.cell_start[row + hi0 + 1], i, xi, yi,
-                                             zi, rci, rc2, sx0, sy, sz, c);
-            if (hi1 >= lo1)
-                scan_interval<PAIR, SHIFT, U, A>(a, a.cell_start[row + lo1], a.cell_start[row + hi1 + 1], i, xi,
-                                                 yi, zi, rci, rc2, sx1, sy, sz, c);
+            scan_interval<PAIR, SHIFT, U, A>(a, q, b0, e0, sx0, sy, sz, c);
+            if (__any(b1 < e1)) scan_interval<PAIR, SHIFT, U, A>(a, q, b1, e1, sx1, sy, sz, c);
         }
     }
 }
 
 template <int PAIR, bool SHIFT, int U, int PREC>
-__global__ void __launch_bounds__(kForceBlock) k_forces(ForceArgs a, double rc_max)
+__global__ void __launch_bounds__(kForceBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_forces(ForceArgs a, double rc_max)
 {
     // hardware (round-robin over XCDs) block order: the cost per particle varies strongly
     // with z through the cutoffs, and interleaving keeps every XCD's share of it even
     const int64_t b = blockIdx.x;
     const int64_t i = b * kForceBlock + threadIdx.x;
+    const bool have = i < a.n;
+    Particle q;
+    q.i = have ? i : 0;
+    const double4 pi = a.pos[q.i];
+    q.x = pi.x;
+    q.y = pi.y;
+    q.z = pi.z;
+    q.rc = pi.w;
+    q.rc2 = q.rc * q.rc;
+    // a non-finite position or a cutoff outside (0, rc_max] would send the box loops out of the
+    // grid: such a particle gets no traversal and a NaN force (flagged below)
+    const bool sane = isfinite(q.x) && isfinite(q.y) && isfinite(q.z) && q.rc > 0.0 && q.rc <= rc_max;
+    const bool live = have && sane;
+    // every lane of the wave takes part in the (wave-uniform) traversal
     Acc c = {};
-    if (i < a.n) {
-        const double4 pi = a.pos[i];
-        const double xi = pi.x, yi = pi.y, zi = pi.z, rci = pi.w;
-        const double rc2 = rci * rci;
-        // a non-finite position or a cutoff outside (0, rc_max] would send the box loops out
-        // of the grid: such a particle gets no traversal and a NaN force (flagged below)
-        const bool sane = isfinite(xi) && isfinite(yi) && isfinite(zi) && rci > 0.0 && rci <= rc_max;
-        if (PREC == DCM_FP64) {
-            if (sane) traverse<PAIR, SHIFT, U, Acc>(a, i, xi, yi, zi, rci, rc2, rc_max, c);
-        } else {
-            Acc32 c32 = {};
-            if (sane) traverse<PAIR, SHIFT, U, Acc32>(a, i, xi, yi, zi, rci, rc2, rc_max, c32);
-            // FP32 sums and their compensation terms, combined in FP64
-            c.fx = (double)c32.fx + (double)c32.cfx;
-            c.fy = (double)c32.fy + (double)c32.cfy;
-            c.fz = (double)c32.fz + (double)c32.cfz;
-            c.e = (double)c32.e + (double)c32.ce;
-            c.wxx = c32.wxx; c.wyy = c32.wyy; c.wzz = c32.wzz;
-            c.wxy = c32.wxy; c.wxz = c32.wxz; c.wyz = c32.wyz;
-            c.eshift = c32.eshift;
-            c.pairs = c32.pairs;
-        }
+    if (PREC == DCM_FP64) {
+        traverse<PAIR, SHIFT, U, Acc>(a, live, q, rc_max, c);
+    } else {
+        Acc32 c32 = {};
+        traverse<PAIR, SHIFT, U, Acc32>(a, live, q, rc_max, c32);
+        // FP32 sums and their compensation terms, combined in FP64
+        c.fx = (double)c32.fx + (double)c32.cfx;
+        c.fy = (double)c32.fy + (double)c32.cfy;
+        c.fz = (double)c32.fz + (double)c32.cfz;
+        c.e = (double)c32.e + (double)c32.ce;
+        c.wxx = c32.wxx; c.wyy = c32.wyy; c.wzz = c32.wzz;
+        c.wxy = c32.wxy; c.wxz = c32.wxz; c.wyz = c32.wyz;
+        c.eshift = c32.eshift;
+        c.pairs = c32.pairs;
+    }
+    if (have) {
+        const double rc2 = q.rc2;
         if (!sane) c.fx = NAN;
         // e_i = 1/2 sum 4 eps (sr12 - sr6); W_i = 1/2 sum dx (x) f
         double e = 0.5 * a.eps4 * c.e;

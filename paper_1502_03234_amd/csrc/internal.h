@@ -30,7 +30,20 @@ struct Grid {
     double h[3];        // box edges L_k / N_k
     double L[3];        // periodic box
     int64_t G;          // N_x N_y N_z
+    int32_t sy, sz;     // log2 of the y and z extent of a force row (0 or 1; see box_key)
 };
+
+// Sort key (storage order) of box (a, b, c). Boxes are grouped into force rows of 2^sy x 2^sz
+// boxes in y and z; keys run over force rows, then x, then the box's place inside its force
+// row. The boxes of one force row and an x-interval are therefore one contiguous key range, and
+// with sy = sz = 0 the key is the plain linear index (c N_y + b) N_x + a. Every box keeps its own
+// contiguous key, so per-box counts are key-range lengths in either order.
+__host__ __device__ inline uint32_t box_key(const Grid &g, int32_t a, int32_t b, int32_t c)
+{
+    const uint32_t row = (uint32_t)(c >> g.sz) * (uint32_t)(g.n[1] >> g.sy) + (uint32_t)(b >> g.sy);
+    const uint32_t sub = ((uint32_t)(c & ((1 << g.sz) - 1)) << g.sy) | (uint32_t)(b & ((1 << g.sy) - 1));
+    return ((row * (uint32_t)g.n[0] + (uint32_t)a) << (g.sy + g.sz)) | sub;
+}
 
 // One copy of the per-particle state in cell-sorted order.
 struct PSet {
@@ -93,7 +106,7 @@ void launch_distance(const Grid &g, double cap, const uint8_t *label, double *di
 void launch_cutoffs(const Grid &g, PSet s, int64_t n, const double *dist, double cap,
                     double rc_min, double rc_max, double alpha, double a, double b, hipStream_t st);
 void launch_cap_copy(const double *dist, double cap, double *out, int64_t G, hipStream_t st);
-void launch_count_from_ranges(const uint32_t *cell_start, int64_t G, uint32_t *out, hipStream_t st);
+void launch_count_from_ranges(const Grid &g, const uint32_t *cell_start, uint32_t *out, hipStream_t st);
 
 // force.hip
 struct ForceArgs {

@@ -47,7 +47,7 @@ __global__ void k_wrap_key(Grid g, PSet s, int64_t n, uint32_t *key, uint32_t *v
     int32_t a = box_of(p.x, g.h[0], g.n[0]);
     int32_t b = box_of(p.y, g.h[1], g.n[1]);
     int32_t c = box_of(p.z, g.h[2], g.n[2]);
-    key[i] = (uint32_t)(((int64_t)c * g.n[1] + b) * g.n[0] + a);
+    key[i] = box_key(g, a, b, c);
     val[i] = (uint32_t)i;
 }
 
