@@ -395,25 +395,49 @@ __device__ double godunov(double a0, double a1, double a2, double h0, double h1,
     return d;
 }
 
-__global__ void k_dist_init(const uint8_t *label, int64_t G, double *dist)
-{
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < G) dist[c] = label[c] == 1 ? 0.0 : INFINITY;
-}
 
 // One global relaxation pass over LDS tiles. Two copies of the distance grid alternate;
 // cur[t] says which copy holds tile t's values as of the end of the previous pass. A tile
 // marked dirty loads its boxes and a one-box halo (each from the copy current for the tile that
-// owns it), relaxes its liquid boxes with synchronous (Jacobi) updates in double-buffered LDS
-// until nothing changes (halo held fixed), and writes the result into its other copy. Every
-// read of a pass sees the previous pass's state, so the outcome does not depend on the order
-// in which tiles run. A tile that lowers a value on a face marks the tile across that face
-// dirty for the next pass. Passes repeat until one changes nothing.
+// owns it) and relaxes its liquid boxes to local convergence with the halo held fixed, then
+// writes the result into its other copy. Inside the tile the boxes are relaxed in red-black
+// order: all boxes of one parity of (x + y + z), then all of the other, each reading only
+// boxes of the opposite parity, so the outcome does not depend on thread timing and information
+// crosses two boxes per sweep. Every read of a pass sees the previous pass's state, so the
+// outcome does not depend on the order in which tiles run either. A tile that lowers a value on
+// a face marks the tile across that face dirty for the next pass. Passes repeat until one
+// changes nothing.
 constexpr int TX = 16, TY = 8, TZ = 8;
 constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
 constexpr int kTileThreads = 256;
-constexpr int kPerThread = TX * TY * TZ / kTileThreads;
 constexpr int kLocalMax = 128;
+static_assert(TX % 2 == 0 && TX * TY * TZ == 4 * kTileThreads, "two boxes of each parity per thread");
+
+__device__ __forceinline__ int tile_of(const Grid &g, int64_t x, int64_t y, int64_t z)
+{
+    const int ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY;
+    return (int)(((z / TZ) * nty + y / TY) * ntx + x / TX);
+}
+
+// Initial distances (0 on vapor boxes, infinity elsewhere); the tiles holding a liquid box next
+// to a vapor box are the only ones the first pass can change, and they start dirty.
+__global__ void k_dist_init(Grid g, const uint8_t *label, double *dist, uint32_t *dirty)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.G) return;
+    const bool vap = label[c] == 1;
+    dist[c] = vap ? 0.0 : INFINITY;
+    if (vap) return;
+    int64_t i, j, k;
+    coords(g, c, i, j, k);
+    const int64_t xm = i == 0 ? g.n[0] - 1 : i - 1, xp = i == g.n[0] - 1 ? 0 : i + 1;
+    const int64_t ym = j == 0 ? g.n[1] - 1 : j - 1, yp = j == g.n[1] - 1 ? 0 : j + 1;
+    const int64_t zm = k == 0 ? g.n[2] - 1 : k - 1, zp = k == g.n[2] - 1 ? 0 : k + 1;
+    const bool front = label[lin(g, xm, j, k)] == 1 || label[lin(g, xp, j, k)] == 1 ||
+                       label[lin(g, i, ym, k)] == 1 || label[lin(g, i, yp, k)] == 1 ||
+                       label[lin(g, i, j, zm)] == 1 || label[lin(g, i, j, zp)] == 1;
+    if (front) dirty[tile_of(g, i, j, k)] = 1u;
+}
 
 __global__ void __launch_bounds__(kTileThreads) k_dist_tiles(Grid g, const uint8_t *label, double *d0,
                                                              double *d1, double cap, uint32_t *changed,
@@ -431,8 +455,7 @@ __global__ void __launch_bounds__(kTileThreads) k_dist_tiles(Grid g, const uint8
         if (threadIdx.x == 0) { cnext[b] = mycur; dflag[b] = 0u; }
         return;
     }
-    __shared__ double t[2][HZ][HY][HX];
-    __shared__ int any;
+    __shared__ double t[HZ][HY][HX];
     __shared__ int faces[6];
     const int ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY, ntz = (g.n[2] + TZ - 1) / TZ;
     const int bx = b % ntx, by = (b / ntx) % nty, bz = b / (ntx * nty);
@@ -448,59 +471,52 @@ __global__ void __launch_bounds__(kTileThreads) k_dist_tiles(Grid g, const uint8
             int cx = gx < 0 ? gx + g.n[0] : (gx == g.n[0] ? 0 : gx);
             int cy = gy < 0 ? gy + g.n[1] : (gy == g.n[1] ? 0 : gy);
             int cz = gz < 0 ? gz + g.n[2] : (gz == g.n[2] ? 0 : gz);
-            int owner = ((cz / TZ) * nty + cy / TY) * ntx + cx / TX;
-            const double *src = cprev[owner] ? d1 : d0;
+            const double *src = cprev[tile_of(g, cx, cy, cz)] ? d1 : d0;
             v = src[lin(g, cx, cy, cz)];
         }
-        t[0][hz][hy][hx] = v;
-        t[1][hz][hy][hx] = v;
+        t[hz][hy][hx] = v;
     }
-    int own[kPerThread];
-    bool liq[kPerThread];
-    for (int r = 0; r < kPerThread; ++r) {
-        int q = threadIdx.x + r * kTileThreads;
-        int lx = q % TX, ly = (q / TX) % TY, lz = q / (TX * TY);
-        own[r] = q;
-        int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-        liq[r] = gx < g.n[0] && gy < g.n[1] && gz < g.n[2] && label[lin(g, gx, gy, gz)] != 1;
-    }
-    __syncthreads();
-    int src = 0;
-    for (int sweep = 0; sweep < kLocalMax; ++sweep) {
-        if (threadIdx.x == 0) any = 0;
-        __syncthreads();
-        bool ch = false;
-        for (int r = 0; r < kPerThread; ++r) {
-            int q = own[r];
-            int hx = q % TX + 1, hy = (q / TX) % TY + 1, hz = q / (TX * TY) + 1;
-            double old = t[src][hz][hy][hx];
-            double nv = old;
-            if (liq[r]) {
-                double ax = fmin(t[src][hz][hy][hx - 1], t[src][hz][hy][hx + 1]);
-                double ay = fmin(t[src][hz][hy - 1][hx], t[src][hz][hy + 1][hx]);
-                double az = fmin(t[src][hz - 1][hy][hx], t[src][hz + 1][hy][hx]);
-                if (!(isinf(ax) && isinf(ay) && isinf(az))) {
-                    double db = godunov(ax, ay, az, g.h[0], g.h[1], g.h[2]);
-                    if (db <= cap && db < old) { nv = db; ch = true; }
-                }
-            }
-            t[src ^ 1][hz][hy][hx] = nv;
+    // this thread's boxes: the m-th (m = 0, 1) box of parity p, counting along x-rows, which
+    // hold TX / 2 boxes of each parity
+    int bxs[2][2], bys[2][2], bzs[2][2];
+    bool liq[2][2];
+    for (int p = 0; p < 2; ++p)
+        for (int m = 0; m < 2; ++m) {
+            const int kk = threadIdx.x + m * kTileThreads;
+            const int row = kk / (TX / 2), pos = kk % (TX / 2);
+            const int ly = row % TY, lz = row / TY;
+            const int lx = 2 * pos + ((ly + lz + p) & 1);
+            bxs[p][m] = lx + 1; bys[p][m] = ly + 1; bzs[p][m] = lz + 1;
+            const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+            liq[p][m] = gx < g.n[0] && gy < g.n[1] && gz < g.n[2] && label[lin(g, gx, gy, gz)] != 1;
         }
-        if (ch) any = 1;
-        __syncthreads();
-        const int stop = any == 0;
-        src ^= 1;
-        __syncthreads();
-        if (stop) break;
+    __syncthreads();
+    bool local_done = false;
+    for (int sweep = 0; sweep < kLocalMax; ++sweep) {
+        bool ch = false;
+        for (int p = 0; p < 2; ++p) {
+            for (int m = 0; m < 2; ++m) {
+                if (!liq[p][m]) continue;
+                const int hx = bxs[p][m], hy = bys[p][m], hz = bzs[p][m];
+                const double old = t[hz][hy][hx];
+                const double ax = fmin(t[hz][hy][hx - 1], t[hz][hy][hx + 1]);
+                const double ay = fmin(t[hz][hy - 1][hx], t[hz][hy + 1][hx]);
+                const double az = fmin(t[hz - 1][hy][hx], t[hz + 1][hy][hx]);
+                if (isinf(ax) && isinf(ay) && isinf(az)) continue;
+                const double db = godunov(ax, ay, az, g.h[0], g.h[1], g.h[2]);
+                if (db <= cap && db < old) { t[hz][hy][hx] = db; ch = true; }
+            }
+            if (p == 0) __syncthreads();
+        }
+        if (!__syncthreads_or(ch)) { local_done = true; break; }
     }
     // write back into the tile's other copy (only if something changed)
     bool wrote = false;
-    for (int r = 0; r < kPerThread; ++r) {
-        int q = own[r];
+    for (int q = threadIdx.x; q < TX * TY * TZ; q += kTileThreads) {
         int lx = q % TX, ly = (q / TX) % TY, lz = q / (TX * TY);
         int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
         if (gx >= g.n[0] || gy >= g.n[1] || gz >= g.n[2]) continue;
-        double v = t[src][lz + 1][ly + 1][lx + 1];
+        double v = t[lz + 1][ly + 1][lx + 1];
         // the loaded value (the tile's own copy): compare to detect a change
         double was = (mycur ? d1 : d0)[lin(g, gx, gy, gz)];
         if (v < was) {
@@ -513,19 +529,14 @@ __global__ void __launch_bounds__(kTileThreads) k_dist_tiles(Grid g, const uint8
             if (lz == TZ - 1 || gz == g.n[2] - 1) faces[5] = 1;
         }
     }
-    __shared__ int tile_wrote;
-    if (threadIdx.x == 0) tile_wrote = 0;
-    __syncthreads();
-    if (wrote) tile_wrote = 1;
-    __syncthreads();
+    const bool tile_wrote = __syncthreads_or(wrote);
     if (tile_wrote) {
         double *dst = mycur ? d0 : d1;
-        for (int r = 0; r < kPerThread; ++r) {
-            int q = own[r];
+        for (int q = threadIdx.x; q < TX * TY * TZ; q += kTileThreads) {
             int lx = q % TX, ly = (q / TX) % TY, lz = q / (TX * TY);
             int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
             if (gx >= g.n[0] || gy >= g.n[1] || gz >= g.n[2]) continue;
-            dst[lin(g, gx, gy, gz)] = t[src][lz + 1][ly + 1][lx + 1];
+            dst[lin(g, gx, gy, gz)] = t[lz + 1][ly + 1][lx + 1];
         }
     }
     if (threadIdx.x == 0) {
@@ -541,6 +552,8 @@ __global__ void __launch_bounds__(kTileThreads) k_dist_tiles(Grid g, const uint8
                 if (faces[2 + f]) dnext[(bz * nty + nby[f]) * ntx + bx] = 1u;
                 if (faces[4 + f]) dnext[(nbz[f] * nty + by) * ntx + bx] = 1u;
             }
+            // a tile stopped by the sweep limit runs again
+            if (!local_done) dnext[b] = 1u;
         }
     }
 }
@@ -687,10 +700,9 @@ void launch_distance(const Grid &g, double cap, const uint8_t *label, double *di
 {
     int ms = max_distance_sweeps(g, cap);
     launch_fill_u32(w.changed, 0u, ms + 1, st);
-    hipLaunchKernelGGL(k_dist_init, dim3(grid1(g.G)), dim3(kBlock), 0, st, label, g.G, dist);
     const unsigned ntiles = (unsigned)distance_tiles(g);
-    launch_fill_u32(w.tdirty, 1u, ntiles, st);
-    launch_fill_u32(w.tdirty + ntiles, 0u, ntiles, st);
+    launch_fill_u32(w.tdirty, 0u, 2 * (int64_t)ntiles, st);
+    hipLaunchKernelGGL(k_dist_init, dim3(grid1(g.G)), dim3(kBlock), 0, st, g, label, dist, w.tdirty);
     launch_fill_u32(w.tcur, 0u, 2 * (int64_t)ntiles, st);
     for (int it = 0; it < ms; ++it)
         hipLaunchKernelGGL(k_dist_tiles, dim3(ntiles), dim3(kTileThreads), 0, st, g, label, dist, w.dist2, cap,
