@@ -283,9 +283,13 @@ __global__ void __launch_bounds__(kCtBoxes) k_cc_local(Grid g, const uint8_t *la
 // faces look at their +x / +y / +z neighbour. Only "fewer than `limit` boxes" matters, and a
 // piece that already has `limit` boxes inside its tile is large whatever it joins, so a face
 // is joined only when at least one of its two pieces is small; a small piece still ends in
-// the same tree as every piece it touches, and the size count below is exact below `limit`.
+// the same tree as every piece it touches. When a small piece joins a large one, the large
+// side's face box is tagged (psize = kTouched) so that the size count below sees the tree as
+// large.
+constexpr uint32_t kTouched = 0xffffffffu;
+
 __global__ void k_cc_merge(Grid g, const uint8_t *label, uint8_t phase, uint32_t *parent,
-                           const uint32_t *psize, uint32_t limit)
+                           uint32_t *psize, uint32_t limit)
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.G || label[c] != phase) return;
@@ -298,11 +302,16 @@ __global__ void k_cc_merge(Grid g, const uint8_t *label, uint8_t phase, uint32_t
     int64_t nb[3] = {fx ? lin(g, i + 1 == g.n[0] ? 0 : i + 1, j, k) : -1,
                      fy ? lin(g, i, j + 1 == g.n[1] ? 0 : j + 1, k) : -1,
                      fz ? lin(g, i, j, k + 1 == g.n[2] ? 0 : k + 1) : -1};
+    // piece sizes only move from a value >= limit to kTouched (also >= limit) while this runs,
+    // so every thread takes the same small / large decisions
     const bool small = psize[c] < limit;
     for (int q = 0; q < 3; ++q) {
         if (nb[q] < 0 || label[nb[q]] != phase) continue;
-        if (!small && psize[nb[q]] >= limit) continue;
+        const bool nsmall = psize[nb[q]] < limit;
+        if (!small && !nsmall) continue;
         unite(parent, (uint32_t)c, (uint32_t)nb[q]);
+        if (!small) psize[c] = kTouched;
+        if (!nsmall) psize[nb[q]] = kTouched;
     }
 }
 
@@ -315,33 +324,47 @@ __global__ void k_cc_flatten(int64_t G, uint32_t *parent)
     parent[c] = find_root(parent, (uint32_t)c);
 }
 
-// Component sizes, counted only until they reach `limit` (only "size < limit" matters).
-__global__ void k_cc_size(int64_t G, const uint32_t *parent, uint32_t *csize, uint32_t limit)
+// Component sizes, counted only until they reach `limit` (only "size < limit" matters). Boxes
+// of small pieces count one each; a tagged box of a large piece (which joined a small one)
+// lifts its tree to `limit`. Trees made of large pieces only hold no small box and are never
+// looked at.
+__global__ void k_cc_size(int64_t G, const uint32_t *parent, const uint32_t *psize, uint32_t *csize,
+                          uint32_t limit)
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t r = c < G ? parent[c] : kInvalid;
-    bool active = r != kInvalid;
+    const uint32_t ps = r != kInvalid ? psize[c] : 0u;
+    const bool small = r != kInvalid && ps < limit;
+    const bool touched = r != kInvalid && ps == kTouched;
+    bool active = small || touched;
     const unsigned lane = __lane_id();
+    const unsigned long long smallmask = __ballot(small), touchedmask = __ballot(touched);
     unsigned long long pending = __ballot(active);
     while (pending) {
         int leader = __ffsll((long long)pending) - 1;
         uint32_t rl = __shfl(r, leader, 64);
         unsigned long long peers = __ballot(active && r == rl);
         if ((int)lane == leader) {
-            uint32_t cur = __hip_atomic_load(csize + rl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (cur < limit) atomicAdd(csize + rl, (uint32_t)__popcll(peers));
+            if (peers & touchedmask) {
+                atomicMax(csize + rl, limit);
+            } else {
+                uint32_t cur = __hip_atomic_load(csize + rl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (cur < limit) atomicAdd(csize + rl, (uint32_t)__popcll(peers & smallmask));
+            }
         }
         if (peers & (1ull << lane)) active = false;
         pending &= ~peers;
     }
 }
 
+// Boxes of small components change phase; boxes of large pieces belong to large components.
 __global__ void k_cc_flip(int64_t G, uint8_t *label, uint8_t phase, const uint32_t *parent,
-                          const uint32_t *csize, uint32_t limit, long long *stats, int slot)
+                          const uint32_t *psize, const uint32_t *csize, uint32_t limit, long long *stats,
+                          int slot)
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool flip = false, root = false;
-    if (c < G && label[c] == phase) {
+    if (c < G && label[c] == phase && psize[c] < limit) {
         uint32_t r = parent[c];
         if (csize[r] < limit) {
             flip = true;
@@ -673,12 +696,13 @@ void launch_segment(const Grid &g, const uint32_t *img, const double *km, int32_
         hipLaunchKernelGGL(k_cc_local, dim3(nct), dim3(kCtBoxes), 0, st, g, w.label, phase, w.parent, w.csize,
                            w.gtmp);
         hipLaunchKernelGGL(k_cc_merge, dim3(grid1(g.G)), dim3(kBlock), 0, st, g, w.label, phase, w.parent,
-                           (const uint32_t *)w.gtmp, (uint32_t)min_component);
+                           w.gtmp, (uint32_t)min_component);
         hipLaunchKernelGGL(k_cc_flatten, dim3(grid1(g.G)), dim3(kBlock), 0, st, g.G, w.parent);
-        hipLaunchKernelGGL(k_cc_size, dim3(grid1(g.G)), dim3(kBlock), 0, st, g.G, w.parent, w.csize,
-                           (uint32_t)min_component);
+        hipLaunchKernelGGL(k_cc_size, dim3(grid1(g.G)), dim3(kBlock), 0, st, g.G, w.parent,
+                           (const uint32_t *)w.gtmp, w.csize, (uint32_t)min_component);
         hipLaunchKernelGGL(k_cc_flip, dim3(grid1(g.G)), dim3(kBlock), 0, st, g.G, w.label, phase,
-                           w.parent, w.csize, (uint32_t)min_component, w.stats, 1 + pass);
+                           w.parent, (const uint32_t *)w.gtmp, w.csize, (uint32_t)min_component, w.stats,
+                           1 + pass);
     }
 }
 
