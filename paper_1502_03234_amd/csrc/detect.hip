@@ -212,7 +212,8 @@ __device__ void unite(uint32_t *parent, uint32_t a, uint32_t b)
 // Block-local labelling: each workgroup owns a CT^3 tile of boxes, joins same-phase face
 // neighbours inside the tile with a union-find in LDS, and writes for every box of the phase
 // the global index of its tile-local root (the smallest member of its tile-local piece: local
-// and global linear orders agree inside a tile). csize is cleared on the way.
+// and global linear orders agree inside a tile). csize is cleared on the way for the boxes of the
+// phase (the only boxes that can be roots).
 constexpr int CT = 8;
 constexpr int kCtBoxes = CT * CT * CT;
 
@@ -255,6 +256,21 @@ __global__ void __launch_bounds__(kCtBoxes) k_cc_local(Grid g, const uint8_t *la
     const bool in = gx < g.n[0] && gy < g.n[1] && gz < g.n[2];
     const int64_t c = in ? lin(g, gx, gy, gz) : 0;
     const bool mine = in && label[c] == phase;
+    // a tile whose boxes all have the phase (or none does) needs no union-find: its in-grid
+    // boxes form one box-shaped piece whose smallest member is the tile's first box
+    const int nmine = __syncthreads_count(mine), nin = __syncthreads_count(in);
+    if (nmine == 0 || nmine == nin) {
+        if (in) {
+            if (mine) {
+                csize[c] = 0;
+                parent[c] = (uint32_t)lin(g, x0, y0, z0);
+                psize[c] = (uint32_t)nmine;
+            } else {
+                parent[c] = kInvalid;
+            }
+        }
+        return;
+    }
     lp[l] = mine ? (uint32_t)l : kInvalid;
     lc[l] = 0;
     __syncthreads();
@@ -268,8 +284,8 @@ __global__ void __launch_bounds__(kCtBoxes) k_cc_local(Grid g, const uint8_t *la
     if (mine) atomicAdd(lc + r, 1u);
     __syncthreads();
     if (in) {
-        csize[c] = 0;
         if (mine) {
+            csize[c] = 0;
             int rx = r % CT, ry = (r / CT) % CT, rz = r / (CT * CT);
             parent[c] = (uint32_t)lin(g, x0 + rx, y0 + ry, z0 + rz);
             psize[c] = lc[r];
