@@ -122,6 +122,71 @@ def precision_study(nsteps: int, sample: int = 2000):
     print(json.dumps(out), flush=True)
 
 
+def droplet_study(nsteps: int, sample: int = 2000):
+    """Non-planar interface: the 1,000,000-particle droplet (radius 66.83, box 166^3, vapor at
+    0.01), both forms, shifted pair energies, detection every 2nd step. Reports the detected
+    segmentation against the analytic sphere (boxes whose centre lies more than 3 sigma from the
+    sphere must carry its label; the radius of a sphere with the detected liquid volume), the
+    per-atom force error of each form against the FP64 oracle on sampled particles at steps 0
+    and nsteps, the total-energy drift per particle, and atom-steps/s over the nsteps."""
+    import numpy as np
+    import torch
+    import oracle as O
+    from paper_1502_03234_amd import dcm, synth
+
+    st = synth.named("droplet1m")
+    R, c = st.meta["radius"], st.meta["centre"]
+    po = O.params(st.box, energy_shift=1)
+    idx = np.sort(np.random.default_rng(11).choice(st.n, sample, replace=False))
+    out = {"study": "droplet", "workload": f"LJ droplet {st.n_liquid} particles (R = {R:.3f}) + "
+           f"{st.n_vapor} vapor, box 166^3, shifted pair energies, detect every 2nd step",
+           "n_particles": st.n, "steps": nsteps, "forms": {}}
+    for name, prec in (("f64", dcm.DCM_FP64), ("f32c", dcm.DCM_FP32C)):
+        p = dcm.params(st.box, precision=prec, energy_shift=1)
+        s = dcm.System(p, st.x, st.v)
+        det = s.detect()
+        dims = dcm.dcm_grid_dims(p)
+        lab = det["label"].cpu().numpy().reshape(dims[2], dims[1], dims[0])
+        h = [st.box[k] / dims[k] for k in range(3)]
+        zc, yc, xc = np.meshgrid(*[(np.arange(dims[k]) + 0.5) * h[k] for k in (2, 1, 0)], indexing="ij")
+        r = np.sqrt((xc - c) ** 2 + (yc - c) ** 2 + (zc - c) ** 2)
+        far = np.abs(r - R) > 3.0
+        wrong = lab != (r > R)
+        seg = {"far_boxes": int(far.sum()), "far_label_errors": int((wrong & far).sum()),
+               "max_error_distance_from_sphere": float(np.abs(r - R)[wrong].max()) if wrong.any() else 0.0,
+               "radius_from_liquid_volume": float((3.0 * np.prod(h) * (lab == 0).sum() / (4.0 * np.pi)) ** (1 / 3)),
+               "radius_analytic": float(R)}
+        errs, energies = [], []
+        ms = None
+        for leg in (0, nsteps):
+            if leg:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                th = dcm.thermo_records(s.step(leg))
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3 / leg
+                energies += [q["ke"] + q["pe"] for q in th]
+            fo = s.forces(per_atom=False, thermo=(not energies))
+            if not energies:
+                energies.append(sum(dcm.thermo_records(fo["thermo"])[0][k] for k in ("ke", "pe")))
+            x, v, rc, k = s.state()
+            torch.cuda.synchronize()
+            ref = O.forces(po, x.cpu().numpy(), rc.cpu().numpy(), subset=idx)
+            f = fo["f"].cpu().numpy()[:, idx]
+            frms = np.sqrt(np.mean(np.sum(ref.f ** 2, axis=0)))
+            e = np.linalg.norm(f - ref.f, axis=0) / np.maximum(np.linalg.norm(ref.f, axis=0), frms)
+            errs.append({"step": k, "max": float(e.max()), "rms": float(np.sqrt(np.mean(e ** 2)))})
+            log(f"droplet {name} step {k}: force error max {e.max():.3e}")
+        s.check()
+        en = np.array(energies) / st.n
+        out["forms"][name] = {"segmentation": seg, "force_error": errs,
+                              "drift_per_particle": float(en[-1] - en[0]),
+                              "max_excursion_per_particle": float(np.max(np.abs(en - en[0]))),
+                              "ms_per_step": ms, "atom_steps_per_s": st.n * 1e3 / ms}
+        s.close()
+    print(json.dumps(out), flush=True)
+
+
 def serving_study(nseeds: int, nsys: int = 64, nsteps: int = 100, load: float = 0.8):
     """Serving form against one-system-at-a-time solves on the same Poisson traces.
 
@@ -239,6 +304,8 @@ def main():
                     help="only create the system and run K force evaluations (counter passes)")
     ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
                     help="256k slab: NVE drift and force error vs the oracle for both forms")
+    ap.add_argument("--droplet-study", type=int, default=0, metavar="STEPS",
+                    help="droplet (non-planar interface) study of both forms over STEPS steps")
     ap.add_argument("--serve", type=int, default=0, metavar="SEEDS",
                     help="serving study: 64 systems, Poisson arrivals, server vs sequential")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -267,6 +334,9 @@ def main():
         return
     if args.serve:
         serving_study(args.serve)
+        return
+    if args.droplet_study:
+        droplet_study(args.droplet_study)
         return
     log(f"generating {WORKLOAD}")
     state = synth.named(WORKLOAD)
