@@ -120,7 +120,7 @@ dcm_status dcm_workspace_bytes(const dcm_params *p, int64_t n, size_t *bytes);
  * dcm_workspace_bytes. Enqueues: periodic wrap, binning, interface detection and the
  * force evaluation k = 0, so the system is ready for dcm_step. Synchronizes the stream
  * once to validate inputs.
- * DCM_E_INVALID: n < 2 or n >= 2^31; box edge <= 0; bin <= 0; rc_min <= 0 or
+ * DCM_E_INVALID: n < 2 or n >= 2^26 (67,108,864); box edge <= 0; bin <= 0; rc_min <= 0 or
  *   rc_min > rc_max; rc_max >= min(L)/2 (minimum image); N_k < 3; N_k < 2 ceil(rc_max/h_k)
  *   + 2 (a stencil would reach a cell twice); alpha == 0 with rc_min != rc_max;
  *   smooth_passes outside 0..4; min_component < 0; detect_every < 0; dt, mass or sigma

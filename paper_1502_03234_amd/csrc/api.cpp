@@ -73,7 +73,8 @@ bool grid_of(const dcm_params *p, Grid &g)
 dcm_status validate(const dcm_params *p, int64_t n, Grid &g)
 {
     if (!p) return fail(DCM_E_INVALID, "params is NULL");
-    if (n < 2 || n >= ((int64_t)1 << 31)) return fail(DCM_E_INVALID, "n = %lld outside [2, 2^31)", (long long)n);
+    // the pair-force kernel reads positions through a buffer descriptor with 32-bit byte offsets
+    if (n < 2 || n >= ((int64_t)1 << 26)) return fail(DCM_E_INVALID, "n = %lld outside [2, 2^26)", (long long)n);
     if (!grid_of(p, g)) return fail(DCM_E_INVALID, "box edges and bin must be positive and finite");
     if (g.G >= ((int64_t)1 << 31)) return fail(DCM_E_INVALID, "grid of %lld boxes is too large", (long long)g.G);
     if (!(p->rc_min > 0.0) || !(p->rc_min <= p->rc_max))

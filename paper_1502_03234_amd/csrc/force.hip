@@ -12,7 +12,9 @@
 // better L2 reuse between neighbouring waves. The row loops are uniform over the wave, in row
 // offsets relative to each lane's own force row, so the lanes of one row scan the same
 // neighbour rows together. Candidates are loaded four at a time with all loads issued before
-// use (the loop is bound by memory latency otherwise). Periodic images are handled per
+// use (the loop is bound by memory latency otherwise), through a buffer descriptor of the
+// position array: 32-bit offsets, and the up to three slots read past an interval's end need no
+// clamp (reads beyond the array return zeros; such slots are masked out). Periodic images are handled per
 // interval: a wrapped interval adds the box edge to x_j, so dx = x_i - (x_j + shift) is the same
 // number the minimum-image convention gives.
 //
@@ -162,35 +164,53 @@ struct Particle {
 // All candidates of one slot interval [jb, je) (empty for lanes without one), U loads in flight
 // at a time; the particle itself is skipped. The loop runs until the wave's longest interval is
 // done.
+// Position record of slot j through the buffer descriptor of the position array: 32-bit byte
+// offsets, and reads past the array's last record return zeros instead of touching memory.
+template <int PAIR>
+__device__ __forceinline__ double4 load_pos(__amdgpu_buffer_rsrc_t rs, uint32_t j)
+{
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 xy = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rs, j * 32u, 0, 0));
+    double4 p;
+    p.x = xy.x;
+    p.y = xy.y;
+    if (PAIR == DCM_PAIR_MAX) {
+        const d2 zw = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rs, j * 32u + 16u, 0, 0));
+        p.z = zw.x;
+        p.w = zw.y;
+    } else {
+        p.z = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, j * 32u + 16u, 0, 0));
+        p.w = 0.0;
+    }
+    return p;
+}
+
 template <int PAIR, bool SHIFT, bool IMAGE, int U, typename A>
-__device__ __forceinline__ void scan(const ForceArgs &a, const Particle &q, uint32_t jb, uint32_t je,
-                                     double sx, double sy, double sz, A &c)
+__device__ __forceinline__ void scan(const ForceArgs &a, __amdgpu_buffer_rsrc_t rs, const Particle &q, uint32_t jb,
+                                     uint32_t je, double sx, double sy, double sz, A &c)
 {
     const uint32_t len = je - jb;
     for (uint32_t t = 0; __any(t < len); t += U) {
         double4 p[U];
-        uint32_t jj[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            jj[u] = t + u < len ? jb + t + u : (uint32_t)q.i;
-            p[u] = a.pos[jj[u]];
-        }
+        for (int u = 0; u < U; ++u) p[u] = load_pos<PAIR>(rs, jb + t + u);
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            interact<PAIR, SHIFT, IMAGE>(a, p[u], jj[u] != (uint32_t)q.i, q.x, q.y, q.z, q.rc, q.rc2, sx, sy, sz, c);
+            interact<PAIR, SHIFT, IMAGE>(a, p[u], t + u < len && jb + t + u != (uint32_t)q.i, q.x, q.y, q.z, q.rc,
+                                         q.rc2, sx, sy, sz, c);
     }
 }
 
 // The image variant runs only for waves in which some lane's interval is a periodic image.
 template <int PAIR, bool SHIFT, int U, typename A>
-__device__ __forceinline__ void scan_interval(const ForceArgs &a, const Particle &q, uint32_t jb, uint32_t je,
-                                              double sx, double sy, double sz, A &c)
+__device__ __forceinline__ void scan_interval(const ForceArgs &a, __amdgpu_buffer_rsrc_t rs, const Particle &q,
+                                              uint32_t jb, uint32_t je, double sx, double sy, double sz, A &c)
 {
     const bool image = jb < je && (sx != 0.0 || sy != 0.0 || sz != 0.0);
     if (__any(image))
-        scan<PAIR, SHIFT, true, U, A>(a, q, jb, je, sx, sy, sz, c);
+        scan<PAIR, SHIFT, true, U, A>(a, rs, q, jb, je, sx, sy, sz, c);
     else
-        scan<PAIR, SHIFT, false, U, A>(a, q, jb, je, sx, sy, sz, c);
+        scan<PAIR, SHIFT, false, U, A>(a, rs, q, jb, je, sx, sy, sz, c);
 }
 
 __device__ __forceinline__ int wave_min(int v)
@@ -227,6 +247,9 @@ __device__ __forceinline__ void traverse(const ForceArgs &a, bool live, const Pa
     const int zlo_r = live ? floor_mul(q.z - rs, iHz) - Zi : INT_MAX;
     const int zhi_r = live ? floor_mul(q.z + rs, iHz) - Zi : INT_MIN;
     const int zb = wave_min(zlo_r), ze = wave_max(zhi_r);
+    // descriptor of the position array (gfx9 raw buffer; the record count is in bytes)
+    const __amdgpu_buffer_rsrc_t pb =
+        __builtin_amdgcn_make_buffer_rsrc((void *)a.pos, 0, (int)((uint32_t)a.n * 32u), 0x00020000);
     for (int dZ = zb; dZ <= ze; ++dZ) {
         const int Z = Zi + dZ;
         const double zlo = Z * Hz;
@@ -273,8 +296,8 @@ __device__ __forceinline__ void traverse(const ForceArgs &a, bool live, const Pa
                     e1 = a.cell_start[(row + (uint32_t)hi1 + 1u) << gs];
                 }
             }
-            scan_interval<PAIR, SHIFT, U, A>(a, q, b0, e0, sx0, sy, sz, c);
-            if (__any(b1 < e1)) scan_interval<PAIR, SHIFT, U, A>(a, q, b1, e1, sx1, sy, sz, c);
+            scan_interval<PAIR, SHIFT, U, A>(a, pb, q, b0, e0, sx0, sy, sz, c);
+            if (__any(b1 < e1)) scan_interval<PAIR, SHIFT, U, A>(a, pb, q, b1, e1, sx1, sy, sz, c);
         }
     }
 }

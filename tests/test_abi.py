@@ -85,6 +85,11 @@ def test_invalid_n_and_workspace(dcm):
     with pytest.raises(dcm.DcmError) as e:
         dcm.dcm_workspace_bytes(p, 1)
     assert e.value.status == dcm.DCM_E_INVALID
+    # positions are addressed with 32-bit byte offsets: n stays below 2^26
+    assert dcm.dcm_workspace_bytes(p, (1 << 26) - 1) > 0
+    with pytest.raises(dcm.DcmError) as e:
+        dcm.dcm_workspace_bytes(p, 1 << 26)
+    assert e.value.status == dcm.DCM_E_INVALID
     # a missing workspace is rejected before any device work
     h = C.c_void_p()
     st = dcm._lib.dcm_create(C.byref(p), 1000, None, 0, None, None, None, C.byref(h))
