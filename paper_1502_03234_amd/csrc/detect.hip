@@ -397,24 +397,26 @@ __global__ void k_cc_flip(int64_t G, uint8_t *label, uint8_t phase, const uint32
 }
 
 // ---- distance (Godunov relaxation) ----------------------------------------------------
-__device__ __forceinline__ void cswap(double &a, double &b, double &ha, double &hb)
+__device__ __forceinline__ void cswap(double &a, double &b, double &ha, double &hb, double &wa, double &wb)
 {
     if (b < a) {
         double t = a; a = b; b = t;
         t = ha; ha = hb; hb = t;
+        t = wa; wa = wb; wb = t;
     }
 }
 
-// Larger root of sum_k ((d - a_k)^+ / h_k)^2 = 1 over the axes whose a_k lie below d.
-__device__ double godunov(double a0, double a1, double a2, double h0, double h1, double h2)
+// Larger root of sum_k ((d - a_k)^+ / h_k)^2 = 1 over the axes whose a_k lie below d; w_k is
+// 1 / h_k^2, passed in so that the weights are computed once per tile, not per update.
+__device__ double godunov(double a0, double a1, double a2, double h0, double h1, double h2, double w0, double w1,
+                          double w2)
 {
-    cswap(a0, a1, h0, h1);
-    cswap(a1, a2, h1, h2);
-    cswap(a0, a1, h0, h1);
+    cswap(a0, a1, h0, h1, w0, w1);
+    cswap(a1, a2, h1, h2, w1, w2);
+    cswap(a0, a1, h0, h1, w0, w1);
     if (isinf(a0)) return INFINITY;
     double d = a0 + h0;
     if (d > a1) {
-        double w0 = 1.0 / (h0 * h0), w1 = 1.0 / (h1 * h1);
         double sw = w0 + w1;
         double swa = w0 * a0 + w1 * a1;
         double dd = a0 - a1;
@@ -422,7 +424,6 @@ __device__ double godunov(double a0, double a1, double a2, double h0, double h1,
         if (disc < 0.0) disc = 0.0;
         d = (swa + sqrt(disc)) / sw;
         if (d > a2) {
-            double w2 = 1.0 / (h2 * h2);
             sw = w0 + w1 + w2;
             swa = w0 * a0 + w1 * a1 + w2 * a2;
             double d01 = a0 - a1, d02 = a0 - a2, d12 = a1 - a2;
@@ -433,7 +434,6 @@ __device__ double godunov(double a0, double a1, double a2, double h0, double h1,
     }
     return d;
 }
-
 
 // One global relaxation pass over LDS tiles. Two copies of the distance grid alternate;
 // cur[t] says which copy holds tile t's values as of the end of the previous pass. A tile
@@ -500,6 +500,15 @@ __global__ void __launch_bounds__(kTileThreads) k_dist_tiles(Grid g, const uint8
     const int bx = b % ntx, by = (b / ntx) % nty, bz = b / (ntx * nty);
     const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
     if (threadIdx.x < 6) faces[threadIdx.x] = 0;
+    // which copy is current for this tile and its 26 periodic neighbours (the owners of every
+    // halo box)
+    __shared__ uint32_t ncur[27];
+    if (threadIdx.x < 27) {
+        const int dx = threadIdx.x % 3 - 1, dy = (threadIdx.x / 3) % 3 - 1, dz = threadIdx.x / 9 - 1;
+        const int nx = (bx + dx + ntx) % ntx, ny = (by + dy + nty) % nty, nz = (bz + dz + ntz) % ntz;
+        ncur[threadIdx.x] = cprev[(nz * nty + ny) * ntx + nx];
+    }
+    __syncthreads();
     // positions one box outside the grid hold the periodic neighbour (the only outside
     // positions a grid box reads); positions further out (partial tiles) hold infinity
     for (int q = threadIdx.x; q < HX * HY * HZ; q += kTileThreads) {
@@ -510,7 +519,12 @@ __global__ void __launch_bounds__(kTileThreads) k_dist_tiles(Grid g, const uint8
             int cx = gx < 0 ? gx + g.n[0] : (gx == g.n[0] ? 0 : gx);
             int cy = gy < 0 ? gy + g.n[1] : (gy == g.n[1] ? 0 : gy);
             int cz = gz < 0 ? gz + g.n[2] : (gz == g.n[2] ? 0 : gz);
-            const double *src = cprev[tile_of(g, cx, cy, cz)] ? d1 : d0;
+            // owner tile relative to this one, -1, 0 or +1 per axis after the periodic wrap
+            int ox = cx / TX - bx, oy = cy / TY - by, oz = cz / TZ - bz;
+            ox = ox > 1 ? ox - ntx : (ox < -1 ? ox + ntx : ox);
+            oy = oy > 1 ? oy - nty : (oy < -1 ? oy + nty : oy);
+            oz = oz > 1 ? oz - ntz : (oz < -1 ? oz + ntz : oz);
+            const double *src = ncur[(oz + 1) * 9 + (oy + 1) * 3 + (ox + 1)] ? d1 : d0;
             v = src[lin(g, cx, cy, cz)];
         }
         t[hz][hy][hx] = v;
@@ -529,7 +543,12 @@ __global__ void __launch_bounds__(kTileThreads) k_dist_tiles(Grid g, const uint8
             const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
             liq[p][m] = gx < g.n[0] && gy < g.n[1] && gz < g.n[2] && label[lin(g, gx, gy, gz)] != 1;
         }
+    const double wx = 1.0 / (g.h[0] * g.h[0]), wy = 1.0 / (g.h[1] * g.h[1]), wz = 1.0 / (g.h[2] * g.h[2]);
     __syncthreads();
+    // the loaded values of this thread's boxes (the tile's own copy), to detect changes
+    double init[2][2];
+    for (int p = 0; p < 2; ++p)
+        for (int m = 0; m < 2; ++m) init[p][m] = t[bzs[p][m]][bys[p][m]][bxs[p][m]];
     bool local_done = false;
     for (int sweep = 0; sweep < kLocalMax; ++sweep) {
         bool ch = false;
@@ -542,7 +561,7 @@ __global__ void __launch_bounds__(kTileThreads) k_dist_tiles(Grid g, const uint8
                 const double ay = fmin(t[hz][hy - 1][hx], t[hz][hy + 1][hx]);
                 const double az = fmin(t[hz - 1][hy][hx], t[hz + 1][hy][hx]);
                 if (isinf(ax) && isinf(ay) && isinf(az)) continue;
-                const double db = godunov(ax, ay, az, g.h[0], g.h[1], g.h[2]);
+                const double db = godunov(ax, ay, az, g.h[0], g.h[1], g.h[2], wx, wy, wz);
                 if (db <= cap && db < old) { t[hz][hy][hx] = db; ch = true; }
             }
             if (p == 0) __syncthreads();
@@ -551,23 +570,21 @@ __global__ void __launch_bounds__(kTileThreads) k_dist_tiles(Grid g, const uint8
     }
     // write back into the tile's other copy (only if something changed)
     bool wrote = false;
-    for (int q = threadIdx.x; q < TX * TY * TZ; q += kTileThreads) {
-        int lx = q % TX, ly = (q / TX) % TY, lz = q / (TX * TY);
-        int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-        if (gx >= g.n[0] || gy >= g.n[1] || gz >= g.n[2]) continue;
-        double v = t[lz + 1][ly + 1][lx + 1];
-        // the loaded value (the tile's own copy): compare to detect a change
-        double was = (mycur ? d1 : d0)[lin(g, gx, gy, gz)];
-        if (v < was) {
-            wrote = true;
-            if (lx == 0) faces[0] = 1;
-            if (lx == TX - 1 || gx == g.n[0] - 1) faces[1] = 1;
-            if (ly == 0) faces[2] = 1;
-            if (ly == TY - 1 || gy == g.n[1] - 1) faces[3] = 1;
-            if (lz == 0) faces[4] = 1;
-            if (lz == TZ - 1 || gz == g.n[2] - 1) faces[5] = 1;
+    for (int p = 0; p < 2; ++p)
+        for (int m = 0; m < 2; ++m) {
+            const int lx = bxs[p][m] - 1, ly = bys[p][m] - 1, lz = bzs[p][m] - 1;
+            const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+            if (gx >= g.n[0] || gy >= g.n[1] || gz >= g.n[2]) continue;
+            if (t[lz + 1][ly + 1][lx + 1] < init[p][m]) {
+                wrote = true;
+                if (lx == 0) faces[0] = 1;
+                if (lx == TX - 1 || gx == g.n[0] - 1) faces[1] = 1;
+                if (ly == 0) faces[2] = 1;
+                if (ly == TY - 1 || gy == g.n[1] - 1) faces[3] = 1;
+                if (lz == 0) faces[4] = 1;
+                if (lz == TZ - 1 || gz == g.n[2] - 1) faces[5] = 1;
+            }
         }
-    }
     const bool tile_wrote = __syncthreads_or(wrote);
     if (tile_wrote) {
         double *dst = mycur ? d0 : d1;
