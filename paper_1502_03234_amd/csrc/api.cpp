@@ -136,7 +136,7 @@ size_t layout(dcm_system *s, void *ws)
     s->val = b.take<uint32_t>(n);
     s->key_alt = b.take<uint32_t>(n);
     s->val_alt = b.take<uint32_t>(n);
-    s->sort_scratch = b.take<uint8_t>(sort_scratch_bytes(n));
+    s->sort_scratch = b.take<uint8_t>(sort_scratch_bytes(n, G));
     s->gw.cell_start = b.take<uint32_t>(G + 1);
     s->gw.g = b.take<uint32_t>(G);
     s->gw.gtmp = b.take<uint32_t>(G);
@@ -199,7 +199,7 @@ void rebin_sorted(dcm_system *s, hipStream_t st)
 {
     PSet from = s->set[s->cur], to = s->set[1 - s->cur];
     launch_radix_sort(s->key, s->val, s->key_alt, s->val_alt, s->sort_scratch, s->n, s->bits, st);
-    launch_cell_ranges(s->key, s->n, s->grid.G, s->gw.cell_start, st);
+    launch_cell_ranges(s->key, s->n, s->grid.G, s->gw.cell_start, s->sort_scratch, st);
     launch_cell_fixup(s->gw.cell_start, s->grid.G, s->val, from.id, st);
     launch_gather(from, to, s->val, s->n, st);
     s->cur = 1 - s->cur;

@@ -81,13 +81,13 @@ struct GridWork {
 
 // ---- launchers (each enqueues on `st`; no synchronization) ------------------------------
 // sort.hip
-size_t sort_scratch_bytes(int64_t n);
+size_t sort_scratch_bytes(int64_t n, int64_t G);
 void launch_wrap_key(const Grid &g, PSet s, int64_t n, uint32_t *key, uint32_t *val, hipStream_t st);
 void launch_init_ids(PSet s, int64_t n, hipStream_t st);
 void launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key_alt, uint32_t *val_alt,
                        void *scratch, int64_t n, int bits, hipStream_t st);
 void launch_cell_ranges(const uint32_t *key_sorted, int64_t n, int64_t G, uint32_t *cell_start,
-                        hipStream_t st);
+                        void *sort_scratch, hipStream_t st);
 void launch_cell_fixup(const uint32_t *cell_start, int64_t G, uint32_t *val, const uint32_t *id_old,
                        hipStream_t st);
 void launch_gather(PSet from, PSet to, const uint32_t *perm, int64_t n, hipStream_t st);

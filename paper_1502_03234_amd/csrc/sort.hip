@@ -148,7 +148,9 @@ __global__ void __launch_bounds__(kBlock) k_digit_scan(uint32_t *tile_counts, in
     if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
 }
 
-// Stable scatter of one radix pass.
+// Stable scatter of one radix pass. The tile's keys are first placed in LDS in tile-local digit
+// order, then written out in that order, so consecutive threads write consecutive slots of a
+// digit's run in the output.
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t *key, const uint32_t *val,
                                                           uint32_t *key_out, uint32_t *val_out,
                                                           int64_t n, int shift,
@@ -157,12 +159,15 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t *key, c
 {
     __shared__ uint32_t whist[kWaves][kDigits];
     __shared__ uint32_t gbase[kDigits];
+    __shared__ uint32_t tbase[kDigits];
     __shared__ uint32_t lds[kWaves];
+    __shared__ uint32_t sk[kTile], sv[kTile];
     const int tid = threadIdx.x, w = tid >> 6;
     const unsigned lane = lane_id();
     for (int d = tid; d < kWaves * kDigits; d += kBlock) (&whist[0][0])[d] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)w * 64 * kItems;
+    const int64_t tile0 = (int64_t)blockIdx.x * kTile;
+    const int64_t base = tile0 + (int64_t)w * 64 * kItems;
     uint32_t k[kItems], v[kItems], dg[kItems], rk[kItems];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
@@ -179,8 +184,9 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t *key, c
     }
     __syncthreads();
     {
-        // digit base = exclusive scan over digit totals + this tile's prefix for the digit;
-        // per-wave bases = exclusive scan over the waves of the tile
+        // global digit base = exclusive scan over digit totals + this tile's prefix for the
+        // digit; tile-local digit base = exclusive scan over the tile's digit counts; per-wave
+        // bases = exclusive scan over the waves of the tile
         uint32_t excl;
         block_exclusive_scan(digit_total[tid], &excl, lds);
         uint32_t acc = 0;
@@ -189,6 +195,9 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t *key, c
             whist[q][tid] = acc;
             acc += c;
         }
+        uint32_t texcl;
+        block_exclusive_scan(acc, &texcl, lds);
+        tbase[tid] = texcl;
         gbase[tid] = excl + tile_prefix[(int64_t)tid * ntiles + blockIdx.x];
     }
     __syncthreads();
@@ -196,22 +205,64 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t *key, c
     for (int r = 0; r < kItems; ++r) {
         int64_t i = base + r * 64 + lane;
         if (i < n) {
-            uint32_t dst = gbase[dg[r]] + whist[w][dg[r]] + rk[r];
-            key_out[dst] = k[r];
-            val_out[dst] = v[r];
+            const uint32_t p = tbase[dg[r]] + whist[w][dg[r]] + rk[r];
+            sk[p] = k[r];
+            sv[p] = v[r];
         }
+    }
+    __syncthreads();
+    const int64_t left = n - tile0;
+    const int cnt = left < kTile ? (int)left : kTile;
+    for (int q = tid; q < cnt; q += kBlock) {
+        const uint32_t kk = sk[q];
+        const uint32_t d = (kk >> shift) & (kDigits - 1);
+        const uint32_t dst = gbase[d] + ((uint32_t)q - tbase[d]);
+        key_out[dst] = kk;
+        val_out[dst] = sv[q];
     }
 }
 
-// Box starts from sorted keys: the slot where key changes from a to b is the start of every
-// box in (a, b]; boxes before the first key start at 0, after the last at n.
-__global__ void k_cell_ranges(const uint32_t *key, int64_t n, int64_t G, uint32_t *cell_start)
+// Box starts from sorted keys, cell_start[c] = number of keys below c, in two steps. First the
+// start of every run of kRangeBoxes keys: the slot where the key changes from a to b starts
+// every run whose first key lies in (a, b] (runs before the first key start at 0, after the
+// last at n). Then one workgroup per run stages the run's keys in LDS and every box of the run
+// finds its start by binary search, so the box starts are written in order.
+constexpr int kRangeBoxes = 1024;                   // boxes per run (4 per thread)
+constexpr int kRangeKeys = 4096;                    // keys a run can stage in LDS
+
+__global__ void k_run_starts(const uint32_t *key, int64_t n, int64_t nruns, uint32_t *run_start)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i > n) return;
-    int64_t lo = (i == 0) ? 0 : (int64_t)key[i - 1] + 1;
-    int64_t hi = (i == n) ? G : (int64_t)key[i];
-    for (int64_t c = lo; c <= hi; ++c) cell_start[c] = (uint32_t)i;
+    int64_t lo = (i == 0) ? 0 : (int64_t)(key[i - 1] / kRangeBoxes) + 1;
+    int64_t hi = (i == n) ? nruns : (int64_t)(key[i] / kRangeBoxes);
+    for (int64_t r = lo; r <= hi; ++r) run_start[r] = (uint32_t)i;
+}
+
+__global__ void __launch_bounds__(kBlock) k_cell_ranges(const uint32_t *key, int64_t G, const uint32_t *run_start,
+                                                        uint32_t *cell_start)
+{
+    __shared__ uint32_t sk[kRangeKeys];
+    const int64_t c0 = (int64_t)blockIdx.x * kRangeBoxes;
+    const uint32_t lo = run_start[blockIdx.x], hi = run_start[blockIdx.x + 1];
+    const uint32_t m = hi - lo;
+    const bool staged = m <= (uint32_t)kRangeKeys;
+    if (staged)
+        for (uint32_t q = threadIdx.x; q < m; q += kBlock) sk[q] = key[lo + q];
+    __syncthreads();
+    for (int r = 0; r < kRangeBoxes / kBlock; ++r) {
+        const int64_t c = c0 + r * kBlock + threadIdx.x;
+        if (c > G) break;
+        // first position in [0, m) whose key is >= c
+        uint32_t a = 0, b = m;
+        while (a < b) {
+            const uint32_t mid = (a + b) >> 1;
+            const uint32_t km = staged ? sk[mid] : key[lo + mid];
+            if ((int64_t)km < c) a = mid + 1;
+            else b = mid;
+        }
+        cell_start[c] = lo + a;
+    }
 }
 
 // Inside each box, order slots by particle id (insertion sort; boxes hold a few particles).
@@ -251,10 +302,11 @@ inline unsigned grid1(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock);
 
 }  // namespace
 
-size_t sort_scratch_bytes(int64_t n)
+size_t sort_scratch_bytes(int64_t n, int64_t G)
 {
     int64_t ntiles = (n + kTile - 1) / kTile;
-    return sizeof(uint32_t) * ((size_t)kDigits * (size_t)ntiles + kDigits);
+    int64_t nruns = G / kRangeBoxes + 1;              // runs covering boxes 0..G
+    return sizeof(uint32_t) * ((size_t)kDigits * (size_t)ntiles + kDigits + (size_t)nruns + 1);
 }
 
 void launch_wrap_key(const Grid &g, PSet s, int64_t n, uint32_t *key, uint32_t *val, hipStream_t st)
@@ -295,10 +347,14 @@ void launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key_alt, uint32_t
 }
 
 void launch_cell_ranges(const uint32_t *key_sorted, int64_t n, int64_t G, uint32_t *cell_start,
-                        hipStream_t st)
+                        void *scratch, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cell_ranges, dim3(grid1(n + 1)), dim3(kBlock), 0, st, key_sorted, n, G,
-                       cell_start);
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    uint32_t *run_start = (uint32_t *)scratch + (size_t)kDigits * (size_t)ntiles + kDigits;
+    const int64_t nruns = G / kRangeBoxes + 1;
+    hipLaunchKernelGGL(k_run_starts, dim3(grid1(n + 1)), dim3(kBlock), 0, st, key_sorted, n, nruns, run_start);
+    hipLaunchKernelGGL(k_cell_ranges, dim3((unsigned)nruns), dim3(kBlock), 0, st, key_sorted, G,
+                       (const uint32_t *)run_start, cell_start);
 }
 
 void launch_cell_fixup(const uint32_t *cell_start, int64_t G, uint32_t *val, const uint32_t *id_old,
