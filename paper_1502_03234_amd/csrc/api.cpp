@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -157,6 +158,7 @@ size_t layout(dcm_system *s, void *ws)
     s->nkb = stream_blocks(n);
     s->fparts = b.take<Partial>(s->nfb);
     s->kparts = b.take<Partial>(s->nkb);
+    s->rparts = b.take<Partial>(reduce_stage_partials());
     return b.off + 256;
 }
 
@@ -198,7 +200,10 @@ void stage_end(dcm_system *s, hipStream_t st)
 void rebin_sorted(dcm_system *s, hipStream_t st)
 {
     PSet from = s->set[s->cur], to = s->set[1 - s->cur];
-    launch_radix_sort(s->key, s->val, s->key_alt, s->val_alt, s->sort_scratch, s->n, s->bits, st);
+    if (launch_radix_sort(s->key, s->val, s->key_alt, s->val_alt, s->sort_scratch, s->n, s->bits, st)) {
+        std::swap(s->key, s->key_alt);
+        std::swap(s->val, s->val_alt);
+    }
     launch_cell_ranges(s->key, s->n, s->grid.G, s->gw.cell_start, s->sort_scratch, st);
     launch_cell_fixup(s->gw.cell_start, s->grid.G, s->val, from.id, st);
     launch_gather(from, to, s->val, s->n, st);
@@ -397,7 +402,7 @@ dcm_status dcm_compute_forces(dcm_system *s, dcm_stream_t stream, double *d_f, d
     if (d_f) launch_unsort(s->set[s->cur], s->fx, s->fy, s->fz, s->n, nullptr, nullptr, nullptr, d_f, st);
     if (d_th) {
         launch_ke_only(s->set[s->cur], s->n, s->kparts, st);
-        launch_reduce_thermo(s->fparts, s->nfb, s->kparts, s->nkb, s->p.mass, s->k, d_th, st);
+        launch_reduce_thermo(s->fparts, s->nfb, s->kparts, s->nkb, s->p.mass, s->k, d_th, s->rparts, st);
     }
     return hip_status("dcm_compute_forces");
 }
@@ -415,7 +420,7 @@ dcm_status dcm_step(dcm_system *s, int32_t nsteps, dcm_stream_t stream, dcm_ther
         stage_end(s, st);
         if (q > 1 && d_th) {
             stage_begin(s, 8, st);
-            launch_reduce_thermo(s->fparts, s->nfb, s->kparts, s->nkb, s->p.mass, s->k - 1, d_th + (q - 2), st);
+            launch_reduce_thermo(s->fparts, s->nfb, s->kparts, s->nkb, s->p.mass, s->k - 1, d_th + (q - 2), s->rparts, st);
             stage_end(s, st);
         }
         stage_begin(s, 1, st);
@@ -430,7 +435,7 @@ dcm_status dcm_step(dcm_system *s, int32_t nsteps, dcm_stream_t stream, dcm_ther
         stage_end(s, st);
         if (d_th) {
             stage_begin(s, 8, st);
-            launch_reduce_thermo(s->fparts, s->nfb, s->kparts, s->nkb, s->p.mass, s->k, d_th + (nsteps - 1), st);
+            launch_reduce_thermo(s->fparts, s->nfb, s->kparts, s->nkb, s->p.mass, s->k, d_th + (nsteps - 1), s->rparts, st);
             stage_end(s, st);
         }
     }

@@ -81,12 +81,27 @@ __global__ void __launch_bounds__(kBlock) k_hist(const uint32_t *img, int64_t G,
     __shared__ uint32_t lh[kLdsBins];
     for (int b = threadIdx.x; b < kLdsBins; b += kBlock) lh[b] = 0;
     __syncthreads();
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < G;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t v = img[c];
-        if (v < (uint32_t)kLdsBins) atomicAdd(&lh[v], 1u);
-        else if (v < (uint32_t)kHistBins) atomicAdd(&hist[v], 1u);
-        else atomicOr(flags, kFlagHistOverflow);
+    // boxes share few values (empty vapor, bulk liquid), so lanes holding the same value add
+    // once per wave: the lowest such lane adds their number
+    const unsigned lane = __lane_id();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t c0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t cb = (int64_t)blockIdx.x * blockDim.x; cb < G; cb += stride) {
+        const int64_t c = cb + (c0 - (int64_t)blockIdx.x * blockDim.x);
+        const bool in = c < G;
+        const uint32_t v = in ? img[c] : 0u;
+        const bool lds_bin = in && v < (uint32_t)kLdsBins;
+        unsigned long long peers = __ballot(lds_bin);
+        for (int bit = 0; bit < 13; ++bit) {
+            const bool b = (v >> bit) & 1u;
+            const unsigned long long bal = __ballot(b);
+            peers &= b ? bal : ~bal;
+        }
+        if (lds_bin && (peers & ((1ull << lane) - 1ull)) == 0ull) atomicAdd(&lh[v], (uint32_t)__popcll(peers));
+        else if (in && !lds_bin) {
+            if (v < (uint32_t)kHistBins) atomicAdd(&hist[v], 1u);
+            else atomicOr(flags, kFlagHistOverflow);
+        }
     }
     __syncthreads();
     for (int b = threadIdx.x; b < kLdsBins; b += kBlock)
@@ -95,24 +110,16 @@ __global__ void __launch_bounds__(kBlock) k_hist(const uint32_t *img, int64_t G,
 
 constexpr int kTmThreads = 1024;
 
-template <typename T>
-__device__ T block_sum_1024(T v, T *lds /*[16]*/)
-{
-    const int tid = threadIdx.x, w = tid >> 6;
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if ((tid & 63) == 0) lds[w] = v;
-    __syncthreads();
-    T s = 0;
-    for (int q = 0; q < kTmThreads / 64; ++q) s += lds[q];
-    __syncthreads();
-    return s;
-}
+// Two-means on the histogram: the occupied range [min, max] is found by the whole block, copied
+// to LDS, and the Lloyd iterations then run in one wave with shuffle reductions only. All sums
+// are exact integers, so their order does not matter.
+constexpr int kTmLds = 16384;
 
 __global__ void __launch_bounds__(kTmThreads) k_two_means(const uint32_t *hist, double *km,
                                                           long long *stats_iter)
 {
-    __shared__ long long l64[16];
     __shared__ int lmn[16], lmx[16];
+    __shared__ uint32_t lh[kTmLds];
     const int tid = threadIdx.x, w = tid >> 6;
     int mn = kHistBins, mx = -1;
     for (int b = tid; b < kHistBins; b += kTmThreads)
@@ -125,8 +132,12 @@ __global__ void __launch_bounds__(kTmThreads) k_two_means(const uint32_t *hist, 
     __syncthreads();
     mn = kHistBins; mx = -1;
     for (int q = 0; q < 16; ++q) { mn = min(mn, lmn[q]); mx = max(mx, lmx[q]); }
-    __syncthreads();
     if (mx < 0) mn = mx = 0;                    // empty histogram (cannot happen for G >= 27)
+    const bool staged = mx - mn + 1 <= kTmLds;
+    if (staged)
+        for (int b = mn + tid; b <= mx; b += kTmThreads) lh[b - mn] = hist[b];
+    __syncthreads();
+    if (w != 0) return;
     if (mn == mx) {
         if (tid == 0) {
             km[0] = (double)mn; km[1] = (double)mx; km[2] = (double)mn - 1.0;
@@ -138,17 +149,19 @@ __global__ void __launch_bounds__(kTmThreads) k_two_means(const uint32_t *hist, 
     long long prev = -1;
     int it;
     for (it = 1; it <= 1000; ++it) {
-        double m = 0.5 * (cv + cl);
+        const double m = 0.5 * (cv + cl);
         long long sv = 0, nv = 0, sl = 0, nl = 0;
-        for (int b = mn + tid; b <= mx; b += kTmThreads) {
-            long long c = hist[b];
+        for (int b = mn + tid; b <= mx; b += 64) {
+            const long long c = staged ? lh[b - mn] : hist[b];
             if ((double)b > m) { sl += c * b; nl += c; }
             else               { sv += c * b; nv += c; }
         }
-        sv = block_sum_1024(sv, l64);
-        nv = block_sum_1024(nv, l64);
-        sl = block_sum_1024(sl, l64);
-        nl = block_sum_1024(nl, l64);
+        for (int off = 32; off > 0; off >>= 1) {
+            sv += __shfl_xor(sv, off, 64);
+            nv += __shfl_xor(nv, off, 64);
+            sl += __shfl_xor(sl, off, 64);
+            nl += __shfl_xor(nl, off, 64);
+        }
         cv = (double)sv / (double)nv;
         cl = (double)sl / (double)nl;
         if (nl == prev) break;

@@ -120,25 +120,29 @@ __global__ void __launch_bounds__(kBlock) k_kick(PSet s, const double *fx, const
     if (threadIdx.x == 0) ke_partials[blockIdx.x].ke = t;
 }
 
-constexpr int kRedThreads = 1024;
 
 // Sums of the force-workgroup partials (e, W, pairs) and kick-workgroup partials (sum v^2) in
 // a fixed order: thread t adds partials t, t + 1024, ...; then a fixed tree.
-__global__ void __launch_bounds__(kRedThreads) k_reduce_thermo(const Partial *fp, int nf,
-                                                               const Partial *kp, int nk,
-                                                               double mass, long long step,
-                                                               dcm_thermo *out)
+// First stage of the thermo reduction: workgroup b sums its contiguous share of the force and
+// kinetic-energy partials in a fixed order.
+constexpr int kRedStage = 32;                      // workgroups of the first stage
+
+__global__ void __launch_bounds__(kBlock) k_reduce_stage(const Partial *fp, int nf, const Partial *kp, int nk,
+                                                        Partial *out_f, Partial *out_k)
 {
-    __shared__ double lds[kRedThreads / 64][8];
-    __shared__ long long ldp[kRedThreads / 64];
+    __shared__ double lds[kBlock / 64][8];
+    __shared__ long long ldp[kBlock / 64];
+    const int fchunk = (nf + kRedStage - 1) / kRedStage, kchunk = (nk + kRedStage - 1) / kRedStage;
+    const int f0 = blockIdx.x * fchunk, f1 = min(nf, f0 + fchunk);
+    const int k0 = blockIdx.x * kchunk, k1 = min(nk, k0 + kchunk);
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     long long pc = 0;
-    for (int q = threadIdx.x; q < nf; q += kRedThreads) {
+    for (int q = f0 + threadIdx.x; q < f1; q += kBlock) {
         v[0] += fp[q].e;
         for (int r = 0; r < 6; ++r) v[1 + r] += fp[q].w[r];
         pc += fp[q].pairs;
     }
-    for (int q = threadIdx.x; q < nk; q += kRedThreads) v[7] += kp[q].ke;
+    for (int q = k0 + threadIdx.x; q < k1; q += kBlock) v[7] += kp[q].ke;
 #pragma unroll
     for (int r = 0; r < 8; ++r)
         for (int off = 32; off > 0; off >>= 1) v[r] += __shfl_xor(v[r], off, 64);
@@ -150,15 +154,41 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce_thermo(const Partial *fp
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        dcm_thermo t = {};
-        double ke = 0.0;
-        for (int q = 0; q < kRedThreads / 64; ++q) {
-            t.pe += lds[q][0];
-            for (int r = 0; r < 6; ++r) t.virial[r] += lds[q][1 + r];
-            ke += lds[q][7];
-            t.pairs += ldp[q];
+        Partial pf = {}, pk = {};
+        for (int q = 0; q < kBlock / 64; ++q) {
+            pf.e += lds[q][0];
+            for (int r = 0; r < 6; ++r) pf.w[r] += lds[q][1 + r];
+            pf.pairs += ldp[q];
+            pk.ke += lds[q][7];
         }
-        t.ke = 0.5 * mass * ke;
+        out_f[blockIdx.x] = pf;
+        out_k[blockIdx.x] = pk;
+    }
+}
+
+// Second stage: one wave sums the first stage's results in a fixed order.
+__global__ void __launch_bounds__(64) k_reduce_thermo(const Partial *sf, const Partial *sk, double mass,
+                                                      long long step, dcm_thermo *out)
+{
+    const int q = threadIdx.x;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    long long pc = 0;
+    if (q < kRedStage) {
+        v[0] = sf[q].e;
+        for (int r = 0; r < 6; ++r) v[1 + r] = sf[q].w[r];
+        pc = sf[q].pairs;
+        v[7] = sk[q].ke;
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+        for (int off = 32; off > 0; off >>= 1) v[r] += __shfl_xor(v[r], off, 64);
+    for (int off = 32; off > 0; off >>= 1) pc += __shfl_xor(pc, off, 64);
+    if (q == 0) {
+        dcm_thermo t = {};
+        t.pe = v[0];
+        for (int r = 0; r < 6; ++r) t.virial[r] = v[1 + r];
+        t.pairs = pc;
+        t.ke = 0.5 * mass * v[7];
         t.step = step;
         *out = t;
     }
@@ -248,11 +278,15 @@ void launch_ke_only(PSet s, int64_t n, Partial *ke_partials, hipStream_t st)
 }
 
 void launch_reduce_thermo(const Partial *force_parts, int nforce, const Partial *ke_parts, int nke,
-                          double mass, long long step, dcm_thermo *out, hipStream_t st)
+                          double mass, long long step, dcm_thermo *out, Partial *stage, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce_thermo, dim3(1), dim3(kRedThreads), 0, st, force_parts, nforce,
-                       ke_parts, nke, mass, step, out);
+    hipLaunchKernelGGL(k_reduce_stage, dim3(kRedStage), dim3(kBlock), 0, st, force_parts, nforce, ke_parts, nke,
+                       stage, stage + kRedStage);
+    hipLaunchKernelGGL(k_reduce_thermo, dim3(1), dim3(64), 0, st, (const Partial *)stage,
+                       (const Partial *)(stage + kRedStage), mass, step, out);
 }
+
+int reduce_stage_partials() { return 2 * kRedStage; }
 
 void launch_unsort(PSet s, const double *fx, const double *fy, const double *fz, int64_t n,
                    double *x_out, double *v_out, double *rc_out, double *f_out, hipStream_t st)

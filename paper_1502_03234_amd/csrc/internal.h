@@ -84,7 +84,8 @@ struct GridWork {
 size_t sort_scratch_bytes(int64_t n, int64_t G);
 void launch_wrap_key(const Grid &g, PSet s, int64_t n, uint32_t *key, uint32_t *val, hipStream_t st);
 void launch_init_ids(PSet s, int64_t n, hipStream_t st);
-void launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key_alt, uint32_t *val_alt,
+// Returns true when the sorted keys and values end in key_alt / val_alt.
+bool launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key_alt, uint32_t *val_alt,
                        void *scratch, int64_t n, int bits, hipStream_t st);
 void launch_cell_ranges(const uint32_t *key_sorted, int64_t n, int64_t G, uint32_t *cell_start,
                         void *sort_scratch, hipStream_t st);
@@ -142,7 +143,8 @@ void launch_kick(PSet s, const double *fx, const double *fy, const double *fz, i
                  double hdt, Partial *ke_partials, hipStream_t st);
 void launch_ke_only(PSet s, int64_t n, Partial *ke_partials, hipStream_t st);
 void launch_reduce_thermo(const Partial *force_parts, int nforce, const Partial *ke_parts, int nke,
-                          double mass, long long step, dcm_thermo *out, hipStream_t st);
+                          double mass, long long step, dcm_thermo *out, Partial *stage, hipStream_t st);
+int reduce_stage_partials();
 void launch_unsort(PSet s, const double *fx, const double *fy, const double *fz, int64_t n,
                    double *x_out, double *v_out, double *rc_out, double *f_out, hipStream_t st);
 void launch_load_state(PSet s, const double *x, const double *v, const double *rc, int64_t n,
@@ -173,7 +175,7 @@ struct dcm_system {
     uint32_t *key, *val, *key_alt, *val_alt;
     void *sort_scratch;
     dcm::GridWork gw;
-    dcm::Partial *fparts, *kparts;
+    dcm::Partial *fparts, *kparts, *rparts;
     int nfb, nkb;
     int64_t k;
     bool profiling;

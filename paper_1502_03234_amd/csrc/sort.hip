@@ -321,7 +321,7 @@ void launch_init_ids(PSet s, int64_t n, hipStream_t st)
 
 // Sorts (key, val) by key over the low `bits` bits. The result ends in (key, val): an odd
 // number of passes finishes with a copy back from the alternate buffers.
-void launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key_alt, uint32_t *val_alt,
+bool launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key_alt, uint32_t *val_alt,
                        void *scratch, int64_t n, int bits, hipStream_t st)
 {
     int64_t ntiles = (n + kTile - 1) / kTile;
@@ -340,10 +340,8 @@ void launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key_alt, uint32_t
         uint32_t *t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
     }
-    if (ki != key) {
-        launch_copy_bytes(key, ki, sizeof(uint32_t) * (size_t)n, st);
-        launch_copy_bytes(val, vi, sizeof(uint32_t) * (size_t)n, st);
-    }
+    // after an odd number of passes the sorted keys and values are in the alternate buffers
+    return ki != key;
 }
 
 void launch_cell_ranges(const uint32_t *key_sorted, int64_t n, int64_t G, uint32_t *cell_start,
