@@ -176,8 +176,10 @@ dcm_status dcm_check(dcm_system *s, dcm_stream_t stream);
 /* Per-stage timing with HIP events on the system's stream (off by default). Stages:
  * 0 kick/drift/key, 1 sort and cell ranges, 2 smoothing, 3 two-means, 4 labels and
  * components, 5 distance, 6 interpolation and cutoffs, 7 pair forces, 8 reductions.
- * dcm_stage_times synchronizes and returns total milliseconds and launch counts per stage
- * (arrays of DCM_NSTAGES) accumulated since profiling was switched on. */
+ * on: 0 off, 1 every stage, 2 the pair-force stage only (two events per force launch).
+ * DCM_E_INVALID for another level. dcm_stage_times synchronizes and returns total
+ * milliseconds and launch counts per stage (arrays of DCM_NSTAGES) accumulated since
+ * profiling was first switched on. */
 #define DCM_NSTAGES 9
 dcm_status dcm_set_profiling(dcm_system *s, int32_t on);
 dcm_status dcm_stage_times(dcm_system *s, double *h_ms, int64_t *h_counts);

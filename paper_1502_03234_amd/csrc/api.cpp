@@ -180,7 +180,9 @@ void init_derived(dcm_system *s)
 
 void stage_begin(dcm_system *s, int stage, hipStream_t st)
 {
-    if (!s->profiling) return;
+    s->stage_open = false;
+    if (s->profiling == 0 || (s->profiling == 2 && stage != 7)) return;
+    s->stage_open = true;
     Event e;
     if (!s->spare.empty()) { e = s->spare.back(); s->spare.pop_back(); }
     else { (void)hipEventCreate(&e.a); (void)hipEventCreate(&e.b); }
@@ -191,7 +193,8 @@ void stage_begin(dcm_system *s, int stage, hipStream_t st)
 
 void stage_end(dcm_system *s, hipStream_t st)
 {
-    if (!s->profiling || s->events.empty()) return;
+    if (!s->stage_open) return;
+    s->stage_open = false;
     (void)hipEventRecord(s->events.back().b, st);
 }
 
@@ -471,7 +474,8 @@ dcm_status dcm_check(dcm_system *s, dcm_stream_t stream)
 dcm_status dcm_set_profiling(dcm_system *s, int32_t on)
 {
     if (!s) return fail(DCM_E_INVALID, "system is NULL");
-    s->profiling = on != 0;
+    if (on < 0 || on > 2) return fail(DCM_E_INVALID, "profiling level must be 0, 1 or 2");
+    s->profiling = on;
     return DCM_OK;
 }
 

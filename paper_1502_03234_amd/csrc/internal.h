@@ -178,7 +178,8 @@ struct dcm_system {
     dcm::Partial *fparts, *kparts, *rparts;
     int nfb, nkb;
     int64_t k;
-    bool profiling;
+    int profiling;          // 0 off, 1 every stage, 2 the pair-force stage only
+    bool stage_open;        // the current stage's start event was recorded
     std::vector<dcm::Event> events, spare;
     double ms[DCM_NSTAGES];
     int64_t counts[DCM_NSTAGES];

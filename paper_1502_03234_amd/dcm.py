@@ -195,8 +195,9 @@ def dcm_check(h: int, stream=None):
     _check(_lib.dcm_check(h, _stream(stream)))
 
 
-def dcm_set_profiling(h: int, on: bool):
-    _check(_lib.dcm_set_profiling(h, 1 if on else 0))
+def dcm_set_profiling(h: int, on):
+    """on: False/0 off, True/1 every stage, 2 the pair-force stage only."""
+    _check(_lib.dcm_set_profiling(h, int(on)))
 
 
 def dcm_stage_times(h: int):

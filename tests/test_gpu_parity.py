@@ -177,6 +177,28 @@ def test_detect_schedule_and_determinism(slab16k):
         assert np.array_equal(a, b)
 
 
+def test_schedule_by_stage_counts(slab16k):
+    """The per-step schedule: binning and forces on every force evaluation, detection (smoothing,
+    two-means, components, distance, cutoffs) on the even ones; profiling level 2 records the
+    force launches only."""
+    p, _ = make(slab16k)
+    s = dcm.System(p, slab16k.x, slab16k.v)
+    dcm.dcm_set_profiling(s.h, 1)
+    s.step(6)
+    c = {k: v[1] for k, v in dcm.dcm_stage_times(s.h).items()}
+    assert c["forces"] == 6 and c["sort"] == 6 and c["kick_drift_key"] >= 6
+    for stage in ("smooth", "two_means", "segment", "distance", "cutoffs"):
+        assert c[stage] == 3, (stage, c)
+    dcm.dcm_set_profiling(s.h, 2)
+    s.step(4)
+    c2 = {k: v[1] for k, v in dcm.dcm_stage_times(s.h).items()}
+    assert c2["forces"] == 10
+    assert all(c2[k] == c[k] for k in c if k != "forces"), (c, c2)
+    with pytest.raises(dcm.DcmError):
+        dcm.dcm_set_profiling(s.h, 3)
+    s.close()
+
+
 def test_checkpoint_resume_bitwise(slab16k):
     p, _ = make(slab16k)
     a = dcm.System(p, slab16k.x, slab16k.v)
