@@ -27,8 +27,8 @@ WORKLOAD = "slab2m"
 # HBM-side bytes per k_forces launch from FETCH_SIZE/WRITE_SIZE counter runs, scaled by a plain
 # 1 GiB copy (profiles/k_forces_slab2m_traffic.md). Valid only for the kernel source it was
 # taken on: reported as null once csrc/force.hip no longer hashes to this value.
-FORCE_TRAFFIC_BYTES = 2.183e9
-FORCE_TRAFFIC_SRC = "2e534dc4ea158279"
+FORCE_TRAFFIC_BYTES = 2.225e9
+FORCE_TRAFFIC_SRC = "df64ab782ec30fbf"
 
 
 def force_traffic():

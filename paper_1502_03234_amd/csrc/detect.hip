@@ -81,27 +81,12 @@ __global__ void __launch_bounds__(kBlock) k_hist(const uint32_t *img, int64_t G,
     __shared__ uint32_t lh[kLdsBins];
     for (int b = threadIdx.x; b < kLdsBins; b += kBlock) lh[b] = 0;
     __syncthreads();
-    // boxes share few values (empty vapor, bulk liquid), so lanes holding the same value add
-    // once per wave: the lowest such lane adds their number
-    const unsigned lane = __lane_id();
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t c0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int64_t cb = (int64_t)blockIdx.x * blockDim.x; cb < G; cb += stride) {
-        const int64_t c = cb + (c0 - (int64_t)blockIdx.x * blockDim.x);
-        const bool in = c < G;
-        const uint32_t v = in ? img[c] : 0u;
-        const bool lds_bin = in && v < (uint32_t)kLdsBins;
-        unsigned long long peers = __ballot(lds_bin);
-        for (int bit = 0; bit < 13; ++bit) {
-            const bool b = (v >> bit) & 1u;
-            const unsigned long long bal = __ballot(b);
-            peers &= b ? bal : ~bal;
-        }
-        if (lds_bin && (peers & ((1ull << lane) - 1ull)) == 0ull) atomicAdd(&lh[v], (uint32_t)__popcll(peers));
-        else if (in && !lds_bin) {
-            if (v < (uint32_t)kHistBins) atomicAdd(&hist[v], 1u);
-            else atomicOr(flags, kFlagHistOverflow);
-        }
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < G;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t v = img[c];
+        if (v < (uint32_t)kLdsBins) atomicAdd(&lh[v], 1u);
+        else if (v < (uint32_t)kHistBins) atomicAdd(&hist[v], 1u);
+        else atomicOr(flags, kFlagHistOverflow);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < kLdsBins; b += kBlock)
