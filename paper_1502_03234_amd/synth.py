@@ -250,6 +250,43 @@ def droplet(n_drop: int, box_side: float, *, seed: int, rho_vapor: float = 0.01,
                  meta=dict(kind="droplet", seed=seed, radius=R, centre=c))
 
 
+# -- degenerate test states ---------------------------------------------------------------------
+def lattice(n_side: int, box_side: float, *, seed: int, jitter: float = 0.05,
+            temperature: float = 0.7) -> State:
+    """One particle near the centre of every box of a cubic n_side^3 grid of edge box_side /
+    n_side (density (n_side / box_side)^3): every box holds exactly one particle, so the density
+    image is constant and there is no interface."""
+    L = float(box_side)
+    h = L / n_side
+    g = (np.arange(n_side, dtype=np.float64) + 0.5) * h
+    Z, Y, X = np.meshgrid(g, g, g, indexing="ij")
+    x = np.stack([X.ravel(), Y.ravel(), Z.ravel()])
+    n = x.shape[1]
+    x = x + (2.0 * SplitMix64(seed, _TAG_JITTER).uniform(3 * n).reshape(3, n) - 1.0) * jitter
+    v = _velocities(SplitMix64(seed, _TAG_VELOCITY), n, temperature)
+    return State(x=np.ascontiguousarray(x), v=np.ascontiguousarray(v), box=(L, L, L), n_liquid=n,
+                 n_vapor=0, temperature=temperature, meta=dict(kind="lattice", seed=seed))
+
+
+def gas(n: int, box, *, seed: int, temperature: float = 0.7, exclusion: float = 1.0) -> State:
+    """n particles uniform in the box with no two closer than `exclusion` (a dilute gas: no
+    liquid anywhere)."""
+    box = tuple(float(b) for b in box)
+    x = _place_vapor(SplitMix64(seed, _TAG_VAPOR), np.zeros((3, 0)), box, n,
+                     lambda p: np.zeros(len(p), bool), exclusion)
+    v = _velocities(SplitMix64(seed, _TAG_VELOCITY), n, temperature)
+    return State(x=np.ascontiguousarray(x), v=np.ascontiguousarray(v), box=box, n_liquid=0, n_vapor=n,
+                 temperature=temperature, meta=dict(kind="gas", seed=seed))
+
+
+def pair(r: float, box_side: float) -> State:
+    """Two particles at rest a distance r apart along x, straddling the periodic x face."""
+    L = float(box_side)
+    x = np.array([[L - 0.5 * r, 0.5 * r], [0.5 * L, 0.5 * L], [0.5 * L, 0.5 * L]], dtype=np.float64)
+    return State(x=x, v=np.zeros((3, 2)), box=(L, L, L), n_liquid=0, n_vapor=2, temperature=0.0,
+                 meta=dict(kind="pair", r=r))
+
+
 # -- named workloads --------------------------------------------------------------------------
 # Slab workloads: 98 % of the particles in the liquid slab (|z - 30| < 12.5, density 0.8 on
 # FCC sites with vacancies) and 2 % vapor, box Lx x Ly x 60.

@@ -1,0 +1,99 @@
+"""Degenerate and edge inputs of the HIP path against the CPU oracle (through the C ABI): a
+density image without an interface, a gas with no liquid, two particles, positions outside the
+box, other detection schedules, other smoothing and removal settings."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle as O  # noqa: E402
+from paper_1502_03234_amd import dcm, synth  # noqa: E402
+from test_gpu_parity import FORCE_TOL, check_system, make, rc_close, say  # noqa: E402
+
+
+def test_uniform_lattice_has_no_interface():
+    """One particle per box: the smoothed image is constant, two-means has a single level, every
+    box is liquid, every distance is the band cap and every cutoff is r_c^min (Eq. 7)."""
+    st = synth.lattice(16, 16.0, seed=5)
+    p, po = make(st)
+    s = check_system(st, p, po, "lattice 16^3")
+    det = s.detect()
+    torch.cuda.synchronize()
+    km = det["km"].cpu().numpy()
+    assert km[0] == km[1] == 64.0
+    assert not det["label"].cpu().numpy().any()
+    assert np.all(det["dist"].cpu().numpy() == p.rc_max + 1.0)
+    assert np.all(det["rc"].cpu().numpy() == p.rc_min)
+    s.close()
+
+
+def test_dilute_gas():
+    st = synth.gas(500, (20.0, 20.0, 20.0), seed=6)
+    p, po = make(st)
+    check_system(st, p, po, "gas 500").close()
+
+
+def test_two_particles_closed_form():
+    """Two particles 1.5 apart across the periodic x face: F = 24 eps (2 (s/r)^12 - (s/r)^6) / r
+    along the line, equal and opposite (both cutoffs exceed r)."""
+    r = 1.5
+    st = synth.pair(r, 14.0)
+    p, po = make(st)
+    s = check_system(st, p, po, "pair")
+    f = s.forces()["f"].cpu().numpy()
+    mag = 24.0 * (2.0 * r ** -12 - r ** -6) / r
+    # particle 0 sits at x = L - r/2, its partner's image at L + r/2: the force on 0 points to -x
+    # when repulsive (mag > 0)
+    assert abs(f[0, 0] - (-mag)) <= 1e-12 * abs(mag) and abs(f[0, 1] - mag) <= 1e-12 * abs(mag)
+    assert np.all(f[1:] == 0.0)
+    s.close()
+
+
+def test_positions_outside_the_box_are_wrapped(slab16k):
+    """Inputs moved by -1, 0, 1 or 2 box lengths per particle wrap exactly as the oracle wraps
+    them (checked bit for bit inside check_system)."""
+    k = (np.arange(slab16k.n) % 4 - 1)[None, :]
+    st = synth.State(x=np.ascontiguousarray(slab16k.x + k * np.asarray(slab16k.box)[:, None]),
+                     v=slab16k.v, box=slab16k.box, n_liquid=slab16k.n_liquid, n_vapor=slab16k.n_vapor,
+                     temperature=slab16k.temperature, meta=dict(slab16k.meta))
+    assert st.x.min() < 0.0 and st.x.max() > max(slab16k.box)
+    p, po = make(st)
+    check_system(st, p, po, "slab16k shifted by whole boxes").close()
+
+
+@pytest.mark.parametrize("de,detections", [(0, 0), (1, 6), (3, 2)])
+def test_other_detection_schedules(slab16k, de, detections):
+    p, po = make(slab16k, detect_every=de)
+    s = dcm.System(p, slab16k.x, slab16k.v)
+    x0, v0, rc0, _ = s.state()
+    f0 = s.forces()["f"]
+    torch.cuda.synchronize()
+    dcm.dcm_set_profiling(s.h, 1)
+    s.step(1)
+    x1, v1, rc1, _ = s.state()
+    torch.cuda.synchronize()
+    rs = O.RunState(x0.cpu().numpy(), v0.cpu().numpy(), rc0.cpu().numpy(), f0.cpu().numpy(), 0)
+    O.run(po, rs, 1)
+    assert np.max(np.abs(x1.cpu().numpy() - rs.x)) < 1e-13
+    if de == 1:
+        assert rc_close(rc1.cpu().numpy(), rs.rc)        # step 1 re-detects
+    else:
+        assert np.array_equal(rc1.cpu().numpy(), rs.rc)
+    s.step(5)
+    c = {k: v[1] for k, v in dcm.dcm_stage_times(s.h).items()}
+    say(f"detect_every={de}: stage counts {c}")
+    assert c["forces"] == 6 and c["sort"] == 6
+    assert c["distance"] == detections and c["cutoffs"] == detections
+    s.check()
+    s.close()
+
+
+@pytest.mark.parametrize("kw", [dict(smooth_passes=2, min_component=0),
+                                dict(smooth_passes=0, min_component=100)])
+def test_smoothing_and_removal_settings(slab16k, kw):
+    p, po = make(slab16k, **kw)
+    check_system(slab16k, p, po, f"slab16k {kw}").close()
