@@ -54,6 +54,9 @@ enum {
 enum { DCM_FP64 = 0, DCM_FP32C = 1 };       /* plain FP64 / FP32 pair math, compensated sums */
 enum { DCM_PAIR_I = 0, DCM_PAIR_MAX = 1 };  /* pair (i,j) used iff r < r_c[i] (Alg. 3.2) /
                                                iff r < max(r_c[i], r_c[j]) (symmetric)     */
+/* Ensemble of dcm_step: NVE velocity Verlet, or NVT with one Nose-Hoover thermostat
+ * (the thesis runs its systems at constant N, V, T, Section 6). */
+enum { DCM_NVE = 0, DCM_NOSE_HOOVER = 1 };
 
 typedef void *dcm_stream_t;                 /* a hipStream_t */
 
@@ -73,16 +76,22 @@ typedef struct {
     int32_t pair_rule;      /* DCM_PAIR_I or DCM_PAIR_MAX                                 */
     int32_t energy_shift;   /* 1: pair energy V(r) - V(r_c) (forces unchanged) [0]        */
     double dt;              /* velocity-Verlet time step [0.005]                          */
+    double temperature;     /* thermostat target T* = k_B T / epsilon (NVT, Section 6) [0.7] */
+    double tdamp;           /* thermostat relaxation time tau [0.5]; Q = g T* tau^2          */
+    int32_t thermostat;     /* DCM_NVE or DCM_NOSE_HOOVER [DCM_NVE]                       */
 } dcm_params;
 
 /* One thermodynamic record (all FP64 sums in a fixed reduction order).
  * ke = m/2 sum |v|^2; pe = sum_i e_i with e_i = 1/2 sum_j V(r_ij) over the pairs i uses;
  * virial[6] = sum_i 1/2 sum_j r_ij (x) f_ij in the order xx, yy, zz, xy, xz, yz;
- * pairs = number of ordered pairs (i, j) used; step = force-evaluation index k. */
+ * pairs = number of ordered pairs (i, j) used; step = force-evaluation index k;
+ * xi, eta = Nose-Hoover friction and its time integral after the step (0 under NVE): the
+ * extended energy ke + pe + Q xi^2 / 2 + g T* eta is conserved (g = 3n - 3). */
 typedef struct {
     double ke, pe, virial[6];
     int64_t pairs;
     int64_t step;
+    double xi, eta;
 } dcm_thermo;
 
 /* Optional outputs of an interface detection. Each member is a caller device pointer
@@ -124,7 +133,8 @@ dcm_status dcm_workspace_bytes(const dcm_params *p, int64_t n, size_t *bytes);
  *   rc_min > rc_max; rc_max >= min(L)/2 (minimum image); N_k < 3; N_k < 2 ceil(rc_max/h_k)
  *   + 2 (a stencil would reach a cell twice); alpha == 0 with rc_min != rc_max;
  *   smooth_passes outside 0..4; min_component < 0; detect_every < 0; dt, mass or sigma
- *   <= 0; epsilon < 0; unknown precision or pair_rule.
+ *   <= 0; epsilon < 0; unknown precision, pair_rule or thermostat; under DCM_NOSE_HOOVER
+ *   temperature or tdamp <= 0.
  * DCM_E_WORKSPACE: d_ws NULL, misaligned or too small. DCM_E_NONFINITE: a non-finite
  * coordinate or velocity. DCM_E_HIP: a HIP call failed. *out is set only on DCM_OK. */
 dcm_status dcm_create(const dcm_params *p, int64_t n, void *d_ws, size_t ws_bytes,
@@ -159,8 +169,17 @@ dcm_status dcm_compute_forces(dcm_system *s, dcm_stream_t stream, double *d_f, d
 
 /* Advance nsteps velocity-Verlet steps (Eq. 1-2): v += dt/(2m) F; x += dt v; wrap;
  * re-bin; re-detect the interface when k % detect_every == 0; forces (Alg. 3.2);
- * v += dt/(2m) F. d_th (optional) receives nsteps records, one per step. nsteps >= 0. */
+ * v += dt/(2m) F. Under DCM_NOSE_HOOVER each step starts and ends with half a thermostat
+ * step: xi += dt/4 G; v *= exp(-xi dt/2); eta += xi dt/2; xi += dt/4 G, with
+ * G = (2 ke - g T*)/Q recomputed from the rescaled ke. d_th (optional) receives nsteps
+ * records, one per step. nsteps >= 0. */
 dcm_status dcm_step(dcm_system *s, int32_t nsteps, dcm_stream_t stream, dcm_thermo *d_th);
+
+/* Nose-Hoover state {xi, eta} (host arrays of 2 doubles), e.g. to checkpoint and resume an
+ * NVT run bit for bit with dcm_create_from_state. Both synchronize the stream. A system starts
+ * at {0, 0}. DCM_E_INVALID for NULL arguments or non-finite values. */
+dcm_status dcm_get_thermostat(dcm_system *s, dcm_stream_t stream, double h_xi_eta[2]);
+dcm_status dcm_set_thermostat(dcm_system *s, dcm_stream_t stream, const double h_xi_eta[2]);
 
 /* Copy the current state out (caller order; each pointer optional): d_x, d_v [3][n],
  * d_rc [n]. *h_step (host, optional) receives the force-evaluation index k. */

@@ -41,12 +41,13 @@ class Params(C.Structure):
                 ("mass", C.c_double), ("rc_min", C.c_double), ("rc_max", C.c_double),
                 ("alpha", C.c_double), ("bin", C.c_double), ("smooth_passes", C.c_int32),
                 ("min_component", C.c_int32), ("detect_every", C.c_int32),
-                ("pair_rule", C.c_int32), ("energy_shift", C.c_int32), ("dt", C.c_double)]
+                ("pair_rule", C.c_int32), ("energy_shift", C.c_int32), ("dt", C.c_double),
+                ("temperature", C.c_double), ("tdamp", C.c_double), ("thermostat", C.c_int32)]
 
 
 class Thermo(C.Structure):
     _fields_ = [("ke", C.c_double), ("pe", C.c_double), ("virial", C.c_double * 6),
-                ("pairs", C.c_int64), ("step", C.c_int64)]
+                ("pairs", C.c_int64), ("step", C.c_int64), ("xi", C.c_double), ("eta", C.c_double)]
 
 
 class DetectOut(C.Structure):
@@ -84,7 +85,7 @@ def lib():
         L.orc_interp.restype = d
         L.orc_detect.argtypes = [P, i64, vp, C.POINTER(DetectOut)]
         L.orc_forces.argtypes = [P, i64, vp, vp, i64, vp, i32, vp, vp, vp, vp]
-        L.orc_run.argtypes = [P, i64, vp, vp, vp, vp, i64, i32, i32, vp]
+        L.orc_run.argtypes = [P, i64, vp, vp, vp, vp, i64, i32, i32, vp, vp]
         _lib = L
     return _lib
 
@@ -95,7 +96,7 @@ def _p(a):
 
 def params(box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_min=2.5, rc_max=6.0, alpha=-0.5,
            bin=1.0, smooth_passes=1, min_component=27, detect_every=2, pair_rule=0,
-           energy_shift=0, dt=0.005) -> Params:
+           energy_shift=0, dt=0.005, temperature=0.7, tdamp=0.5, thermostat=0) -> Params:
     p = Params()
     p.box[:] = [float(b) for b in box]
     p.epsilon, p.sigma, p.mass = epsilon, sigma, mass
@@ -103,6 +104,7 @@ def params(box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_min=2.5, rc_max=6.0, alp
     p.smooth_passes, p.min_component = smooth_passes, min_component
     p.detect_every, p.pair_rule, p.energy_shift = detect_every, pair_rule, energy_shift
     p.dt = dt
+    p.temperature, p.tdamp, p.thermostat = temperature, tdamp, thermostat
     return p
 
 
@@ -257,6 +259,8 @@ class RunState:
     rc: np.ndarray
     f: np.ndarray
     k: int
+    xi: float = 0.0
+    eta: float = 0.0
 
 
 def prepare(p: Params, x: np.ndarray, v: np.ndarray, method: int = 1) -> RunState:
@@ -270,8 +274,10 @@ def prepare(p: Params, x: np.ndarray, v: np.ndarray, method: int = 1) -> RunStat
 def run(p: Params, st: RunState, nsteps: int, method: int = 1):
     """Advance st in place by nsteps velocity-Verlet steps; returns the thermo records."""
     th = (Thermo * max(nsteps, 1))()
+    nh = np.array([st.xi, st.eta], np.float64)
     lib().orc_run(C.byref(p), st.x.shape[1], _p(st.x), _p(st.v), _p(st.rc), _p(st.f), st.k,
-                  nsteps, method, C.cast(th, C.c_void_p))
+                  nsteps, method, _p(nh), C.cast(th, C.c_void_p))
     st.k += nsteps
-    return [dict(ke=t.ke, pe=t.pe, virial=np.array(t.virial[:]), pairs=t.pairs, step=t.step)
-            for t in th[:nsteps]]
+    st.xi, st.eta = float(nh[0]), float(nh[1])
+    return [dict(ke=t.ke, pe=t.pe, virial=np.array(t.virial[:]), pairs=t.pairs, step=t.step,
+                 xi=t.xi, eta=t.eta) for t in th[:nsteps]]

@@ -16,7 +16,9 @@
  *   orc_cutoff              Section 3.1, Eq. 7-8 (exponential cutoff function)
  *   orc_forces              Section 2.2, Eq. 4 and Section 3.2, Alg. 3.2 (full pair loop,
  *                           the pair is used iff r < r_c[i]; only f_i is updated)
- *   orc_run                 Eq. 1-2 advanced with velocity Verlet
+ *   orc_run                 Eq. 1-2 advanced with velocity Verlet; optionally at constant
+ *                           temperature (the thesis's runs are NVT, Section 6) with one
+ *                           Nose-Hoover thermostat in a symmetric splitting
  *
  * No blocking, fusion or reordering beyond what those passages state.
  * Build: gcc -O2 -ffp-contract=off (no fast-math).
@@ -456,13 +458,44 @@ void orc_forces(const orc_params *p, int64_t n, const double *x, const double *r
     free(head); free(next); free(cid);
 }
 
+/* ---- Nose-Hoover thermostat ---------------------------------------------------------------
+ * Equations of motion at constant temperature: dv/dt = f/m - xi v, dxi/dt = (sum m v^2 -
+ * g T*)/Q, deta/dt = xi, with g = 3n - 3 thermalised degrees of freedom (the friction scales
+ * the total momentum, which therefore stays at its initial value) and Q = g T* tau^2. The
+ * quantity K + U + Q xi^2/2 + g T* eta is conserved. Half a thermostat step (dt/2), taken at
+ * the start and at the end of each velocity-Verlet step: xi advances a quarter step at the
+ * current K; the velocities are damped by exp(-xi dt/2); eta advances half a step; xi advances
+ * its second quarter step at the damped K. */
+static double kinetic(const orc_params *p, int64_t n, const double *v)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < 3 * n; ++i) s += v[i] * v[i];
+    return 0.5 * p->mass * s;
+}
+
+static void nh_half_step(const orc_params *p, int64_t n, double *v, double nh[2])
+{
+    double g = 3.0 * (double)n - 3.0;
+    double gT = g * p->temperature;
+    double Q = gT * p->tdamp * p->tdamp;
+    double K = kinetic(p, n, v);
+    nh[0] += 0.25 * p->dt * (2.0 * K - gT) / Q;
+    double s = exp(-0.5 * p->dt * nh[0]);
+    for (int64_t i = 0; i < 3 * n; ++i) v[i] *= s;
+    nh[1] += 0.5 * p->dt * nh[0];
+    K = kinetic(p, n, v);
+    nh[0] += 0.25 * p->dt * (2.0 * K - gT) / Q;
+}
+
 /* ---- velocity-Verlet steps (Eq. 1-2) ----------------------------------------------------
  * On entry f holds the forces of the current state and rc its cutoffs; k0 is the index of
  * the force evaluation that produced f. Each step: v += (dt/2m) f; x += dt v; wrap; the
  * force evaluation k = k0 + s first re-detects the interface when k % detect_every == 0;
- * forces; v += (dt/2m) f; record KE = m/2 sum v^2, PE = sum e_i, W = sum W_i. */
+ * forces; v += (dt/2m) f; record KE = m/2 sum v^2, PE = sum e_i, W = sum W_i. With the
+ * thermostat on, half a thermostat step comes before the first kick and after the second;
+ * nh = {xi, eta} carries its state in and out (left alone otherwise). */
 int orc_run(const orc_params *p, int64_t n, double *x, double *v, double *rc, double *f,
-            int64_t k0, int32_t nsteps, int32_t method, orc_thermo *th)
+            int64_t k0, int32_t nsteps, int32_t method, double nh[2], orc_thermo *th)
 {
     int32_t d[3]; double h[3];
     orc_grid(p, d, h);
@@ -481,23 +514,26 @@ int orc_run(const orc_params *p, int64_t n, double *x, double *v, double *rc, do
     o.rc = rc;
     for (int32_t s = 1; s <= nsteps; ++s) {
         int64_t k = k0 + s;
+        if (p->thermostat) nh_half_step(p, n, v, nh);
         for (int64_t i = 0; i < 3 * n; ++i) v[i] = v[i] + hdt * f[i];
         for (int64_t i = 0; i < 3 * n; ++i) x[i] = x[i] + p->dt * v[i];
         orc_wrap(p, n, x);
         if (p->detect_every > 0 && k % p->detect_every == 0) orc_detect(p, n, x, &o);
         orc_forces(p, n, x, rc, n, NULL, method, f, e, w, np);
         for (int64_t i = 0; i < 3 * n; ++i) v[i] = v[i] + hdt * f[i];
+        if (p->thermostat) nh_half_step(p, n, v, nh);
         if (th) {
             orc_thermo *t = &th[s - 1];
             memset(t, 0, sizeof *t);
-            for (int64_t i = 0; i < 3 * n; ++i) t->ke += v[i] * v[i];
-            t->ke *= 0.5 * p->mass;
+            t->ke = kinetic(p, n, v);
             for (int64_t i = 0; i < n; ++i) {
                 t->pe += e[i];
                 for (int c = 0; c < 6; ++c) t->virial[c] += w[c * n + i];
                 t->pairs += np[i];
             }
             t->step = k;
+            t->xi = nh[0];
+            t->eta = nh[1];
         }
     }
     free(e); free(w); free(np);

@@ -20,11 +20,14 @@ typedef struct {
     double bin;
     int32_t smooth_passes, min_component, detect_every, pair_rule, energy_shift;
     double dt;
+    double temperature, tdamp;   /* Nose-Hoover target T* and relaxation time tau       */
+    int32_t thermostat;          /* 0: constant energy, 1: Nose-Hoover (constant T)     */
 } orc_params;
 
 typedef struct {
     double ke, pe, virial[6];
     int64_t pairs, step;
+    double xi, eta;              /* thermostat friction and its time integral           */
 } orc_thermo;
 
 /* outputs of one interface detection (every array caller-allocated) */
@@ -60,6 +63,6 @@ void    orc_forces(const orc_params *p, int64_t n, const double *x, const double
                    int64_t m, const int64_t *subset, int32_t method,
                    double *f, double *e, double *w, int64_t *pairs);
 int     orc_run(const orc_params *p, int64_t n, double *x, double *v, double *rc, double *f,
-                int64_t k0, int32_t nsteps, int32_t method, orc_thermo *th);
+                int64_t k0, int32_t nsteps, int32_t method, double nh[2], orc_thermo *th);
 
 #endif

@@ -100,6 +100,11 @@ dcm_status validate(const dcm_params *p, int64_t n, Grid &g)
         return fail(DCM_E_INVALID, "dt, mass and sigma must be positive, epsilon non-negative");
     if (p->precision != DCM_FP64 && p->precision != DCM_FP32C) return fail(DCM_E_INVALID, "unknown precision");
     if (p->pair_rule != DCM_PAIR_I && p->pair_rule != DCM_PAIR_MAX) return fail(DCM_E_INVALID, "unknown pair_rule");
+    if (p->thermostat != DCM_NVE && p->thermostat != DCM_NOSE_HOOVER) return fail(DCM_E_INVALID, "unknown thermostat");
+    if (p->thermostat == DCM_NOSE_HOOVER &&
+        (!(p->temperature > 0.0) || !(p->tdamp > 0.0) || !std::isfinite(p->temperature) || !std::isfinite(p->tdamp)))
+        return fail(DCM_E_INVALID, "the thermostat needs temperature > 0 and tdamp > 0 (got %g, %g)",
+                    p->temperature, p->tdamp);
     return DCM_OK;
 }
 
@@ -159,6 +164,7 @@ size_t layout(dcm_system *s, void *ws)
     s->fparts = b.take<Partial>(s->nfb);
     s->kparts = b.take<Partial>(s->nkb);
     s->rparts = b.take<Partial>(reduce_stage_partials());
+    s->nh = b.take<double>(4);
     return b.off + 256;
 }
 
@@ -176,6 +182,12 @@ void init_derived(dcm_system *s)
         s->cut_b = p.rc_max;
     }
     s->bits = key_bits(s->grid.G);
+    // g = 3n - 3: the thermostat leaves the total momentum unchanged (it scales it), so the
+    // centre-of-mass degrees of freedom are not thermalised
+    const double g = 3.0 * (double)s->n - 3.0;
+    s->nhc.dt = p.dt;
+    s->nhc.gT = g * p.temperature;
+    s->nhc.Q = g * p.temperature * p.tdamp * p.tdamp;
 }
 
 void stage_begin(dcm_system *s, int stage, hipStream_t st)
@@ -293,6 +305,7 @@ dcm_status create_impl(const dcm_params *p, int64_t n, void *d_ws, size_t ws_byt
     s->k = from_state ? step : 0;
     hipStream_t st = (hipStream_t)stream;
     launch_fill_u32(s->gw.flags, 0u, 1, st);
+    launch_fill_u32((uint32_t *)s->nh, 0u, 8, st);
     launch_check_finite(d_x, 3 * n, s->gw.flags, st);
     launch_check_finite(d_v, 3 * n, s->gw.flags, st);
     launch_load_state(s->set[0], d_x, d_v, from_state ? d_rc : nullptr, n, p->rc_max, st);
@@ -321,6 +334,41 @@ dcm_status create_impl(const dcm_params *p, int64_t n, void *d_ws, size_t ws_byt
     }
     *out = s;
     return DCM_OK;
+}
+
+// Thermostatted steps: each is U_NH(dt/2) kick drift [re-bin, detect, forces] kick U_NH(dt/2).
+// The opening half uses the kinetic energy of the velocities in memory (a pass of its own on the
+// first step of a call, else the one fused into the previous step's closing scaling), so a run
+// split over several calls, or resumed from a checkpoint, takes the same bits as one call.
+void step_nose_hoover(dcm_system *s, int32_t nsteps, hipStream_t st, dcm_thermo *d_th)
+{
+    for (int32_t q = 1; q <= nsteps; ++q) {
+        s->k += 1;
+        stage_begin(s, 8, st);
+        if (q == 1) launch_ke_only(s->set[s->cur], s->n, s->kparts, st);
+        launch_reduce_thermo(s->fparts, 0, s->kparts, s->nkb, s->p.mass, s->k, nullptr, s->rparts, s->nh,
+                             kNhStart, s->nhc, st);
+        stage_end(s, st);
+        stage_begin(s, 0, st);
+        launch_kick_drift_key(s->grid, s->set[s->cur], s->fx, s->fy, s->fz, s->n, s->hdt, s->p.dt, 0,
+                              s->nh + 2, s->key, s->val, s->kparts, st);
+        stage_end(s, st);
+        stage_begin(s, 1, st);
+        rebin_sorted(s, st);
+        stage_end(s, st);
+        if (s->p.detect_every > 0 && s->k % s->p.detect_every == 0) detect(s, st);
+        forces(s, st, nullptr, nullptr, nullptr);
+        stage_begin(s, 0, st);
+        launch_kick(s->set[s->cur], s->fx, s->fy, s->fz, s->n, s->hdt, s->kparts, st);
+        stage_end(s, st);
+        stage_begin(s, 8, st);
+        launch_reduce_thermo(s->fparts, s->nfb, s->kparts, s->nkb, s->p.mass, s->k,
+                             d_th ? d_th + (q - 1) : nullptr, s->rparts, s->nh, kNhEnd, s->nhc, st);
+        stage_end(s, st);
+        stage_begin(s, 0, st);
+        launch_scale(s->set[s->cur], s->n, s->nh + 2, s->kparts, st);
+        stage_end(s, st);
+    }
 }
 
 }  // namespace
@@ -405,7 +453,8 @@ dcm_status dcm_compute_forces(dcm_system *s, dcm_stream_t stream, double *d_f, d
     if (d_f) launch_unsort(s->set[s->cur], s->fx, s->fy, s->fz, s->n, nullptr, nullptr, nullptr, d_f, st);
     if (d_th) {
         launch_ke_only(s->set[s->cur], s->n, s->kparts, st);
-        launch_reduce_thermo(s->fparts, s->nfb, s->kparts, s->nkb, s->p.mass, s->k, d_th, s->rparts, st);
+        launch_reduce_thermo(s->fparts, s->nfb, s->kparts, s->nkb, s->p.mass, s->k, d_th, s->rparts, s->nh,
+                             kNhNone, s->nhc, st);
     }
     return hip_status("dcm_compute_forces");
 }
@@ -415,15 +464,20 @@ dcm_status dcm_step(dcm_system *s, int32_t nsteps, dcm_stream_t stream, dcm_ther
     if (!s) return fail(DCM_E_INVALID, "system is NULL");
     if (nsteps < 0) return fail(DCM_E_INVALID, "nsteps must be >= 0");
     hipStream_t st = (hipStream_t)stream;
+    if (s->p.thermostat == DCM_NOSE_HOOVER) {
+        step_nose_hoover(s, nsteps, st, d_th);
+        return hip_status("dcm_step");
+    }
     for (int32_t q = 1; q <= nsteps; ++q) {
         s->k += 1;
         stage_begin(s, 0, st);
         launch_kick_drift_key(s->grid, s->set[s->cur], s->fx, s->fy, s->fz, s->n, s->hdt, s->p.dt,
-                              q > 1 ? 1 : 0, s->key, s->val, s->kparts, st);
+                              q > 1 ? 1 : 0, nullptr, s->key, s->val, s->kparts, st);
         stage_end(s, st);
         if (q > 1 && d_th) {
             stage_begin(s, 8, st);
-            launch_reduce_thermo(s->fparts, s->nfb, s->kparts, s->nkb, s->p.mass, s->k - 1, d_th + (q - 2), s->rparts, st);
+            launch_reduce_thermo(s->fparts, s->nfb, s->kparts, s->nkb, s->p.mass, s->k - 1, d_th + (q - 2),
+                                 s->rparts, s->nh, kNhNone, s->nhc, st);
             stage_end(s, st);
         }
         stage_begin(s, 1, st);
@@ -438,11 +492,38 @@ dcm_status dcm_step(dcm_system *s, int32_t nsteps, dcm_stream_t stream, dcm_ther
         stage_end(s, st);
         if (d_th) {
             stage_begin(s, 8, st);
-            launch_reduce_thermo(s->fparts, s->nfb, s->kparts, s->nkb, s->p.mass, s->k, d_th + (nsteps - 1), s->rparts, st);
+            launch_reduce_thermo(s->fparts, s->nfb, s->kparts, s->nkb, s->p.mass, s->k, d_th + (nsteps - 1),
+                                 s->rparts, s->nh, kNhNone, s->nhc, st);
             stage_end(s, st);
         }
     }
     return hip_status("dcm_step");
+}
+
+dcm_status dcm_get_thermostat(dcm_system *s, dcm_stream_t stream, double h_xi_eta[2])
+{
+    if (!s || !h_xi_eta) return fail(DCM_E_INVALID, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    double t[2];
+    (void)hipMemcpyAsync(t, s->nh, sizeof t, hipMemcpyDeviceToHost, st);
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(DCM_E_HIP, "dcm_get_thermostat: %s", hipGetErrorString(e));
+    h_xi_eta[0] = t[0];
+    h_xi_eta[1] = t[1];
+    return hip_status("dcm_get_thermostat");
+}
+
+dcm_status dcm_set_thermostat(dcm_system *s, dcm_stream_t stream, const double h_xi_eta[2])
+{
+    if (!s || !h_xi_eta) return fail(DCM_E_INVALID, "NULL argument");
+    if (!std::isfinite(h_xi_eta[0]) || !std::isfinite(h_xi_eta[1]))
+        return fail(DCM_E_INVALID, "thermostat state must be finite");
+    hipStream_t st = (hipStream_t)stream;
+    const double t[2] = {h_xi_eta[0], h_xi_eta[1]};
+    (void)hipMemcpyAsync(s->nh, t, sizeof t, hipMemcpyHostToDevice, st);
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(DCM_E_HIP, "dcm_set_thermostat: %s", hipGetErrorString(e));
+    return hip_status("dcm_set_thermostat");
 }
 
 dcm_status dcm_get_state(dcm_system *s, dcm_stream_t stream, double *d_x, double *d_v, double *d_rc,

@@ -6,6 +6,12 @@
 // (the kinetic energy of the completed step is taken between the two kicks); the arithmetic is
 // the same sequence of operations as two separate kernels. Thermodynamic sums are formed per
 // workgroup and then over workgroups in a fixed order, so every run gives the same bits.
+//
+// Under the Nose-Hoover thermostat a step is wrapped in two half thermostat steps (a symmetric
+// Trotter splitting of the equations of motion with friction xi). The thermostat variables
+// live on the device: the last wave of the thermo reduction, which owns the kinetic energy,
+// advances them, and the streaming kernels read the velocity scale from device memory, so a
+// thermostatted step needs no host round trip either.
 #include "internal.h"
 
 namespace dcm {
@@ -61,14 +67,21 @@ __global__ void k_copy_bytes(uint8_t *dst, const uint8_t *src, size_t bytes)
 __global__ void __launch_bounds__(kBlock) k_kick_drift_key(Grid g, PSet s, const double *fx,
                                                            const double *fy, const double *fz,
                                                            int64_t n, double hdt, double dt,
-                                                           int second_kick, uint32_t *key,
-                                                           uint32_t *val, Partial *ke_partials)
+                                                           int second_kick, const double *scale,
+                                                           uint32_t *key, uint32_t *val,
+                                                           Partial *ke_partials)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double ke = 0.0;
     if (i < n) {
         double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
         const double f0 = fx[i], f1 = fy[i], f2 = fz[i];
+        if (scale) {                  // opening thermostat half step
+            const double c = *scale;
+            vx = vx * c;
+            vy = vy * c;
+            vz = vz * c;
+        }
         if (second_kick) {            // close the previous step
             vx = vx + hdt * f0;
             vy = vy + hdt * f1;
@@ -98,18 +111,27 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift_key(Grid g, PSet s, const
     }
 }
 
+// mode 0: kinetic-energy partials only; 1: half kick v += hdt F; 2: thermostat scaling
+// v *= *scale. Every mode leaves the workgroup's sum of |v|^2 (after the update) in ke_partials.
 __global__ void __launch_bounds__(kBlock) k_kick(PSet s, const double *fx, const double *fy,
                                                  const double *fz, int64_t n, double hdt,
-                                                 int apply, Partial *ke_partials)
+                                                 int mode, const double *scale, Partial *ke_partials)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double ke = 0.0;
     if (i < n) {
         double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
-        if (apply) {
+        if (mode == 1) {
             vx = vx + hdt * fx[i];
             vy = vy + hdt * fy[i];
             vz = vz + hdt * fz[i];
+        } else if (mode == 2) {
+            const double c = *scale;
+            vx = vx * c;
+            vy = vy * c;
+            vz = vz * c;
+        }
+        if (mode != 0) {
             s.vx[i] = vx;
             s.vy[i] = vy;
             s.vz[i] = vz;
@@ -121,8 +143,6 @@ __global__ void __launch_bounds__(kBlock) k_kick(PSet s, const double *fx, const
 }
 
 
-// Sums of the force-workgroup partials (e, W, pairs) and kick-workgroup partials (sum v^2) in
-// a fixed order: thread t adds partials t, t + 1024, ...; then a fixed tree.
 // First stage of the thermo reduction: workgroup b sums its contiguous share of the force and
 // kinetic-energy partials in a fixed order.
 constexpr int kRedStage = 32;                      // workgroups of the first stage
@@ -166,9 +186,30 @@ __global__ void __launch_bounds__(kBlock) k_reduce_stage(const Partial *fp, int 
     }
 }
 
-// Second stage: one wave sums the first stage's results in a fixed order.
+// Half a Nose-Hoover step at kinetic energy K, on nh = {xi, eta, scale}: the friction advances
+// a quarter step with G = (2K - g T*)/Q, the velocities (through the scale, and K with them)
+// are damped by exp(-xi dt/2), eta advances half a step, and the friction its second quarter
+// with the damped K. Returns the damped K.
+__device__ double nh_half(double K, double *nh, const NhConst &c)
+{
+    double xi = nh[0], eta = nh[1];
+    xi = xi + 0.25 * c.dt * ((2.0 * K - c.gT) / c.Q);
+    const double sc = exp(-0.5 * c.dt * xi);
+    K = K * sc * sc;
+    eta = eta + 0.5 * c.dt * xi;
+    xi = xi + 0.25 * c.dt * ((2.0 * K - c.gT) / c.Q);
+    nh[0] = xi;
+    nh[1] = eta;
+    nh[2] = sc;
+    return K;
+}
+
+// Second stage: one wave sums the first stage's results in a fixed order. nh_mode 0 writes the
+// record (with the thermostat state nh, if given); kNhStart/kNhEnd also take half a thermostat
+// step with the summed kinetic energy, kNhEnd recording the damped kinetic energy.
 __global__ void __launch_bounds__(64) k_reduce_thermo(const Partial *sf, const Partial *sk, double mass,
-                                                      long long step, dcm_thermo *out)
+                                                      long long step, dcm_thermo *out, double *nh,
+                                                      int nh_mode, NhConst c)
 {
     const int q = threadIdx.x;
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -184,13 +225,19 @@ __global__ void __launch_bounds__(64) k_reduce_thermo(const Partial *sf, const P
         for (int off = 32; off > 0; off >>= 1) v[r] += __shfl_xor(v[r], off, 64);
     for (int off = 32; off > 0; off >>= 1) pc += __shfl_xor(pc, off, 64);
     if (q == 0) {
-        dcm_thermo t = {};
-        t.pe = v[0];
-        for (int r = 0; r < 6; ++r) t.virial[r] = v[1 + r];
-        t.pairs = pc;
-        t.ke = 0.5 * mass * v[7];
-        t.step = step;
-        *out = t;
+        double ke = 0.5 * mass * v[7];
+        if (nh_mode != kNhNone) ke = nh_half(ke, nh, c);
+        if (out) {
+            dcm_thermo t = {};
+            t.pe = v[0];
+            for (int r = 0; r < 6; ++r) t.virial[r] = v[1 + r];
+            t.pairs = pc;
+            t.ke = ke;
+            t.step = step;
+            t.xi = nh ? nh[0] : 0.0;
+            t.eta = nh ? nh[1] : 0.0;
+            *out = t;
+        }
     }
 }
 
@@ -258,32 +305,41 @@ void launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t st)
 
 void launch_kick_drift_key(const Grid &g, PSet s, const double *fx, const double *fy,
                            const double *fz, int64_t n, double hdt, double dt, int second_kick,
-                           uint32_t *key, uint32_t *val, Partial *ke_partials, hipStream_t st)
+                           const double *scale, uint32_t *key, uint32_t *val, Partial *ke_partials,
+                           hipStream_t st)
 {
     hipLaunchKernelGGL(k_kick_drift_key, dim3(grid1(n)), dim3(kBlock), 0, st, g, s, fx, fy, fz, n,
-                       hdt, dt, second_kick, key, val, ke_partials);
+                       hdt, dt, second_kick, scale, key, val, ke_partials);
 }
 
 void launch_kick(PSet s, const double *fx, const double *fy, const double *fz, int64_t n,
                  double hdt, Partial *ke_partials, hipStream_t st)
 {
     hipLaunchKernelGGL(k_kick, dim3(grid1(n)), dim3(kBlock), 0, st, s, fx, fy, fz, n, hdt, 1,
-                       ke_partials);
+                       (const double *)nullptr, ke_partials);
+}
+
+void launch_scale(PSet s, int64_t n, const double *scale, Partial *ke_partials, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_kick, dim3(grid1(n)), dim3(kBlock), 0, st, s, (const double *)nullptr,
+                       (const double *)nullptr, (const double *)nullptr, n, 0.0, 2, scale, ke_partials);
 }
 
 void launch_ke_only(PSet s, int64_t n, Partial *ke_partials, hipStream_t st)
 {
     hipLaunchKernelGGL(k_kick, dim3(grid1(n)), dim3(kBlock), 0, st, s, (const double *)nullptr,
-                       (const double *)nullptr, (const double *)nullptr, n, 0.0, 0, ke_partials);
+                       (const double *)nullptr, (const double *)nullptr, n, 0.0, 0,
+                       (const double *)nullptr, ke_partials);
 }
 
 void launch_reduce_thermo(const Partial *force_parts, int nforce, const Partial *ke_parts, int nke,
-                          double mass, long long step, dcm_thermo *out, Partial *stage, hipStream_t st)
+                          double mass, long long step, dcm_thermo *out, Partial *stage, double *nh,
+                          int nh_mode, const NhConst &c, hipStream_t st)
 {
     hipLaunchKernelGGL(k_reduce_stage, dim3(kRedStage), dim3(kBlock), 0, st, force_parts, nforce, ke_parts, nke,
                        stage, stage + kRedStage);
     hipLaunchKernelGGL(k_reduce_thermo, dim3(1), dim3(64), 0, st, (const Partial *)stage,
-                       (const Partial *)(stage + kRedStage), mass, step, out);
+                       (const Partial *)(stage + kRedStage), mass, step, out, nh, nh_mode, c);
 }
 
 int reduce_stage_partials() { return 2 * kRedStage; }

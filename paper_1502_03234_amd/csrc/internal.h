@@ -59,6 +59,13 @@ struct Partial {
     long long pad;
 };
 
+// Constants of the Nose-Hoover half step: time step, g T* (g = 3n - 3 degrees of freedom) and
+// the thermostat mass Q = g T* tau^2.
+struct NhConst {
+    double dt, gT, Q;
+};
+enum { kNhNone = 0, kNhStart = 1, kNhEnd = 2 };
+
 // Scratch of the grid pipeline (interface detection), G entries each unless noted.
 struct GridWork {
     uint32_t *cell_start;   // [G + 1] first sorted slot of each box (Eq. 9 counts = differences)
@@ -138,12 +145,17 @@ void launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t st)
 int stream_blocks(int64_t n);
 void launch_kick_drift_key(const Grid &g, PSet s, const double *fx, const double *fy,
                            const double *fz, int64_t n, double hdt, double dt, int second_kick,
-                           uint32_t *key, uint32_t *val, Partial *ke_partials, hipStream_t st);
+                           const double *scale, uint32_t *key, uint32_t *val, Partial *ke_partials,
+                           hipStream_t st);
 void launch_kick(PSet s, const double *fx, const double *fy, const double *fz, int64_t n,
                  double hdt, Partial *ke_partials, hipStream_t st);
 void launch_ke_only(PSet s, int64_t n, Partial *ke_partials, hipStream_t st);
+void launch_scale(PSet s, int64_t n, const double *scale, Partial *ke_partials, hipStream_t st);
+// Sums the partials into *out (optional); with nh_mode kNhStart/kNhEnd the final wave also takes
+// half a thermostat step on nh = {xi, eta, scale} with the summed kinetic energy.
 void launch_reduce_thermo(const Partial *force_parts, int nforce, const Partial *ke_parts, int nke,
-                          double mass, long long step, dcm_thermo *out, Partial *stage, hipStream_t st);
+                          double mass, long long step, dcm_thermo *out, Partial *stage, double *nh,
+                          int nh_mode, const NhConst &c, hipStream_t st);
 int reduce_stage_partials();
 void launch_unsort(PSet s, const double *fx, const double *fy, const double *fz, int64_t n,
                    double *x_out, double *v_out, double *rc_out, double *f_out, hipStream_t st);
@@ -176,6 +188,8 @@ struct dcm_system {
     void *sort_scratch;
     dcm::GridWork gw;
     dcm::Partial *fparts, *kparts, *rparts;
+    double *nh;             // Nose-Hoover state {xi, eta, velocity scale of the last half step}
+    dcm::NhConst nhc;
     int nfb, nkb;
     int64_t k;
     int profiling;          // 0 off, 1 every stage, 2 the pair-force stage only

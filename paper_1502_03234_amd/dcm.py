@@ -19,6 +19,7 @@ DCM_E_INVALID, DCM_E_WORKSPACE, DCM_E_HIP, DCM_E_BUDGET = -1, -2, -3, -4
 DCM_E_NONFINITE, DCM_E_UNKNOWN_TICKET, DCM_E_NOT_CONVERGED = -5, -6, -7
 DCM_FP64, DCM_FP32C = 0, 1
 DCM_PAIR_I, DCM_PAIR_MAX = 0, 1
+DCM_NVE, DCM_NOSE_HOOVER = 0, 1
 DCM_NSTAGES = 9
 STAGES = ["kick_drift_key", "sort", "smooth", "two_means", "segment", "distance", "cutoffs",
           "forces", "reduce"]
@@ -36,15 +37,16 @@ class Params(C.Structure):
                 ("alpha", C.c_double), ("bin", C.c_double), ("smooth_passes", C.c_int32),
                 ("min_component", C.c_int32), ("detect_every", C.c_int32),
                 ("precision", C.c_int32), ("pair_rule", C.c_int32), ("energy_shift", C.c_int32),
-                ("dt", C.c_double)]
+                ("dt", C.c_double), ("temperature", C.c_double), ("tdamp", C.c_double),
+                ("thermostat", C.c_int32)]
 
 
 class Thermo(C.Structure):
     _fields_ = [("ke", C.c_double), ("pe", C.c_double), ("virial", C.c_double * 6),
-                ("pairs", C.c_int64), ("step", C.c_int64)]
+                ("pairs", C.c_int64), ("step", C.c_int64), ("xi", C.c_double), ("eta", C.c_double)]
 
 
-THERMO_DOUBLES = C.sizeof(Thermo) // 8     # 10 doubles per record
+THERMO_DOUBLES = C.sizeof(Thermo) // 8     # 12 doubles per record
 
 
 class ServerStats(C.Structure):
@@ -76,6 +78,8 @@ _SIGS = {
     "dcm_detect_interface": ([_vp, _vp, C.POINTER(DetectOut)], _i32),
     "dcm_compute_forces": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "dcm_step": ([_vp, _i32, _vp, _vp], _i32),
+    "dcm_get_thermostat": ([_vp, _vp, _vp], _i32),
+    "dcm_set_thermostat": ([_vp, _vp, _vp], _i32),
     "dcm_get_state": ([_vp, _vp, _vp, _vp, _vp, C.POINTER(_i64)], _i32),
     "dcm_check": ([_vp, _vp], _i32),
     "dcm_set_profiling": ([_vp, _i32], _i32),
@@ -121,13 +125,15 @@ def _stream(stream=None) -> int:
 
 def params(box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_min=2.5, rc_max=6.0, alpha=-0.5, bin=1.0,
            smooth_passes=1, min_component=27, detect_every=2, precision=DCM_FP64,
-           pair_rule=DCM_PAIR_I, energy_shift=0, dt=0.005) -> Params:
+           pair_rule=DCM_PAIR_I, energy_shift=0, dt=0.005, temperature=0.7, tdamp=0.5,
+           thermostat=DCM_NVE) -> Params:
     p = Params()
     p.box[:] = [float(b) for b in box]
     p.epsilon, p.sigma, p.mass = epsilon, sigma, mass
     p.rc_min, p.rc_max, p.alpha, p.bin = rc_min, rc_max, alpha, bin
     p.smooth_passes, p.min_component, p.detect_every = smooth_passes, min_component, detect_every
     p.precision, p.pair_rule, p.energy_shift, p.dt = precision, pair_rule, energy_shift, dt
+    p.temperature, p.tdamp, p.thermostat = temperature, tdamp, thermostat
     return p
 
 
@@ -183,6 +189,17 @@ def dcm_compute_forces(h: int, stream=None, f=None, e=None, w=None, pairs=None, 
 
 def dcm_step(h: int, nsteps: int, stream=None, thermo=None):
     _check(_lib.dcm_step(h, int(nsteps), _stream(stream), _ptr(thermo)))
+
+
+def dcm_get_thermostat(h: int, stream=None):
+    t = (C.c_double * 2)()
+    _check(_lib.dcm_get_thermostat(h, _stream(stream), t))
+    return float(t[0]), float(t[1])
+
+
+def dcm_set_thermostat(h: int, xi: float, eta: float, stream=None):
+    t = (C.c_double * 2)(float(xi), float(eta))
+    _check(_lib.dcm_set_thermostat(h, _stream(stream), t))
 
 
 def dcm_get_state(h: int, stream=None, x=None, v=None, rc=None) -> int:
@@ -272,7 +289,8 @@ def dcm_poll(sv: int, ticket: int, n: int):
     if st == DCM_PENDING:
         return st, None, None, None
     _check(st)
-    rec = dict(ke=th.ke, pe=th.pe, virial=list(th.virial), pairs=th.pairs, step=th.step)
+    rec = dict(ke=th.ke, pe=th.pe, virial=list(th.virial), pairs=th.pairs, step=th.step, xi=th.xi,
+               eta=th.eta)
     return st, x, v, rec
 
 
@@ -299,7 +317,8 @@ def thermo_records(t: torch.Tensor):
     a = t.detach().cpu().view(torch.float64).reshape(-1, THERMO_DOUBLES)
     ints = t.detach().cpu().view(torch.int64).reshape(-1, THERMO_DOUBLES)
     return [dict(ke=float(r[0]), pe=float(r[1]), virial=r[2:8].numpy().copy(),
-                 pairs=int(i[8]), step=int(i[9])) for r, i in zip(a, ints)]
+                 pairs=int(i[8]), step=int(i[9]), xi=float(r[10]), eta=float(r[11]))
+            for r, i in zip(a, ints)]
 
 
 class System:
@@ -369,3 +388,9 @@ class System:
 
     def check(self):
         dcm_check(self.h, self.stream)
+
+    def thermostat(self):
+        return dcm_get_thermostat(self.h, self.stream)
+
+    def set_thermostat(self, xi: float, eta: float):
+        dcm_set_thermostat(self.h, xi, eta, self.stream)

@@ -68,6 +68,10 @@ def test_grid_dims_and_workspace(dcm):
     dict(precision=7),
     dict(pair_rule=3),
     dict(min_component=-1),
+    dict(thermostat=2),
+    dict(thermostat=1, temperature=0.0),
+    dict(thermostat=1, tdamp=-1.0),
+    dict(thermostat=1, tdamp=float("inf")),
 ])
 def test_invalid_parameters_rejected(dcm, bad):
     kw = dict(box=(28.0, 28.0, 60.0))

@@ -524,3 +524,96 @@ def test_nve_drift_static_limit(orc):
     th = orc.run(p, st, 200, method=0)
     E = np.array([t["ke"] + t["pe"] for t in th]) / s.n
     assert np.max(np.abs(E - E[0])) < 5e-3
+
+
+# ---------------------------------------------------------------- Nose-Hoover thermostat (NVT)
+def _nh_free(orc, dt, nsteps, tdamp=0.5, temp=0.7, n=64, seed=11):
+    rng = np.random.default_rng(seed)
+    L = 20.0
+    x = rng.random((3, n)) * L
+    v = rng.normal(size=(3, n)) * 1.3
+    p = orc.params((L, L, L), epsilon=0.0, detect_every=0, dt=dt, thermostat=1, temperature=temp,
+                   tdamp=tdamp)
+    st = orc.RunState(x, v.copy(), np.full(n, 2.5), np.zeros((3, n)), 0)
+    th = orc.run(p, st, nsteps, method=0)
+    return v, th
+
+
+def _nh_free_ode(v0, t_end, tdamp=0.5, temp=0.7):
+    """Nose-Hoover flow of free particles (m = 1) integrated by scipy: dK/dt = -2 xi K,
+    dxi/dt = (2K - g T*)/Q, deta/dt = xi, with g = 3n - 3 and Q = g T* tau^2."""
+    from scipy.integrate import solve_ivp
+    n = v0.shape[1]
+    g = 3 * n - 3
+    Q = g * temp * tdamp ** 2
+
+    def rhs(_, y):
+        K, xi, _eta = y
+        return [-2 * xi * K, (2 * K - g * temp) / Q, xi]
+
+    sol = solve_ivp(rhs, (0, t_end), [0.5 * np.sum(v0 ** 2), 0.0, 0.0], method="DOP853",
+                    rtol=1e-13, atol=1e-15)
+    return sol.y[:, -1]
+
+
+def test_nose_hoover_free_particles_second_order(orc):
+    """Free particles under the thermostat: (K, xi, eta) after t = 2 against a tight scipy
+    solution of the Nose-Hoover flow; the error falls fourfold per halving of dt (symmetric
+    splitting, second order). A wrong factor, sign or the unscaled K in the second quarter
+    step breaks either the agreement or the order."""
+    errs = []
+    for dt in (0.02, 0.01, 0.005):
+        v0, th = _nh_free(orc, dt, int(round(2.0 / dt)))
+        ref = _nh_free_ode(v0, 2.0)
+        got = np.array([th[-1]["ke"], th[-1]["xi"], th[-1]["eta"]])
+        assert abs(got[0] - ref[0]) < 1e-3 * ref[0]
+        errs.append(np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)))
+    assert errs[-1] < 3e-5          # about 0.6 dt^2 at dt = 0.005
+    for a, b in zip(errs, errs[1:]):
+        assert 3.5 < a / b < 4.5, errs
+
+
+def test_nose_hoover_damps_toward_target(orc):
+    """The friction grows while the kinetic temperature exceeds T* and the velocities all shrink
+    by one common factor."""
+    v0, th = _nh_free(orc, 0.005, 40)
+    n = v0.shape[1]
+    assert 0.5 * np.sum(v0 ** 2) * 2 / (3 * n - 3) > 0.7
+    xi = np.array([t["xi"] for t in th])
+    assert np.all(np.diff(xi) > 0)
+    assert th[-1]["ke"] < 0.5 * np.sum(v0 ** 2)
+
+
+def test_nose_hoover_large_tau_is_nve(orc):
+    """With tau -> infinity the thermostat mass diverges and the steps reduce to velocity Verlet."""
+    from paper_1502_03234_amd import synth
+    s = synth.small_slab(800, (14.0, 14.0, 20.0), seed=7)
+    p0 = orc.params(s.box, rc_min=2.5, rc_max=2.5, detect_every=0)
+    p1 = orc.params(s.box, rc_min=2.5, rc_max=2.5, detect_every=0, thermostat=1, tdamp=1e9)
+    a = orc.prepare(p0, s.x, s.v, method=0)
+    b = orc.prepare(p1, s.x, s.v, method=0)
+    ta = orc.run(p0, a, 10, method=0)
+    tb = orc.run(p1, b, 10, method=0)
+    assert np.max(np.abs(a.v - b.v)) < 1e-12
+    assert np.max(np.abs(a.x - b.x)) < 1e-12
+    assert abs(ta[-1]["ke"] - tb[-1]["ke"]) < 1e-12 * ta[-1]["ke"]
+    assert ta[-1]["xi"] == 0.0 and ta[-1]["eta"] == 0.0 and abs(tb[-1]["xi"]) < 1e-12
+
+
+@pytest.mark.slow
+def test_nose_hoover_extended_energy_conserved(orc):
+    """Shifted static-cutoff NVT from a state hotter than T*: K + U changes by far more than the
+    extended energy K + U + Q xi^2/2 + g T* eta, which stays as flat as NVE's K + U does."""
+    from paper_1502_03234_amd import synth
+    s = synth.small_slab(1500, (16.0, 16.0, 24.0), seed=5)
+    temp, tau = 0.7, 0.2
+    p = orc.params(s.box, rc_min=2.5, rc_max=2.5, detect_every=0, energy_shift=1, thermostat=1,
+                   temperature=temp, tdamp=tau)
+    st = orc.prepare(p, s.x, s.v * 1.5, method=0)
+    th = orc.run(p, st, 200, method=0)
+    g = 3 * s.n - 3
+    Q = g * temp * tau ** 2
+    E = np.array([t["ke"] + t["pe"] for t in th]) / s.n
+    H = np.array([t["ke"] + t["pe"] + 0.5 * Q * t["xi"] ** 2 + g * temp * t["eta"] for t in th]) / s.n
+    assert np.ptp(E) > 0.1
+    assert np.max(np.abs(H - H[0])) < 5e-3
