@@ -57,6 +57,10 @@ enum { DCM_PAIR_I = 0, DCM_PAIR_MAX = 1 };  /* pair (i,j) used iff r < r_c[i] (A
 /* Ensemble of dcm_step: NVE velocity Verlet, or NVT with one Nose-Hoover thermostat
  * (the thesis runs its systems at constant N, V, T, Section 6). */
 enum { DCM_NVE = 0, DCM_NOSE_HOOVER = 1 };
+/* Shape of the cutoff function between the interface (d = 0) and d = r_c^max: Eq. 7-8's
+ * exponential, or the linear ramp r_c^max + (r_c^min - r_c^max) d / r_c^max that Section 3.1
+ * and Section 6 (Fig. 34-35) compare it with. */
+enum { DCM_CUTOFF_EXP = 0, DCM_CUTOFF_LINEAR = 1 };
 
 typedef void *dcm_stream_t;                 /* a hipStream_t */
 
@@ -79,6 +83,7 @@ typedef struct {
     double temperature;     /* thermostat target T* = k_B T / epsilon (NVT, Section 6) [0.7] */
     double tdamp;           /* thermostat relaxation time tau [0.5]; Q = g T* tau^2          */
     int32_t thermostat;     /* DCM_NVE or DCM_NOSE_HOOVER [DCM_NVE]                       */
+    int32_t cutoff_shape;   /* DCM_CUTOFF_EXP or DCM_CUTOFF_LINEAR [DCM_CUTOFF_EXP]       */
 } dcm_params;
 
 /* One thermodynamic record (all FP64 sums in a fixed reduction order).
@@ -131,7 +136,8 @@ dcm_status dcm_workspace_bytes(const dcm_params *p, int64_t n, size_t *bytes);
  * once to validate inputs.
  * DCM_E_INVALID: n < 2 or n >= 2^26 (67,108,864); box edge <= 0; bin <= 0; rc_min <= 0 or
  *   rc_min > rc_max; rc_max >= min(L)/2 (minimum image); N_k < 3; N_k < 2 ceil(rc_max/h_k)
- *   + 2 (a stencil would reach a cell twice); alpha == 0 with rc_min != rc_max;
+ *   + 2 (a stencil would reach a cell twice); alpha == 0 with rc_min != rc_max
+ *   under DCM_CUTOFF_EXP; unknown cutoff_shape;
  *   smooth_passes outside 0..4; min_component < 0; detect_every < 0; dt, mass or sigma
  *   <= 0; epsilon < 0; unknown precision, pair_rule or thermostat; under DCM_NOSE_HOOVER
  *   temperature or tdamp <= 0.

@@ -42,7 +42,7 @@ class Params(C.Structure):
                 ("alpha", C.c_double), ("bin", C.c_double), ("smooth_passes", C.c_int32),
                 ("min_component", C.c_int32), ("detect_every", C.c_int32),
                 ("pair_rule", C.c_int32), ("energy_shift", C.c_int32), ("dt", C.c_double),
-                ("temperature", C.c_double), ("tdamp", C.c_double), ("thermostat", C.c_int32)]
+                ("temperature", C.c_double), ("tdamp", C.c_double), ("thermostat", C.c_int32), ("cutoff_shape", C.c_int32)]
 
 
 class Thermo(C.Structure):
@@ -85,6 +85,7 @@ def lib():
         L.orc_interp.restype = d
         L.orc_detect.argtypes = [P, i64, vp, C.POINTER(DetectOut)]
         L.orc_forces.argtypes = [P, i64, vp, vp, i64, vp, i32, vp, vp, vp, vp]
+        L.orc_forces_images.argtypes = [P, i64, vp, d, i64, vp, vp, vp]
         L.orc_run.argtypes = [P, i64, vp, vp, vp, vp, i64, i32, i32, vp, vp]
         _lib = L
     return _lib
@@ -96,7 +97,8 @@ def _p(a):
 
 def params(box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_min=2.5, rc_max=6.0, alpha=-0.5,
            bin=1.0, smooth_passes=1, min_component=27, detect_every=2, pair_rule=0,
-           energy_shift=0, dt=0.005, temperature=0.7, tdamp=0.5, thermostat=0) -> Params:
+           energy_shift=0, dt=0.005, temperature=0.7, tdamp=0.5, thermostat=0,
+           cutoff_shape=0) -> Params:
     p = Params()
     p.box[:] = [float(b) for b in box]
     p.epsilon, p.sigma, p.mass = epsilon, sigma, mass
@@ -105,6 +107,7 @@ def params(box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_min=2.5, rc_max=6.0, alp
     p.detect_every, p.pair_rule, p.energy_shift = detect_every, pair_rule, energy_shift
     p.dt = dt
     p.temperature, p.tdamp, p.thermostat = temperature, tdamp, thermostat
+    p.cutoff_shape = cutoff_shape
     return p
 
 
@@ -245,6 +248,20 @@ def forces(p: Params, x: np.ndarray, rc: np.ndarray, subset=None, method: int = 
     lib().orc_forces(C.byref(p), n, _p(x), _p(rc), m, None if sub is None else _p(sub), method,
                      _p(out.f), _p(out.e), _p(out.w), _p(out.pairs))
     return out
+
+
+def forces_images(p: Params, x: np.ndarray, R: float, subset=None):
+    """Exact reference forces (Eq. 20's F^exact): full LJ over all images within R.
+    Returns (f [3][m], e [m])."""
+    x = np.ascontiguousarray(x, np.float64)
+    n = x.shape[1]
+    sub = None if subset is None else np.ascontiguousarray(subset, np.int64)
+    m = n if sub is None else sub.size
+    f = np.zeros((3, m))
+    e = np.zeros(m)
+    lib().orc_forces_images(C.byref(p), n, _p(x), float(R), m, None if sub is None else _p(sub),
+                            _p(f), _p(e))
+    return f, e
 
 
 def thermo_of(fr: Forces, v: np.ndarray, mass: float = 1.0) -> dict:

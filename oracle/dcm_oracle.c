@@ -13,9 +13,12 @@
  *   orc_distance            Section 4.3, Eq. 15-19, Alg. 4.2 (fast sweeping, repeated
  *                           until nothing changes; band limited as in Section 4.3.2)
  *   orc_interp              Section 3, Eq. 5-6, Alg. 3.1 (trilinear interpolation)
- *   orc_cutoff              Section 3.1, Eq. 7-8 (exponential cutoff function)
+ *   orc_cutoff              Section 3.1, Eq. 7-8 (exponential cutoff function; or the
+ *                           linear ramp that Section 6 compares it with)
  *   orc_forces              Section 2.2, Eq. 4 and Section 3.2, Alg. 3.2 (full pair loop,
  *                           the pair is used iff r < r_c[i]; only f_i is updated)
+ *   orc_forces_images       the exact forces of Eq. 20's accuracy measure: Eq. 4 with no
+ *                           cutoff, over every periodic image within a radius R
  *   orc_run                 Eq. 1-2 advanced with velocity Verlet; optionally at constant
  *                           temperature (the thesis's runs are NVT, Section 6) with one
  *                           Nose-Hoover thermostat in a symmetric splitting
@@ -286,12 +289,14 @@ int64_t orc_distance(const int32_t d[3], const double h[3], double cap, const ui
     return rounds;
 }
 
-/* ---- exponential cutoff function (Eq. 7-8) --------------------------------------------- */
+/* ---- cutoff function (Eq. 7-8; linear ramp as the alternative of Section 6) ------------- */
 double orc_cutoff(const orc_params *p, double d)
 {
     if (p->rc_min == p->rc_max) return p->rc_max;
     if (d <= 0.0) return p->rc_max;
     if (d >= p->rc_max) return p->rc_min;
+    if (p->cutoff_shape == 1)                  /* linear ramp from r_c^max at d = 0 */
+        return p->rc_max + (p->rc_min - p->rc_max) * (d / p->rc_max);
     double a = (p->rc_max - p->rc_min) / (exp2(p->alpha * p->rc_max) - 1.0);
     double b = p->rc_min - a;
     return a * exp2(p->alpha * (p->rc_max - d)) + b;
@@ -456,6 +461,41 @@ void orc_forces(const orc_params *p, int64_t n, const double *x, const double *r
         store(&a, s, m, f, e, w, pairs);
     }
     free(head); free(next); free(cid);
+}
+
+/* ---- exact reference forces (F^exact of Eq. 20) ------------------------------------------
+ * The full Lennard-Jones force of Eq. 4, with no cutoff function, summed over every particle j
+ * and every periodic image x_j + (a L_x, b L_y, c L_z) closer than R to x_i; R may exceed half
+ * the box. The lattice sum converges absolutely, so only its part beyond R is missing. Outputs
+ * for the listed particles (subset NULL: all n): f [3][m], e [m] = 1/2 sum_j V(r_ij). */
+void orc_forces_images(const orc_params *p, int64_t n, const double *x, double R, int64_t m,
+                       const int64_t *subset, double *f, double *e)
+{
+    int64_t K[3];
+    for (int k = 0; k < 3; ++k) K[k] = (int64_t)ceil(R / p->box[k]) + 1;
+    for (int64_t s = 0; s < m; ++s) {
+        int64_t i = subset ? subset[s] : s;
+        double acc[3] = {0.0, 0.0, 0.0}, en = 0.0;
+        for (int64_t j = 0; j < n; ++j)
+            for (int64_t a = -K[0]; a <= K[0]; ++a)
+                for (int64_t b = -K[1]; b <= K[1]; ++b)
+                    for (int64_t c = -K[2]; c <= K[2]; ++c) {
+                        if (j == i && a == 0 && b == 0 && c == 0) continue;
+                        double d[3];
+                        d[0] = x[i] - (x[j] + (double)a * p->box[0]);
+                        d[1] = x[n + i] - (x[n + j] + (double)b * p->box[1]);
+                        d[2] = x[2 * n + i] - (x[2 * n + j] + (double)c * p->box[2]);
+                        double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                        if (!(r2 < R * R)) continue;
+                        double sr2 = p->sigma * p->sigma / r2;
+                        double sr6 = sr2 * sr2 * sr2;
+                        double fr = 24.0 * p->epsilon * sr6 * (2.0 * sr6 - 1.0) / r2;
+                        for (int k = 0; k < 3; ++k) acc[k] += fr * d[k];
+                        en += 4.0 * p->epsilon * sr6 * (sr6 - 1.0);
+                    }
+        for (int k = 0; k < 3; ++k) f[k * m + s] = acc[k];
+        if (e) e[s] = 0.5 * en;
+    }
 }
 
 /* ---- Nose-Hoover thermostat ---------------------------------------------------------------

@@ -22,6 +22,7 @@ typedef struct {
     double dt;
     double temperature, tdamp;   /* Nose-Hoover target T* and relaxation time tau       */
     int32_t thermostat;          /* 0: constant energy, 1: Nose-Hoover (constant T)     */
+    int32_t cutoff_shape;        /* 0: exponential (Eq. 7-8), 1: linear ramp            */
 } orc_params;
 
 typedef struct {
@@ -62,6 +63,8 @@ int     orc_detect(const orc_params *p, int64_t n, const double *x, orc_detect_o
 void    orc_forces(const orc_params *p, int64_t n, const double *x, const double *rc,
                    int64_t m, const int64_t *subset, int32_t method,
                    double *f, double *e, double *w, int64_t *pairs);
+void    orc_forces_images(const orc_params *p, int64_t n, const double *x, double R, int64_t m,
+                          const int64_t *subset, double *f, double *e);
 int     orc_run(const orc_params *p, int64_t n, double *x, double *v, double *rc, double *f,
                 int64_t k0, int32_t nsteps, int32_t method, double nh[2], orc_thermo *th);
 

@@ -91,7 +91,10 @@ dcm_status validate(const dcm_params *p, int64_t n, Grid &g)
     // the stencil in units of two boxes (a lane's rows then never meet the same storage row twice)
     g.sy = (g.n[1] % 2 == 0 && g.n[1] >= 2 * (int)std::ceil(p->rc_max / g.h[1]) + 6) ? 1 : 0;
     g.sz = (g.n[2] % 2 == 0 && g.n[2] >= 2 * (int)std::ceil(p->rc_max / g.h[2]) + 6) ? 1 : 0;
-    if (p->alpha == 0.0 && p->rc_min != p->rc_max) return fail(DCM_E_INVALID, "alpha must be non-zero");
+    if (p->cutoff_shape != DCM_CUTOFF_EXP && p->cutoff_shape != DCM_CUTOFF_LINEAR)
+        return fail(DCM_E_INVALID, "unknown cutoff_shape");
+    if (p->cutoff_shape == DCM_CUTOFF_EXP && p->alpha == 0.0 && p->rc_min != p->rc_max)
+        return fail(DCM_E_INVALID, "alpha must be non-zero");
     if (!std::isfinite(p->alpha)) return fail(DCM_E_INVALID, "alpha must be finite");
     if (p->smooth_passes < 0 || p->smooth_passes > 4) return fail(DCM_E_INVALID, "smooth_passes must be 0..4");
     if (p->min_component < 0) return fail(DCM_E_INVALID, "min_component must be >= 0");
@@ -174,7 +177,7 @@ void init_derived(dcm_system *s)
     s->hdt = 0.5 * p.dt / p.mass;
     double hmax = std::max(s->grid.h[0], std::max(s->grid.h[1], s->grid.h[2]));
     s->cap = p.rc_max + hmax;
-    if (p.rc_min != p.rc_max) {
+    if (p.rc_min != p.rc_max && p.cutoff_shape == DCM_CUTOFF_EXP) {
         s->cut_a = (p.rc_max - p.rc_min) / (std::exp2(p.alpha * p.rc_max) - 1.0);
         s->cut_b = p.rc_min - s->cut_a;
     } else {
@@ -244,7 +247,7 @@ void detect(dcm_system *s, hipStream_t st)
     stage_end(s, st);
     stage_begin(s, 6, st);
     launch_cutoffs(g, s->set[s->cur], s->n, w.dist, s->cap, s->p.rc_min, s->p.rc_max, s->p.alpha,
-                   s->cut_a, s->cut_b, st);
+                   s->cut_a, s->cut_b, s->p.cutoff_shape == DCM_CUTOFF_LINEAR ? 1 : 0, st);
     stage_end(s, st);
 }
 

@@ -644,7 +644,7 @@ __global__ void k_cap_copy(const double *dist, double cap, double *out, int64_t 
 __device__ __forceinline__ double lerp(double a, double b, double t) { return a + t * (b - a); }
 
 __global__ void k_cutoffs(Grid g, PSet s, int64_t n, const double *dist, double cap, double rc_min,
-                          double rc_max, double alpha, double a, double b)
+                          double rc_max, double alpha, double a, double b, int linear)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
@@ -674,6 +674,7 @@ __global__ void k_cutoffs(Grid g, PSet s, int64_t n, const double *dist, double 
     double rc;
     if (rc_min == rc_max || d <= 0.0) rc = rc_max;
     else if (d >= rc_max) rc = rc_min;
+    else if (linear) rc = rc_max + (rc_min - rc_max) * (d / rc_max);
     else rc = a * exp2(alpha * (rc_max - d)) + b;
     q.w = rc;
     s.pos[p] = q;
@@ -773,10 +774,10 @@ void launch_cap_copy(const double *dist, double cap, double *out, int64_t G, hip
 }
 
 void launch_cutoffs(const Grid &g, PSet s, int64_t n, const double *dist, double cap, double rc_min,
-                    double rc_max, double alpha, double a, double b, hipStream_t st)
+                    double rc_max, double alpha, double a, double b, int linear, hipStream_t st)
 {
     hipLaunchKernelGGL(k_cutoffs, dim3(grid1(n)), dim3(kBlock), 0, st, g, s, n, dist, cap, rc_min,
-                       rc_max, alpha, a, b);
+                       rc_max, alpha, a, b, linear);
 }
 
 }  // namespace dcm

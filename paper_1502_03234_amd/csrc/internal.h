@@ -112,7 +112,7 @@ int64_t distance_tiles(const Grid &g);
 void launch_distance(const Grid &g, double cap, const uint8_t *label, double *dist, GridWork w,
                      hipStream_t st);
 void launch_cutoffs(const Grid &g, PSet s, int64_t n, const double *dist, double cap,
-                    double rc_min, double rc_max, double alpha, double a, double b, hipStream_t st);
+                    double rc_min, double rc_max, double alpha, double a, double b, int linear, hipStream_t st);
 void launch_cap_copy(const double *dist, double cap, double *out, int64_t G, hipStream_t st);
 void launch_count_from_ranges(const Grid &g, const uint32_t *cell_start, uint32_t *out, hipStream_t st);
 

@@ -20,6 +20,7 @@ DCM_E_NONFINITE, DCM_E_UNKNOWN_TICKET, DCM_E_NOT_CONVERGED = -5, -6, -7
 DCM_FP64, DCM_FP32C = 0, 1
 DCM_PAIR_I, DCM_PAIR_MAX = 0, 1
 DCM_NVE, DCM_NOSE_HOOVER = 0, 1
+DCM_CUTOFF_EXP, DCM_CUTOFF_LINEAR = 0, 1
 DCM_NSTAGES = 9
 STAGES = ["kick_drift_key", "sort", "smooth", "two_means", "segment", "distance", "cutoffs",
           "forces", "reduce"]
@@ -38,7 +39,7 @@ class Params(C.Structure):
                 ("min_component", C.c_int32), ("detect_every", C.c_int32),
                 ("precision", C.c_int32), ("pair_rule", C.c_int32), ("energy_shift", C.c_int32),
                 ("dt", C.c_double), ("temperature", C.c_double), ("tdamp", C.c_double),
-                ("thermostat", C.c_int32)]
+                ("thermostat", C.c_int32), ("cutoff_shape", C.c_int32)]
 
 
 class Thermo(C.Structure):
@@ -126,7 +127,7 @@ def _stream(stream=None) -> int:
 def params(box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_min=2.5, rc_max=6.0, alpha=-0.5, bin=1.0,
            smooth_passes=1, min_component=27, detect_every=2, precision=DCM_FP64,
            pair_rule=DCM_PAIR_I, energy_shift=0, dt=0.005, temperature=0.7, tdamp=0.5,
-           thermostat=DCM_NVE) -> Params:
+           thermostat=DCM_NVE, cutoff_shape=DCM_CUTOFF_EXP) -> Params:
     p = Params()
     p.box[:] = [float(b) for b in box]
     p.epsilon, p.sigma, p.mass = epsilon, sigma, mass
@@ -134,6 +135,7 @@ def params(box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_min=2.5, rc_max=6.0, alp
     p.smooth_passes, p.min_component, p.detect_every = smooth_passes, min_component, detect_every
     p.precision, p.pair_rule, p.energy_shift, p.dt = precision, pair_rule, energy_shift, dt
     p.temperature, p.tdamp, p.thermostat = temperature, tdamp, thermostat
+    p.cutoff_shape = cutoff_shape
     return p
 
 

@@ -41,12 +41,12 @@ def dist_ulps(cap, hmin):
     return 2 * int(np.ceil(cap / hmin))
 
 
-def rc_close(rc, ref, rc_min=2.5, rc_max=6.0, alpha=-0.5, h=1.0):
+def rc_close(rc, ref, rc_min=2.5, rc_max=6.0, alpha=-0.5, h=1.0, linear=False):
     """Cutoffs within the propagated bound: box distances may differ by dist_ulps ulp of the
-    band cap, the cutoff function's slope is at most |a alpha ln 2| (Eq. 7-8), plus 4 ulp of r_c
-    itself for the exponential."""
+    band cap, the cutoff function's slope is at most |a alpha ln 2| (Eq. 7-8; (r_c^max -
+    r_c^min) / r_c^max for the linear ramp), plus 4 ulp of r_c itself for the exponential."""
     a = (rc_max - rc_min) / (2.0 ** (alpha * rc_max) - 1.0) if rc_min != rc_max else 0.0
-    slope = abs(a * alpha * np.log(2.0))
+    slope = (rc_max - rc_min) / rc_max if linear else abs(a * alpha * np.log(2.0))
     cap = rc_max + h
     tol = slope * dist_ulps(cap, h) * np.spacing(cap) + ULP_TOL * np.spacing(np.maximum(np.abs(rc), np.abs(ref)))
     return np.all(np.abs(np.asarray(rc) - np.asarray(ref)) <= tol)
@@ -89,7 +89,7 @@ def check_system(state, p, po, name):
     assert st[0] == od.stats[0] and np.array_equal(st[1:5], od.stats[1:5]), (st, od.stats)
     assert ulp_close(det["dist"].cpu().numpy(), od.dist, dist_ulps(p.rc_max + 1.0, 1.0)), "distances"
     rc_gpu = rc.cpu().numpy()
-    assert rc_close(rc_gpu, od.rc, p.rc_min, p.rc_max, p.alpha), "cutoffs"
+    assert rc_close(rc_gpu, od.rc, p.rc_min, p.rc_max, p.alpha, linear=p.cutoff_shape == 1), "cutoffs"
     assert ulp_close(det["rc"].cpu().numpy(), rc_gpu, 0)
     ref = O.forces(po, xw, rc_gpu)
     err = force_err(fo["f"].cpu().numpy(), ref.f)
@@ -125,6 +125,13 @@ def test_ragged_slabs(n, box, seed):
     st = synth.small_slab(n, box, seed)
     p, po = make(st)
     check_system(st, p, po, f"slab n={n}").close()
+
+
+def test_linear_cutoff_shape(slab16k):
+    """The linear ramp of Section 6 through the whole path (3.0 / 7.0, Fig. 35c's pair)."""
+    p, po = make(slab16k, rc_min=3.0, rc_max=7.0, cutoff_shape=dcm.DCM_CUTOFF_LINEAR)
+    s = check_system(slab16k, p, po, "slab16k linear 3/7")
+    s.close()
 
 
 def test_static_limit_and_symmetric_rule(slab16k):

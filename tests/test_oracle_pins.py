@@ -42,6 +42,23 @@ def test_cutoff_shape(orc):
     assert all(orc.cutoff(ps, d) == 4.0 for d in (-1, 0, 2, 9))
 
 
+def test_linear_cutoff_and_exponential_above_it(orc):
+    """The linear ramp runs from r_c^max at the interface to r_c^min at d = r_c^max; with
+    alpha < 0 the exponential of Eq. 7 is concave there, so it lies above the ramp (it gives
+    more particles a larger cutoff, as Section 6 states) and meets it at both ends."""
+    for rmin, rmax in ((2.5, 6.0), (3.0, 8.0), (4.5, 9.5)):
+        pl = orc.params((30, 30, 30), rc_min=rmin, rc_max=rmax, cutoff_shape=1)
+        pe = orc.params((30, 30, 30), rc_min=rmin, rc_max=rmax, alpha=-0.5)
+        ds = np.linspace(0.0, rmax, 97)[1:-1]
+        lin = np.array([orc.cutoff(pl, d) for d in ds])
+        assert np.allclose(lin, rmax + (rmin - rmax) * ds / rmax, rtol=0, atol=1e-14)
+        assert np.allclose(np.diff(lin, 2), 0.0, atol=1e-12)
+        assert orc.cutoff(pl, 0.0) == rmax and orc.cutoff(pl, rmax) == rmin and orc.cutoff(pl, -2) == rmax
+        ex = np.array([orc.cutoff(pe, d) for d in ds])
+        assert np.all(ex > lin)
+        assert abs(orc.cutoff(pe, 1e-9) - orc.cutoff(pl, 1e-9)) < 1e-8
+
+
 # ---------------------------------------------------------------- Lennard-Jones (Eq. 4)
 def _two(orc, r, rc=(6.0, 6.0), L=40.0, axis=(1.0, 0.0, 0.0), **kw):
     p = orc.params((L, L, L), **kw)
@@ -617,3 +634,74 @@ def test_nose_hoover_extended_energy_conserved(orc):
     H = np.array([t["ke"] + t["pe"] + 0.5 * Q * t["xi"] ** 2 + g * temp * t["eta"] for t in th]) / s.n
     assert np.ptp(E) > 0.1
     assert np.max(np.abs(H - H[0])) < 5e-3
+
+
+# ---------------------------------------------------------------- exact reference (Eq. 20)
+def _fcc(rnn, k):
+    a = rnn * math.sqrt(2.0)
+    base = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
+    pts = np.array([(i + b[0], j + b[1], l + b[2]) for i in range(k) for j in range(k)
+                    for l in range(k) for b in base]) * a
+    return np.ascontiguousarray(pts.T), k * a, 4.0 / a ** 3
+
+
+def test_image_sum_fcc_lattice_constants(orc):
+    """Perfect FCC crystal, nearest neighbours at 1.1 sigma, 5^3 cubic cells: the energy per
+    particle of the image sum within R plus the continuum tail beyond R equals the lattice sum
+    2 (A12 / r^12 - A6 / r^6) with the Lennard-Jones-Ingham constants A12 = 12.13188,
+    A6 = 14.45392, to a few percent of that tail; R = 12 exceeds half the box (images). Every
+    force vanishes by symmetry."""
+    rnn = 1.1
+    x, L, rho = _fcc(rnn, 5)
+    p = orc.params((L, L, L))
+    exact = 2.0 * (12.13188 / rnn ** 12 - 14.45392 / rnn ** 6)
+    for R in (6.0, 9.0, 12.0):
+        f, e = orc.forces_images(p, x, R)
+        tail = 8.0 * math.pi * rho * (1.0 / (9.0 * R ** 9) - 1.0 / (3.0 * R ** 3))
+        assert abs(e.mean() + tail - exact) < 0.05 * abs(tail), (R, e.mean(), tail, exact)
+        assert abs(e.mean() - exact) > 0.5 * abs(tail)
+        assert np.abs(f).max() < 1e-12
+
+
+def test_image_sum_equals_static_cutoff_below_half_box(orc):
+    """For R < L/2 only the nearest image can lie within R: the image sum is the static-cutoff
+    force with r_c = R (unshifted), pair set included."""
+    from paper_1502_03234_amd import synth
+    s = synth.small_slab(600, (12.0, 12.0, 16.0), seed=21)
+    p = orc.params(s.box, rc_min=5.5, rc_max=5.5)
+    x = orc.wrap(p, s.x)
+    f, e = orc.forces_images(p, x, 5.5)
+    ref = orc.forces(p, x, np.full(s.n, 5.5), method=0)
+    scale = np.abs(ref.f).max()
+    assert np.max(np.abs(f - ref.f)) < 1e-12 * scale
+    assert np.max(np.abs(e - ref.e)) < 1e-12 * np.abs(ref.e).max()
+
+
+def test_image_sum_newton_and_gradient(orc):
+    """R beyond half the box: the image sum keeps Newton's third law (sum F = 0) and its
+    forces are minus the gradient of its total energy (central differences)."""
+    rng = np.random.default_rng(5)
+    L = np.array([7.0, 7.5, 9.0])
+    n = 40
+    x = np.ascontiguousarray(rng.random((3, n)) * L[:, None])
+    # keep particles apart so the energy is smooth: rejection of close pairs (minimum image)
+    for _ in range(200):
+        d = x[:, :, None] - x[:, None, :]
+        d -= L[:, None, None] * np.rint(d / L[:, None, None])
+        r = np.sqrt((d ** 2).sum(0)) + np.eye(n) * 10
+        bad = np.nonzero(r.min(1) < 0.95)[0]
+        if not len(bad):
+            break
+        x[:, bad[0]] = rng.random(3) * L
+    p = orc.params(tuple(L))
+    R = 8.0
+    f, e = orc.forces_images(p, x, R)
+    assert np.max(np.abs(f.sum(axis=1))) < 1e-10 * np.abs(f).sum()
+    h = 1e-6
+    for i, k in ((0, 0), (7, 1), (23, 2)):
+        xp, xm = x.copy(), x.copy()
+        xp[k, i] += h
+        xm[k, i] -= h
+        # pairs crossing R change the energy discontinuously; none lie within h of R here
+        dE = (orc.forces_images(p, xp, R)[1].sum() - orc.forces_images(p, xm, R)[1].sum()) / (2 * h)
+        assert abs(-dE - f[k, i]) < 1e-5 * max(1.0, abs(f[k, i])), (i, k, dE, f[k, i])
