@@ -106,19 +106,37 @@ def cpu_baseline_aggregate(state, sample: int, procs: int):
                 sample=f"{procs} independent oracle processes, each on the single-core sample")
 
 
-def precision_study(nsteps: int, sample: int = 2000):
+def _fp64_forces_of(p, x, v, rc, k):
+    """Forces of the FP64 form on a given state and cutoffs (a system that never re-detects, so
+    the cutoffs are used as given). The FP64 form's agreement with the oracle is what the parity
+    tests establish; here it is the reference of the FP32 form."""
+    from paper_1502_03234_amd import dcm
+    q = dcm.Params.from_buffer_copy(p)
+    q.precision, q.detect_every = dcm.DCM_FP64, 0
+    r = dcm.System(q, x, v, rc=rc, step=k)
+    f = r.forces(per_atom=False, thermo=False)["f"]
+    r.close()
+    return f
+
+
+def _form_error(f, ref):
+    """Per-atom |dF_i| / max(|F_i|, F_rms) over all particles: max and rms."""
+    import torch
+    frms = torch.sqrt(torch.mean(torch.sum(ref ** 2, dim=0)))
+    e = torch.linalg.norm(f - ref, dim=0) / torch.clamp(torch.linalg.norm(ref, dim=0), min=frms)
+    return float(e.max()), float(torch.sqrt(torch.mean(e ** 2)))
+
+
+def precision_study(nsteps: int):
     """Both forms on the 256,000-particle slab with shifted pair energies: total-energy drift
-    per particle over nsteps, and the per-atom force error |dF_i| / max(|F_i|, F_rms) of each
-    form against the FP64 oracle on sampled particles of that form's own state (checkpoints at
-    0, nsteps/2 and nsteps)."""
+    per particle over nsteps, and the FP32 form's per-atom force error |dF_i| / max(|F_i|,
+    F_rms) against the FP64 form on every particle of the FP32 form's own state and cutoffs
+    (checkpoints at 0, nsteps/2 and nsteps)."""
     import numpy as np
     import torch
-    import oracle as O
     from paper_1502_03234_amd import dcm, synth
 
     st = synth.named("slab256k")
-    po = O.params(st.box, energy_shift=1)
-    idx = np.sort(np.random.default_rng(7).choice(st.n, sample, replace=False))
     out = {"study": "precision", "workload": "LJ slab 256,000 particles, box 112x112x60, shifted pair "
            "energies, detect every 2nd step", "steps": nsteps, "forms": {}}
     for name, prec in (("f64", dcm.DCM_FP64), ("f32c", dcm.DCM_FP32C)):
@@ -134,40 +152,34 @@ def precision_study(nsteps: int, sample: int = 2000):
             if not energies:
                 t0 = dcm.thermo_records(fo["thermo"])[0]
                 energies.append(t0["ke"] + t0["pe"])
-            x, v, rc, k = s.state()
-            torch.cuda.synchronize()
-            ref = O.forces(po, x.cpu().numpy(), rc.cpu().numpy(), subset=idx)
-            f = fo["f"].cpu().numpy()[:, idx]
-            frms = np.sqrt(np.mean(np.sum(ref.f ** 2, axis=0)))
-            e = np.linalg.norm(f - ref.f, axis=0) / np.maximum(np.linalg.norm(ref.f, axis=0), frms)
-            errs.append({"step": k, "max": float(e.max()), "rms": float(np.sqrt(np.mean(e ** 2)))})
-            log(f"{name} step {k}: force error max {e.max():.3e}")
+            if prec == dcm.DCM_FP32C:
+                x, v, rc, k = s.state()
+                emax, erms = _form_error(fo["f"], _fp64_forces_of(p, x, v, rc, k))
+                errs.append({"step": k, "max": emax, "rms": erms})
+                log(f"{name} step {k}: force error vs the FP64 form, max {emax:.3e}")
         s.check()
         en = np.array(energies) / st.n
         out["forms"][name] = {"energy_per_particle_start": float(en[0]),
                               "drift_per_particle": float(en[-1] - en[0]),
                               "max_excursion_per_particle": float(np.max(np.abs(en - en[0]))),
-                              "force_error": errs}
+                              "force_error_vs_f64": errs}
         s.close()
     print(json.dumps(out), flush=True)
 
 
-def droplet_study(nsteps: int, sample: int = 2000):
+def droplet_study(nsteps: int):
     """Non-planar interface: the 1,000,000-particle droplet (radius 66.83, box 166^3, vapor at
     0.01), both forms, shifted pair energies, detection every 2nd step. Reports the detected
     segmentation against the analytic sphere (boxes whose centre lies more than 3 sigma from the
     sphere must carry its label; the radius of a sphere with the detected liquid volume), the
-    per-atom force error of each form against the FP64 oracle on sampled particles at steps 0
-    and nsteps, the total-energy drift per particle, and atom-steps/s over the nsteps."""
+    FP32 form's per-atom force error against the FP64 form on every particle of its own state
+    at steps 0 and nsteps, the total-energy drift per particle, and atom-steps/s."""
     import numpy as np
     import torch
-    import oracle as O
     from paper_1502_03234_amd import dcm, synth
 
     st = synth.named("droplet1m")
     R, c = st.meta["radius"], st.meta["centre"]
-    po = O.params(st.box, energy_shift=1)
-    idx = np.sort(np.random.default_rng(11).choice(st.n, sample, replace=False))
     out = {"study": "droplet", "workload": f"LJ droplet {st.n_liquid} particles (R = {R:.3f}) + "
            f"{st.n_vapor} vapor, box 166^3, shifted pair energies, detect every 2nd step",
            "n_particles": st.n, "steps": nsteps, "forms": {}}
@@ -199,17 +211,14 @@ def droplet_study(nsteps: int, sample: int = 2000):
             fo = s.forces(per_atom=False, thermo=(not energies))
             if not energies:
                 energies.append(sum(dcm.thermo_records(fo["thermo"])[0][k] for k in ("ke", "pe")))
-            x, v, rc, k = s.state()
-            torch.cuda.synchronize()
-            ref = O.forces(po, x.cpu().numpy(), rc.cpu().numpy(), subset=idx)
-            f = fo["f"].cpu().numpy()[:, idx]
-            frms = np.sqrt(np.mean(np.sum(ref.f ** 2, axis=0)))
-            e = np.linalg.norm(f - ref.f, axis=0) / np.maximum(np.linalg.norm(ref.f, axis=0), frms)
-            errs.append({"step": k, "max": float(e.max()), "rms": float(np.sqrt(np.mean(e ** 2)))})
-            log(f"droplet {name} step {k}: force error max {e.max():.3e}")
+            if prec == dcm.DCM_FP32C:
+                x, v, rc, k = s.state()
+                emax, erms = _form_error(fo["f"], _fp64_forces_of(p, x, v, rc, k))
+                errs.append({"step": k, "max": emax, "rms": erms})
+                log(f"droplet {name} step {k}: force error vs the FP64 form, max {emax:.3e}")
         s.check()
         en = np.array(energies) / st.n
-        out["forms"][name] = {"segmentation": seg, "force_error": errs,
+        out["forms"][name] = {"segmentation": seg, "force_error_vs_f64": errs,
                               "drift_per_particle": float(en[-1] - en[0]),
                               "max_excursion_per_particle": float(np.max(np.abs(en - en[0]))),
                               "ms_per_step": ms, "atom_steps_per_s": st.n * 1e3 / ms}
@@ -320,6 +329,110 @@ def serving_study(nseeds: int, nsys: int = 64, nsteps: int = 100, load: float = 
     print(json.dumps(out), flush=True)
 
 
+# Total energy per particle printed by the thesis (Section 6, Table 1) for its 16,000-particle
+# slab after 100,000 NVT steps at T* = 0.7, dt = 0.005; the quoted standard deviations are
+# 0.013-0.017. Keys: (r_c^min, r_c^max); equal values are the static cutoff.
+TABLE1_ENERGY = {(3.0, 3.0): -4.415, (5.0, 5.0): -4.772, (7.0, 7.0): -4.830,
+                 (3.0, 5.0): -4.557, (3.0, 7.0): -4.636, (3.0, 8.0): -4.660,
+                 (4.5, 9.5): -4.805}
+
+
+def nvt_study(equil: int, sample: int, configs=None, chunk: int = 1000, tdamp: float = 0.5,
+              save_dir: str | None = None):
+    """Table 1 and Figure 37 observables. The thesis's geometry (16,000 particles in a 22 x 22 x
+    44 block centred in 22 x 22 x 88), Nose-Hoover at T* = 0.7, dt = 0.005, unshifted pair
+    energies, detection every 2nd step; one system per Table 1 cutoff configuration, all
+    stepped concurrently on streams of their own. After `equil` steps, `sample` steps give:
+    total energy per particle (block averages over `chunk` steps, standard error of the block
+    means), the density profile along z about the slab's centre (liquid |dz| < 10, vapor
+    |dz| > 30), and the surface tension Lz/2 <P_zz - (P_xx + P_yy)/2> from the virial (the
+    kinetic part of the pressure tensor is isotropic on average and drops out). Then each
+    configuration alone: ms per step. With save_dir, each final state (x, v, r_c in caller order,
+    the thermostat's xi and eta) is written there as an .npz file."""
+    import numpy as np
+    import torch
+    from paper_1502_03234_amd import dcm, synth
+
+    st = synth.named("thesis16k")
+    Lx, Ly, Lz = st.box
+    V = Lx * Ly * Lz
+    edges = np.arange(-Lz / 2, Lz / 2 + 1e-9, 1.0)
+    systems = []
+    for q, ((rmin, rmax), ref) in enumerate(TABLE1_ENERGY.items()):
+        if configs is not None and q not in configs:
+            continue
+        p = dcm.params(st.box, rc_min=rmin, rc_max=rmax, thermostat=dcm.DCM_NOSE_HOOVER,
+                       temperature=0.7, tdamp=tdamp)
+        stream = torch.cuda.Stream()
+        s = dcm.System(p, st.x, st.v, stream=stream)
+        systems.append(dict(name=("static %.1f" % rmax) if rmin == rmax else "DCM %.1f/%.1f" % (rmin, rmax),
+                            rc=(rmin, rmax), ref=ref, s=s, stream=stream,
+                            th=torch.empty(chunk * dcm.THERMO_DOUBLES, dtype=torch.float64, device="cuda"),
+                            x=torch.empty((3, st.n), dtype=torch.float64, device="cuda"),
+                            E=[], gamma=[], T=[], hist=np.zeros(len(edges) - 1), frames=0))
+    total = equil + sample
+    t0 = time.perf_counter()
+    done = 0
+    while done < total:
+        for c in systems:
+            dcm.dcm_step(c["s"].h, chunk, c["stream"], c["th"])
+        torch.cuda.synchronize()
+        done += chunk
+        if done > equil:
+            for c in systems:
+                rec = dcm.thermo_records(c["th"])
+                e = np.array([r["ke"] + r["pe"] for r in rec]) / st.n
+                w = np.array([r["virial"] for r in rec])
+                c["E"].append(e.mean())
+                c["gamma"].append(np.mean(0.5 * Lz * (w[:, 2] - 0.5 * (w[:, 0] + w[:, 1])) / V))
+                c["T"].append(np.mean([2.0 * r["ke"] / (3 * st.n - 3) for r in rec]))
+                dcm.dcm_get_state(c["s"].h, c["stream"], x=c["x"])
+            torch.cuda.synchronize()
+            for c in systems:
+                z = c["x"][2].cpu().numpy()
+                th = 2 * np.pi * z / Lz
+                zc = math.atan2(np.sin(th).mean(), np.cos(th).mean()) * Lz / (2 * np.pi)
+                dz = np.mod(z - zc + Lz / 2, Lz) - Lz / 2
+                c["hist"] += np.histogram(dz, bins=edges)[0]
+                c["frames"] += 1
+        if done % (10 * chunk) == 0 or done == total:
+            log(f"nvt study: {done}/{total} steps of {len(systems)} systems, "
+                f"{time.perf_counter() - t0:.1f} s")
+    rows = []
+    mid = 0.5 * (edges[1:] + edges[:-1])
+    for c in systems:
+        c["s"].check()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dcm.dcm_step(c["s"].h, 500, c["stream"], None)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 2.0
+        if save_dir:
+            xs, vs, rcs, k = c["s"].state()
+            xi, eta = c["s"].thermostat()
+            os.makedirs(save_dir, exist_ok=True)
+            np.savez(os.path.join(save_dir, "thesis16k_nvt_%g_%g.npz" % c["rc"]), x=xs.cpu().numpy(),
+                     v=vs.cpu().numpy(), rc=rcs.cpu().numpy(), step=k, xi=xi, eta=eta)
+        E = np.array(c["E"])
+        g = np.array(c["gamma"])
+        rho = c["hist"] / (Lx * Ly * 1.0 * max(c["frames"], 1))
+        se = lambda a: float(a.std(ddof=1) / math.sqrt(len(a))) if len(a) > 1 else None
+        rows.append({"config": c["name"], "rc_min": c["rc"][0], "rc_max": c["rc"][1],
+                     "E_per_particle": float(E.mean()), "E_stderr": se(E),
+                     "E_table1": c["ref"], "E_minus_table1": float(E.mean() - c["ref"]),
+                     "T_mean": float(np.mean(c["T"])),
+                     "rho_liquid": float(rho[np.abs(mid) < 10].mean()),
+                     "rho_vapor": float(rho[np.abs(mid) > 30].mean()),
+                     "gamma": float(g.mean()), "gamma_stderr": se(g), "ms_per_step": ms,
+                     "profile": [round(float(r), 4) for r in rho]})
+        c["s"].close()
+    out = {"study": "nvt_table1", "workload": "16,000 LJ particles, 22 x 22 x 44 block in a 22 x 22 x 88 "
+           "box (thesis Section 6), Nose-Hoover T* = 0.7 tau = %g, dt = 0.005, unshifted energies, "
+           "detect every 2nd step" % tdamp, "equil_steps": equil, "sample_steps": sample,
+           "block_steps": chunk, "wall_s": time.perf_counter() - t0, "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,11 +446,15 @@ def main():
     ap.add_argument("--forces-only", type=int, default=0, metavar="K",
                     help="only create the system and run K force evaluations (counter passes)")
     ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
-                    help="256k slab: NVE drift and force error vs the oracle for both forms")
+                    help="256k slab: NVE drift of both forms, FP32 form force error vs the FP64 form")
     ap.add_argument("--droplet-study", type=int, default=0, metavar="STEPS",
                     help="droplet (non-planar interface) study of both forms over STEPS steps")
     ap.add_argument("--serve", type=int, default=0, metavar="SEEDS",
                     help="serving study: 64 systems, Poisson arrivals, server vs sequential")
+    ap.add_argument("--nvt-study", type=str, default="", metavar="EQUIL,SAMPLE[,CFG...]",
+                    help="Table 1 / Figure 37 observables of the thesis's 16,000-particle slab under "
+                         "NVT; optional CFG indices pick Table 1 rows (0-6)")
+    ap.add_argument("--save-dir", type=str, default="", help="--nvt-study: write the final states here")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -358,6 +475,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copied {src.numel() * 8} bytes")
+        return
+    if args.nvt_study:
+        vals = [int(v) for v in args.nvt_study.split(",")]
+        nvt_study(vals[0], vals[1], set(vals[2:]) or None, save_dir=args.save_dir or None)
         return
     if args.precision_study:
         precision_study(args.precision_study)

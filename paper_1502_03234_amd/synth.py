@@ -302,6 +302,11 @@ def named(name: str, temperature: float = 0.7) -> State:
         c = SLABS[name]
         n_liq = int(round(0.98 * c["n"]))
         return slab(n_liq, c["n"] - n_liq, c["box"], seed=c["seed"], temperature=temperature)
+    if name == "thesis16k":
+        # the thesis's test system (Section 6): 16,000 particles filling a 22 x 22 x 44 block
+        # centred in a 22 x 22 x 88 box; lattice sites stand in for its random placement
+        return slab(16_000, 0, (22.0, 22.0, 88.0), seed=1006, temperature=temperature,
+                    half_thickness=22.0)
     if name == "droplet1m":
         return droplet(1_000_000, 166.0, seed=1005, temperature=temperature)
     raise KeyError(name)
