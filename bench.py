@@ -433,6 +433,111 @@ def nvt_study(equil: int, sample: int, configs=None, chunk: int = 1000, tdamp: f
     print(json.dumps(out), flush=True)
 
 
+def accuracy_study(equil: int, R: float = 20.0, time_steps: int = 200):
+    """Force accuracy of the cutoff method (Section 6.1.1, Eq. 20; Figures 34-36 analogues) on
+    the thesis's 16,000-particle slab. The lattice start is equilibrated for `equil` NVT steps
+    (Nose-Hoover, T* = 0.7, static cutoff 5.0); on that one state, the exact forces are the
+    full Lennard-Jones image sum within R (dcm_exact_forces), and every (r_c^min, r_c^max,
+    cutoff shape) configuration of the grid below is evaluated on the same positions: interface
+    detection, cutoffs, Alg. 3.2 forces. Errors per configuration:
+      rel_rms = sqrt(sum_i |F_i - F_i^ex|^2 / sum_i |F_i^ex|^2)   (Eq. 20 with the vector
+                quotient read as a ratio of mean squares, well conditioned where F^ex ~ 0);
+      eq20_mag = sqrt(mean_i (|F_i - F_i^ex| / |F_i^ex|)^2)       (Eq. 20 per particle with
+                magnitudes; dominated by particles whose exact force is small);
+    and the mean signed error of F_z in 2-sigma slices about the slab's centre (Figure 35).
+    ms/step is timed over `time_steps` NVE steps from that state for each configuration, and for
+    each accuracy threshold the cheapest configuration meeting it is listed (Figure 36's
+    arrows), by pairs per particle and by step time."""
+    import numpy as np
+    import torch
+    from paper_1502_03234_amd import dcm, synth
+
+    st = synth.named("thesis16k")
+    Lz = st.box[2]
+    t0 = time.perf_counter()
+    p_eq = dcm.params(st.box, rc_min=5.0, rc_max=5.0, thermostat=dcm.DCM_NOSE_HOOVER,
+                      temperature=0.7, tdamp=0.5)
+    s = dcm.System(p_eq, st.x, st.v)
+    chunk = 10000
+    for k in range(0, equil, chunk):
+        s.step(min(chunk, equil - k), thermo=False)
+        torch.cuda.synchronize()
+        log(f"accuracy study: equilibrated {min(k + chunk, equil)}/{equil} steps")
+    s.check()
+    x, v, _, _ = s.state()
+    fex = s.exact_forces(R)
+    torch.cuda.synchronize()
+    s.close()
+    fex_h = fex.cpu().numpy()
+    xw = x.cpu().numpy()
+    th = 2 * np.pi * xw[2] / Lz
+    zc = math.atan2(np.sin(th).mean(), np.cos(th).mean()) * Lz / (2 * np.pi)
+    dz = np.mod(xw[2] - zc + Lz / 2, Lz) - Lz / 2
+    edges = np.arange(-Lz / 2, Lz / 2 + 1e-9, 2.0)
+    sl = np.clip(np.digitize(dz, edges) - 1, 0, len(edges) - 2)
+    nslab = np.bincount(sl, minlength=len(edges) - 1)
+    fex_rms = float(np.sqrt(np.mean(np.sum(fex_h ** 2, axis=0))))
+    log(f"accuracy study: exact forces (R = {R}), F_rms = {fex_rms:.4f}")
+
+    grid = []
+    for rmin in (2.5, 3.0, 3.5, 4.0, 4.5, 5.0, 6.0, 7.0):
+        for rmax in (3.0, 4.0, 5.0, 5.5, 6.0, 7.0, 8.0, 9.0, 10.0):
+            if rmax < rmin:
+                continue
+            shapes = (dcm.DCM_CUTOFF_EXP,) if rmin == rmax else (dcm.DCM_CUTOFF_EXP, dcm.DCM_CUTOFF_LINEAR)
+            for shape in shapes:
+                grid.append((rmin, rmax, shape))
+    rows = []
+    for rmin, rmax, shape in grid:
+        p = dcm.params(st.box, rc_min=rmin, rc_max=rmax, cutoff_shape=shape)
+        s = dcm.System(p, x, v)
+        fo = s.forces(per_atom=False, thermo=True)
+        f = fo["f"]
+        _, _, rc, _ = s.state()
+        torch.cuda.synchronize()
+        pairs = dcm.thermo_records(fo["thermo"])[0]["pairs"]
+        d = f.cpu().numpy() - fex_h
+        dn = np.linalg.norm(d, axis=0)
+        en = np.linalg.norm(fex_h, axis=0)
+        ok = en > 0
+        prof = np.bincount(sl, weights=d[2], minlength=len(edges) - 1) / np.maximum(nslab, 1)
+        s.step(10, thermo=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.step(time_steps, thermo=False)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3 / time_steps
+        s.check()
+        s.close()
+        name = ("static %.1f" % rmin) if rmin == rmax else \
+            "DCM %.1f/%.1f %s" % (rmin, rmax, "exp" if shape == dcm.DCM_CUTOFF_EXP else "linear")
+        rows.append({"config": name, "rc_min": rmin, "rc_max": rmax,
+                     "shape": "exp" if shape == dcm.DCM_CUTOFF_EXP else "linear",
+                     "rel_rms": float(np.sqrt(np.sum(dn ** 2) / np.sum(en ** 2))),
+                     "eq20_mag": float(np.sqrt(np.mean((dn[ok] / en[ok]) ** 2))),
+                     "max_abs": float(dn.max()), "mean_rc": float(rc.mean()),
+                     "pairs_per_particle": pairs / st.n,
+                     "ms_per_step": ms, "dFz_profile": [round(float(q), 6) for q in prof]})
+        log(f"accuracy study: {name}: rel_rms {rows[-1]['rel_rms']:.5f}, {ms:.3f} ms/step")
+    # cheapest configuration meeting each threshold, by pairs per particle (the work of
+    # Alg. 3.2, which sets the step time of large systems) and by the measured step time (a
+    # 16,000-particle step is mostly launch latency on one GPU)
+    best = []
+    for thr in (0.005, 0.003, 0.002, 0.0015, 0.00133, 0.001, 0.0007, 0.0005, 0.0003, 0.0002, 0.0001):
+        cand = [r for r in rows if r["shape"] == "exp" and r["rel_rms"] <= thr]
+        if cand:
+            b = min(cand, key=lambda r: r["pairs_per_particle"])
+            t = min(cand, key=lambda r: r["ms_per_step"])
+            best.append({"threshold": thr, "by_pairs": b["config"], "rel_rms": b["rel_rms"],
+                         "pairs_per_particle": b["pairs_per_particle"], "by_time": t["config"],
+                         "ms_per_step": t["ms_per_step"]})
+    out = {"study": "accuracy", "workload": "thesis 16,000-particle slab (22 x 22 x 44 block in 22 x 22 "
+           f"x 88), NVT-equilibrated {equil} steps at static r_c = 5.0, T* = 0.7", "R_exact": R,
+           "F_rms_exact": fex_rms, "slices_2sigma_from": float(edges[0]), "rows": rows,
+           "fastest_meeting_threshold": best, "wall_s": time.perf_counter() - t0}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -454,6 +559,9 @@ def main():
     ap.add_argument("--nvt-study", type=str, default="", metavar="EQUIL,SAMPLE[,CFG...]",
                     help="Table 1 / Figure 37 observables of the thesis's 16,000-particle slab under "
                          "NVT; optional CFG indices pick Table 1 rows (0-6)")
+    ap.add_argument("--accuracy-study", type=int, default=-1, metavar="EQUIL",
+                    help="force accuracy (Eq. 20) of a grid of cutoff configurations against the "
+                         "exact image sum, on the thesis slab after EQUIL NVT steps")
     ap.add_argument("--save-dir", type=str, default="", help="--nvt-study: write the final states here")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES (HBM counter calibration)")
@@ -475,6 +583,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copied {src.numel() * 8} bytes")
+        return
+    if args.accuracy_study >= 0:
+        accuracy_study(args.accuracy_study)
         return
     if args.nvt_study:
         vals = [int(v) for v in args.nvt_study.split(",")]

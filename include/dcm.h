@@ -173,6 +173,18 @@ dcm_status dcm_detect_interface(dcm_system *s, dcm_stream_t stream, const dcm_de
 dcm_status dcm_compute_forces(dcm_system *s, dcm_stream_t stream, double *d_f, double *d_e,
                               double *d_w, uint32_t *d_pairs, dcm_thermo *d_th);
 
+/* The exact forces of the accuracy measure of Section 6.1.1 (F^exact in Eq. 20): the full
+ * Lennard-Jones force and energy of Eq. 4, with no cutoff, summed over every particle j and
+ * every periodic image x_j + (a L_x, b L_y, c L_z) closer than R to particle i (the particle's
+ * own images included). R may exceed half the box; the lattice sum converges absolutely, so
+ * only its part beyond R is missing (of order rho R^-4 for a particle at a planar interface).
+ * Evaluated on the current positions; outputs in caller order, each optional (NULL):
+ * d_f [3][n], d_e [n] = 1/2 sum_j V(r_ij). Does not change the system's forces or cutoffs.
+ * Not part of the per-step path: one lane per particle visits every box within R.
+ * DCM_E_INVALID for s NULL, R <= 0 or not finite, or R so large that the kernel would visit
+ * more than 4e10 boxes (n (2 ceil(R/h_x) + 3)(2 ceil(R/h_y) + 3)(2 ceil(R/h_z) + 3)). */
+dcm_status dcm_exact_forces(dcm_system *s, double R, dcm_stream_t stream, double *d_f, double *d_e);
+
 /* Advance nsteps velocity-Verlet steps (Eq. 1-2): v += dt/(2m) F; x += dt v; wrap;
  * re-bin; re-detect the interface when k % detect_every == 0; forces (Alg. 3.2);
  * v += dt/(2m) F. Under DCM_NOSE_HOOVER each step starts and ends with half a thermostat

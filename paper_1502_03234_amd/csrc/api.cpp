@@ -19,6 +19,9 @@ using namespace dcm;
 
 namespace {
 
+// work guard of dcm_exact_forces (about a second of the image-sum kernel)
+constexpr double kMaxImageBoxVisits = 4e10;
+
 thread_local std::string g_last_error;
 
 dcm_status fail(dcm_status s, const char *fmt, ...)
@@ -460,6 +463,19 @@ dcm_status dcm_compute_forces(dcm_system *s, dcm_stream_t stream, double *d_f, d
                              kNhNone, s->nhc, st);
     }
     return hip_status("dcm_compute_forces");
+}
+
+dcm_status dcm_exact_forces(dcm_system *s, double R, dcm_stream_t stream, double *d_f, double *d_e)
+{
+    if (!s) return fail(DCM_E_INVALID, "system is NULL");
+    if (!(R > 0.0) || !std::isfinite(R)) return fail(DCM_E_INVALID, "R must be positive and finite");
+    if (image_box_visits(s->grid, s->n, R) > kMaxImageBoxVisits)
+        return fail(DCM_E_INVALID, "R = %g needs more than %.0e box visits for %lld particles", R,
+                    kMaxImageBoxVisits, (long long)s->n);
+    if (!d_f && !d_e) return DCM_OK;
+    launch_forces_images(s->grid, s->set[s->cur], s->gw.cell_start, s->n, R, s->p.epsilon, s->p.sigma, d_f,
+                         d_e, (hipStream_t)stream);
+    return hip_status("dcm_exact_forces");
 }
 
 dcm_status dcm_step(dcm_system *s, int32_t nsteps, dcm_stream_t stream, dcm_thermo *d_th)

@@ -139,6 +139,12 @@ struct ForceArgs {
 int force_blocks(int64_t n);
 void launch_forces(const ForceArgs &a, hipStream_t st);
 
+// exact.hip
+// Upper bound of the box visits of launch_forces_images (work guard).
+double image_box_visits(const Grid &g, int64_t n, double R);
+void launch_forces_images(const Grid &g, PSet s, const uint32_t *cell_start, int64_t n, double R,
+                          double epsilon, double sigma, double *f_out, double *e_out, hipStream_t st);
+
 // integrate.hip
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t st);
 void launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t st);

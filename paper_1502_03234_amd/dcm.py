@@ -79,6 +79,7 @@ _SIGS = {
     "dcm_detect_interface": ([_vp, _vp, C.POINTER(DetectOut)], _i32),
     "dcm_compute_forces": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "dcm_step": ([_vp, _i32, _vp, _vp], _i32),
+    "dcm_exact_forces": ([_vp, C.c_double, _vp, _vp, _vp], _i32),
     "dcm_get_thermostat": ([_vp, _vp, _vp], _i32),
     "dcm_set_thermostat": ([_vp, _vp, _vp], _i32),
     "dcm_get_state": ([_vp, _vp, _vp, _vp, _vp, C.POINTER(_i64)], _i32),
@@ -187,6 +188,10 @@ def dcm_detect_interface(h: int, stream=None, **outs):
 def dcm_compute_forces(h: int, stream=None, f=None, e=None, w=None, pairs=None, thermo=None):
     _check(_lib.dcm_compute_forces(h, _stream(stream), _ptr(f), _ptr(e), _ptr(w), _ptr(pairs),
                                    _ptr(thermo)))
+
+
+def dcm_exact_forces(h: int, R: float, stream=None, f=None, e=None):
+    _check(_lib.dcm_exact_forces(h, float(R), _stream(stream), _ptr(f), _ptr(e)))
 
 
 def dcm_step(h: int, nsteps: int, stream=None, thermo=None):
@@ -372,6 +377,13 @@ class System:
             o["thermo"] = self._t(THERMO_DOUBLES, torch.float64)
         dcm_compute_forces(self.h, self.stream, **o)
         return o
+
+    def exact_forces(self, R: float, energy=False):
+        """Eq. 20's reference: full LJ over every image within R (forces [3][n], energies [n])."""
+        f = self._t((3, self.n), torch.float64)
+        e = self._t(self.n, torch.float64) if energy else None
+        dcm_exact_forces(self.h, R, self.stream, f=f, e=e)
+        return (f, e) if energy else f
 
     def set_cutoffs(self, rc):
         dcm_set_cutoffs(self.h, torch.as_tensor(rc, dtype=torch.float64).to(self.device).contiguous(),
