@@ -338,7 +338,7 @@ TABLE1_ENERGY = {(3.0, 3.0): -4.415, (5.0, 5.0): -4.772, (7.0, 7.0): -4.830,
 
 
 def nvt_study(equil: int, sample: int, configs=None, chunk: int = 1000, tdamp: float = 0.5,
-              save_dir: str | None = None):
+              save_dir: str | None = None, detect_kw: dict | None = None):
     """Table 1 and Figure 37 observables. The thesis's geometry (16,000 particles in a 22 x 22 x
     44 block centred in 22 x 22 x 88), Nose-Hoover at T* = 0.7, dt = 0.005, unshifted pair
     energies, detection every 2nd step; one system per Table 1 cutoff configuration, all
@@ -362,7 +362,7 @@ def nvt_study(equil: int, sample: int, configs=None, chunk: int = 1000, tdamp: f
         if configs is not None and q not in configs:
             continue
         p = dcm.params(st.box, rc_min=rmin, rc_max=rmax, thermostat=dcm.DCM_NOSE_HOOVER,
-                       temperature=0.7, tdamp=tdamp)
+                       temperature=0.7, tdamp=tdamp, **(detect_kw or {}))
         stream = torch.cuda.Stream()
         s = dcm.System(p, st.x, st.v, stream=stream)
         systems.append(dict(name=("static %.1f" % rmax) if rmin == rmax else "DCM %.1f/%.1f" % (rmin, rmax),
@@ -429,11 +429,12 @@ def nvt_study(equil: int, sample: int, configs=None, chunk: int = 1000, tdamp: f
     out = {"study": "nvt_table1", "workload": "16,000 LJ particles, 22 x 22 x 44 block in a 22 x 22 x 88 "
            "box (thesis Section 6), Nose-Hoover T* = 0.7 tau = %g, dt = 0.005, unshifted energies, "
            "detect every 2nd step" % tdamp, "equil_steps": equil, "sample_steps": sample,
-           "block_steps": chunk, "wall_s": time.perf_counter() - t0, "rows": rows}
+           "block_steps": chunk, "detection": detect_kw or {}, "wall_s": time.perf_counter() - t0,
+           "rows": rows}
     print(json.dumps(out), flush=True)
 
 
-def accuracy_study(equil: int, R: float = 20.0, time_steps: int = 200):
+def accuracy_study(equil: int, R: float = 20.0, time_steps: int = 200, detect_kw: dict | None = None):
     """Force accuracy of the cutoff method (Section 6.1.1, Eq. 20; Figures 34-36 analogues) on
     the thesis's 16,000-particle slab. The lattice start is equilibrated for `equil` NVT steps
     (Nose-Hoover, T* = 0.7, static cutoff 5.0); on that one state, the exact forces are the
@@ -489,7 +490,12 @@ def accuracy_study(equil: int, R: float = 20.0, time_steps: int = 200):
                 grid.append((rmin, rmax, shape))
     rows = []
     for rmin, rmax, shape in grid:
-        p = dcm.params(st.box, rc_min=rmin, rc_max=rmax, cutoff_shape=shape)
+        try:
+            p = dcm.params(st.box, rc_min=rmin, rc_max=rmax, cutoff_shape=shape, **(detect_kw or {}))
+            dcm.dcm_workspace_bytes(p, st.n)
+        except dcm.DcmError as exc:       # e.g. a stencil wider than the box at coarse bins
+            log(f"accuracy study: skipping {rmin}/{rmax}: {exc}")
+            continue
         s = dcm.System(p, x, v)
         fo = s.forces(per_atom=False, thermo=True)
         f = fo["f"]
@@ -534,8 +540,14 @@ def accuracy_study(equil: int, R: float = 20.0, time_steps: int = 200):
     out = {"study": "accuracy", "workload": "thesis 16,000-particle slab (22 x 22 x 44 block in 22 x 22 "
            f"x 88), NVT-equilibrated {equil} steps at static r_c = 5.0, T* = 0.7", "R_exact": R,
            "F_rms_exact": fex_rms, "slices_2sigma_from": float(edges[0]), "rows": rows,
-           "fastest_meeting_threshold": best, "wall_s": time.perf_counter() - t0}
+           "fastest_meeting_threshold": best, "detection": detect_kw or {},
+           "wall_s": time.perf_counter() - t0}
     print(json.dumps(out), flush=True)
+
+
+def _detect_kw(args) -> dict:
+    return dict(bin=args.study_bin, smooth_passes=args.study_smooth,
+                min_component=args.study_min_component)
 
 
 def main():
@@ -562,6 +574,11 @@ def main():
     ap.add_argument("--accuracy-study", type=int, default=-1, metavar="EQUIL",
                     help="force accuracy (Eq. 20) of a grid of cutoff configurations against the "
                          "exact image sum, on the thesis slab after EQUIL NVT steps")
+    ap.add_argument("--study-bin", type=float, default=1.0,
+                    help="--nvt-study / --accuracy-study: density box edge (the thesis uses ~2.6)")
+    ap.add_argument("--study-smooth", type=int, default=1, help="studies: smoothing passes")
+    ap.add_argument("--study-min-component", type=int, default=27,
+                    help="studies: components below this many boxes are removed")
     ap.add_argument("--save-dir", type=str, default="", help="--nvt-study: write the final states here")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES (HBM counter calibration)")
@@ -585,11 +602,12 @@ def main():
         log(f"copied {src.numel() * 8} bytes")
         return
     if args.accuracy_study >= 0:
-        accuracy_study(args.accuracy_study)
+        accuracy_study(args.accuracy_study, detect_kw=_detect_kw(args))
         return
     if args.nvt_study:
         vals = [int(v) for v in args.nvt_study.split(",")]
-        nvt_study(vals[0], vals[1], set(vals[2:]) or None, save_dir=args.save_dir or None)
+        nvt_study(vals[0], vals[1], set(vals[2:]) or None, save_dir=args.save_dir or None,
+                  detect_kw=_detect_kw(args))
         return
     if args.precision_study:
         precision_study(args.precision_study)
