@@ -14,6 +14,17 @@
 #include <vector>
 
 #include "internal.h"
+#include "launch.h"
+
+namespace dcm {
+
+Recorder *&current_recorder()
+{
+    static thread_local Recorder *r = nullptr;
+    return r;
+}
+
+}  // namespace dcm
 
 using namespace dcm;
 

@@ -13,6 +13,7 @@
 //                    sweep changes nothing
 //   cutoffs          Alg. 3.1 trilinear interpolation of box-centre distances, then Eq. 7-8
 #include "internal.h"
+#include "launch.h"
 
 namespace dcm {
 
@@ -34,10 +35,26 @@ __device__ __forceinline__ void coords(const Grid &g, int64_t c, int64_t &i, int
 }
 
 // ---- smoothing ------------------------------------------------------------------------
-__global__ void k_smooth_axis(Grid g, const uint32_t *in, const uint32_t *cell_start, uint32_t *out,
-                              int axis)
+struct KSmoothAxis {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        Grid g;
+        const uint32_t *in;
+        const uint32_t *cell_start;
+        uint32_t *out;
+        int axis;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
+};
+
+__device__ void KSmoothAxis::run(const Args &args_, uint32_t blk, uint32_t)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    Grid g = args_.g;
+    const uint32_t *in = args_.in;
+    const uint32_t *cell_start = args_.cell_start;
+    uint32_t *out = args_.out;
+    int axis = args_.axis;
+    int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
     if (c >= g.G) return;
     int64_t i, j, k;
     coords(g, c, i, j, k);
@@ -62,9 +79,22 @@ __global__ void k_smooth_axis(Grid g, const uint32_t *in, const uint32_t *cell_s
     out[c] = a + 2u * b + d;
 }
 
-__global__ void k_count_from_ranges(Grid g, const uint32_t *cell_start, uint32_t *out)
+struct KCountFromRanges {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        Grid g;
+        const uint32_t *cell_start;
+        uint32_t *out;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
+};
+
+__device__ void KCountFromRanges::run(const Args &args_, uint32_t blk, uint32_t)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    Grid g = args_.g;
+    const uint32_t *cell_start = args_.cell_start;
+    uint32_t *out = args_.out;
+    int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
     if (c >= g.G) return;
     int64_t i, j, k;
     coords(g, c, i, j, k);
@@ -75,14 +105,28 @@ __global__ void k_count_from_ranges(Grid g, const uint32_t *cell_start, uint32_t
 // ---- histogram and two-means ----------------------------------------------------------
 constexpr int kLdsBins = 8192;
 
-__global__ void __launch_bounds__(kBlock) k_hist(const uint32_t *img, int64_t G, uint32_t *hist,
-                                                 uint32_t *flags)
+struct KHist {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        const uint32_t *img;
+        int64_t G;
+        uint32_t *hist;
+        uint32_t *flags;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
+};
+
+__device__ void KHist::run(const Args &args_, uint32_t blk, uint32_t nblk)
 {
+    const uint32_t *img = args_.img;
+    int64_t G = args_.G;
+    uint32_t *hist = args_.hist;
+    uint32_t *flags = args_.flags;
     __shared__ uint32_t lh[kLdsBins];
     for (int b = threadIdx.x; b < kLdsBins; b += kBlock) lh[b] = 0;
     __syncthreads();
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < G;
-         c += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t c = (int64_t)blk * blockDim.x + threadIdx.x; c < G;
+         c += (int64_t)nblk * blockDim.x) {
         uint32_t v = img[c];
         if (v < (uint32_t)kLdsBins) atomicAdd(&lh[v], 1u);
         else if (v < (uint32_t)kHistBins) atomicAdd(&hist[v], 1u);
@@ -100,9 +144,21 @@ constexpr int kTmThreads = 1024;
 // are exact integers, so their order does not matter.
 constexpr int kTmLds = 16384;
 
-__global__ void __launch_bounds__(kTmThreads) k_two_means(const uint32_t *hist, double *km,
-                                                          long long *stats_iter)
+struct KTwoMeans {
+    static constexpr int kThreads = kTmThreads, kWaves = 0;
+    struct Args {
+        const uint32_t *hist;
+        double *km;
+        long long *stats_iter;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
+};
+
+__device__ void KTwoMeans::run(const Args &args_, uint32_t, uint32_t)
 {
+    const uint32_t *hist = args_.hist;
+    double *km = args_.km;
+    long long *stats_iter = args_.stats_iter;
     __shared__ int lmn[16], lmx[16];
     __shared__ uint32_t lh[kTmLds];
     const int tid = threadIdx.x, w = tid >> 6;
@@ -159,9 +215,26 @@ __global__ void __launch_bounds__(kTmThreads) k_two_means(const uint32_t *hist, 
 }
 
 // ---- labels and components ------------------------------------------------------------
-__global__ void k_threshold(const uint32_t *img, const double *km, int64_t G, uint8_t *raw, uint8_t *label)
+struct KThreshold {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        const uint32_t *img;
+        const double *km;
+        int64_t G;
+        uint8_t *raw;
+        uint8_t *label;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
+};
+
+__device__ void KThreshold::run(const Args &args_, uint32_t blk, uint32_t)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t *img = args_.img;
+    const double *km = args_.km;
+    int64_t G = args_.G;
+    uint8_t *raw = args_.raw;
+    uint8_t *label = args_.label;
+    int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
     if (c >= G) return;
     uint8_t s = ((double)img[c] > km[2]) ? 0 : 1;
     raw[c] = s;
@@ -240,13 +313,31 @@ __device__ __forceinline__ void lunite(uint32_t *lp, uint32_t a, uint32_t b)
     }
 }
 
-__global__ void __launch_bounds__(kCtBoxes) k_cc_local(Grid g, const uint8_t *label, uint8_t phase,
-                                                      uint32_t *parent, uint32_t *csize, uint32_t *psize)
+struct KCcLocal {
+    static constexpr int kThreads = kCtBoxes, kWaves = 0;
+    struct Args {
+        Grid g;
+        const uint8_t *label;
+        uint8_t phase;
+        uint32_t *parent;
+        uint32_t *csize;
+        uint32_t *psize;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
+};
+
+__device__ void KCcLocal::run(const Args &args_, uint32_t blk, uint32_t)
 {
+    Grid g = args_.g;
+    const uint8_t *label = args_.label;
+    uint8_t phase = args_.phase;
+    uint32_t *parent = args_.parent;
+    uint32_t *csize = args_.csize;
+    uint32_t *psize = args_.psize;
     __shared__ uint32_t lp[kCtBoxes];
     __shared__ uint32_t lc[kCtBoxes];
     const int ntx = (g.n[0] + CT - 1) / CT, nty = (g.n[1] + CT - 1) / CT;
-    const int b = blockIdx.x;
+    const int b = blk;
     const int x0 = (b % ntx) * CT, y0 = ((b / ntx) % nty) * CT, z0 = (b / (ntx * nty)) * CT;
     const int l = threadIdx.x;
     const int lx = l % CT, ly = (l / CT) % CT, lz = l / (CT * CT);
@@ -302,10 +393,28 @@ __global__ void __launch_bounds__(kCtBoxes) k_cc_local(Grid g, const uint8_t *la
 // large.
 constexpr uint32_t kTouched = 0xffffffffu;
 
-__global__ void k_cc_merge(Grid g, const uint8_t *label, uint8_t phase, uint32_t *parent,
-                           uint32_t *psize, uint32_t limit)
+struct KCcMerge {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        Grid g;
+        const uint8_t *label;
+        uint8_t phase;
+        uint32_t *parent;
+        uint32_t *psize;
+        uint32_t limit;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
+};
+
+__device__ void KCcMerge::run(const Args &args_, uint32_t blk, uint32_t)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    Grid g = args_.g;
+    const uint8_t *label = args_.label;
+    uint8_t phase = args_.phase;
+    uint32_t *parent = args_.parent;
+    uint32_t *psize = args_.psize;
+    uint32_t limit = args_.limit;
+    int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
     if (c >= g.G || label[c] != phase) return;
     int64_t i, j, k;
     coords(g, c, i, j, k);
@@ -329,9 +438,20 @@ __global__ void k_cc_merge(Grid g, const uint8_t *label, uint8_t phase, uint32_t
     }
 }
 
-__global__ void k_cc_flatten(int64_t G, uint32_t *parent)
+struct KCcFlatten {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        int64_t G;
+        uint32_t *parent;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
+};
+
+__device__ void KCcFlatten::run(const Args &args_, uint32_t blk, uint32_t)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t G = args_.G;
+    uint32_t *parent = args_.parent;
+    int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
     if (c >= G) return;
     uint32_t p = parent[c];
     if (p == kInvalid) return;
@@ -342,10 +462,26 @@ __global__ void k_cc_flatten(int64_t G, uint32_t *parent)
 // of small pieces count one each; a tagged box of a large piece (which joined a small one)
 // lifts its tree to `limit`. Trees made of large pieces only hold no small box and are never
 // looked at.
-__global__ void k_cc_size(int64_t G, const uint32_t *parent, const uint32_t *psize, uint32_t *csize,
-                          uint32_t limit)
+struct KCcSize {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        int64_t G;
+        const uint32_t *parent;
+        const uint32_t *psize;
+        uint32_t *csize;
+        uint32_t limit;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
+};
+
+__device__ void KCcSize::run(const Args &args_, uint32_t blk, uint32_t)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t G = args_.G;
+    const uint32_t *parent = args_.parent;
+    const uint32_t *psize = args_.psize;
+    uint32_t *csize = args_.csize;
+    uint32_t limit = args_.limit;
+    int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
     uint32_t r = c < G ? parent[c] : kInvalid;
     const uint32_t ps = r != kInvalid ? psize[c] : 0u;
     const bool small = r != kInvalid && ps < limit;
@@ -372,11 +508,34 @@ __global__ void k_cc_size(int64_t G, const uint32_t *parent, const uint32_t *psi
 }
 
 // Boxes of small components change phase; boxes of large pieces belong to large components.
-__global__ void k_cc_flip(int64_t G, uint8_t *label, uint8_t phase, const uint32_t *parent,
-                          const uint32_t *psize, const uint32_t *csize, uint32_t limit, long long *stats,
-                          int slot)
+struct KCcFlip {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        int64_t G;
+        uint8_t *label;
+        uint8_t phase;
+        const uint32_t *parent;
+        const uint32_t *psize;
+        const uint32_t *csize;
+        uint32_t limit;
+        long long *stats;
+        int slot;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
+};
+
+__device__ void KCcFlip::run(const Args &args_, uint32_t blk, uint32_t)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t G = args_.G;
+    uint8_t *label = args_.label;
+    uint8_t phase = args_.phase;
+    const uint32_t *parent = args_.parent;
+    const uint32_t *psize = args_.psize;
+    const uint32_t *csize = args_.csize;
+    uint32_t limit = args_.limit;
+    long long *stats = args_.stats;
+    int slot = args_.slot;
+    int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
     bool flip = false, root = false;
     if (c < G && label[c] == phase && psize[c] < limit) {
         uint32_t r = parent[c];
@@ -458,9 +617,24 @@ __device__ __forceinline__ int tile_of(const Grid &g, int64_t x, int64_t y, int6
 
 // Initial distances (0 on vapor boxes, infinity elsewhere); the tiles holding a liquid box next
 // to a vapor box are the only ones the first pass can change, and they start dirty.
-__global__ void k_dist_init(Grid g, const uint8_t *label, double *dist, uint32_t *dirty)
+struct KDistInit {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        Grid g;
+        const uint8_t *label;
+        double *dist;
+        uint32_t *dirty;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
+};
+
+__device__ void KDistInit::run(const Args &args_, uint32_t blk, uint32_t)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    Grid g = args_.g;
+    const uint8_t *label = args_.label;
+    double *dist = args_.dist;
+    uint32_t *dirty = args_.dirty;
+    int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
     if (c >= g.G) return;
     const bool vap = label[c] == 1;
     dist[c] = vap ? 0.0 : INFINITY;
@@ -476,12 +650,35 @@ __global__ void k_dist_init(Grid g, const uint8_t *label, double *dist, uint32_t
     if (front) dirty[tile_of(g, i, j, k)] = 1u;
 }
 
-__global__ void __launch_bounds__(kTileThreads) k_dist_tiles(Grid g, const uint8_t *label, double *d0,
-                                                             double *d1, double cap, uint32_t *changed,
-                                                             uint32_t *dirty, uint32_t *cur, int it)
+struct KDistTiles {
+    static constexpr int kThreads = kTileThreads, kWaves = 0;
+    struct Args {
+        Grid g;
+        const uint8_t *label;
+        double *d0;
+        double *d1;
+        double cap;
+        uint32_t *changed;
+        uint32_t *dirty;
+        uint32_t *cur;
+        int it;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
+};
+
+__device__ void KDistTiles::run(const Args &args_, uint32_t blk, uint32_t nblk)
 {
-    const int b = blockIdx.x;
-    const int ntiles = gridDim.x;
+    Grid g = args_.g;
+    const uint8_t *label = args_.label;
+    double *d0 = args_.d0;
+    double *d1 = args_.d1;
+    double cap = args_.cap;
+    uint32_t *changed = args_.changed;
+    uint32_t *dirty = args_.dirty;
+    uint32_t *cur = args_.cur;
+    int it = args_.it;
+    const int b = blk;
+    const int ntiles = nblk;
     uint32_t *dflag = dirty + (it & 1) * ntiles, *dnext = dirty + ((it + 1) & 1) * ntiles;
     const uint32_t *cprev = cur + (it & 1) * ntiles;
     uint32_t *cnext = cur + ((it + 1) & 1) * ntiles;
@@ -613,9 +810,24 @@ __global__ void __launch_bounds__(kTileThreads) k_dist_tiles(Grid g, const uint8
 }
 
 // Final values into d0: boxes whose tile ended with the second copy current are copied.
-__global__ void k_dist_gather(Grid g, double *d0, const double *d1, const uint32_t *cur_final)
+struct KDistGather {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        Grid g;
+        double *d0;
+        const double *d1;
+        const uint32_t *cur_final;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
+};
+
+__device__ void KDistGather::run(const Args &args_, uint32_t blk, uint32_t)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    Grid g = args_.g;
+    double *d0 = args_.d0;
+    const double *d1 = args_.d1;
+    const uint32_t *cur_final = args_.cur_final;
+    int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
     if (c >= g.G) return;
     int64_t i, j, k;
     coords(g, c, i, j, k);
@@ -624,9 +836,24 @@ __global__ void k_dist_gather(Grid g, double *d0, const double *d1, const uint32
     if (cur_final[owner]) d0[c] = d1[c];
 }
 
-__global__ void k_dist_finish(const uint32_t *changed, int max_sweeps, long long *sweeps, uint32_t *flags)
+struct KDistFinish {
+    static constexpr int kThreads = 64, kWaves = 0;
+    struct Args {
+        const uint32_t *changed;
+        int max_sweeps;
+        long long *sweeps;
+        uint32_t *flags;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
+};
+
+__device__ void KDistFinish::run(const Args &args_, uint32_t blk, uint32_t)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint32_t *changed = args_.changed;
+    int max_sweeps = args_.max_sweeps;
+    long long *sweeps = args_.sweeps;
+    uint32_t *flags = args_.flags;
+    if (threadIdx.x != 0 || blk != 0) return;
     int used = max_sweeps;
     for (int s = 0; s < max_sweeps; ++s)
         if (changed[s] == 0) { used = s + 1; break; }
@@ -634,19 +861,62 @@ __global__ void k_dist_finish(const uint32_t *changed, int max_sweeps, long long
     if (changed[max_sweeps - 1] != 0) atomicOr(flags, kFlagNotConverged);
 }
 
-__global__ void k_cap_copy(const double *dist, double cap, double *out, int64_t G)
+struct KCapCopy {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        const double *dist;
+        double cap;
+        double *out;
+        int64_t G;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
+};
+
+__device__ void KCapCopy::run(const Args &args_, uint32_t blk, uint32_t)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double *dist = args_.dist;
+    double cap = args_.cap;
+    double *out = args_.out;
+    int64_t G = args_.G;
+    int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
     if (c < G) out[c] = fmin(dist[c], cap);
 }
 
 // ---- per-particle distance and cutoff -------------------------------------------------
 __device__ __forceinline__ double lerp(double a, double b, double t) { return a + t * (b - a); }
 
-__global__ void k_cutoffs(Grid g, PSet s, int64_t n, const double *dist, double cap, double rc_min,
-                          double rc_max, double alpha, double a, double b, int linear)
+struct KCutoffs {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        Grid g;
+        PSet s;
+        int64_t n;
+        const double *dist;
+        double cap;
+        double rc_min;
+        double rc_max;
+        double alpha;
+        double a;
+        double b;
+        int linear;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
+};
+
+__device__ void KCutoffs::run(const Args &args_, uint32_t blk, uint32_t)
 {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    Grid g = args_.g;
+    PSet s = args_.s;
+    int64_t n = args_.n;
+    const double *dist = args_.dist;
+    double cap = args_.cap;
+    double rc_min = args_.rc_min;
+    double rc_max = args_.rc_max;
+    double alpha = args_.alpha;
+    double a = args_.a;
+    double b = args_.b;
+    int linear = args_.linear;
+    int64_t p = (int64_t)blk * blockDim.x + threadIdx.x;
     if (p >= n) return;
     double4 q = s.pos[p];
     double x[3] = {q.x, q.y, q.z};
@@ -684,7 +954,7 @@ __global__ void k_cutoffs(Grid g, PSet s, int64_t n, const double *dist, double 
 
 void launch_count_from_ranges(const Grid &g, const uint32_t *cell_start, uint32_t *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_count_from_ranges, dim3(grid1(g.G)), dim3(kBlock), 0, st, g, cell_start, out);
+    emit<KCountFromRanges>({g, cell_start, out}, grid1(g.G), st);
 }
 
 // `passes` rounds of x, y, z [1,2,1] passes; the first reads counts from cell ranges when
@@ -702,7 +972,7 @@ void launch_smooth(const Grid &g, int passes, const uint32_t *cell_start, const 
     const uint32_t *cs = cell_start;
     for (int s = 0; s < total; ++s) {
         uint32_t *dst = ((total - 1 - s) % 2 == 0) ? out : tmp;
-        hipLaunchKernelGGL(k_smooth_axis, dim3(grid1(g.G)), dim3(kBlock), 0, st, g, src, cs, dst, s % 3);
+        emit<KSmoothAxis>({g, src, cs, dst, s % 3}, grid1(g.G), st);
         src = dst;
         cs = nullptr;
     }
@@ -713,28 +983,25 @@ void launch_two_means(const Grid &g, const uint32_t *img, GridWork w, long long 
 {
     launch_fill_u32(w.hist, 0u, kHistBins, st);
     unsigned nb = (unsigned)std::min<int64_t>((g.G + kBlock - 1) / kBlock, 1024);
-    hipLaunchKernelGGL(k_hist, dim3(nb), dim3(kBlock), 0, st, img, g.G, w.hist, w.flags);
-    hipLaunchKernelGGL(k_two_means, dim3(1), dim3(kTmThreads), 0, st, w.hist, w.km, stats_out);
+    emit<KHist>({img, g.G, w.hist, w.flags}, nb, st);
+    emit<KTwoMeans>({w.hist, w.km, stats_out}, 1, st);
 }
 
 void launch_segment(const Grid &g, const uint32_t *img, const double *km, int32_t min_component,
                     GridWork w, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_threshold, dim3(grid1(g.G)), dim3(kBlock), 0, st, img, km, g.G, w.raw, w.label);
+    emit<KThreshold>({img, km, g.G, w.raw, w.label}, grid1(g.G), st);
     if (min_component <= 1) return;                 // no component can be smaller
     for (int pass = 0; pass < 2; ++pass) {
         uint8_t phase = pass == 0 ? 1 : 0;
         unsigned nct = (unsigned)(((g.n[0] + CT - 1) / CT) * ((g.n[1] + CT - 1) / CT) * ((g.n[2] + CT - 1) / CT));
-        hipLaunchKernelGGL(k_cc_local, dim3(nct), dim3(kCtBoxes), 0, st, g, w.label, phase, w.parent, w.csize,
-                           w.gtmp);
-        hipLaunchKernelGGL(k_cc_merge, dim3(grid1(g.G)), dim3(kBlock), 0, st, g, w.label, phase, w.parent,
-                           w.gtmp, (uint32_t)min_component);
-        hipLaunchKernelGGL(k_cc_flatten, dim3(grid1(g.G)), dim3(kBlock), 0, st, g.G, w.parent);
-        hipLaunchKernelGGL(k_cc_size, dim3(grid1(g.G)), dim3(kBlock), 0, st, g.G, w.parent,
-                           (const uint32_t *)w.gtmp, w.csize, (uint32_t)min_component);
-        hipLaunchKernelGGL(k_cc_flip, dim3(grid1(g.G)), dim3(kBlock), 0, st, g.G, w.label, phase,
-                           w.parent, (const uint32_t *)w.gtmp, w.csize, (uint32_t)min_component, w.stats,
-                           1 + pass);
+        emit<KCcLocal>({g, w.label, phase, w.parent, w.csize, w.gtmp}, nct, st);
+        emit<KCcMerge>({g, w.label, phase, w.parent, w.gtmp, (uint32_t)min_component}, grid1(g.G), st);
+        emit<KCcFlatten>({g.G, w.parent}, grid1(g.G), st);
+        emit<KCcSize>({g.G, w.parent, (const uint32_t *)w.gtmp, w.csize, (uint32_t)min_component},
+                       grid1(g.G), st);
+        emit<KCcFlip>({g.G, w.label, phase, w.parent, (const uint32_t *)w.gtmp, w.csize,
+                       (uint32_t)min_component, w.stats, 1 + pass}, grid1(g.G), st);
     }
 }
 
@@ -758,26 +1025,24 @@ void launch_distance(const Grid &g, double cap, const uint8_t *label, double *di
     launch_fill_u32(w.changed, 0u, ms + 1, st);
     const unsigned ntiles = (unsigned)distance_tiles(g);
     launch_fill_u32(w.tdirty, 0u, 2 * (int64_t)ntiles, st);
-    hipLaunchKernelGGL(k_dist_init, dim3(grid1(g.G)), dim3(kBlock), 0, st, g, label, dist, w.tdirty);
+    emit<KDistInit>({g, label, dist, w.tdirty}, grid1(g.G), st);
     launch_fill_u32(w.tcur, 0u, 2 * (int64_t)ntiles, st);
     for (int it = 0; it < ms; ++it)
-        hipLaunchKernelGGL(k_dist_tiles, dim3(ntiles), dim3(kTileThreads), 0, st, g, label, dist, w.dist2, cap,
-                           w.changed, w.tdirty, w.tcur, it);
-    hipLaunchKernelGGL(k_dist_gather, dim3(grid1(g.G)), dim3(kBlock), 0, st, g, dist, (const double *)w.dist2,
-                       (const uint32_t *)(w.tcur + (ms & 1) * ntiles));
-    hipLaunchKernelGGL(k_dist_finish, dim3(1), dim3(64), 0, st, w.changed, ms, w.stats + 5, w.flags);
+        emit<KDistTiles>({g, label, dist, w.dist2, cap, w.changed, w.tdirty, w.tcur, it}, ntiles, st);
+    emit<KDistGather>({g, dist, (const double *)w.dist2, (const uint32_t *)(w.tcur + (ms & 1) * ntiles)},
+                   grid1(g.G), st);
+    emit<KDistFinish>({w.changed, ms, w.stats + 5, w.flags}, 1, st);
 }
 
 void launch_cap_copy(const double *dist, double cap, double *out, int64_t G, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cap_copy, dim3(grid1(G)), dim3(kBlock), 0, st, dist, cap, out, G);
+    emit<KCapCopy>({dist, cap, out, G}, grid1(G), st);
 }
 
 void launch_cutoffs(const Grid &g, PSet s, int64_t n, const double *dist, double cap, double rc_min,
                     double rc_max, double alpha, double a, double b, int linear, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cutoffs, dim3(grid1(n)), dim3(kBlock), 0, st, g, s, n, dist, cap, rc_min,
-                       rc_max, alpha, a, b, linear);
+    emit<KCutoffs>({g, s, n, dist, cap, rc_min, rc_max, alpha, a, b, linear}, grid1(n), st);
 }
 
 }  // namespace dcm

@@ -8,6 +8,7 @@
 // per-step path: one lane per particle walks every box whose nearest point lies within R,
 // image shift included, in the cell-sorted storage.
 #include "internal.h"
+#include "launch.h"
 
 namespace dcm {
 
@@ -38,13 +39,42 @@ __device__ __forceinline__ double gap(int32_t o, double h)
     return a > 1 ? (double)(a - 1) * h : 0.0;
 }
 
-__global__ void __launch_bounds__(kBlock) k_forces_images(Grid g, PSet s, const uint32_t *cell_start,
-                                                          int64_t n, double R, double eps4,
-                                                          double eps24, double sig2, int32_t mx,
-                                                          int32_t my, int32_t mz, double *f_out,
-                                                          double *e_out)
+struct KForcesImages {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        Grid g;
+        PSet s;
+        const uint32_t *cell_start;
+        int64_t n;
+        double R;
+        double eps4;
+        double eps24;
+        double sig2;
+        int32_t mx;
+        int32_t my;
+        int32_t mz;
+        double *f_out;
+        double *e_out;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
+};
+
+__device__ void KForcesImages::run(const Args &args_, uint32_t blk, uint32_t)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    Grid g = args_.g;
+    PSet s = args_.s;
+    const uint32_t *cell_start = args_.cell_start;
+    int64_t n = args_.n;
+    double R = args_.R;
+    double eps4 = args_.eps4;
+    double eps24 = args_.eps24;
+    double sig2 = args_.sig2;
+    int32_t mx = args_.mx;
+    int32_t my = args_.my;
+    int32_t mz = args_.mz;
+    double *f_out = args_.f_out;
+    double *e_out = args_.e_out;
+    const int64_t p = (int64_t)blk * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const double4 q = s.pos[p];
     const int32_t a = box_of(q.x, g.h[0], g.n[0]);
@@ -114,9 +144,9 @@ double image_box_visits(const Grid &g, int64_t n, double R)
 void launch_forces_images(const Grid &g, PSet s, const uint32_t *cell_start, int64_t n, double R,
                           double epsilon, double sigma, double *f_out, double *e_out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_forces_images, dim3(grid1(n)), dim3(kBlock), 0, st, g, s, cell_start, n, R,
-                       4.0 * epsilon, 24.0 * epsilon, sigma * sigma, image_reach(R, g.h[0]),
-                       image_reach(R, g.h[1]), image_reach(R, g.h[2]), f_out, e_out);
+    emit<KForcesImages>({g, s, cell_start, n, R, 4.0 * epsilon, 24.0 * epsilon, sigma * sigma,
+                   image_reach(R, g.h[0]), image_reach(R, g.h[1]), image_reach(R, g.h[2]), f_out, e_out},
+                   grid1(n), st);
 }
 
 }  // namespace dcm

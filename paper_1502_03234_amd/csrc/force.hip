@@ -25,6 +25,7 @@
 #include <climits>
 
 #include "internal.h"
+#include "launch.h"
 
 namespace dcm {
 
@@ -302,13 +303,25 @@ __device__ __forceinline__ void traverse(const ForceArgs &a, bool live, const Pa
     }
 }
 
+// Compiled for 4 waves per SIMD (128 VGPRs per lane).
 template <int PAIR, bool SHIFT, int U, int PREC>
-__global__ void __launch_bounds__(kForceBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
-k_forces(ForceArgs a, double rc_max)
+struct KForces {
+    static constexpr int kThreads = kForceBlock, kWaves = 4;
+    struct Args {
+        ForceArgs a;
+        double rc_max;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t);
+};
+
+template <int PAIR, bool SHIFT, int U, int PREC>
+__device__ void KForces<PAIR, SHIFT, U, PREC>::run(const Args &args_, uint32_t blk, uint32_t)
 {
+    const ForceArgs &a = args_.a;
+    const double rc_max = args_.rc_max;
     // hardware (round-robin over XCDs) block order: the cost per particle varies strongly
     // with z through the cutoffs, and interleaving keeps every XCD's share of it even
-    const int64_t b = blockIdx.x;
+    const int64_t b = blk;
     const int64_t i = b * kForceBlock + threadIdx.x;
     const bool have = i < a.n;
     Particle q;
@@ -408,13 +421,13 @@ template <int PREC>
 static void launch_prec(const ForceArgs &a, int nb, hipStream_t st)
 {
     constexpr int U = 4;
-    const double rc_max = a.rc_max;
+    const uint32_t blocks = (uint32_t)nb;
     if (a.pair_rule == DCM_PAIR_MAX) {
-        if (a.energy_shift) hipLaunchKernelGGL((k_forces<DCM_PAIR_MAX, true, U, PREC>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
-        else hipLaunchKernelGGL((k_forces<DCM_PAIR_MAX, false, U, PREC>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
+        if (a.energy_shift) emit<KForces<DCM_PAIR_MAX, true, U, PREC>>({a, a.rc_max}, blocks, st);
+        else emit<KForces<DCM_PAIR_MAX, false, U, PREC>>({a, a.rc_max}, blocks, st);
     } else {
-        if (a.energy_shift) hipLaunchKernelGGL((k_forces<DCM_PAIR_I, true, U, PREC>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
-        else hipLaunchKernelGGL((k_forces<DCM_PAIR_I, false, U, PREC>), dim3(nb), dim3(kForceBlock), 0, st, a, rc_max);
+        if (a.energy_shift) emit<KForces<DCM_PAIR_I, true, U, PREC>>({a, a.rc_max}, blocks, st);
+        else emit<KForces<DCM_PAIR_I, false, U, PREC>>({a, a.rc_max}, blocks, st);
     }
 }
 

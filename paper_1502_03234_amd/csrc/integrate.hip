@@ -13,6 +13,7 @@
 // advances them, and the streaming kernels read the velocity scale from device memory, so a
 // thermostatted step needs no host round trip either.
 #include "internal.h"
+#include "launch.h"
 
 namespace dcm {
 
@@ -48,30 +49,56 @@ __device__ double block_sum(double v)
     return s;
 }
 
-__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t count)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = v;
-}
-
-__global__ void k_copy_bytes(uint8_t *dst, const uint8_t *src, size_t bytes)
-{
-    size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 16;
-    if (i + 16 <= bytes && (((uintptr_t)dst | (uintptr_t)src) & 15) == 0) {
-        *(uint4 *)(dst + i) = *(const uint4 *)(src + i);
-    } else {
-        for (size_t q = i; q < i + 16 && q < bytes; ++q) dst[q] = src[q];
+struct KFillU32 {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args { uint32_t *p; uint32_t v; int64_t count; };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t)
+    {
+        int64_t i = (int64_t)blk * kThreads + threadIdx.x;
+        if (i < a.count) a.p[i] = a.v;
     }
-}
+};
 
-__global__ void __launch_bounds__(kBlock) k_kick_drift_key(Grid g, PSet s, const double *fx,
-                                                           const double *fy, const double *fz,
-                                                           int64_t n, double hdt, double dt,
-                                                           int second_kick, const double *scale,
-                                                           uint32_t *key, uint32_t *val,
-                                                           Partial *ke_partials)
+struct KCopyBytes {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args { uint8_t *dst; const uint8_t *src; size_t bytes; };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t)
+    {
+        size_t i = ((size_t)blk * kThreads + threadIdx.x) * 16;
+        if (i + 16 <= a.bytes && (((uintptr_t)a.dst | (uintptr_t)a.src) & 15) == 0) {
+            *(uint4 *)(a.dst + i) = *(const uint4 *)(a.src + i);
+        } else {
+            for (size_t q = i; q < i + 16 && q < a.bytes; ++q) a.dst[q] = a.src[q];
+        }
+    }
+};
+
+struct KKickDriftKey {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        Grid g;
+        PSet s;
+        const double *fx, *fy, *fz;
+        int64_t n;
+        double hdt, dt;
+        int second_kick;
+        const double *scale;
+        uint32_t *key, *val;
+        Partial *ke_partials;
+    };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t);
+};
+
+__device__ void KKickDriftKey::run(const Args &a, uint32_t blk, uint32_t)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const Grid &g = a.g;
+    const PSet &s = a.s;
+    const double *fx = a.fx, *fy = a.fy, *fz = a.fz;
+    const int64_t n = a.n;
+    const double hdt = a.hdt, dt = a.dt;
+    const int second_kick = a.second_kick;
+    const double *scale = a.scale;
+    int64_t i = (int64_t)blk * kThreads + threadIdx.x;
     double ke = 0.0;
     if (i < n) {
         double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
@@ -99,25 +126,43 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift_key(Grid g, PSet s, const
         s.vx[i] = vx;
         s.vy[i] = vy;
         s.vz[i] = vz;
-        int32_t a = box_of(p.x, g.h[0], g.n[0]);
-        int32_t b = box_of(p.y, g.h[1], g.n[1]);
-        int32_t c = box_of(p.z, g.h[2], g.n[2]);
-        key[i] = box_key(g, a, b, c);
-        val[i] = (uint32_t)i;
+        const int32_t ba = box_of(p.x, g.h[0], g.n[0]);
+        const int32_t bb = box_of(p.y, g.h[1], g.n[1]);
+        const int32_t bc = box_of(p.z, g.h[2], g.n[2]);
+        a.key[i] = box_key(g, ba, bb, bc);
+        a.val[i] = (uint32_t)i;
     }
     if (second_kick) {
         double t = block_sum(ke);
-        if (threadIdx.x == 0) ke_partials[blockIdx.x].ke = t;
+        if (threadIdx.x == 0) a.ke_partials[blk].ke = t;
     }
 }
 
 // mode 0: kinetic-energy partials only; 1: half kick v += hdt F; 2: thermostat scaling
 // v *= *scale. Every mode leaves the workgroup's sum of |v|^2 (after the update) in ke_partials.
-__global__ void __launch_bounds__(kBlock) k_kick(PSet s, const double *fx, const double *fy,
-                                                 const double *fz, int64_t n, double hdt,
-                                                 int mode, const double *scale, Partial *ke_partials)
+struct KKick {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        PSet s;
+        const double *fx, *fy, *fz;
+        int64_t n;
+        double hdt;
+        int mode;
+        const double *scale;
+        Partial *ke_partials;
+    };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t);
+};
+
+__device__ void KKick::run(const Args &a, uint32_t blk, uint32_t)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const PSet &s = a.s;
+    const double *fx = a.fx, *fy = a.fy, *fz = a.fz;
+    const int64_t n = a.n;
+    const double hdt = a.hdt;
+    const int mode = a.mode;
+    const double *scale = a.scale;
+    int64_t i = (int64_t)blk * kThreads + threadIdx.x;
     double ke = 0.0;
     if (i < n) {
         double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
@@ -139,7 +184,7 @@ __global__ void __launch_bounds__(kBlock) k_kick(PSet s, const double *fx, const
         ke = vx * vx + vy * vy + vz * vz;
     }
     double t = block_sum(ke);
-    if (threadIdx.x == 0) ke_partials[blockIdx.x].ke = t;
+    if (threadIdx.x == 0) a.ke_partials[blk].ke = t;
 }
 
 
@@ -147,14 +192,21 @@ __global__ void __launch_bounds__(kBlock) k_kick(PSet s, const double *fx, const
 // kinetic-energy partials in a fixed order.
 constexpr int kRedStage = 32;                      // workgroups of the first stage
 
-__global__ void __launch_bounds__(kBlock) k_reduce_stage(const Partial *fp, int nf, const Partial *kp, int nk,
-                                                        Partial *out_f, Partial *out_k)
+struct KReduceStage {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args { const Partial *fp; int nf; const Partial *kp; int nk; Partial *out_f, *out_k; };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t);
+};
+
+__device__ void KReduceStage::run(const Args &a, uint32_t blk, uint32_t)
 {
+    const Partial *fp = a.fp, *kp = a.kp;
+    const int nf = a.nf, nk = a.nk;
     __shared__ double lds[kBlock / 64][8];
     __shared__ long long ldp[kBlock / 64];
     const int fchunk = (nf + kRedStage - 1) / kRedStage, kchunk = (nk + kRedStage - 1) / kRedStage;
-    const int f0 = blockIdx.x * fchunk, f1 = min(nf, f0 + fchunk);
-    const int k0 = blockIdx.x * kchunk, k1 = min(nk, k0 + kchunk);
+    const int f0 = (int)blk * fchunk, f1 = min(nf, f0 + fchunk);
+    const int k0 = (int)blk * kchunk, k1 = min(nk, k0 + kchunk);
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     long long pc = 0;
     for (int q = f0 + threadIdx.x; q < f1; q += kBlock) {
@@ -181,8 +233,8 @@ __global__ void __launch_bounds__(kBlock) k_reduce_stage(const Partial *fp, int 
             pf.pairs += ldp[q];
             pk.ke += lds[q][7];
         }
-        out_f[blockIdx.x] = pf;
-        out_k[blockIdx.x] = pk;
+        a.out_f[blk] = pf;
+        a.out_k[blk] = pk;
     }
 }
 
@@ -207,10 +259,29 @@ __device__ double nh_half(double K, double *nh, const NhConst &c)
 // Second stage: one wave sums the first stage's results in a fixed order. nh_mode 0 writes the
 // record (with the thermostat state nh, if given); kNhStart/kNhEnd also take half a thermostat
 // step with the summed kinetic energy, kNhEnd recording the damped kinetic energy.
-__global__ void __launch_bounds__(64) k_reduce_thermo(const Partial *sf, const Partial *sk, double mass,
-                                                      long long step, dcm_thermo *out, double *nh,
-                                                      int nh_mode, NhConst c)
+struct KReduceThermo {
+    static constexpr int kThreads = 64, kWaves = 0;
+    struct Args {
+        const Partial *sf, *sk;
+        double mass;
+        long long step;
+        dcm_thermo *out;
+        double *nh;
+        int nh_mode;
+        NhConst c;
+    };
+    static __device__ void run(const Args &a, uint32_t, uint32_t);
+};
+
+__device__ void KReduceThermo::run(const Args &a, uint32_t, uint32_t)
 {
+    const Partial *sf = a.sf, *sk = a.sk;
+    const double mass = a.mass;
+    const long long step = a.step;
+    dcm_thermo *out = a.out;
+    double *nh = a.nh;
+    const int nh_mode = a.nh_mode;
+    const NhConst &c = a.c;
     const int q = threadIdx.x;
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     long long pc = 0;
@@ -241,10 +312,24 @@ __global__ void __launch_bounds__(64) k_reduce_thermo(const Partial *sf, const P
     }
 }
 
-__global__ void k_unsort(PSet s, const double *fx, const double *fy, const double *fz, int64_t n,
-                         double *x_out, double *v_out, double *rc_out, double *f_out)
+struct KUnsort {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        PSet s;
+        const double *fx, *fy, *fz;
+        int64_t n;
+        double *x_out, *v_out, *rc_out, *f_out;
+    };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t);
+};
+
+__device__ void KUnsort::run(const Args &a, uint32_t blk, uint32_t)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const PSet &s = a.s;
+    const double *fx = a.fx, *fy = a.fy, *fz = a.fz;
+    const int64_t n = a.n;
+    double *x_out = a.x_out, *v_out = a.v_out, *rc_out = a.rc_out, *f_out = a.f_out;
+    int64_t i = (int64_t)blk * kThreads + threadIdx.x;
     if (i >= n) return;
     const uint32_t id = s.id[i];
     if (x_out || rc_out) {
@@ -256,10 +341,19 @@ __global__ void k_unsort(PSet s, const double *fx, const double *fy, const doubl
     if (f_out) { f_out[id] = fx[i]; f_out[n + id] = fy[i]; f_out[2 * n + id] = fz[i]; }
 }
 
-__global__ void k_load_state(PSet s, const double *x, const double *v, const double *rc, int64_t n,
-                             double rc_fill)
+struct KLoadState {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args { PSet s; const double *x, *v, *rc; int64_t n; double rc_fill; };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t);
+};
+
+__device__ void KLoadState::run(const Args &a, uint32_t blk, uint32_t)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const PSet &s = a.s;
+    const double *x = a.x, *v = a.v, *rc = a.rc;
+    const int64_t n = a.n;
+    const double rc_fill = a.rc_fill;
+    int64_t i = (int64_t)blk * kThreads + threadIdx.x;
     if (i >= n) return;
     s.pos[i] = make_double4(x[i], x[n + i], x[2 * n + i], rc ? rc[i] : rc_fill);
     s.vx[i] = v[i];
@@ -268,22 +362,29 @@ __global__ void k_load_state(PSet s, const double *x, const double *v, const dou
     s.id[i] = (uint32_t)i;
 }
 
-__global__ void k_scatter_rc(PSet s, const double *rc_in, int64_t n, double rc_min, double rc_max,
-                             uint32_t *flags)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double r = rc_in[s.id[i]];
-    if (!(r >= rc_min && r <= rc_max)) atomicOr(flags, kFlagBadCutoff);
-    s.pos[i].w = r;
-}
+struct KScatterRc {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args { PSet s; const double *rc_in; int64_t n; double rc_min, rc_max; uint32_t *flags; };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t)
+    {
+        int64_t i = (int64_t)blk * kThreads + threadIdx.x;
+        if (i >= a.n) return;
+        double r = a.rc_in[a.s.id[i]];
+        if (!(r >= a.rc_min && r <= a.rc_max)) atomicOr(a.flags, kFlagBadCutoff);
+        a.s.pos[i].w = r;
+    }
+};
 
-__global__ void k_check_finite(const double *a, int64_t count, uint32_t *flags)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool bad = i < count && !isfinite(a[i]);
-    if (__ballot(bad) && __lane_id() == 0) atomicOr(flags, kFlagNonFinite);
-}
+struct KCheckFinite {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args { const double *v; int64_t count; uint32_t *flags; };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t)
+    {
+        int64_t i = (int64_t)blk * kThreads + threadIdx.x;
+        bool bad = i < a.count && !isfinite(a.v[i]);
+        if (__ballot(bad) && __lane_id() == 0) atomicOr(a.flags, kFlagNonFinite);
+    }
+};
 
 }  // namespace
 
@@ -292,15 +393,14 @@ int stream_blocks(int64_t n) { return (int)grid1(n); }
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t st)
 {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid1(count)), dim3(kBlock), 0, st, p, v, count);
+    emit<KFillU32>({p, v, count}, grid1(count), st);
 }
 
 void launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t st)
 {
     if (bytes == 0) return;
     size_t chunks = (bytes + 15) / 16;
-    hipLaunchKernelGGL(k_copy_bytes, dim3(grid1((int64_t)chunks)), dim3(kBlock), 0, st,
-                       (uint8_t *)dst, (const uint8_t *)src, bytes);
+    emit<KCopyBytes>({(uint8_t *)dst, (const uint8_t *)src, bytes}, grid1((int64_t)chunks), st);
 }
 
 void launch_kick_drift_key(const Grid &g, PSet s, const double *fx, const double *fy,
@@ -308,38 +408,31 @@ void launch_kick_drift_key(const Grid &g, PSet s, const double *fx, const double
                            const double *scale, uint32_t *key, uint32_t *val, Partial *ke_partials,
                            hipStream_t st)
 {
-    hipLaunchKernelGGL(k_kick_drift_key, dim3(grid1(n)), dim3(kBlock), 0, st, g, s, fx, fy, fz, n,
-                       hdt, dt, second_kick, scale, key, val, ke_partials);
+    emit<KKickDriftKey>({g, s, fx, fy, fz, n, hdt, dt, second_kick, scale, key, val, ke_partials}, grid1(n), st);
 }
 
 void launch_kick(PSet s, const double *fx, const double *fy, const double *fz, int64_t n,
                  double hdt, Partial *ke_partials, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_kick, dim3(grid1(n)), dim3(kBlock), 0, st, s, fx, fy, fz, n, hdt, 1,
-                       (const double *)nullptr, ke_partials);
+    emit<KKick>({s, fx, fy, fz, n, hdt, 1, nullptr, ke_partials}, grid1(n), st);
 }
 
 void launch_scale(PSet s, int64_t n, const double *scale, Partial *ke_partials, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_kick, dim3(grid1(n)), dim3(kBlock), 0, st, s, (const double *)nullptr,
-                       (const double *)nullptr, (const double *)nullptr, n, 0.0, 2, scale, ke_partials);
+    emit<KKick>({s, nullptr, nullptr, nullptr, n, 0.0, 2, scale, ke_partials}, grid1(n), st);
 }
 
 void launch_ke_only(PSet s, int64_t n, Partial *ke_partials, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_kick, dim3(grid1(n)), dim3(kBlock), 0, st, s, (const double *)nullptr,
-                       (const double *)nullptr, (const double *)nullptr, n, 0.0, 0,
-                       (const double *)nullptr, ke_partials);
+    emit<KKick>({s, nullptr, nullptr, nullptr, n, 0.0, 0, nullptr, ke_partials}, grid1(n), st);
 }
 
 void launch_reduce_thermo(const Partial *force_parts, int nforce, const Partial *ke_parts, int nke,
                           double mass, long long step, dcm_thermo *out, Partial *stage, double *nh,
                           int nh_mode, const NhConst &c, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_reduce_stage, dim3(kRedStage), dim3(kBlock), 0, st, force_parts, nforce, ke_parts, nke,
-                       stage, stage + kRedStage);
-    hipLaunchKernelGGL(k_reduce_thermo, dim3(1), dim3(64), 0, st, (const Partial *)stage,
-                       (const Partial *)(stage + kRedStage), mass, step, out, nh, nh_mode, c);
+    emit<KReduceStage>({force_parts, nforce, ke_parts, nke, stage, stage + kRedStage}, kRedStage, st);
+    emit<KReduceThermo>({stage, stage + kRedStage, mass, step, out, nh, nh_mode, c}, 1, st);
 }
 
 int reduce_stage_partials() { return 2 * kRedStage; }
@@ -347,26 +440,24 @@ int reduce_stage_partials() { return 2 * kRedStage; }
 void launch_unsort(PSet s, const double *fx, const double *fy, const double *fz, int64_t n,
                    double *x_out, double *v_out, double *rc_out, double *f_out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_unsort, dim3(grid1(n)), dim3(kBlock), 0, st, s, fx, fy, fz, n, x_out, v_out,
-                       rc_out, f_out);
+    emit<KUnsort>({s, fx, fy, fz, n, x_out, v_out, rc_out, f_out}, grid1(n), st);
 }
 
 void launch_load_state(PSet s, const double *x, const double *v, const double *rc, int64_t n,
                        double rc_fill, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_load_state, dim3(grid1(n)), dim3(kBlock), 0, st, s, x, v, rc, n, rc_fill);
+    emit<KLoadState>({s, x, v, rc, n, rc_fill}, grid1(n), st);
 }
 
 void launch_scatter_rc(PSet s, const double *rc_in, int64_t n, double rc_min, double rc_max,
                        uint32_t *flags, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_scatter_rc, dim3(grid1(n)), dim3(kBlock), 0, st, s, rc_in, n, rc_min, rc_max,
-                       flags);
+    emit<KScatterRc>({s, rc_in, n, rc_min, rc_max, flags}, grid1(n), st);
 }
 
 void launch_check_finite(const double *a, int64_t count, uint32_t *flags, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_check_finite, dim3(grid1(count)), dim3(kBlock), 0, st, a, count, flags);
+    emit<KCheckFinite>({a, count, flags}, grid1(count), st);
 }
 
 }  // namespace dcm

@@ -7,6 +7,7 @@
 // internal order -- and with it every summation order -- is a function of the state alone.
 // The box counts b_ijk of Eq. 9 are differences of consecutive box starts.
 #include "internal.h"
+#include "launch.h"
 
 namespace dcm {
 
@@ -15,7 +16,7 @@ namespace {
 constexpr int kRadixBits = 8;
 constexpr int kDigits = 1 << kRadixBits;
 constexpr int kItems = 8;                          // keys per thread per tile
-constexpr int kWaves = kBlock / 64;
+constexpr int kBlockWaves = kBlock / 64;
 constexpr int kTile = kBlock * kItems;             // 2048 keys per tile
 
 __device__ __forceinline__ double wrap1(double x, double L)
@@ -35,10 +36,18 @@ __device__ __forceinline__ int32_t box_of(double x, double h, int32_t N)
     return i;
 }
 
-__global__ void k_wrap_key(Grid g, PSet s, int64_t n, uint32_t *key, uint32_t *val)
+struct KWrapKey {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args { Grid g; PSet s; int64_t n; uint32_t *key, *val; };
+    static __device__ void run(const Args &args, uint32_t blk, uint32_t);
+};
+
+__device__ void KWrapKey::run(const Args &args, uint32_t blk, uint32_t)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const Grid &g = args.g;
+    const PSet &s = args.s;
+    int64_t i = (int64_t)blk * kThreads + threadIdx.x;
+    if (i >= args.n) return;
     double4 p = s.pos[i];
     p.x = wrap1(p.x, g.L[0]);
     p.y = wrap1(p.y, g.L[1]);
@@ -47,15 +56,19 @@ __global__ void k_wrap_key(Grid g, PSet s, int64_t n, uint32_t *key, uint32_t *v
     int32_t a = box_of(p.x, g.h[0], g.n[0]);
     int32_t b = box_of(p.y, g.h[1], g.n[1]);
     int32_t c = box_of(p.z, g.h[2], g.n[2]);
-    key[i] = box_key(g, a, b, c);
-    val[i] = (uint32_t)i;
+    args.key[i] = box_key(g, a, b, c);
+    args.val[i] = (uint32_t)i;
 }
 
-__global__ void k_init_ids(PSet s, int64_t n)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) s.id[i] = (uint32_t)i;
-}
+struct KInitIds {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args { PSet s; int64_t n; };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t)
+    {
+        int64_t i = (int64_t)blk * kThreads + threadIdx.x;
+        if (i < a.n) a.s.id[i] = (uint32_t)i;
+    }
+};
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
@@ -73,15 +86,23 @@ __device__ __forceinline__ unsigned long long peer_mask(uint32_t digit, bool val
 }
 
 // Per-tile digit counts: tile_counts[d * ntiles + t].
-__global__ void __launch_bounds__(kBlock) k_radix_count(const uint32_t *key, int64_t n, int shift,
-                                                        uint32_t *tile_counts, int64_t ntiles)
+struct KRadixCount {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args { const uint32_t *key; int64_t n; int shift; uint32_t *tile_counts; int64_t ntiles; };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t);
+};
+
+__device__ void KRadixCount::run(const Args &a, uint32_t blk, uint32_t)
 {
-    __shared__ uint32_t whist[kWaves][kDigits];
+    const uint32_t *key = a.key;
+    const int64_t n = a.n;
+    const int shift = a.shift;
+    __shared__ uint32_t whist[kBlockWaves][kDigits];
     const int tid = threadIdx.x, w = tid >> 6;
     const unsigned lane = lane_id();
-    for (int d = tid; d < kWaves * kDigits; d += kBlock) (&whist[0][0])[d] = 0;
+    for (int d = tid; d < kBlockWaves * kDigits; d += kBlock) (&whist[0][0])[d] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)w * 64 * kItems;
+    const int64_t base = (int64_t)blk * kTile + (int64_t)w * 64 * kItems;
     for (int r = 0; r < kItems; ++r) {
         int64_t i = base + r * 64 + lane;
         bool valid = i < n;
@@ -93,13 +114,13 @@ __global__ void __launch_bounds__(kBlock) k_radix_count(const uint32_t *key, int
     __syncthreads();
     for (int d = tid; d < kDigits; d += kBlock) {
         uint32_t c = 0;
-        for (int q = 0; q < kWaves; ++q) c += whist[q][d];
-        tile_counts[(int64_t)d * ntiles + blockIdx.x] = c;
+        for (int q = 0; q < kBlockWaves; ++q) c += whist[q][d];
+        a.tile_counts[(int64_t)d * a.ntiles + blk] = c;
     }
 }
 
 // Exclusive scan of 256 values held one per thread (blockDim == 256); returns the total.
-__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *out_excl, uint32_t *lds /*[kWaves]*/)
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *out_excl, uint32_t *lds /*[kBlockWaves]*/)
 {
     const int tid = threadIdx.x, w = tid >> 6;
     const unsigned lane = lane_id();
@@ -112,7 +133,7 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *out_excl, uint32_
     if (lane == 63) lds[w] = incl;
     __syncthreads();
     uint32_t wbase = 0, total = 0;
-    for (int q = 0; q < kWaves; ++q) {
+    for (int q = 0; q < kBlockWaves; ++q) {
         if (q < w) wbase += lds[q];
         total += lds[q];
     }
@@ -122,11 +143,17 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *out_excl, uint32_
 }
 
 // One block per digit: exclusive scan of its per-tile counts (in place) and the digit total.
-__global__ void __launch_bounds__(kBlock) k_digit_scan(uint32_t *tile_counts, int64_t ntiles,
-                                                       uint32_t *digit_total)
+struct KDigitScan {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args { uint32_t *tile_counts; int64_t ntiles; uint32_t *digit_total; };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t);
+};
+
+__device__ void KDigitScan::run(const Args &a, uint32_t blk, uint32_t)
 {
-    __shared__ uint32_t lds[kWaves];
-    uint32_t *row = tile_counts + (int64_t)blockIdx.x * ntiles;
+    __shared__ uint32_t lds[kBlockWaves];
+    const int64_t ntiles = a.ntiles;
+    uint32_t *row = a.tile_counts + (int64_t)blk * ntiles;
     uint32_t carry = 0;
     for (int64_t start = 0; start < ntiles; start += kBlock * 4) {
         uint32_t v[4], s = 0;
@@ -145,28 +172,44 @@ __global__ void __launch_bounds__(kBlock) k_digit_scan(uint32_t *tile_counts, in
         }
         carry += total;
     }
-    if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
+    if (threadIdx.x == 0) a.digit_total[blk] = carry;
 }
 
 // Stable scatter of one radix pass. The tile's keys are first placed in LDS in tile-local digit
 // order, then written out in that order, so consecutive threads write consecutive slots of a
 // digit's run in the output.
-__global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t *key, const uint32_t *val,
-                                                          uint32_t *key_out, uint32_t *val_out,
-                                                          int64_t n, int shift,
-                                                          const uint32_t *tile_prefix, int64_t ntiles,
-                                                          const uint32_t *digit_total)
+struct KRadixScatter {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        const uint32_t *key, *val;
+        uint32_t *key_out, *val_out;
+        int64_t n;
+        int shift;
+        const uint32_t *tile_prefix;
+        int64_t ntiles;
+        const uint32_t *digit_total;
+    };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t);
+};
+
+__device__ void KRadixScatter::run(const Args &a, uint32_t blk, uint32_t)
 {
-    __shared__ uint32_t whist[kWaves][kDigits];
+    const uint32_t *key = a.key, *val = a.val;
+    uint32_t *key_out = a.key_out, *val_out = a.val_out;
+    const int64_t n = a.n;
+    const int shift = a.shift;
+    const uint32_t *tile_prefix = a.tile_prefix, *digit_total = a.digit_total;
+    const int64_t ntiles = a.ntiles;
+    __shared__ uint32_t whist[kBlockWaves][kDigits];
     __shared__ uint32_t gbase[kDigits];
     __shared__ uint32_t tbase[kDigits];
-    __shared__ uint32_t lds[kWaves];
+    __shared__ uint32_t lds[kBlockWaves];
     __shared__ uint32_t sk[kTile], sv[kTile];
     const int tid = threadIdx.x, w = tid >> 6;
     const unsigned lane = lane_id();
-    for (int d = tid; d < kWaves * kDigits; d += kBlock) (&whist[0][0])[d] = 0;
+    for (int d = tid; d < kBlockWaves * kDigits; d += kBlock) (&whist[0][0])[d] = 0;
     __syncthreads();
-    const int64_t tile0 = (int64_t)blockIdx.x * kTile;
+    const int64_t tile0 = (int64_t)blk * kTile;
     const int64_t base = tile0 + (int64_t)w * 64 * kItems;
     uint32_t k[kItems], v[kItems], dg[kItems], rk[kItems];
 #pragma unroll
@@ -190,7 +233,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t *key, c
         uint32_t excl;
         block_exclusive_scan(digit_total[tid], &excl, lds);
         uint32_t acc = 0;
-        for (int q = 0; q < kWaves; ++q) {
+        for (int q = 0; q < kBlockWaves; ++q) {
             uint32_t c = whist[q][tid];
             whist[q][tid] = acc;
             acc += c;
@@ -198,7 +241,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t *key, c
         uint32_t texcl;
         block_exclusive_scan(acc, &texcl, lds);
         tbase[tid] = texcl;
-        gbase[tid] = excl + tile_prefix[(int64_t)tid * ntiles + blockIdx.x];
+        gbase[tid] = excl + tile_prefix[(int64_t)tid * ntiles + blk];
     }
     __syncthreads();
 #pragma unroll
@@ -230,21 +273,33 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t *key, c
 constexpr int kRangeBoxes = 1024;                   // boxes per run (4 per thread)
 constexpr int kRangeKeys = 4096;                    // keys a run can stage in LDS
 
-__global__ void k_run_starts(const uint32_t *key, int64_t n, int64_t nruns, uint32_t *run_start)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > n) return;
-    int64_t lo = (i == 0) ? 0 : (int64_t)(key[i - 1] / kRangeBoxes) + 1;
-    int64_t hi = (i == n) ? nruns : (int64_t)(key[i] / kRangeBoxes);
-    for (int64_t r = lo; r <= hi; ++r) run_start[r] = (uint32_t)i;
-}
+struct KRunStarts {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args { const uint32_t *key; int64_t n, nruns; uint32_t *run_start; };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t)
+    {
+        int64_t i = (int64_t)blk * kThreads + threadIdx.x;
+        if (i > a.n) return;
+        int64_t lo = (i == 0) ? 0 : (int64_t)(a.key[i - 1] / kRangeBoxes) + 1;
+        int64_t hi = (i == a.n) ? a.nruns : (int64_t)(a.key[i] / kRangeBoxes);
+        for (int64_t r = lo; r <= hi; ++r) a.run_start[r] = (uint32_t)i;
+    }
+};
 
-__global__ void __launch_bounds__(kBlock) k_cell_ranges(const uint32_t *key, int64_t G, const uint32_t *run_start,
-                                                        uint32_t *cell_start)
+struct KCellRanges {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args { const uint32_t *key; int64_t G; const uint32_t *run_start; uint32_t *cell_start; };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t);
+};
+
+__device__ void KCellRanges::run(const Args &args, uint32_t blk, uint32_t)
 {
+    const uint32_t *key = args.key;
+    const int64_t G = args.G;
+    uint32_t *cell_start = args.cell_start;
     __shared__ uint32_t sk[kRangeKeys];
-    const int64_t c0 = (int64_t)blockIdx.x * kRangeBoxes;
-    const uint32_t lo = run_start[blockIdx.x], hi = run_start[blockIdx.x + 1];
+    const int64_t c0 = (int64_t)blk * kRangeBoxes;
+    const uint32_t lo = args.run_start[blk], hi = args.run_start[blk + 1];
     const uint32_t m = hi - lo;
     const bool staged = m <= (uint32_t)kRangeKeys;
     if (staged)
@@ -266,10 +321,18 @@ __global__ void __launch_bounds__(kBlock) k_cell_ranges(const uint32_t *key, int
 }
 
 // Inside each box, order slots by particle id (insertion sort; boxes hold a few particles).
-__global__ void k_cell_fixup(const uint32_t *cell_start, int64_t G, uint32_t *val, const uint32_t *id)
+struct KCellFixup {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args { const uint32_t *cell_start; int64_t G; uint32_t *val; const uint32_t *id; };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t);
+};
+
+__device__ void KCellFixup::run(const Args &a, uint32_t blk, uint32_t)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= G) return;
+    const uint32_t *cell_start = a.cell_start, *id = a.id;
+    uint32_t *val = a.val;
+    int64_t c = (int64_t)blk * kThreads + threadIdx.x;
+    if (c >= a.G) return;
     uint32_t s = cell_start[c], e = cell_start[c + 1];
     if (e - s < 2) return;
     for (uint32_t q = s + 1; q < e; ++q) {
@@ -286,10 +349,18 @@ __global__ void k_cell_fixup(const uint32_t *cell_start, int64_t G, uint32_t *va
     }
 }
 
-__global__ void k_gather(PSet from, PSet to, const uint32_t *perm, int64_t n)
+struct KGather {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args { PSet from, to; const uint32_t *perm; int64_t n; };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t);
+};
+
+__device__ void KGather::run(const Args &a, uint32_t blk, uint32_t)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const PSet &from = a.from, &to = a.to;
+    const uint32_t *perm = a.perm;
+    int64_t i = (int64_t)blk * kThreads + threadIdx.x;
+    if (i >= a.n) return;
     uint32_t o = perm[i];
     to.pos[i] = from.pos[o];
     to.vx[i] = from.vx[o];
@@ -311,12 +382,12 @@ size_t sort_scratch_bytes(int64_t n, int64_t G)
 
 void launch_wrap_key(const Grid &g, PSet s, int64_t n, uint32_t *key, uint32_t *val, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_wrap_key, dim3(grid1(n)), dim3(kBlock), 0, st, g, s, n, key, val);
+    emit<KWrapKey>({g, s, n, key, val}, grid1(n), st);
 }
 
 void launch_init_ids(PSet s, int64_t n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_init_ids, dim3(grid1(n)), dim3(kBlock), 0, st, s, n);
+    emit<KInitIds>({s, n}, grid1(n), st);
 }
 
 // Sorts (key, val) by key over the low `bits` bits. The result ends in (key, val): an odd
@@ -331,12 +402,9 @@ bool launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key_alt, uint32_t
     int passes = (bits + kRadixBits - 1) / kRadixBits;
     for (int p = 0; p < passes; ++p) {
         int shift = p * kRadixBits;
-        hipLaunchKernelGGL(k_radix_count, dim3((unsigned)ntiles), dim3(kBlock), 0, st, ki, n, shift,
-                           tile_counts, ntiles);
-        hipLaunchKernelGGL(k_digit_scan, dim3(kDigits), dim3(kBlock), 0, st, tile_counts, ntiles,
-                           digit_total);
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(kBlock), 0, st, ki, vi, ko,
-                           vo, n, shift, tile_counts, ntiles, digit_total);
+        emit<KRadixCount>({ki, n, shift, tile_counts, ntiles}, (uint32_t)ntiles, st);
+        emit<KDigitScan>({tile_counts, ntiles, digit_total}, kDigits, st);
+        emit<KRadixScatter>({ki, vi, ko, vo, n, shift, tile_counts, ntiles, digit_total}, (uint32_t)ntiles, st);
         uint32_t *t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
     }
@@ -350,20 +418,19 @@ void launch_cell_ranges(const uint32_t *key_sorted, int64_t n, int64_t G, uint32
     const int64_t ntiles = (n + kTile - 1) / kTile;
     uint32_t *run_start = (uint32_t *)scratch + (size_t)kDigits * (size_t)ntiles + kDigits;
     const int64_t nruns = G / kRangeBoxes + 1;
-    hipLaunchKernelGGL(k_run_starts, dim3(grid1(n + 1)), dim3(kBlock), 0, st, key_sorted, n, nruns, run_start);
-    hipLaunchKernelGGL(k_cell_ranges, dim3((unsigned)nruns), dim3(kBlock), 0, st, key_sorted, G,
-                       (const uint32_t *)run_start, cell_start);
+    emit<KRunStarts>({key_sorted, n, nruns, run_start}, grid1(n + 1), st);
+    emit<KCellRanges>({key_sorted, G, run_start, cell_start}, (uint32_t)nruns, st);
 }
 
 void launch_cell_fixup(const uint32_t *cell_start, int64_t G, uint32_t *val, const uint32_t *id_old,
                        hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cell_fixup, dim3(grid1(G)), dim3(kBlock), 0, st, cell_start, G, val, id_old);
+    emit<KCellFixup>({cell_start, G, val, id_old}, grid1(G), st);
 }
 
 void launch_gather(PSet from, PSet to, const uint32_t *perm, int64_t n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gather, dim3(grid1(n)), dim3(kBlock), 0, st, from, to, perm, n);
+    emit<KGather>({from, to, perm, n}, grid1(n), st);
 }
 
 }  // namespace dcm
