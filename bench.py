@@ -265,7 +265,7 @@ def serving_study(nseeds: int, nsys: int = 64, nsteps: int = 100, load: float = 
     foot = [dcm.dcm_workspace_bytes(p, s.n) + 48 * s.n + 4096 for s, p in zip(systems, params)]
     budget = max(int(0.25 * sum(foot)), max(foot) + 4096)
     pool = dcm.workspace(int(1.25 * budget))
-    seq_lat, srv_lat, seq_tp, srv_tp = [], [], [], []
+    seq_lat, srv_lat, seq_tp, srv_tp, srv_stats = [], [], [], [], []
     atom_steps = float(sizes.sum()) * nsteps
     for seed in range(1, nseeds + 1):
         order = np.random.default_rng(seed).permutation(nsys)
@@ -300,7 +300,10 @@ def serving_study(nseeds: int, nsys: int = 64, nsteps: int = 100, load: float = 
         srv_lat += list(done.values())
         srv_tp.append(atom_steps / (last - arr[0]))
         log(f"seed {seed}: server p50 {np.percentile(list(done.values()), 50):.3f}s, "
-            f"batches {stats['batches']}, sequential p50 {np.percentile(lat, 50):.3f}s")
+            f"batches {stats['batches']}, groupings {stats['groupings']} "
+            f"({stats['grouping_ms']:.1f} ms), grouped/eager periods {stats['grouped_steps']}/"
+            f"{stats['eager_steps']}, sequential p50 {np.percentile(lat, 50):.3f}s")
+        srv_stats.append(stats)
     # saturated: every request arrives at t = 0; makespan against the sum of service times
     sv = dcm.dcm_server_create(budget, pool)
     t0 = time.perf_counter()
@@ -312,8 +315,10 @@ def serving_study(nseeds: int, nsys: int = 64, nsteps: int = 100, load: float = 
                 del tickets[tk]
         time.sleep(0.0005)
     makespan = time.perf_counter() - t0
+    sat_stats = dcm.dcm_server_query(sv)
     dcm.dcm_server_destroy(sv)
-    log(f"saturated: server makespan {makespan:.3f}s, sequential {svc.sum():.3f}s")
+    log(f"saturated: server makespan {makespan:.3f}s, sequential {svc.sum():.3f}s, batches "
+        f"{sat_stats['batches']}, groupings {sat_stats['groupings']} ({sat_stats['grouping_ms']:.1f} ms)")
     out = {"study": "serving", "systems": nsys, "steps_each": nsteps, "seeds": nseeds,
            "particles_total": int(sizes.sum()), "load": load, "arrival_rate_per_s": rate,
            "hbm_budget_bytes": budget, "sequential_capacity_req_per_s": cap,
@@ -324,7 +329,9 @@ def serving_study(nseeds: int, nsys: int = 64, nsteps: int = 100, load: float = 
                           "p50_latency_s": float(np.percentile(seq_lat, 50)),
                           "p99_latency_s": float(np.percentile(seq_lat, 99))},
            "saturated": {"server_atom_steps_per_s": atom_steps / makespan,
-                         "sequential_atom_steps_per_s": atom_steps / float(svc.sum())},
+                         "sequential_atom_steps_per_s": atom_steps / float(svc.sum()),
+                         "makespan_s": makespan, "server_stats": sat_stats},
+           "server_stats_per_seed": srv_stats,
            "samples": len(srv_lat)}
     print(json.dumps(out), flush=True)
 

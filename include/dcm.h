@@ -262,20 +262,29 @@ dcm_status dcm_grid_distance(const int32_t dims[3], const double h[3], double ca
  *
  * A worker thread admits queued requests in arrival order while the front request's device
  * footprint (its dcm_workspace_bytes plus state staging and thermo records) fits the
- * remaining HBM budget and a free range of the pool. Admitted systems stay resident, each on
- * its own stream; the step sequence of one detection period is captured once into a hipGraph
- * and replayed for all resident systems every batch (remaining steps shorter than a period
- * run as ordinary launches). Results are copied to host memory on completion.
+ * remaining HBM budget and a free range of the pool. Admitted systems stay resident. When the
+ * resident set changes, the launches of one detection period are recorded for every system;
+ * systems whose periods launch the same kernels in the same order form a group, and each
+ * launch position becomes one batched launch over all members' workgroups, captured with the
+ * rest of the group's period into one hipGraph. Every batch replays each group's graph, so
+ * stepping all resident systems costs the launches of one system. Remaining steps shorter than
+ * a period, and systems the argument tables have no room for, run as ordinary launches.
+ * Results are copied to host memory on completion.
  * Thread safety: submit/poll/query may be called from any one thread at a time. */
 typedef struct dcm_server dcm_server;
 
 typedef struct {
     int64_t submitted, admitted, completed, rejected, queued, running, batches;
     size_t bytes_in_use;
+    int64_t groupings;      /* times the resident systems were regrouped (record + capture)  */
+    double grouping_ms;     /* host milliseconds spent regrouping                            */
+    int64_t grouped_steps;  /* system-periods run by batched graphs                          */
+    int64_t eager_steps;    /* system-periods (or tails) run by ordinary launches            */
 } dcm_server_stats;
 
 /* d_pool: caller-owned device memory of pool_bytes (256-byte aligned) the server sub-allocates;
- * hbm_budget <= pool_bytes caps the bytes resident at once. Work queued on `stream` is waited
+ * hbm_budget <= pool_bytes caps the bytes resident at once. The last min(pool_bytes / 16,
+ * 16 MiB) of the pool hold the argument tables of the batched launches; systems go in the rest. Work queued on `stream` is waited
  * for first. DCM_E_INVALID for a NULL/misaligned pool or a budget of 0 or above pool_bytes. */
 dcm_status dcm_server_create(size_t hbm_budget, void *d_pool, size_t pool_bytes, dcm_stream_t stream,
                              dcm_server **out);

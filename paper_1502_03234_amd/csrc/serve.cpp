@@ -3,12 +3,16 @@
 // A worker thread owns the GPU side. Requests queue in arrival order; the front request is
 // admitted when its device footprint (system workspace, staging and thermo records) fits the
 // remaining HBM budget and a free range of the caller's pool. An admitted system stays
-// resident on its own stream. Its step sequence over one detection period (2 steps for
-// detect_every = 2) is captured once into a hipGraph; every batch replays the graphs of all
-// resident systems, each on its stream, so small systems run concurrently and the per-step
-// host launch cost is one graph launch per system. A system whose remaining step count is
-// shorter than the period finishes with ordinary launches. Finished systems are copied back to
-// host memory and released; dcm_poll hands the result to the caller.
+// resident. Whenever the set of resident systems changes, the launch sequence of one detection
+// period (2 steps for detect_every = 2) is recorded for every system without running it, and
+// systems whose sequences name the same kernels in the same order form a group. Each position
+// of a group's sequence becomes one batched launch over all of its systems' workgroups (their
+// argument records in a device table, see launch.h), and the group's whole period is captured
+// into one hipGraph. A batch replays every group's graph on the server's stream, so a period
+// of all resident systems costs as many launches as a period of one system. A system whose
+// remaining step count is shorter than the period finishes with ordinary launches on its own
+// stream. Finished systems are copied back to host memory and released; dcm_poll hands the
+// result to the caller.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -20,6 +24,11 @@
 #include <vector>
 
 #include "internal.h"
+#include "launch.h"
+
+using dcm::current_recorder;
+using dcm::Launch;
+using dcm::Recorder;
 
 namespace {
 
@@ -38,8 +47,8 @@ struct Req {
     size_t off = 0, bytes = 0, ws_bytes = 0;
     dcm_system *sys = nullptr;
     hipStream_t stream = nullptr;
-    hipGraphExec_t graph = nullptr;
     int period = 2;
+    bool grouped = false;           // stepped by its group's graph in the current batch
     int32_t done_steps = 0;
     int last_record = 0;
     double *d_x = nullptr, *d_v = nullptr;
@@ -48,6 +57,19 @@ struct Req {
 };
 
 int gcd(int a, int b) { return b ? gcd(b, a % b) : a; }
+
+// Systems stepped together: one recorded period per member, all naming the same kernels.
+struct Group {
+    std::vector<Req *> members;
+    hipGraphExec_t graph = nullptr;
+};
+
+// Bytes of the pool kept for the batched launches' argument and workgroup tables.
+size_t table_reserve(size_t pool_bytes)
+{
+    const size_t want = std::min<size_t>(pool_bytes / 16, (size_t)16 << 20);
+    return want & ~(size_t)255;
+}
 
 }  // namespace
 
@@ -62,6 +84,15 @@ struct dcm_server {
     std::vector<Req *> running;
     std::vector<std::pair<size_t, size_t>> free_list;   // (offset, size), sorted by offset
     std::thread worker;
+    hipStream_t stream = nullptr;             // batched launches of all groups
+    uint8_t *tables = nullptr;                // [table_bytes] at the end of the pool
+    size_t table_bytes = 0;
+    std::vector<uint8_t> table_host;          // host image of the tables (staging)
+    std::vector<Group> groups;
+    bool regroup = false;                     // the resident set changed since the last grouping
+    hipEvent_t batch_done[2] = {nullptr, nullptr};   // ends of the last two batches
+    int batch_parity = 0;
+    bool in_flight = false;                   // the previous batch may still be running
     bool stop = false;
     uint64_t next_ticket = 1;
     dcm_server_stats stats{};
@@ -109,15 +140,14 @@ size_t footprint(const Req *r, size_t ws)
 
 void release_device(Req *r)
 {
-    if (r->graph) (void)hipGraphExecDestroy(r->graph);
     if (r->sys) dcm_destroy(r->sys);
     if (r->stream) (void)hipStreamDestroy(r->stream);
-    r->graph = nullptr;
     r->sys = nullptr;
     r->stream = nullptr;
 }
 
-// Admission: copy the state in, create the system (force evaluation k = 0), capture one period.
+// Admission: copy the state in and create the system (force evaluation k = 0; synchronizes
+// the system's stream).
 dcm_status start(dcm_server *sv, Req *r)
 {
     uint8_t *base = sv->pool + r->off;
@@ -129,41 +159,163 @@ dcm_status start(dcm_server *sv, Req *r)
     if (hipMemcpyAsync(r->d_x, r->hx.data(), nb, hipMemcpyHostToDevice, r->stream) != hipSuccess ||
         hipMemcpyAsync(r->d_v, r->hv.data(), nb, hipMemcpyHostToDevice, r->stream) != hipSuccess)
         return DCM_E_HIP;
-    dcm_status s = dcm_create(&r->p, r->n, base, r->ws_bytes, r->d_x, r->d_v, r->stream, &r->sys);
-    if (s != DCM_OK) return s;
-    if (r->nsteps >= r->period) {
-        if (hipStreamBeginCapture(r->stream, hipStreamCaptureModeRelaxed) != hipSuccess) return DCM_E_HIP;
-        const int64_t k0 = r->sys->k;
-        const int cur0 = r->sys->cur;
-        s = dcm_step(r->sys, r->period, r->stream, r->d_th);
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(r->stream, &g);
-        // capture records the launches without running them: restore the host-side state
-        r->sys->k = k0;
-        r->sys->cur = cur0;
-        if (s != DCM_OK) return s;
-        if (e != hipSuccess || !g) return DCM_E_HIP;
-        e = hipGraphInstantiate(&r->graph, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return DCM_E_HIP;
-    }
-    return DCM_OK;
+    return dcm_create(&r->p, r->n, base, r->ws_bytes, r->d_x, r->d_v, r->stream, &r->sys);
 }
 
-// One batch for one system: a period by graph replay, or the remaining steps eagerly.
-void advance(Req *r)
+// The launches of one period of r, recorded without running them. Recording advances the
+// host-side state exactly as running would (step counter, ping-pong sets and sort buffers);
+// a period is an even number of steps, so every buffer choice is back where it started and
+// only the step counter needs restoring.
+dcm_status record_period(Req *r, Recorder &rec)
 {
-    const int32_t left = r->nsteps - r->done_steps;
-    if (left >= r->period && r->graph) {
-        (void)hipGraphLaunch(r->graph, r->stream);
-        r->sys->k += r->period;
-        r->done_steps += r->period;
-        r->last_record = r->period - 1;
-    } else if (left > 0) {
-        dcm_step(r->sys, left, r->stream, r->d_th);
-        r->done_steps += left;
-        r->last_record = left - 1;
+    dcm_system *s = r->sys;
+    const int64_t k0 = s->k;
+    const int cur0 = s->cur;
+    uint32_t *key0 = s->key, *val0 = s->val;
+    current_recorder() = &rec;
+    const dcm_status st = dcm_step(s, r->period, r->stream, r->d_th);
+    current_recorder() = nullptr;
+    s->k = k0;
+    if (s->cur != cur0 || s->key != key0 || s->val != val0) return DCM_E_INVALID;
+    return st;
+}
+
+bool same_sequence(const Recorder &a, const Recorder &b)
+{
+    if (a.ops.size() != b.ops.size()) return false;
+    for (size_t q = 0; q < a.ops.size(); ++q)
+        if (a.ops[q].batched != b.ops[q].batched || a.ops[q].threads != b.ops[q].threads ||
+            a.ops[q].args.size() != b.ops[q].args.size())
+            return false;
+    return true;
+}
+
+void drop_groups(dcm_server *sv)
+{
+    for (Group &g : sv->groups)
+        if (g.graph) (void)hipGraphExecDestroy(g.graph);
+    sv->groups.clear();
+}
+
+// Table bytes of one group: per position, the members' argument records and first workgroups.
+size_t group_table_bytes(const Recorder &rec, size_t m)
+{
+    size_t b = 0;
+    for (const Launch &l : rec.ops) b += align_up(l.args.size() * m) + align_up(sizeof(uint32_t) * (m + 1));
+    return b;
+}
+
+// Groups the systems that run whole periods this batch, writes their tables into the reserved
+// part of the pool and captures one graph per group. Systems that fit no group (the tables
+// are full, or recording failed) are stepped eagerly instead.
+void regroup(dcm_server *sv)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    (void)hipStreamSynchronize(sv->stream);     // tables of the previous grouping are free
+    sv->in_flight = false;
+    drop_groups(sv);
+    for (Req *r : sv->running) r->grouped = false;
+    std::vector<Recorder> recs;
+    std::vector<std::vector<size_t>> members;   // indices into recs / cand
+    std::vector<Req *> cand;
+    // One radix-sort length for all: a pass over key bits that are zero for a smaller grid
+    // leaves the (stable) order unchanged, and equal pass counts let systems of different grid
+    // sizes share one launch sequence.
+    int bits = 0;
+    for (Req *r : sv->running)
+        if (r->nsteps - r->done_steps >= r->period) bits = std::max(bits, r->sys->bits);
+    for (Req *r : sv->running) {
+        if (r->nsteps - r->done_steps < r->period) continue;
+        r->sys->bits = bits;
+        Recorder rec;
+        if (record_period(r, rec) != DCM_OK) continue;
+        size_t gi = 0;
+        while (gi < members.size() && !same_sequence(recs[members[gi][0]], rec)) ++gi;
+        if (gi == members.size()) members.emplace_back();
+        members[gi].push_back(recs.size());
+        recs.push_back(std::move(rec));
+        cand.push_back(r);
     }
+    size_t used = 0;
+    std::vector<uint8_t> &host = sv->table_host;
+    for (const std::vector<size_t> &mem : members) {
+        const Recorder &first_rec = recs[mem[0]];
+        // as many members as the remaining table space holds
+        size_t m = mem.size();
+        while (m > 0 && used + group_table_bytes(first_rec, m) > sv->table_bytes) --m;
+        if (m == 0) continue;
+        struct Op { const void *fn; uint32_t threads, blocks; size_t tab, first; };
+        std::vector<Op> ops;
+        for (size_t q = 0; q < first_rec.ops.size(); ++q) {
+            const size_t asz = first_rec.ops[q].args.size();
+            Op op{first_rec.ops[q].batched, first_rec.ops[q].threads, 0, used, 0};
+            for (size_t k = 0; k < m; ++k)
+                std::memcpy(host.data() + used + k * asz, recs[mem[k]].ops[q].args.data(), asz);
+            used += align_up(asz * m);
+            op.first = used;
+            uint32_t *fb = (uint32_t *)(host.data() + used);
+            fb[0] = 0;
+            for (size_t k = 0; k < m; ++k) fb[k + 1] = fb[k] + recs[mem[k]].ops[q].blocks;
+            op.blocks = fb[m];
+            used += align_up(sizeof(uint32_t) * (m + 1));
+            ops.push_back(op);
+        }
+        Group g;
+        for (size_t k = 0; k < m; ++k) g.members.push_back(cand[mem[k]]);
+        if (hipStreamBeginCapture(sv->stream, hipStreamCaptureModeRelaxed) != hipSuccess) continue;
+        for (const Op &op : ops) {
+            if (op.blocks == 0) continue;
+            void *tab = sv->tables + op.tab;
+            void *fst = sv->tables + op.first;
+            int nsys = (int)m;
+            void *kargs[] = {&tab, &fst, &nsys};
+            (void)hipLaunchKernel(op.fn, dim3(op.blocks), dim3(op.threads), kargs, 0, sv->stream);
+        }
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(sv->stream, &graph);
+        if (e == hipSuccess && graph) e = hipGraphInstantiate(&g.graph, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess || !g.graph) {
+            (void)hipGetLastError();
+            continue;
+        }
+        for (Req *r : g.members) r->grouped = true;
+        sv->groups.push_back(std::move(g));
+    }
+    if (used) (void)hipMemcpyAsync(sv->tables, host.data(), used, hipMemcpyHostToDevice, sv->stream);
+    (void)hipStreamSynchronize(sv->stream);     // the staging copy may be overwritten again
+    sv->regroup = false;
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stats.groupings += 1;
+    sv->stats.grouping_ms += ms;
+}
+
+// One batch: every group's period by graph replay on the server's stream, every other
+// system its period (or its remaining steps) eagerly on its own stream.
+void advance_all(dcm_server *sv)
+{
+    for (Group &g : sv->groups) (void)hipGraphLaunch(g.graph, sv->stream);
+    int64_t grouped = 0, eager = 0;
+    for (Req *r : sv->running) {
+        const int32_t left = r->nsteps - r->done_steps;
+        if (r->grouped) {
+            r->sys->k += r->period;
+            r->done_steps += r->period;
+            r->last_record = r->period - 1;
+            if (r->nsteps - r->done_steps < r->period) sv->regroup = true;
+            grouped += 1;
+        } else if (left > 0) {
+            const int32_t q = std::min(left, r->period);
+            dcm_step(r->sys, q, r->stream, r->d_th);
+            r->done_steps += q;
+            r->last_record = q - 1;
+            eager += 1;
+        }
+    }
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stats.grouped_steps += grouped;
+    sv->stats.eager_steps += eager;
 }
 
 dcm_status finish(Req *r)
@@ -219,21 +371,38 @@ void worker_loop(dcm_server *sv)
                 continue;
             }
             sv->running.push_back(r);
+            sv->regroup = true;
             std::lock_guard<std::mutex> lk(sv->mu);
             sv->stats.running += 1;
         }
-        for (Req *r : sv->running) advance(r);
+        if (sv->regroup) regroup(sv);
+        advance_all(sv);
         {
             std::lock_guard<std::mutex> lk(sv->mu);
             sv->stats.batches += 1;
         }
+        // Keep one batch in flight: wait for the previous batch, not this one, unless a system
+        // has finished its steps in this batch (its results are read next) or the groups must
+        // change (the tables are rewritten).
+        bool finished = sv->regroup;
+        for (Req *r : sv->running) finished = finished || r->done_steps >= r->nsteps;
+        (void)hipEventRecord(sv->batch_done[sv->batch_parity], sv->stream);
+        if (finished) {
+            (void)hipStreamSynchronize(sv->stream);
+            sv->in_flight = false;
+        } else {
+            if (sv->in_flight) (void)hipEventSynchronize(sv->batch_done[1 - sv->batch_parity]);
+            sv->in_flight = true;
+        }
+        sv->batch_parity = 1 - sv->batch_parity;
         std::vector<Req *> keep;
         for (Req *r : sv->running) {
             if (r->done_steps < r->nsteps) {
-                (void)hipStreamSynchronize(r->stream);
+                if (!r->grouped) (void)hipStreamSynchronize(r->stream);
                 keep.push_back(r);
                 continue;
             }
+            sv->regroup = true;
             dcm_status s = finish(r);
             std::string err = s == DCM_OK ? std::string() : std::string(dcm_last_error());
             release_device(r);
@@ -250,6 +419,7 @@ void worker_loop(dcm_server *sv)
         {
             std::lock_guard<std::mutex> lk(sv->mu);
             if (sv->stop && sv->running.empty()) {
+                drop_groups(sv);
                 for (Req *r : sv->queue) { r->status = DCM_E_INVALID; r->err = "server destroyed"; }
                 sv->queue.clear();
                 return;
@@ -273,9 +443,16 @@ dcm_status dcm_server_create(size_t hbm_budget, void *d_pool, size_t pool_bytes,
     if (!sv) return DCM_E_INVALID;
     sv->budget = hbm_budget;
     sv->pool = (uint8_t *)d_pool;
-    sv->pool_bytes = pool_bytes;
-    sv->free_list.push_back({0, pool_bytes & ~(kAlign - 1)});
-    if (hipGetDevice(&sv->device) != hipSuccess) {
+    sv->table_bytes = table_reserve(pool_bytes);
+    sv->pool_bytes = (pool_bytes - sv->table_bytes) & ~(kAlign - 1);
+    sv->tables = sv->pool + sv->pool_bytes;
+    sv->free_list.push_back({0, sv->pool_bytes});
+    sv->table_host.resize(sv->table_bytes);
+    if (hipGetDevice(&sv->device) != hipSuccess || hipStreamCreate(&sv->stream) != hipSuccess ||
+        hipEventCreateWithFlags(&sv->batch_done[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&sv->batch_done[1], hipEventDisableTiming) != hipSuccess) {
+        if (sv->stream) (void)hipStreamDestroy(sv->stream);
+        if (sv->batch_done[0]) (void)hipEventDestroy(sv->batch_done[0]);
         delete sv;
         return DCM_E_HIP;
     }
@@ -357,6 +534,10 @@ dcm_status dcm_server_destroy(dcm_server *sv)
         sv->cv.notify_all();
     }
     if (sv->worker.joinable()) sv->worker.join();
+    drop_groups(sv);
+    for (hipEvent_t e : sv->batch_done)
+        if (e) (void)hipEventDestroy(e);
+    if (sv->stream) (void)hipStreamDestroy(sv->stream);
     for (auto &kv : sv->reqs) delete kv.second;
     delete sv;
     return DCM_OK;

@@ -53,7 +53,8 @@ THERMO_DOUBLES = C.sizeof(Thermo) // 8     # 12 doubles per record
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
                 ("rejected", C.c_int64), ("queued", C.c_int64), ("running", C.c_int64),
-                ("batches", C.c_int64), ("bytes_in_use", C.c_size_t)]
+                ("batches", C.c_int64), ("bytes_in_use", C.c_size_t), ("groupings", C.c_int64),
+                ("grouping_ms", C.c_double), ("grouped_steps", C.c_int64), ("eager_steps", C.c_int64)]
 
 
 class DetectOut(C.Structure):
