@@ -505,6 +505,44 @@ def test_served_systems_equal_eager_runs_bitwise():
             assert th["ke"] == eth["ke"] and th["pe"] == eth["pe"] and th["pairs"] == eth["pairs"]
 
 
+def test_served_batches_mixed_grids_and_forms_bitwise():
+    """Batched launches over several resident systems give every system the bits of its own
+    eager run: grids whose sorts need 2 and 3 radix passes (the server runs all with 3), the
+    precision form, the thermostat and shifted energies (each its own launch sequence), several
+    systems per group, and a budget that admits them in waves."""
+    specs = [
+        (3000, (16.0, 16.0, 28.0), 8, {}),
+        (4000, (16.0, 16.0, 32.0), 10, {}),
+        (25000, (42.0, 42.0, 40.0), 8, {}),                       # 70,560 boxes: 3 radix passes
+        (5000, (18.0, 18.0, 30.0), 6, {}),
+        (4000, (16.0, 16.0, 32.0), 8, dict(precision=dcm.DCM_FP32C)),
+        (4000, (16.0, 16.0, 32.0), 8, dict(precision=dcm.DCM_FP32C)),
+        (3500, (16.0, 16.0, 30.0), 8, dict(thermostat=dcm.DCM_NOSE_HOOVER)),
+        (3500, (16.0, 16.0, 30.0), 9, dict(energy_shift=1)),
+    ]
+    reqs = []
+    for j, (n, box, ns, kw) in enumerate(specs):
+        st = synth.small_slab(n, box, 300 + j)
+        reqs.append((dcm.params(st.box, **kw), st, ns))
+    say("served batches: %d systems, mixed grids and forms" % len(reqs))
+    got, stats = _serve(reqs, budget=1 << 31, pool_bytes=1 << 31)
+    assert stats["completed"] == len(reqs)
+    assert stats["grouped_steps"] > 0 and stats["groupings"] >= 1
+    for (p, st, ns), (status, x, v, th) in zip(reqs, got):
+        ex, ev, eth = _eager(p, st, ns)
+        assert np.array_equal(x, ex) and np.array_equal(v, ev)
+        assert th["step"] == ns
+        assert th["ke"] == eth["ke"] and th["pe"] == eth["pe"] and th["pairs"] == eth["pairs"]
+    # waves: a budget for about two of the small systems at a time
+    small = [(p, st, ns) for (p, st, ns) in reqs[:2] + reqs[3:4]]
+    budget = int(2.2 * max(dcm.dcm_workspace_bytes(p, st.n) for p, st, _ in small))
+    got, stats = _serve(small, budget=budget, pool_bytes=1 << 30)
+    assert stats["completed"] == len(small)
+    for (p, st, ns), (status, x, v, th) in zip(small, got):
+        ex, ev, _ = _eager(p, st, ns)
+        assert np.array_equal(x, ex) and np.array_equal(v, ev)
+
+
 def test_server_budget_queues_and_rejects():
     sts = [synth.small_slab(3000, (16.0, 16.0, 28.0), 200 + j) for j in range(4)]
     p = dcm.params(sts[0].box)
