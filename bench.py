@@ -24,11 +24,11 @@ sys.path.insert(0, ROOT)
 FP64_VALU_PEAK_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 FLOPS_PER_PAIR = 41              # algorithmic FP64 flops per in-range ordered pair
 WORKLOAD = "slab2m"
-# HBM-side bytes per k_forces launch from FETCH_SIZE/WRITE_SIZE counter runs, scaled by a plain
-# 1 GiB copy (profiles/k_forces_slab2m_traffic.md). Valid only for the kernel source it was
+# HBM-side bytes per force-kernel launch from FETCH_SIZE/WRITE_SIZE counter runs, scaled by a plain
+# 1 GiB copy (profiles/KForces_slab2m_traffic.md). Valid only for the kernel source it was
 # taken on: reported as null once csrc/force.hip no longer hashes to this value.
-FORCE_TRAFFIC_BYTES = 2.225e9
-FORCE_TRAFFIC_SRC = "df64ab782ec30fbf"
+FORCE_TRAFFIC_BYTES = 2.228e9
+FORCE_TRAFFIC_SRC = "03b3471679fb2554"
 
 
 def force_traffic():
@@ -716,7 +716,7 @@ def main():
                                "r_c 2.5..6 (exponential), detect every 2nd step, dt 0.005, NVE",
                    "n_particles": state.n, "grid": list(sysm.dims), "detect_every": 2,
                    "thermo_every_step": True},
-        "roofline": {"bound": "alu", "kernel": "k_forces (FP64 pair forces, energy, virial)",
+        "roofline": {"bound": "alu", "kernel": "KForces (FP64 pair forces, energy, virial)",
                      "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": force_traffic(),
                      "avg_launch_ms": f_avg_s * 1e3, "pairs_per_launch": pairs,
