@@ -543,6 +543,42 @@ def test_served_batches_mixed_grids_and_forms_bitwise():
         assert np.array_equal(x, ex) and np.array_equal(v, ev)
 
 
+def test_server_failed_admission_leaves_others_intact():
+    """A request whose positions are not finite fails at admission with DCM_E_NONFINITE; the
+    requests around it are admitted, batched and finish with the bits of their eager runs."""
+    import time
+    sts = [synth.small_slab(3000, (16.0, 16.0, 28.0), 500 + j) for j in range(3)]
+    p = dcm.params(sts[0].box)
+    bad_x = sts[1].x.copy()
+    bad_x[0, 17] = np.nan
+    pool = dcm.workspace(1 << 30)
+    sv = dcm.dcm_server_create(1 << 29, pool)
+    tickets = [dcm.dcm_submit(sv, p, sts[0].x, sts[0].v, 6),
+               dcm.dcm_submit(sv, p, bad_x, sts[1].v, 6),
+               dcm.dcm_submit(sv, p, sts[2].x, sts[2].v, 6)]
+    res = {}
+    t0 = time.time()
+    while len(res) < 3 and time.time() - t0 < 60:
+        for t in tickets:
+            if t in res:
+                continue
+            if t == tickets[1]:                 # the raw call: the binding raises on errors
+                st = dcm._lib.dcm_poll(sv, t, None, None, None)
+                if st != dcm.DCM_PENDING:
+                    res[t] = (st, None, None)
+            else:
+                r = dcm.dcm_poll(sv, t, sts[0].n)
+                if r[0] == dcm.DCM_OK:
+                    res[t] = r
+        time.sleep(0.002)
+    dcm.dcm_server_destroy(sv)
+    assert len(res) == 3
+    assert res[tickets[1]][0] == dcm.DCM_E_NONFINITE
+    for t, st in ((tickets[0], sts[0]), (tickets[2], sts[2])):
+        ex, ev, _ = _eager(p, st, 6)
+        assert np.array_equal(res[t][1], ex) and np.array_equal(res[t][2], ev)
+
+
 def test_server_budget_queues_and_rejects():
     sts = [synth.small_slab(3000, (16.0, 16.0, 28.0), 200 + j) for j in range(4)]
     p = dcm.params(sts[0].box)
