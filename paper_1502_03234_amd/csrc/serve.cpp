@@ -50,6 +50,7 @@ struct Req {
     int period = 2;
     bool grouped = false;           // stepped by its group's graph in the current batch
     int32_t done_steps = 0;
+    dcm_status failed = DCM_OK;     // a launch for this system failed: it completes with this
     int last_record = 0;
     double *d_x = nullptr, *d_v = nullptr;
     dcm_thermo *d_th = nullptr;
@@ -295,10 +296,22 @@ void regroup(dcm_server *sv)
 // system its period (or its remaining steps) eagerly on its own stream.
 void advance_all(dcm_server *sv)
 {
-    for (Group &g : sv->groups) (void)hipGraphLaunch(g.graph, sv->stream);
+    for (Group &g : sv->groups) {
+        if (hipGraphLaunch(g.graph, sv->stream) == hipSuccess) continue;
+        (void)hipGetLastError();
+        // the members did not step: they end now, with the error, instead of with stale state
+        for (Req *r : g.members) {
+            r->failed = DCM_E_HIP;
+            r->err = "hipGraphLaunch of the batched period failed";
+            r->grouped = false;
+            r->done_steps = r->nsteps;
+        }
+        sv->regroup = true;
+    }
     int64_t grouped = 0, eager = 0;
     for (Req *r : sv->running) {
         const int32_t left = r->nsteps - r->done_steps;
+        if (r->failed != DCM_OK) continue;
         if (r->grouped) {
             r->sys->k += r->period;
             r->done_steps += r->period;
@@ -307,7 +320,13 @@ void advance_all(dcm_server *sv)
             grouped += 1;
         } else if (left > 0) {
             const int32_t q = std::min(left, r->period);
-            dcm_step(r->sys, q, r->stream, r->d_th);
+            const dcm_status st = dcm_step(r->sys, q, r->stream, r->d_th);
+            if (st != DCM_OK) {
+                r->failed = st;
+                r->err = dcm_last_error();
+                r->done_steps = r->nsteps;
+                continue;
+            }
             r->done_steps += q;
             r->last_record = q - 1;
             eager += 1;
@@ -403,8 +422,9 @@ void worker_loop(dcm_server *sv)
                 continue;
             }
             sv->regroup = true;
-            dcm_status s = finish(r);
-            std::string err = s == DCM_OK ? std::string() : std::string(dcm_last_error());
+            dcm_status s = r->failed != DCM_OK ? r->failed : finish(r);
+            std::string err = s == DCM_OK ? std::string()
+                              : (r->failed != DCM_OK ? r->err : std::string(dcm_last_error()));
             release_device(r);
             std::lock_guard<std::mutex> lk(sv->mu);
             r->status = s;
