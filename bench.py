@@ -552,6 +552,46 @@ def accuracy_study(equil: int, R: float = 20.0, time_steps: int = 200, detect_kw
     print(json.dumps(out), flush=True)
 
 
+def profile_study(nsteps: int = 100):
+    """Cutoff profile over the density profile (Figure 33 analogue): the 16,000-particle slab
+    (28 x 28 x 60) after `nsteps` NVE steps, for the default cutoffs (2.5 / 6.0) and the
+    thesis's Figure 33 pair (4.0 / 7.0). Per 1-sigma slice of z: number density, and the mean,
+    minimum and maximum r_c of the particles in the slice."""
+    import numpy as np
+    import torch
+    from paper_1502_03234_amd import dcm, synth
+
+    st = synth.named("slab16k")
+    Lx, Ly, Lz = st.box
+    edges = np.arange(0.0, Lz + 1e-9, 1.0)
+    out = {"study": "cutoff_profile", "workload": f"LJ slab 16,000 particles, box 28x28x60, {nsteps} NVE "
+           "steps, detect every 2nd step", "z_slices": [float(e) for e in edges[:-1]], "configs": []}
+    for rmin, rmax in ((2.5, 6.0), (4.0, 7.0)):
+        s = dcm.System(dcm.params(st.box, rc_min=rmin, rc_max=rmax), st.x, st.v)
+        s.step(nsteps, thermo=False)
+        x, _, rc, k = s.state()
+        torch.cuda.synchronize()
+        s.check()
+        s.close()
+        z = x[2].cpu().numpy()
+        r = rc.cpu().numpy()
+        sl = np.clip(np.digitize(z, edges) - 1, 0, len(edges) - 2)
+        cnt = np.bincount(sl, minlength=len(edges) - 1)
+        mean = np.bincount(sl, weights=r, minlength=len(edges) - 1) / np.maximum(cnt, 1)
+        lo = np.full(len(edges) - 1, np.nan)
+        hi = np.full(len(edges) - 1, np.nan)
+        for q in range(len(edges) - 1):
+            if cnt[q]:
+                lo[q], hi[q] = r[sl == q].min(), r[sl == q].max()
+        out["configs"].append({"rc_min": rmin, "rc_max": rmax, "step": k,
+                               "density": [round(float(c) / (Lx * Ly), 4) for c in cnt],
+                               "rc_mean": [round(float(m), 4) if c else None for m, c in zip(mean, cnt)],
+                               "rc_min_in_slice": [None if np.isnan(v) else round(float(v), 4) for v in lo],
+                               "rc_max_in_slice": [None if np.isnan(v) else round(float(v), 4) for v in hi]})
+        log(f"profile study: {rmin}/{rmax} done at step {k}")
+    print(json.dumps(out), flush=True)
+
+
 def _detect_kw(args) -> dict:
     return dict(bin=args.study_bin, smooth_passes=args.study_smooth,
                 min_component=args.study_min_component)
@@ -581,6 +621,8 @@ def main():
     ap.add_argument("--accuracy-study", type=int, default=-1, metavar="EQUIL",
                     help="force accuracy (Eq. 20) of a grid of cutoff configurations against the "
                          "exact image sum, on the thesis slab after EQUIL NVT steps")
+    ap.add_argument("--profile-study", type=int, default=0, metavar="STEPS",
+                    help="cutoff profile over the density profile of the 16k slab after STEPS steps")
     ap.add_argument("--study-bin", type=float, default=1.0,
                     help="--nvt-study / --accuracy-study: density box edge (the thesis uses ~2.6)")
     ap.add_argument("--study-smooth", type=int, default=1, help="studies: smoothing passes")
@@ -607,6 +649,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copied {src.numel() * 8} bytes")
+        return
+    if args.profile_study:
+        profile_study(args.profile_study)
         return
     if args.accuracy_study >= 0:
         accuracy_study(args.accuracy_study, detect_kw=_detect_kw(args))
