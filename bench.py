@@ -592,6 +592,65 @@ def profile_study(nsteps: int = 100):
     print(json.dumps(out), flush=True)
 
 
+def speedup_study(equil: int = 5000, nsteps: int = 200):
+    """DCM against a static cutoff r_c = r_c^max (Figure 38 analogue) on the thesis's slab
+    geometry at its speedup-measurement size: 192,000 particles in a 76 x 76 x 44 block centred
+    in 76 x 76 x 88, equilibrated `equil` Nose-Hoover steps (T* = 0.7, static r_c = 5.0). From
+    that one state, each configuration runs `nsteps` timed NVE steps (after 10 untimed ones);
+    reports ms per step, the force kernel's ms per launch, pairs per particle and the speedup of
+    DCM over the static cutoff (which runs without interface detection)."""
+    import numpy as np
+    import torch
+    from paper_1502_03234_amd import dcm, synth
+
+    st = synth.named("thesis192k")
+    t0 = time.perf_counter()
+    s = dcm.System(dcm.params(st.box, rc_min=5.0, rc_max=5.0, thermostat=dcm.DCM_NOSE_HOOVER,
+                              temperature=0.7, tdamp=0.5), st.x, st.v)
+    for k in range(0, equil, 1000):
+        s.step(min(1000, equil - k), thermo=False)
+        torch.cuda.synchronize()
+    s.check()
+    x, v, _, _ = s.state()
+    torch.cuda.synchronize()
+    s.close()
+    log(f"speedup study: equilibrated {equil} steps in {time.perf_counter() - t0:.1f} s")
+
+    def run(rmin, rmax):
+        # the static cutoff method has no interface detection
+        de = 0 if rmin == rmax else 2
+        sysm = dcm.System(dcm.params(st.box, rc_min=rmin, rc_max=rmax, detect_every=de), x, v)
+        sysm.step(10, thermo=False)
+        torch.cuda.synchronize()
+        dcm.dcm_set_profiling(sysm.h, 2)            # events around the force launches only
+        t1 = time.perf_counter()
+        th = dcm.thermo_records(sysm.step(nsteps))
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3 / nsteps
+        fms, fcount = dcm.dcm_stage_times(sysm.h)["forces"]
+        sysm.check()
+        sysm.close()
+        return ms, float(np.mean([r["pairs"] for r in th])) / st.n, fms / max(fcount, 1)
+
+    rows = []
+    static = {}
+    for rmin, rmax in ((3.0, 6.0), (3.0, 7.0), (3.0, 8.0), (4.0, 8.0), (4.5, 9.5), (3.0, 10.0)):
+        if rmax not in static:
+            static[rmax] = run(rmax, rmax)
+        ms, pp, fms = run(rmin, rmax)
+        sms, spp, sfms = static[rmax]
+        rows.append({"config": "DCM %.1f/%.1f" % (rmin, rmax), "ms_per_step": ms, "pairs_per_particle": pp,
+                     "force_ms": fms, "static_ms_per_step": sms, "static_pairs_per_particle": spp,
+                     "static_force_ms": sfms, "speedup": sms / ms, "force_speedup": sfms / fms,
+                     "pair_ratio": spp / pp})
+        log(f"speedup study: DCM {rmin}/{rmax}: {ms:.3f} ms (forces {fms:.3f}) vs static {sms:.3f} ms "
+            f"(forces {sfms:.3f}): {sms / ms:.2f}x step, {sfms / fms:.2f}x forces, pairs {pp:.0f} vs {spp:.0f}")
+    out = {"study": "speedup", "workload": "192,000 LJ particles, 76 x 76 x 44 block in 76 x 76 x 88, "
+           f"NVT-equilibrated {equil} steps, then {nsteps} timed NVE steps per configuration, FP64, "
+           "detect every 2nd step", "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def _detect_kw(args) -> dict:
     return dict(bin=args.study_bin, smooth_passes=args.study_smooth,
                 min_component=args.study_min_component)
@@ -621,6 +680,8 @@ def main():
     ap.add_argument("--accuracy-study", type=int, default=-1, metavar="EQUIL",
                     help="force accuracy (Eq. 20) of a grid of cutoff configurations against the "
                          "exact image sum, on the thesis slab after EQUIL NVT steps")
+    ap.add_argument("--speedup-study", type=int, default=0, metavar="EQUIL",
+                    help="DCM vs static r_c^max on the thesis's 192,000-particle slab after EQUIL steps")
     ap.add_argument("--profile-study", type=int, default=0, metavar="STEPS",
                     help="cutoff profile over the density profile of the 16k slab after STEPS steps")
     ap.add_argument("--study-bin", type=float, default=1.0,
@@ -649,6 +710,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copied {src.numel() * 8} bytes")
+        return
+    if args.speedup_study:
+        speedup_study(args.speedup_study)
         return
     if args.profile_study:
         profile_study(args.profile_study)
@@ -722,7 +786,7 @@ def main():
     static = None
     if args.compare_static:
         sysm.close()
-        ps = dcm.params(state.box, rc_min=6.0, rc_max=6.0, precision=prec)
+        ps = dcm.params(state.box, rc_min=6.0, rc_max=6.0, precision=prec, detect_every=0)
         ss = dcm.System(ps, state.x, state.v)
         dcm.dcm_step(ss.h, 3, stream, th)
         torch.cuda.synchronize()

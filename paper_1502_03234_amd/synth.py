@@ -307,6 +307,11 @@ def named(name: str, temperature: float = 0.7) -> State:
         # centred in a 22 x 22 x 88 box; lattice sites stand in for its random placement
         return slab(16_000, 0, (22.0, 22.0, 88.0), seed=1006, temperature=temperature,
                     half_thickness=22.0)
+    if name == "thesis192k":
+        # the same geometry scaled laterally to 192,000 particles (the size of the thesis's
+        # speedup measurements, Section 6.2): a 76 x 76 x 44 block in a 76 x 76 x 88 box
+        return slab(192_000, 0, (76.0, 76.0, 88.0), seed=1007, temperature=temperature,
+                    half_thickness=22.0)
     if name == "droplet1m":
         return droplet(1_000_000, 166.0, seed=1005, temperature=temperature)
     raise KeyError(name)
