@@ -176,6 +176,7 @@ size_t layout(dcm_system *s, void *ws)
     s->gw.tdirty = b.take<uint32_t>(2 * distance_tiles(s->grid));
     s->gw.tcur = b.take<uint32_t>(2 * distance_tiles(s->grid));
     s->gw.dist2 = b.take<double>(G);
+    s->gw.ctile = b.take<uint8_t>(component_tiles(s->grid));
     s->nfb = force_blocks(n);
     s->nkb = stream_blocks(n);
     s->fparts = b.take<Partial>(s->nfb);
@@ -639,6 +640,7 @@ static size_t grid_layout(const Grid &g, GridWork &w, void *ws, double cap)
     w.tdirty = b.take<uint32_t>(2 * distance_tiles(g));
     w.tcur = b.take<uint32_t>(2 * distance_tiles(g));
     w.dist2 = b.take<double>(G);
+    w.ctile = b.take<uint8_t>(component_tiles(g));
     return b.off + 256;
 }
 

@@ -26,12 +26,17 @@ __device__ __forceinline__ int64_t lin(const Grid &g, int64_t i, int64_t j, int6
     return (k * g.n[1] + j) * g.n[0] + i;
 }
 
+// Box coordinates of linear index c. Grids hold fewer than 2^31 boxes (checked when a system
+// or a grid workspace is set up), so 32-bit unsigned division suffices (64-bit division is a
+// long emulated sequence).
 __device__ __forceinline__ void coords(const Grid &g, int64_t c, int64_t &i, int64_t &j, int64_t &k)
 {
-    i = c % g.n[0];
-    int64_t r = c / g.n[0];
-    j = r % g.n[1];
-    k = r / g.n[1];
+    const uint32_t u = (uint32_t)c, nx = (uint32_t)g.n[0], ny = (uint32_t)g.n[1];
+    const uint32_t r = u / nx;
+    const uint32_t z = r / ny;
+    i = (int64_t)(u - r * nx);
+    j = (int64_t)(r - z * ny);
+    k = (int64_t)z;
 }
 
 // ---- smoothing ------------------------------------------------------------------------
@@ -280,11 +285,13 @@ __device__ void unite(uint32_t *parent, uint32_t a, uint32_t b)
     }
 }
 
-// Block-local labelling: each workgroup owns a CT^3 tile of boxes, joins same-phase face
-// neighbours inside the tile with a union-find in LDS, and writes for every box of the phase
-// the global index of its tile-local root (the smallest member of its tile-local piece: local
-// and global linear orders agree inside a tile). csize is cleared on the way for the boxes of the
-// phase (the only boxes that can be roots).
+// Block-local labelling: each workgroup owns a CT^3 tile of boxes and records the tile's kind.
+// A tile without boxes of the phase, or made only of them with at least `limit` in the grid (one
+// piece, large whatever it joins), writes nothing else. Any other tile joins same-phase face
+// neighbours with a union-find in LDS and writes for every box of the phase the global index of
+// its tile-local root (the smallest member of its tile-local piece: local and global linear
+// orders agree inside a tile) and the piece's size; csize is cleared on the way for the boxes of
+// the phase (the only boxes that can be roots).
 constexpr int CT = 8;
 constexpr int kCtBoxes = CT * CT * CT;
 
@@ -313,6 +320,18 @@ __device__ __forceinline__ void lunite(uint32_t *lp, uint32_t a, uint32_t b)
     }
 }
 
+// Tile kinds of one component pass (ctile[t]): kCtFull tiles keep per-box union-find entries;
+// a kCtLarge tile holds only boxes of the phase, at least `limit` of them (one piece that is large
+// whatever it joins); a kCtNone tile holds no box of the phase. Per-box entries of the last two
+// kinds are neither written nor read.
+constexpr uint8_t kCtFull = 0, kCtLarge = 1, kCtNone = 2;
+
+__device__ __forceinline__ int64_t ct_tile(const Grid &g, int64_t i, int64_t j, int64_t k)
+{
+    const int64_t ntx = (g.n[0] + CT - 1) / CT, nty = (g.n[1] + CT - 1) / CT;
+    return ((k / CT) * nty + j / CT) * ntx + i / CT;
+}
+
 struct KCcLocal {
     static constexpr int kThreads = kCtBoxes, kWaves = 0;
     struct Args {
@@ -322,6 +341,8 @@ struct KCcLocal {
         uint32_t *parent;
         uint32_t *csize;
         uint32_t *psize;
+        uint8_t *ctile;
+        uint32_t limit;
     };
     static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
 };
@@ -334,6 +355,8 @@ __device__ void KCcLocal::run(const Args &args_, uint32_t blk, uint32_t)
     uint32_t *parent = args_.parent;
     uint32_t *csize = args_.csize;
     uint32_t *psize = args_.psize;
+    uint8_t *ctile = args_.ctile;
+    const uint32_t limit = args_.limit;
     __shared__ uint32_t lp[kCtBoxes];
     __shared__ uint32_t lc[kCtBoxes];
     const int ntx = (g.n[0] + CT - 1) / CT, nty = (g.n[1] + CT - 1) / CT;
@@ -348,7 +371,12 @@ __device__ void KCcLocal::run(const Args &args_, uint32_t blk, uint32_t)
     // a tile whose boxes all have the phase (or none does) needs no union-find: its in-grid
     // boxes form one box-shaped piece whose smallest member is the tile's first box
     const int nmine = __syncthreads_count(mine), nin = __syncthreads_count(in);
-    if (nmine == 0 || nmine == nin) {
+    if (nmine == 0 || (nmine == nin && (uint32_t)nmine >= limit)) {
+        if (l == 0) ctile[b] = nmine == 0 ? kCtNone : kCtLarge;
+        return;
+    }
+    if (l == 0) ctile[b] = kCtFull;
+    if (nmine == nin) {
         if (in) {
             if (mine) {
                 csize[c] = 0;
@@ -402,6 +430,7 @@ struct KCcMerge {
         uint32_t *parent;
         uint32_t *psize;
         uint32_t limit;
+        const uint8_t *ctile;
     };
     static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
 };
@@ -414,6 +443,7 @@ __device__ void KCcMerge::run(const Args &args_, uint32_t blk, uint32_t)
     uint32_t *parent = args_.parent;
     uint32_t *psize = args_.psize;
     uint32_t limit = args_.limit;
+    const uint8_t *ctile = args_.ctile;
     int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
     if (c >= g.G || label[c] != phase) return;
     int64_t i, j, k;
@@ -422,14 +452,28 @@ __device__ void KCcMerge::run(const Args &args_, uint32_t blk, uint32_t)
     const bool fy = (j % CT) == CT - 1 || j + 1 == g.n[1];
     const bool fz = (k % CT) == CT - 1 || k + 1 == g.n[2];
     if (!(fx || fy || fz)) return;
-    int64_t nb[3] = {fx ? lin(g, i + 1 == g.n[0] ? 0 : i + 1, j, k) : -1,
-                     fy ? lin(g, i, j + 1 == g.n[1] ? 0 : j + 1, k) : -1,
-                     fz ? lin(g, i, j, k + 1 == g.n[2] ? 0 : k + 1) : -1};
-    // piece sizes only move from a value >= limit to kTouched (also >= limit) while this runs,
-    // so every thread takes the same small / large decisions
-    const bool small = psize[c] < limit;
+    const int64_t ip = i + 1 == g.n[0] ? 0 : i + 1, jp = j + 1 == g.n[1] ? 0 : j + 1,
+                  kp = k + 1 == g.n[2] ? 0 : k + 1;
+    const int64_t nb[3] = {fx ? lin(g, ip, j, k) : -1, fy ? lin(g, i, jp, k) : -1, fz ? lin(g, i, j, kp) : -1};
+    const int64_t nt[3] = {ct_tile(g, ip, j, k), ct_tile(g, i, jp, k), ct_tile(g, i, j, kp)};
+    // A box of a kCtLarge tile belongs to a large piece without union-find entries: a small
+    // piece touching it is tagged (psize = kTouched, which the size count reads as "large")
+    // instead of joined. Otherwise piece sizes only move to kTouched (>= limit) while this
+    // runs, and a face is joined when at least one of its two pieces can still be small.
+    const bool large_tile = ctile[ct_tile(g, i, j, k)] != kCtFull;
+    const bool small = !large_tile && psize[c] < limit;
     for (int q = 0; q < 3; ++q) {
         if (nb[q] < 0 || label[nb[q]] != phase) continue;
+        const bool nlarge_tile = ctile[nt[q]] != kCtFull;
+        if (large_tile && nlarge_tile) continue;
+        if (large_tile) {
+            if (psize[nb[q]] < limit) psize[nb[q]] = kTouched;
+            continue;
+        }
+        if (nlarge_tile) {
+            if (small) psize[c] = kTouched;
+            continue;
+        }
         const bool nsmall = psize[nb[q]] < limit;
         if (!small && !nsmall) continue;
         unite(parent, (uint32_t)c, (uint32_t)nb[q]);
@@ -441,18 +485,22 @@ __device__ void KCcMerge::run(const Args &args_, uint32_t blk, uint32_t)
 struct KCcFlatten {
     static constexpr int kThreads = kBlock, kWaves = 0;
     struct Args {
-        int64_t G;
+        Grid g;
         uint32_t *parent;
+        const uint8_t *ctile;
     };
     static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
 };
 
 __device__ void KCcFlatten::run(const Args &args_, uint32_t blk, uint32_t)
 {
-    int64_t G = args_.G;
+    const Grid &g = args_.g;
     uint32_t *parent = args_.parent;
     int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
-    if (c >= G) return;
+    if (c >= g.G) return;
+    int64_t i, j, k;
+    coords(g, c, i, j, k);
+    if (args_.ctile[ct_tile(g, i, j, k)] != kCtFull) return;
     uint32_t p = parent[c];
     if (p == kInvalid) return;
     parent[c] = find_root(parent, (uint32_t)c);
@@ -465,24 +513,31 @@ __device__ void KCcFlatten::run(const Args &args_, uint32_t blk, uint32_t)
 struct KCcSize {
     static constexpr int kThreads = kBlock, kWaves = 0;
     struct Args {
-        int64_t G;
+        Grid g;
         const uint32_t *parent;
         const uint32_t *psize;
         uint32_t *csize;
         uint32_t limit;
+        const uint8_t *ctile;
     };
     static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
 };
 
 __device__ void KCcSize::run(const Args &args_, uint32_t blk, uint32_t)
 {
-    int64_t G = args_.G;
+    const Grid &g = args_.g;
     const uint32_t *parent = args_.parent;
     const uint32_t *psize = args_.psize;
     uint32_t *csize = args_.csize;
     uint32_t limit = args_.limit;
     int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
-    uint32_t r = c < G ? parent[c] : kInvalid;
+    bool full = false;
+    if (c < g.G) {
+        int64_t i, j, k;
+        coords(g, c, i, j, k);
+        full = args_.ctile[ct_tile(g, i, j, k)] == kCtFull;
+    }
+    uint32_t r = full ? parent[c] : kInvalid;
     const uint32_t ps = r != kInvalid ? psize[c] : 0u;
     const bool small = r != kInvalid && ps < limit;
     const bool touched = r != kInvalid && ps == kTouched;
@@ -511,7 +566,7 @@ __device__ void KCcSize::run(const Args &args_, uint32_t blk, uint32_t)
 struct KCcFlip {
     static constexpr int kThreads = kBlock, kWaves = 0;
     struct Args {
-        int64_t G;
+        Grid g;
         uint8_t *label;
         uint8_t phase;
         const uint32_t *parent;
@@ -520,13 +575,14 @@ struct KCcFlip {
         uint32_t limit;
         long long *stats;
         int slot;
+        const uint8_t *ctile;
     };
     static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
 };
 
 __device__ void KCcFlip::run(const Args &args_, uint32_t blk, uint32_t)
 {
-    int64_t G = args_.G;
+    const Grid &g = args_.g;
     uint8_t *label = args_.label;
     uint8_t phase = args_.phase;
     const uint32_t *parent = args_.parent;
@@ -537,7 +593,13 @@ __device__ void KCcFlip::run(const Args &args_, uint32_t blk, uint32_t)
     int slot = args_.slot;
     int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
     bool flip = false, root = false;
-    if (c < G && label[c] == phase && psize[c] < limit) {
+    bool full = false;
+    if (c < g.G) {
+        int64_t i, j, k;
+        coords(g, c, i, j, k);
+        full = args_.ctile[ct_tile(g, i, j, k)] == kCtFull;
+    }
+    if (full && label[c] == phase && psize[c] < limit) {
         uint32_t r = parent[c];
         if (csize[r] < limit) {
             flip = true;
@@ -995,14 +1057,19 @@ void launch_segment(const Grid &g, const uint32_t *img, const double *km, int32_
     for (int pass = 0; pass < 2; ++pass) {
         uint8_t phase = pass == 0 ? 1 : 0;
         unsigned nct = (unsigned)(((g.n[0] + CT - 1) / CT) * ((g.n[1] + CT - 1) / CT) * ((g.n[2] + CT - 1) / CT));
-        emit<KCcLocal>({g, w.label, phase, w.parent, w.csize, w.gtmp}, nct, st);
-        emit<KCcMerge>({g, w.label, phase, w.parent, w.gtmp, (uint32_t)min_component}, grid1(g.G), st);
-        emit<KCcFlatten>({g.G, w.parent}, grid1(g.G), st);
-        emit<KCcSize>({g.G, w.parent, (const uint32_t *)w.gtmp, w.csize, (uint32_t)min_component},
-                       grid1(g.G), st);
-        emit<KCcFlip>({g.G, w.label, phase, w.parent, (const uint32_t *)w.gtmp, w.csize,
-                       (uint32_t)min_component, w.stats, 1 + pass}, grid1(g.G), st);
+        const uint32_t limit = (uint32_t)min_component;
+        emit<KCcLocal>({g, w.label, phase, w.parent, w.csize, w.gtmp, w.ctile, limit}, nct, st);
+        emit<KCcMerge>({g, w.label, phase, w.parent, w.gtmp, limit, w.ctile}, grid1(g.G), st);
+        emit<KCcFlatten>({g, w.parent, w.ctile}, grid1(g.G), st);
+        emit<KCcSize>({g, w.parent, (const uint32_t *)w.gtmp, w.csize, limit, w.ctile}, grid1(g.G), st);
+        emit<KCcFlip>({g, w.label, phase, w.parent, (const uint32_t *)w.gtmp, w.csize, limit, w.stats,
+                       1 + pass, w.ctile}, grid1(g.G), st);
     }
+}
+
+int64_t component_tiles(const Grid &g)
+{
+    return (int64_t)((g.n[0] + CT - 1) / CT) * ((g.n[1] + CT - 1) / CT) * ((g.n[2] + CT - 1) / CT);
 }
 
 int64_t distance_tiles(const Grid &g)

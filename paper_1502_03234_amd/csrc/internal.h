@@ -84,6 +84,7 @@ struct GridWork {
     uint32_t *tdirty;       // [2 * distance_tiles] pass flags of the distance tiles
     uint32_t *tcur;         // [2 * distance_tiles] which distance copy is current per tile
     double *dist2;          // second copy of the distance grid
+    uint8_t *ctile;         // [component_tiles] tile kinds of the current component pass
 };
 
 // ---- launchers (each enqueues on `st`; no synchronization) ------------------------------
@@ -109,6 +110,7 @@ void launch_segment(const Grid &g, const uint32_t *img, const double *km, int32_
                     GridWork w, hipStream_t st);
 int max_distance_sweeps(const Grid &g, double cap);
 int64_t distance_tiles(const Grid &g);
+int64_t component_tiles(const Grid &g);
 void launch_distance(const Grid &g, double cap, const uint8_t *label, double *dist, GridWork w,
                      hipStream_t st);
 void launch_cutoffs(const Grid &g, PSet s, int64_t n, const double *dist, double cap,
