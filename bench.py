@@ -226,11 +226,12 @@ def droplet_study(nsteps: int):
     print(json.dumps(out), flush=True)
 
 
-def serving_study(nseeds: int, nsys: int = 64, nsteps: int = 100, load: float = 0.8):
+def serving_study(nseeds: int, nsys: int = 64, nsteps: int = 100, load: float = 0.8,
+                  droplets: bool = False):
     """Serving form against one-system-at-a-time solves on the same Poisson traces.
 
-    Systems: 64 slabs, N log-uniform on [4,000, 200,000], T* uniform on [0.65, 0.85], 100 steps
-    each. Sequential: every request is solved alone (H2D copy, create, 100 steps, D2H copy);
+    Systems: 64 slabs (with `droplets`, every 4th system a droplet of the same size in vapor),
+    N log-uniform on [4,000, 200,000], T* uniform on [0.65, 0.85], 100 steps each. Sequential: every request is solved alone (H2D copy, create, 100 steps, D2H copy);
     its wall-clock service time is measured once and the FIFO timeline of each trace follows
     from the arrival times (exact for a single FIFO server). Capacity = requests / sum of
     service times; arrivals are Poisson at load x capacity. Server: the same requests are
@@ -241,7 +242,8 @@ def serving_study(nseeds: int, nsys: int = 64, nsteps: int = 100, load: float = 
     from paper_1502_03234_amd import dcm, synth
 
     trace = synth.serving_trace(1, nsys)
-    systems = [synth.serving_system(j, n, t) for j, (n, t) in enumerate(trace)]
+    systems = [synth.serving_droplet(j, n, t) if droplets and j % 4 == 3 else synth.serving_system(j, n, t)
+               for j, (n, t) in enumerate(trace)]
     params = [dcm.params(s.box) for s in systems]
     sizes = np.array([s.n for s in systems])
     log(f"serving: {nsys} systems, {sizes.sum()} particles, sizes {sizes.min()}..{sizes.max()}")
@@ -319,7 +321,7 @@ def serving_study(nseeds: int, nsys: int = 64, nsteps: int = 100, load: float = 
     dcm.dcm_server_destroy(sv)
     log(f"saturated: server makespan {makespan:.3f}s, sequential {svc.sum():.3f}s, batches "
         f"{sat_stats['batches']}, groupings {sat_stats['groupings']} ({sat_stats['grouping_ms']:.1f} ms)")
-    out = {"study": "serving", "systems": nsys, "steps_each": nsteps, "seeds": nseeds,
+    out = {"study": "serving", "mix": "slabs and droplets (every 4th)" if droplets else "slabs", "systems": nsys, "steps_each": nsteps, "seeds": nseeds,
            "particles_total": int(sizes.sum()), "load": load, "arrival_rate_per_s": rate,
            "hbm_budget_bytes": budget, "sequential_capacity_req_per_s": cap,
            "server": {"throughput_atom_steps_per_s": float(np.mean(srv_tp)),
@@ -674,6 +676,8 @@ def main():
                     help="droplet (non-planar interface) study of both forms over STEPS steps")
     ap.add_argument("--serve", type=int, default=0, metavar="SEEDS",
                     help="serving study: 64 systems, Poisson arrivals, server vs sequential")
+    ap.add_argument("--serve-droplets", action="store_true",
+                    help="--serve: every 4th system is a droplet instead of a slab")
     ap.add_argument("--nvt-study", type=str, default="", metavar="EQUIL,SAMPLE[,CFG...]",
                     help="Table 1 / Figure 37 observables of the thesis's 16,000-particle slab under "
                          "NVT; optional CFG indices pick Table 1 rows (0-6)")
@@ -729,7 +733,7 @@ def main():
         precision_study(args.precision_study)
         return
     if args.serve:
-        serving_study(args.serve)
+        serving_study(args.serve, droplets=args.serve_droplets)
         return
     if args.droplet_study:
         droplet_study(args.droplet_study)

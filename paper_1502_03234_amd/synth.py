@@ -334,6 +334,14 @@ def serving_system(j: int, n_target: int, temperature: float) -> State:
     return slab(n_liq, n_vap, (float(L), float(L), 60.0), seed=4000 + j, temperature=temperature)
 
 
+def serving_droplet(j: int, n_target: int, temperature: float) -> State:
+    """Serving-trace droplet j: n_target liquid particles (radius R for density 0.8) centred in a
+    cubic box of side L = max(14, ceil(2 R + 16)) with vapor at 0.01 outside R + 1."""
+    R = (3.0 * n_target / (0.8 * 4.0 * math.pi)) ** (1.0 / 3.0)
+    L = max(14, int(math.ceil(2.0 * R + 16.0)))
+    return droplet(n_target, float(L), seed=5000 + j, temperature=temperature)
+
+
 def serving_trace(trace_seed: int, n_systems: int = 64, n_min: int = 4000, n_max: int = 200_000,
                   t_range=(0.65, 0.85)):
     """(N_target, T*) per system, N log-uniform on [n_min, n_max], T* uniform on t_range."""
