@@ -363,6 +363,38 @@ def test_droplet1m_segmentation_and_sampled_parity():
 
 
 @pytest.mark.slow
+@pytest.mark.parametrize("prec, tol", [(dcm.DCM_FP64, FORCE_TOL), (dcm.DCM_FP32C, 1e-5)])
+def test_slab256k_both_forms_after_steps(prec, tol):
+    """The 256,000-particle slab (the precision form's workload) after 20 steps of each form:
+    the last detection (step 20) equals the oracle's on the same positions, and forces and pair
+    counts of sampled particles match the oracle run on the GPU's cutoffs (FP64 1e-12, FP32
+    form 1e-5 per atom; pair sets equal in both forms)."""
+    st = synth.named("slab256k")
+    p, po = make(st, precision=prec)
+    say(f"slab256k: 20 steps, precision {prec}")
+    s = dcm.System(p, st.x, st.v)
+    s.step(20, thermo=False)
+    fo = s.forces(per_atom=True, thermo=False)
+    x, v, rc, k = s.state()
+    torch.cuda.synchronize()
+    s.check()
+    assert k == 20
+    xw = x.cpu().numpy()
+    od = O.detect(po, xw)
+    rc_gpu = rc.cpu().numpy()
+    assert rc_close(rc_gpu, od.rc), "cutoffs"
+    idx = np.random.default_rng(12).choice(st.n, 2000, replace=False)
+    edge = np.nonzero((xw[1] < 7) | (xw[1] > st.box[1] - 7))[0][:300]
+    idx = np.unique(np.concatenate([idx, edge]))
+    ref = O.forces(po, xw, rc_gpu, subset=idx)
+    err = force_err(fo["f"].cpu().numpy()[:, idx], ref.f)
+    say(f"slab256k precision {prec}: max sampled force error {err.max():.2e}")
+    assert err.max() <= tol
+    assert np.array_equal(fo["pairs"].cpu().numpy()[idx].astype(np.int64), ref.pairs)
+    s.close()
+
+
+@pytest.mark.slow
 def test_slab2m_sampled_parity():
     st = synth.named("slab2m")
     p, po = make(st)
