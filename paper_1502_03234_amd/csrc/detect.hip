@@ -747,7 +747,10 @@ __device__ void KDistTiles::run(const Args &args_, uint32_t blk, uint32_t nblk)
     const bool converged = it > 0 &&
         __hip_atomic_load(changed + it - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
     const uint32_t mycur = cprev[b];
-    if (converged || dflag[b] == 0) {
+    // once a pass has changed nothing, later passes leave every array as it is (the gather
+    // takes the copy flags of the last pass that ran)
+    if (converged) return;
+    if (dflag[b] == 0) {
         if (threadIdx.x == 0) { cnext[b] = mycur; dflag[b] = 0u; }
         return;
     }
@@ -871,14 +874,19 @@ __device__ void KDistTiles::run(const Args &args_, uint32_t blk, uint32_t nblk)
     }
 }
 
-// Final values into d0: boxes whose tile ended with the second copy current are copied.
+// Final values into d0: boxes whose tile ended with the second copy current are copied. The
+// copy flags are those written by the last pass that ran: the first pass that changed nothing
+// (later passes exit at once), or the last pass of the budget.
 struct KDistGather {
     static constexpr int kThreads = kBlock, kWaves = 0;
     struct Args {
         Grid g;
         double *d0;
         const double *d1;
-        const uint32_t *cur_final;
+        const uint32_t *cur;        // [2][tiles] copy flags of even / odd passes
+        const uint32_t *changed;    // [max_sweeps] per-pass change flags
+        int max_sweeps;
+        int ntiles;
     };
     static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
 };
@@ -888,7 +896,10 @@ __device__ void KDistGather::run(const Args &args_, uint32_t blk, uint32_t)
     Grid g = args_.g;
     double *d0 = args_.d0;
     const double *d1 = args_.d1;
-    const uint32_t *cur_final = args_.cur_final;
+    int last = args_.max_sweeps - 1;
+    for (int q = 0; q < args_.max_sweeps; ++q)
+        if (args_.changed[q] == 0) { last = q; break; }
+    const uint32_t *cur_final = args_.cur + ((last + 1) & 1) * args_.ntiles;
     int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
     if (c >= g.G) return;
     int64_t i, j, k;
@@ -1082,7 +1093,7 @@ int max_distance_sweeps(const Grid &g, double cap)
 {
     double hmin = std::min(g.h[0], std::min(g.h[1], g.h[2]));
     int depth = (int)std::ceil(cap / hmin);
-    return depth / std::min(TX, std::min(TY, TZ)) + 12;
+    return depth / std::min(TX, std::min(TY, TZ)) + 24;
 }
 
 void launch_distance(const Grid &g, double cap, const uint8_t *label, double *dist, GridWork w,
@@ -1096,8 +1107,7 @@ void launch_distance(const Grid &g, double cap, const uint8_t *label, double *di
     launch_fill_u32(w.tcur, 0u, 2 * (int64_t)ntiles, st);
     for (int it = 0; it < ms; ++it)
         emit<KDistTiles>({g, label, dist, w.dist2, cap, w.changed, w.tdirty, w.tcur, it}, ntiles, st);
-    emit<KDistGather>({g, dist, (const double *)w.dist2, (const uint32_t *)(w.tcur + (ms & 1) * ntiles)},
-                   grid1(g.G), st);
+    emit<KDistGather>({g, dist, (const double *)w.dist2, w.tcur, w.changed, ms, (int)ntiles}, grid1(g.G), st);
     emit<KDistFinish>({w.changed, ms, w.stats + 5, w.flags}, 1, st);
 }
 
