@@ -42,7 +42,8 @@ class Params(C.Structure):
                 ("alpha", C.c_double), ("bin", C.c_double), ("smooth_passes", C.c_int32),
                 ("min_component", C.c_int32), ("detect_every", C.c_int32),
                 ("pair_rule", C.c_int32), ("energy_shift", C.c_int32), ("dt", C.c_double),
-                ("temperature", C.c_double), ("tdamp", C.c_double), ("thermostat", C.c_int32), ("cutoff_shape", C.c_int32)]
+                ("temperature", C.c_double), ("tdamp", C.c_double), ("thermostat", C.c_int32), ("cutoff_shape", C.c_int32),
+                ("tail", C.c_int32)]
 
 
 class Thermo(C.Structure):
@@ -53,7 +54,8 @@ class Thermo(C.Structure):
 class DetectOut(C.Structure):
     _fields_ = [("count", C.c_void_p), ("smooth", C.c_void_p), ("raw", C.c_void_p),
                 ("label", C.c_void_p), ("dist", C.c_void_p), ("d", C.c_void_p),
-                ("rc", C.c_void_p), ("km", C.c_double * 3), ("stats", C.c_int64 * 6)]
+                ("rc", C.c_void_p), ("km", C.c_double * 3), ("stats", C.c_int64 * 6),
+                ("dist_v", C.c_void_p)]
 
 
 _lib = None
@@ -87,6 +89,10 @@ def lib():
         L.orc_forces.argtypes = [P, i64, vp, vp, i64, vp, i32, vp, vp, vp, vp]
         L.orc_forces_images.argtypes = [P, i64, vp, d, i64, vp, vp, vp]
         L.orc_run.argtypes = [P, i64, vp, vp, vp, vp, i64, i32, i32, vp, vp]
+        L.orc_tail_planar.argtypes = [P, d, d, d, d, vp, vp]
+        L.orc_interp_grad.argtypes = [vp, vp, vp, vp, vp]
+        L.orc_interp_grad.restype = d
+        L.orc_tail.argtypes = [P, vp, vp, vp, i64, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -98,7 +104,7 @@ def _p(a):
 def params(box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_min=2.5, rc_max=6.0, alpha=-0.5,
            bin=1.0, smooth_passes=1, min_component=27, detect_every=2, pair_rule=0,
            energy_shift=0, dt=0.005, temperature=0.7, tdamp=0.5, thermostat=0,
-           cutoff_shape=0) -> Params:
+           cutoff_shape=0, tail=0) -> Params:
     p = Params()
     p.box[:] = [float(b) for b in box]
     p.epsilon, p.sigma, p.mass = epsilon, sigma, mass
@@ -108,6 +114,7 @@ def params(box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_min=2.5, rc_max=6.0, alp
     p.dt = dt
     p.temperature, p.tdamp, p.thermostat = temperature, tdamp, thermostat
     p.cutoff_shape = cutoff_shape
+    p.tail = tail
     return p
 
 
@@ -199,6 +206,42 @@ def interp(dims, h, D: np.ndarray, xp) -> float:
     return lib().orc_interp(_p(dims), _p(h), _p(D), _p(xp))
 
 
+def interp_grad(dims, h, D: np.ndarray, xp):
+    """Trilinear interpolation (Eq. 6) and the gradient of the interpolant: (value, grad[3])."""
+    dims = np.asarray(dims, np.int32)
+    h = np.asarray(h, np.float64)
+    D = np.ascontiguousarray(D, np.float64).ravel()
+    xp = np.asarray(xp, np.float64)
+    g = np.zeros(3)
+    v = lib().orc_interp_grad(_p(dims), _p(h), _p(D), _p(xp), _p(g))
+    return v, g
+
+
+def tail_planar(p: Params, rc: float, delta: float, rho_l: float, rho_v: float):
+    """Eq. 21-22 for a planar interface at signed distance delta (> 0: in the liquid):
+    (force along the normal into the liquid, du)."""
+    fn = np.zeros(1)
+    du = np.zeros(1)
+    lib().orc_tail_planar(C.byref(p), float(rc), float(delta), float(rho_l), float(rho_v),
+                          _p(fn), _p(du))
+    return float(fn[0]), float(du[0])
+
+
+def tail(p: Params, det: "Detection", x: np.ndarray, rc: np.ndarray):
+    """Tail correction of every particle from a detection's distance fields (Eq. 21-22).
+    Returns (f [3][n], du [n]); the pair-energy share of particle i is du[i] / 2."""
+    if det.dist_v is None:
+        raise ValueError("the detection was run without the tail correction's vapor distances")
+    x = np.ascontiguousarray(x, np.float64)
+    rc = np.ascontiguousarray(rc, np.float64)
+    n = x.shape[1]
+    f = np.zeros((3, n))
+    du = np.zeros(n)
+    km = np.ascontiguousarray(det.km, np.float64)
+    lib().orc_tail(C.byref(p), _p(det.dist), _p(det.dist_v), _p(km), n, _p(x), _p(rc), _p(f), _p(du))
+    return f, du
+
+
 @dataclass
 class Detection:
     count: np.ndarray
@@ -210,6 +253,7 @@ class Detection:
     rc: np.ndarray
     km: np.ndarray
     stats: np.ndarray
+    dist_v: np.ndarray | None = None
 
 
 def detect(p: Params, x: np.ndarray) -> Detection:
@@ -220,9 +264,10 @@ def detect(p: Params, x: np.ndarray) -> Detection:
     n = x.shape[1]
     det = Detection(np.zeros(G, np.uint32), np.zeros(G, np.uint32), np.zeros(G, np.uint8),
                     np.zeros(G, np.uint8), np.zeros(G), np.zeros(n), np.zeros(n),
-                    np.zeros(3), np.zeros(6, np.int64))
+                    np.zeros(3), np.zeros(6, np.int64), np.zeros(G) if p.tail else None)
     o = DetectOut(_p(det.count).value, _p(det.smooth).value, _p(det.raw).value,
                   _p(det.label).value, _p(det.dist).value, _p(det.d).value, _p(det.rc).value)
+    o.dist_v = _p(det.dist_v).value if p.tail else None
     lib().orc_detect(C.byref(p), n, _p(x), C.byref(o))
     det.km[:] = o.km[:]
     det.stats[:] = o.stats[:]
@@ -285,7 +330,10 @@ def prepare(p: Params, x: np.ndarray, v: np.ndarray, method: int = 1) -> RunStat
     x = wrap(p, x)
     det = detect(p, x)
     fr = forces(p, x, det.rc, method=method)
-    return RunState(x, np.ascontiguousarray(v, np.float64).copy(), det.rc.copy(), fr.f.copy(), 0)
+    f = fr.f.copy()
+    if p.tail:
+        f += tail(p, det, x, det.rc)[0]
+    return RunState(x, np.ascontiguousarray(v, np.float64).copy(), det.rc.copy(), f, 0)
 
 
 def run(p: Params, st: RunState, nsteps: int, method: int = 1):

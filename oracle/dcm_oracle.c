@@ -19,6 +19,10 @@
  *                           the pair is used iff r < r_c[i]; only f_i is updated)
  *   orc_forces_images       the exact forces of Eq. 20's accuracy measure: Eq. 4 with no
  *                           cutoff, over every periodic image within a radius R
+ *   orc_tail_planar /
+ *   orc_tail                the runtime tail correction of Section 7, Eq. 21-22: the pair
+ *                           energy and force beyond r_c[i] for a planar liquid/vapor model
+ *                           placed by a signed box distance (radial quadrature)
  *   orc_run                 Eq. 1-2 advanced with velocity Verlet; optionally at constant
  *                           temperature (the thesis's runs are NVT, Section 6) with one
  *                           Nose-Hoover thermostat in a symmetric splitting
@@ -328,6 +332,19 @@ double orc_interp(const int32_t d[3], const double h[3], const double *D, const 
     return lerp(c0, c1, t[2]);
 }
 
+/* Distance of every box to the liquid (the same solve with the roles of the phases swapped):
+ * liquid boxes are the zero set. Used by the tail correction to place vapor particles. */
+static int64_t vapor_distance(const int32_t d[3], const double h[3], double cap, const uint8_t *label,
+                              double *D)
+{
+    int64_t G = (int64_t)d[0] * d[1] * d[2];
+    uint8_t *flip = (uint8_t *)malloc((size_t)G);
+    for (int64_t c = 0; c < G; ++c) flip[c] = label[c] == 1 ? 0 : 1;
+    int64_t r = orc_distance(d, h, cap, flip, D);
+    free(flip);
+    return r;
+}
+
 /* ---- the interface detection of Fig. 14, one call ------------------------------------- */
 int orc_detect(const orc_params *p, int64_t n, const double *x, orc_detect_out *o)
 {
@@ -340,6 +357,7 @@ int orc_detect(const orc_params *p, int64_t n, const double *x, orc_detect_out *
     orc_segment(d, o->smooth, o->km[2], p->min_component, o->raw, o->label, o->stats + 1);
     double hmax = fmax(h[0], fmax(h[1], h[2]));
     o->stats[5] = orc_distance(d, h, p->rc_max + hmax, o->label, o->dist);
+    if (p->tail && o->dist_v) vapor_distance(d, h, p->rc_max + hmax, o->label, o->dist_v);
     for (int64_t i = 0; i < n; ++i) {
         double xp[3] = {x[i], x[n + i], x[2 * n + i]};
         o->d[i] = orc_interp(d, h, o->dist, xp);
@@ -527,6 +545,173 @@ static void nh_half_step(const orc_params *p, int64_t n, double *v, double nh[2]
     nh[0] += 0.25 * p->dt * (2.0 * K - gT) / Q;
 }
 
+/* ---- runtime tail correction (Section 7, Eq. 21-22) ------------------------------------
+ * Eq. 22 adds to particle i the pair energy its cutoff leaves out: the integral of V(r) over
+ * the points beyond r_c[i], weighted by the liquid density where they lie in the liquid and by
+ * the vapor density where they lie in the vapor. Its force is the same integral of the pair
+ * force -dV/dx_i (Eq. 21 applied under the integral, over the same pairs beyond the cutoff).
+ * Model of the phases around i: a plane at distance |delta| from i, the liquid on the side of
+ * the unit normal m (delta > 0: i is in the liquid, < 0: in the vapor). On the shell of radius
+ * r about i the liquid is the cap cos(theta) > c0 = -delta / r (clamped to [-1, 1], theta
+ * measured from m): its area is 2 pi r^2 (1 - c0) and its first moment, the integral of
+ * cos(theta) over it, pi r^2 (1 - c0^2). Hence
+ *   du = rho_v int_{r_c}^inf 4 pi r^2 V dr + (rho_l - rho_v) int_{r_c}^inf area(r) V(r) dr
+ *   F  = m (rho_l - rho_v) int_{r_c}^inf moment(r) dV/dr dr
+ * (a uniform density exerts no net force). Shells with r <= |delta| lie wholly in one phase
+ * (moment 0). Every integral over [a, inf) is taken in t = a / r on (0, 1], where each
+ * integrand below is a polynomial in t of degree at most 11, by a 12-point Gauss-Legendre
+ * rule, exact up to rounding. */
+
+/* Gauss-Legendre nodes and weights on [0, 1]: Newton's method on the Legendre polynomial P_m,
+ * evaluated by Bonnet's recursion (j P_j = (2j - 1) z P_{j-1} - (j - 1) P_{j-2}). */
+static void gauss_legendre01(int m, double *t, double *w)
+{
+    const double pi = acos(-1.0);
+    for (int i = 0; i < m; ++i) {
+        double z = cos(pi * (i + 0.75) / (m + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = 0.0;
+            for (int j = 1; j <= m; ++j) {
+                double p2 = p1;
+                p1 = p0;
+                p0 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p2) / j;
+            }
+            dp = m * (z * p0 - p1) / (z * z - 1.0);
+            double step = p0 / dp;
+            z -= step;
+            if (fabs(step) <= 1e-15) break;
+        }
+        t[i] = 0.5 * (1.0 - z);
+        w[i] = 1.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+static double lj_vr(const orc_params *p, double r)
+{
+    double s6 = pow(p->sigma / r, 6.0);
+    return 4.0 * p->epsilon * (s6 * s6 - s6);
+}
+
+static double lj_dv(const orc_params *p, double r)
+{
+    double s6 = pow(p->sigma / r, 6.0);
+    return 4.0 * p->epsilon * (-12.0 * s6 * s6 + 6.0 * s6) / r;
+}
+
+/* kind 0: 4 pi r^2 V (whole shell); 1: liquid cap area times V (r > |delta|);
+ * 2: liquid cap moment times dV/dr (r > |delta|) */
+static double tail_integrand(const orc_params *p, int kind, double r, double delta)
+{
+    const double pi = acos(-1.0);
+    if (kind == 0) return 4.0 * pi * r * r * lj_vr(p, r);
+    double c0 = -delta / r;
+    if (kind == 1) return 2.0 * pi * r * r * (1.0 - c0) * lj_vr(p, r);
+    return pi * r * r * (1.0 - c0 * c0) * lj_dv(p, r);
+}
+
+static double radial(const orc_params *p, double a, int kind, double delta)
+{
+    double t[12], w[12], s = 0.0;
+    gauss_legendre01(12, t, w);
+    for (int i = 0; i < 12; ++i) {
+        double r = a / t[i];
+        s += w[i] * tail_integrand(p, kind, r, delta) * (a / (t[i] * t[i]));
+    }
+    return s;
+}
+
+void orc_tail_planar(const orc_params *p, double rc, double delta, double rho_l, double rho_v,
+                     double *f_normal, double *du)
+{
+    double ad = fabs(delta), a = fmax(rc, ad), drho = rho_l - rho_v;
+    double whole = radial(p, rc, 0, 0.0);
+    /* shells between r_c and |delta| lie wholly in the liquid (delta > 0) or the vapor */
+    double inner = (delta > 0.0 && ad > rc) ? whole - radial(p, ad, 0, 0.0) : 0.0;
+    *du = rho_v * whole + drho * (inner + radial(p, a, 1, delta));
+    *f_normal = drho * radial(p, a, 2, delta);
+}
+
+/* The eight boxes around xp (Alg. 3.1's indexing) and the fractional offsets. */
+static void interp_corners(const int32_t d[3], const double h[3], const double xp[3], int64_t idx[8],
+                           double t[3])
+{
+    int64_t i0[3], i1[3];
+    for (int k = 0; k < 3; ++k) {
+        double u = xp[k] / h[k] - 0.5;
+        double f = floor(u);
+        t[k] = u - f;
+        i0[k] = pmod((int64_t)f, d[k]);
+        i1[k] = pmod(i0[k] + 1, d[k]);
+    }
+    for (int q = 0; q < 8; ++q)
+        idx[q] = IDX(d, (q & 1) ? i1[0] : i0[0], (q & 2) ? i1[1] : i0[1], (q & 4) ? i1[2] : i0[2]);
+}
+
+/* Trilinear interpolation (Eq. 6) and the gradient of the interpolant. */
+double orc_interp_grad(const int32_t d[3], const double h[3], const double *D, const double xp[3],
+                       double grad[3])
+{
+    int64_t idx[8];
+    double t[3], val = 0.0;
+    interp_corners(d, h, xp, idx, t);
+    grad[0] = grad[1] = grad[2] = 0.0;
+    for (int q = 0; q < 8; ++q) {
+        double wx = (q & 1) ? t[0] : 1.0 - t[0];
+        double wy = (q & 2) ? t[1] : 1.0 - t[1];
+        double wz = (q & 4) ? t[2] : 1.0 - t[2];
+        double v = D[idx[q]];
+        val += wx * wy * wz * v;
+        grad[0] += ((q & 1) ? 1.0 : -1.0) * wy * wz * v / h[0];
+        grad[1] += wx * ((q & 2) ? 1.0 : -1.0) * wz * v / h[1];
+        grad[2] += wx * wy * ((q & 4) ? 1.0 : -1.0) * v / h[2];
+    }
+    return val;
+}
+
+/* Tail correction of every particle from one detection's two distance fields.
+ * Signed box value: depth into the liquid less half a box edge (the interface is taken
+ * midway between the last liquid and the first vapor box centre), and minus the depth into
+ * the vapor less half a box edge on vapor boxes; half a box edge is the mean of h / 2.
+ * delta and m are the interpolated signed value at x_i and its normalised gradient. Where all
+ * eight boxes around x_i lie at the band limit (the capped depth) the particle is deep in its
+ * phase: du is the uniform value of that phase and F = 0; a zero gradient gives F = 0.
+ * Densities: the two-means centres (km[1] liquid, km[0] vapor) over the box volume, divided by
+ * 64 per smoothing pass (each pass multiplies a uniform image by 4 along each axis).
+ * Outputs: f [3][n] and du [n] (Eq. 22's du_i; the pair-energy share of i is du_i / 2). */
+void orc_tail(const orc_params *p, const double *Dl, const double *Dv, const double km[3], int64_t n,
+              const double *x, const double *rc, double *f, double *du)
+{
+    int32_t d[3]; double h[3];
+    orc_grid(p, d, h);
+    int64_t G = (int64_t)d[0] * d[1] * d[2];
+    double hmax = fmax(h[0], fmax(h[1], h[2]));
+    double cap = p->rc_max + hmax, s = (h[0] + h[1] + h[2]) / 6.0;
+    double *phi = (double *)malloc(sizeof(double) * (size_t)G);
+    for (int64_t c = 0; c < G; ++c) phi[c] = Dl[c] > 0.0 ? Dl[c] - s : -(Dv[c] - s);
+    double norm = pow(64.0, p->smooth_passes) * h[0] * h[1] * h[2];
+    double rho_v = km[0] / norm, rho_l = km[1] / norm;
+    for (int64_t i = 0; i < n; ++i) {
+        double xp[3] = {x[i], x[n + i], x[2 * n + i]};
+        int64_t idx[8];
+        double t[3], g[3];
+        interp_corners(d, h, xp, idx, t);
+        int deep = 1;
+        for (int q = 0; q < 8; ++q) if (fabs(phi[idx[q]]) < cap - s) deep = 0;
+        f[i] = f[n + i] = f[2 * n + i] = 0.0;
+        if (deep) {
+            double rho = phi[idx[0]] > 0.0 ? rho_l : rho_v;
+            du[i] = rho * radial(p, rc[i], 0, 0.0);
+            continue;
+        }
+        double delta = orc_interp_grad(d, h, phi, xp, g), fn;
+        orc_tail_planar(p, rc[i], delta, rho_l, rho_v, &fn, &du[i]);
+        double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+        if (gn > 0.0)
+            for (int k = 0; k < 3; ++k) f[k * n + i] = fn * g[k] / gn;
+    }
+    free(phi);
+}
+
 /* ---- velocity-Verlet steps (Eq. 1-2) ----------------------------------------------------
  * On entry f holds the forces of the current state and rc its cutoffs; k0 is the index of
  * the force evaluation that produced f. Each step: v += (dt/2m) f; x += dt v; wrap; the
@@ -551,6 +736,15 @@ int orc_run(const orc_params *p, int64_t n, double *x, double *v, double *rc, do
     o.label = (uint8_t *)malloc((size_t)G);
     o.dist = (double *)malloc(sizeof(double) * (size_t)G);
     o.d = (double *)malloc(sizeof(double) * (size_t)n);
+    o.dist_v = p->tail ? (double *)malloc(sizeof(double) * (size_t)G) : NULL;
+    double *ft = p->tail ? (double *)malloc(sizeof(double) * (size_t)n * 3) : NULL;
+    double *du = p->tail ? (double *)malloc(sizeof(double) * (size_t)n) : NULL;
+    if (p->tail) {
+        /* the tail correction needs the fields of a detection: those of the entry state (the
+         * cutoffs passed in rc are kept) */
+        o.rc = o.d;
+        orc_detect(p, n, x, &o);
+    }
     o.rc = rc;
     for (int32_t s = 1; s <= nsteps; ++s) {
         int64_t k = k0 + s;
@@ -560,6 +754,11 @@ int orc_run(const orc_params *p, int64_t n, double *x, double *v, double *rc, do
         orc_wrap(p, n, x);
         if (p->detect_every > 0 && k % p->detect_every == 0) orc_detect(p, n, x, &o);
         orc_forces(p, n, x, rc, n, NULL, method, f, e, w, np);
+        if (p->tail) {
+            orc_tail(p, o.dist, o.dist_v, o.km, n, x, rc, ft, du);
+            for (int64_t i = 0; i < 3 * n; ++i) f[i] += ft[i];
+            for (int64_t i = 0; i < n; ++i) e[i] += 0.5 * du[i];
+        }
         for (int64_t i = 0; i < 3 * n; ++i) v[i] = v[i] + hdt * f[i];
         if (p->thermostat) nh_half_step(p, n, v, nh);
         if (th) {
@@ -578,5 +777,6 @@ int orc_run(const orc_params *p, int64_t n, double *x, double *v, double *rc, do
     }
     free(e); free(w); free(np);
     free(o.count); free(o.smooth); free(o.raw); free(o.label); free(o.dist); free(o.d);
+    free(o.dist_v); free(ft); free(du);
     return 0;
 }

@@ -23,6 +23,7 @@ typedef struct {
     double temperature, tdamp;   /* Nose-Hoover target T* and relaxation time tau       */
     int32_t thermostat;          /* 0: constant energy, 1: Nose-Hoover (constant T)     */
     int32_t cutoff_shape;        /* 0: exponential (Eq. 7-8), 1: linear ramp            */
+    int32_t tail;                /* 1: add the runtime tail correction (Eq. 21-22)      */
 } orc_params;
 
 typedef struct {
@@ -43,6 +44,7 @@ typedef struct {
     double    km[3];   /* vapor centre, liquid centre, threshold        */
     int64_t   stats[6];/* lloyd iters, vapor comps removed, liquid comps removed,
                           vapor boxes flipped, liquid boxes flipped, distance rounds */
+    double   *dist_v;  /* [G] box-liquid distances (computed only when tail is set), capped */
 } orc_detect_out;
 
 int     orc_grid(const orc_params *p, int32_t dims[3], double h[3]);
@@ -65,6 +67,13 @@ void    orc_forces(const orc_params *p, int64_t n, const double *x, const double
                    double *f, double *e, double *w, int64_t *pairs);
 void    orc_forces_images(const orc_params *p, int64_t n, const double *x, double R, int64_t m,
                           const int64_t *subset, double *f, double *e);
+void    orc_tail_planar(const orc_params *p, double rc, double delta, double rho_l, double rho_v,
+                        double *f_normal, double *du);
+double  orc_interp_grad(const int32_t dims[3], const double h[3], const double *D,
+                        const double xp[3], double grad[3]);
+void    orc_tail(const orc_params *p, const double *dist_l, const double *dist_v,
+                 const double km[3], int64_t n, const double *x, const double *rc,
+                 double *f, double *du);
 int     orc_run(const orc_params *p, int64_t n, double *x, double *v, double *rc, double *f,
                 int64_t k0, int32_t nsteps, int32_t method, double nh[2], orc_thermo *th);
 

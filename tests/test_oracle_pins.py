@@ -705,3 +705,138 @@ def test_image_sum_newton_and_gradient(orc):
         # pairs crossing R change the energy discontinuously; none lie within h of R here
         dE = (orc.forces_images(p, xp, R)[1].sum() - orc.forces_images(p, xm, R)[1].sum()) / (2 * h)
         assert abs(-dE - f[k, i]) < 1e-5 * max(1.0, abs(f[k, i])), (i, k, dE, f[k, i])
+
+
+# ---------------------------------------------------------------- tail correction (Eq. 21-22)
+def _lj(r):
+    s6 = r ** -6.0
+    return 4.0 * (s6 * s6 - s6)
+
+
+def _dlj(r):
+    s6 = r ** -6.0
+    return 4.0 * (-12.0 * s6 * s6 + 6.0 * s6) / r
+
+
+def _halfspace_integrals(rc, delta):
+    """Liquid half-space z > -delta beyond r_c in cylindrical coordinates (scipy dblquad):
+    (int V dV, int dV/dr z/r dV). A different decomposition from the oracle's shells."""
+    from scipy.integrate import dblquad
+    lo = lambda z: math.sqrt(max(rc * rc - z * z, 0.0))
+    hi = lambda z: np.inf
+    fe = lambda R, z: _lj(math.hypot(R, z)) * 2.0 * math.pi * R
+    ff = lambda R, z: _dlj(math.hypot(R, z)) * (z / math.hypot(R, z)) * 2.0 * math.pi * R
+    kw = dict(epsabs=1e-13, epsrel=1e-11)
+    e = dblquad(fe, -delta, np.inf, lo, hi, **kw)[0]
+    f = dblquad(ff, -delta, np.inf, lo, hi, **kw)[0]
+    return e, f
+
+
+def _bulk_tail(rho, rc):
+    """Textbook uniform-fluid LJ tail: per-particle energy share (8/3) pi rho [(1/3) rc^-9 - rc^-3]
+    (sigma = epsilon = 1); Eq. 22's du is twice the share."""
+    return 2.0 * (8.0 / 3.0) * math.pi * rho * (rc ** -9 / 3.0 - rc ** -3)
+
+
+@pytest.mark.parametrize("rc,delta", [(3.0, 0.0), (3.0, 1.3), (3.0, -2.2), (2.5, 4.0),
+                                      (3.0, -5.5), (4.2, 3.9)])
+def test_tail_planar_vs_cylindrical_quadrature(orc, rc, delta):
+    rho_l, rho_v = 0.71, 0.023
+    p = orc.params((30, 30, 30), tail=1)
+    fn, du = orc.tail_planar(p, rc, delta, rho_l, rho_v)
+    e_half, f_half = _halfspace_integrals(rc, delta)
+    assert du == pytest.approx(rho_v * _bulk_tail(1.0, rc) + (rho_l - rho_v) * e_half, rel=1e-8)
+    assert fn == pytest.approx((rho_l - rho_v) * f_half, rel=1e-8, abs=1e-12)
+
+
+def test_tail_planar_limits_and_symmetry(orc):
+    p = orc.params((30, 30, 30), tail=1)
+    rho_l, rho_v, rc = 0.7, 0.02, 3.0
+    # deep in either phase: the textbook uniform tail, no force
+    fn, du = orc.tail_planar(p, rc, 1e4, rho_l, rho_v)
+    assert du == pytest.approx(_bulk_tail(rho_l, rc), rel=1e-9) and abs(fn) < 1e-12
+    fn, du = orc.tail_planar(p, rc, -1e4, rho_l, rho_v)
+    assert du == pytest.approx(_bulk_tail(rho_v, rc), rel=1e-9) and abs(fn) < 1e-12
+    # on the plane each shell is half liquid, half vapor
+    fn, du = orc.tail_planar(p, rc, 0.0, rho_l, rho_v)
+    assert du == pytest.approx(0.5 * (rho_l + rho_v) * _bulk_tail(1.0, rc), rel=1e-13)
+    # the missing force points into the liquid on both sides and is even in delta
+    for d in (0.5, 2.0, 3.5, 7.0):
+        a, _ = orc.tail_planar(p, rc, d, rho_l, rho_v)
+        b, _ = orc.tail_planar(p, rc, -d, rho_l, rho_v)
+        assert a > 0.0 and a == pytest.approx(b, rel=1e-13)
+    # equal densities: no interface, no force, the uniform tail
+    fn, du = orc.tail_planar(p, rc, 1.0, 0.5, 0.5)
+    assert fn == 0.0 and du == pytest.approx(_bulk_tail(0.5, rc), rel=1e-13)
+
+
+@pytest.mark.parametrize("delta", [-4.1, -1.7, -0.3, 0.8, 2.6, 3.4, 6.0])
+def test_tail_force_vs_energy_gradient(orc, delta):
+    """The force integral against finite differences of the energy integral. The truncation
+    sphere moves with the particle, so the pair force beyond r_c differs from -d(du)/d(delta)
+    by the surface term -(rho_l - rho_v) V(r_c) pi (r_c^2 - delta^2) while the sphere cuts the
+    plane (divergence theorem), and equals it otherwise."""
+    p = orc.params((30, 30, 30), tail=1)
+    rho_l, rho_v, rc, h = 0.7, 0.02, 3.0, 1e-4
+    fn, _ = orc.tail_planar(p, rc, delta, rho_l, rho_v)
+    up = orc.tail_planar(p, rc, delta + h, rho_l, rho_v)[1]
+    um = orc.tail_planar(p, rc, delta - h, rho_l, rho_v)[1]
+    grad = (up - um) / (2 * h)
+    surface = -(rho_l - rho_v) * _lj(rc) * math.pi * max(rc * rc - delta * delta, 0.0)
+    assert fn == pytest.approx(-grad + surface, rel=1e-6, abs=1e-9)
+
+
+def test_interp_grad_matches_finite_differences(orc):
+    rng = np.random.default_rng(5)
+    dims = np.array([5, 4, 6], np.int32)
+    h = np.array([1.1, 0.9, 1.3])
+    D = rng.normal(size=int(np.prod(dims)))
+    for _ in range(20):
+        xp = rng.uniform(0, 1, 3) * dims * h
+        v, g = orc.interp_grad(dims, h, D, xp)
+        assert v == pytest.approx(orc.interp(dims, h, D, xp), rel=1e-13, abs=1e-13)
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = 1e-6
+            fd = (orc.interp(dims, h, D, xp + e) - orc.interp(dims, h, D, xp - e)) / 2e-6
+            assert g[k] == pytest.approx(fd, rel=1e-6, abs=1e-7)
+
+
+def test_tail_on_a_planar_slab(orc):
+    """Known geometry: liquid boxes k in [6, 14) of a 6 x 6 x 20 grid of unit boxes. The signed
+    value is then the exact distance to the planes z = 6 and z = 14 inside the band, so every
+    particle gets the planar model at its own distance along z, and none in x or y."""
+    dims = np.array([6, 6, 20], np.int32)
+    p = orc.params((6.0, 6.0, 20.0), rc_min=2.5, rc_max=3.0, bin=1.0, smooth_passes=1, tail=1)
+    _, h = orc.grid(p)
+    label = np.ones((20, 6, 6), np.uint8)
+    label[6:14] = 0
+    cap = p.rc_max + 1.0
+    dl = orc.distance(dims, h, cap, label.ravel())[0]
+    dv = orc.distance(dims, h, cap, (1 - label).ravel())[0]
+    rho_l, rho_v = 0.75, 0.05
+    km = np.array([rho_v, rho_l, 0.0]) * 64.0       # one smoothing pass, unit boxes
+    z = np.array([0.7, 2.5, 4.9, 5.5, 6.0, 6.4, 8.0, 9.3, 10.0, 12.2, 13.6, 15.1, 17.9])
+    n = z.size
+    x = np.stack([np.full(n, 2.5), np.full(n, 3.5), z])
+    rc = np.full(n, 2.75)
+
+    class Det:
+        pass
+    det = Det()
+    det.dist, det.dist_v, det.km = dl, dv, km
+    f, du = orc.tail(p, det, x, rc)
+    assert np.all(f[0] == 0.0) and np.all(f[1] == 0.0)
+    for i, zi in enumerate(z):
+        inside = 6.0 <= zi <= 14.0
+        delta = min(zi - 6.0, 14.0 - zi) if inside else -min(abs(zi - 6.0), abs(zi - 14.0),
+                                                               abs(zi - 26.0), abs(zi + 6.0))
+        # the signed values are capped at depth cap - 1/2: a particle whose two boxes along z
+        # both lie there is deep in its phase
+        if abs(delta) > cap - 0.5:
+            want_f, want_u = 0.0, (rho_l if inside else rho_v) * _bulk_tail(1.0, rc[i])
+        else:
+            fn, want_u = orc.tail_planar(p, rc[i], delta, rho_l, rho_v)
+            want_f = fn if zi < 10.0 else -fn       # the liquid lies toward z = 10
+        assert du[i] == pytest.approx(want_u, rel=1e-12, abs=1e-14), (zi, delta)
+        assert f[2, i] == pytest.approx(want_f, rel=1e-12, abs=1e-14), (zi, delta)
