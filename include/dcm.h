@@ -84,6 +84,16 @@ typedef struct {
     double tdamp;           /* thermostat relaxation time tau [0.5]; Q = g T* tau^2          */
     int32_t thermostat;     /* DCM_NVE or DCM_NOSE_HOOVER [DCM_NVE]                       */
     int32_t cutoff_shape;   /* DCM_CUTOFF_EXP or DCM_CUTOFF_LINEAR [DCM_CUTOFF_EXP]       */
+    int32_t tail;           /* 1: runtime tail correction of Section 7, Eq. 21-22 [0]; needs
+                               DCM_PAIR_I and energy_shift 0. Every force evaluation adds to
+                               particle i the pair force, and to e_i half the pair energy
+                               (Eq. 22), of the particles beyond r_c[i], for a planar model of
+                               the two phases: liquid and vapor densities from the two-means
+                               centres (Eq. 14), the plane at the interpolated signed distance
+                               to the interface with the normal its gradient. The signed
+                               distance needs a second distance solve per detection (the
+                               distance of vapor boxes to the liquid). The correction is a mean
+                               field, not conservative, and adds nothing to the virial.     */
 } dcm_params;
 
 /* One thermodynamic record (all FP64 sums in a fixed reduction order).
@@ -111,6 +121,8 @@ typedef struct {
     double *km;        /* [3] vapor centre, liquid centre, threshold (Eq. 14)             */
     int64_t *stats;    /* [6] Lloyd iterations, vapor / liquid components removed,
                           vapor / liquid boxes flipped, distance sweeps                  */
+    double *dist_v;    /* distances of the boxes to the liquid (liquid boxes 0), capped like
+                          dist; only with tail = 1, else DCM_E_INVALID                   */
 } dcm_detect_out;
 
 typedef struct dcm_system dcm_system;

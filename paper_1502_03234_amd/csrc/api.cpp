@@ -122,6 +122,9 @@ dcm_status validate(const dcm_params *p, int64_t n, Grid &g)
         (!(p->temperature > 0.0) || !(p->tdamp > 0.0) || !std::isfinite(p->temperature) || !std::isfinite(p->tdamp)))
         return fail(DCM_E_INVALID, "the thermostat needs temperature > 0 and tdamp > 0 (got %g, %g)",
                     p->temperature, p->tdamp);
+    if (p->tail != 0 && p->tail != 1) return fail(DCM_E_INVALID, "tail must be 0 or 1");
+    if (p->tail && (p->pair_rule != DCM_PAIR_I || p->energy_shift))
+        return fail(DCM_E_INVALID, "the tail correction needs pair_rule DCM_PAIR_I and energy_shift 0");
     return DCM_OK;
 }
 
@@ -177,6 +180,7 @@ size_t layout(dcm_system *s, void *ws)
     s->gw.tcur = b.take<uint32_t>(2 * distance_tiles(s->grid));
     s->gw.dist2 = b.take<double>(G);
     s->gw.ctile = b.take<uint8_t>(component_tiles(s->grid));
+    s->gw.dist_v = s->p.tail ? b.take<double>(G) : nullptr;
     s->nfb = force_blocks(n);
     s->nkb = stream_blocks(n);
     s->fparts = b.take<Partial>(s->nfb);
@@ -243,7 +247,9 @@ void rebin_sorted(dcm_system *s, hipStream_t st)
     s->cur = 1 - s->cur;
 }
 
-void detect(dcm_system *s, hipStream_t st)
+// The detection stages; with_cutoffs = false leaves the cutoffs as they are (the tail
+// correction of a state resumed between detections needs only the distance fields).
+void detect(dcm_system *s, hipStream_t st, bool with_cutoffs = true)
 {
     const Grid &g = s->grid;
     GridWork w = s->gw;
@@ -258,8 +264,10 @@ void detect(dcm_system *s, hipStream_t st)
     launch_segment(g, w.g, w.km, s->p.min_component, w, st);
     stage_end(s, st);
     stage_begin(s, 5, st);
-    launch_distance(g, s->cap, w.label, w.dist, w, st);
+    launch_distance(g, s->cap, w.label, kLabelVapor, w.dist, w, w.stats + 5, st);
+    if (s->p.tail) launch_distance(g, s->cap, w.label, kLabelLiquid, w.dist_v, w, w.stats + 6, st);
     stage_end(s, st);
+    if (!with_cutoffs) return;
     stage_begin(s, 6, st);
     launch_cutoffs(g, s->set[s->cur], s->n, w.dist, s->cap, s->p.rc_min, s->p.rc_max, s->p.alpha,
                    s->cut_a, s->cut_b, s->p.cutoff_shape == DCM_CUTOFF_LINEAR ? 1 : 0, st);
@@ -294,6 +302,29 @@ void forces(dcm_system *s, hipStream_t st, double *e_out, double *w_out, uint32_
     stage_begin(s, 7, st);
     launch_forces(a, st);
     stage_end(s, st);
+    if (s->p.tail) {
+        TailArgs t;
+        t.grid = s->grid;
+        t.pos = a.pos;
+        t.id = a.id;
+        t.n = s->n;
+        t.dist_l = s->gw.dist;
+        t.dist_v = s->gw.dist_v;
+        t.km = s->gw.km;
+        t.cap = s->cap;
+        t.half_edge = (s->grid.h[0] + s->grid.h[1] + s->grid.h[2]) / 6.0;
+        t.inv_norm = 1.0 / (std::pow(64.0, s->p.smooth_passes) * s->grid.h[0] * s->grid.h[1] * s->grid.h[2]);
+        t.epsilon = s->p.epsilon;
+        t.sigma = s->p.sigma;
+        t.fx = s->fx;
+        t.fy = s->fy;
+        t.fz = s->fz;
+        t.e_out = e_out;
+        t.partials = s->fparts;
+        stage_begin(s, 7, st);
+        launch_tail(t, st);
+        stage_end(s, st);
+    }
 }
 
 dcm_status create_impl(const dcm_params *p, int64_t n, void *d_ws, size_t ws_bytes, const double *d_x,
@@ -332,6 +363,7 @@ dcm_status create_impl(const dcm_params *p, int64_t n, void *d_ws, size_t ws_byt
     rebin_sorted(s, st);
     bool redetect = !from_state || (p->detect_every > 0 && step % p->detect_every == 0);
     if (redetect) detect(s, st);
+    else if (p->tail) detect(s, st, false);
     forces(s, st, nullptr, nullptr, nullptr);
     uint32_t flags = 0;
     (void)hipMemcpyAsync(&flags, s->gw.flags, sizeof flags, hipMemcpyDeviceToHost, st);
@@ -446,6 +478,7 @@ dcm_status dcm_set_cutoffs(dcm_system *s, dcm_stream_t stream, const double *d_r
 dcm_status dcm_detect_interface(dcm_system *s, dcm_stream_t stream, const dcm_detect_out *o)
 {
     if (!s) return fail(DCM_E_INVALID, "system is NULL");
+    if (o && o->dist_v && !s->p.tail) return fail(DCM_E_INVALID, "dist_v needs the tail correction (tail = 1)");
     hipStream_t st = (hipStream_t)stream;
     detect(s, st);
     if (o) {
@@ -458,6 +491,7 @@ dcm_status dcm_detect_interface(dcm_system *s, dcm_stream_t stream, const dcm_de
         if (o->rc) launch_unsort(s->set[s->cur], s->fx, s->fy, s->fz, s->n, nullptr, nullptr, o->rc, nullptr, st);
         if (o->km) launch_copy_bytes(o->km, s->gw.km, 3 * sizeof(double), st);
         if (o->stats) launch_copy_bytes(o->stats, s->gw.stats, 6 * sizeof(long long), st);
+        if (o->dist_v) launch_cap_copy(s->gw.dist_v, s->cap, o->dist_v, G, st);
     }
     return hip_status("dcm_detect_interface");
 }
@@ -641,6 +675,7 @@ static size_t grid_layout(const Grid &g, GridWork &w, void *ws, double cap)
     w.tcur = b.take<uint32_t>(2 * distance_tiles(g));
     w.dist2 = b.take<double>(G);
     w.ctile = b.take<uint8_t>(component_tiles(g));
+    w.dist_v = nullptr;
     return b.off + 256;
 }
 
@@ -754,7 +789,7 @@ dcm_status dcm_grid_distance(const int32_t dims[3], const double h[3], double ca
     hipStream_t st = (hipStream_t)stream;
     launch_fill_u32(w.flags, 0u, 1, st);
     launch_fill_u32((uint32_t *)w.stats, 0u, 16, st);
-    launch_distance(g, cap, d_label, d_dist, w, st);
+    launch_distance(g, cap, d_label, kLabelVapor, d_dist, w, w.stats + 5, st);
     launch_cap_copy(d_dist, cap, d_dist, g.G, st);
     if (d_sweeps) launch_copy_bytes(d_sweeps, w.stats + 5, sizeof(long long), st);
     return hip_status("dcm_grid_distance");

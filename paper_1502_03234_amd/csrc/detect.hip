@@ -677,8 +677,9 @@ __device__ __forceinline__ int tile_of(const Grid &g, int64_t x, int64_t y, int6
     return (int)(((z / TZ) * nty + y / TY) * ntx + x / TX);
 }
 
-// Initial distances (0 on vapor boxes, infinity elsewhere); the tiles holding a liquid box next
-// to a vapor box are the only ones the first pass can change, and they start dirty.
+// Initial distances (0 on the boxes labelled `zero`, the vapor for the interface distance,
+// infinity elsewhere); the tiles holding another box next to a zero box are the only ones the
+// first pass can change, and they start dirty.
 struct KDistInit {
     static constexpr int kThreads = kBlock, kWaves = 0;
     struct Args {
@@ -686,6 +687,7 @@ struct KDistInit {
         const uint8_t *label;
         double *dist;
         uint32_t *dirty;
+        uint8_t zero;
     };
     static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
 };
@@ -696,19 +698,20 @@ __device__ void KDistInit::run(const Args &args_, uint32_t blk, uint32_t)
     const uint8_t *label = args_.label;
     double *dist = args_.dist;
     uint32_t *dirty = args_.dirty;
+    const uint8_t zero = args_.zero;
     int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
     if (c >= g.G) return;
-    const bool vap = label[c] == 1;
-    dist[c] = vap ? 0.0 : INFINITY;
-    if (vap) return;
+    const bool z0 = label[c] == zero;
+    dist[c] = z0 ? 0.0 : INFINITY;
+    if (z0) return;
     int64_t i, j, k;
     coords(g, c, i, j, k);
     const int64_t xm = i == 0 ? g.n[0] - 1 : i - 1, xp = i == g.n[0] - 1 ? 0 : i + 1;
     const int64_t ym = j == 0 ? g.n[1] - 1 : j - 1, yp = j == g.n[1] - 1 ? 0 : j + 1;
     const int64_t zm = k == 0 ? g.n[2] - 1 : k - 1, zp = k == g.n[2] - 1 ? 0 : k + 1;
-    const bool front = label[lin(g, xm, j, k)] == 1 || label[lin(g, xp, j, k)] == 1 ||
-                       label[lin(g, i, ym, k)] == 1 || label[lin(g, i, yp, k)] == 1 ||
-                       label[lin(g, i, j, zm)] == 1 || label[lin(g, i, j, zp)] == 1;
+    const bool front = label[lin(g, xm, j, k)] == zero || label[lin(g, xp, j, k)] == zero ||
+                       label[lin(g, i, ym, k)] == zero || label[lin(g, i, yp, k)] == zero ||
+                       label[lin(g, i, j, zm)] == zero || label[lin(g, i, j, zp)] == zero;
     if (front) dirty[tile_of(g, i, j, k)] = 1u;
 }
 
@@ -724,6 +727,7 @@ struct KDistTiles {
         uint32_t *dirty;
         uint32_t *cur;
         int it;
+        uint8_t zero;
     };
     static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
 };
@@ -739,6 +743,7 @@ __device__ void KDistTiles::run(const Args &args_, uint32_t blk, uint32_t nblk)
     uint32_t *dirty = args_.dirty;
     uint32_t *cur = args_.cur;
     int it = args_.it;
+    const uint8_t zero = args_.zero;
     const int b = blk;
     const int ntiles = nblk;
     uint32_t *dflag = dirty + (it & 1) * ntiles, *dnext = dirty + ((it + 1) & 1) * ntiles;
@@ -801,7 +806,7 @@ __device__ void KDistTiles::run(const Args &args_, uint32_t blk, uint32_t nblk)
             const int lx = 2 * pos + ((ly + lz + p) & 1);
             bxs[p][m] = lx + 1; bys[p][m] = ly + 1; bzs[p][m] = lz + 1;
             const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-            liq[p][m] = gx < g.n[0] && gy < g.n[1] && gz < g.n[2] && label[lin(g, gx, gy, gz)] != 1;
+            liq[p][m] = gx < g.n[0] && gy < g.n[1] && gz < g.n[2] && label[lin(g, gx, gy, gz)] != zero;
         }
     const double wx = 1.0 / (g.h[0] * g.h[0]), wy = 1.0 / (g.h[1] * g.h[1]), wz = 1.0 / (g.h[2] * g.h[2]);
     __syncthreads();
@@ -1096,19 +1101,19 @@ int max_distance_sweeps(const Grid &g, double cap)
     return depth / std::min(TX, std::min(TY, TZ)) + 24;
 }
 
-void launch_distance(const Grid &g, double cap, const uint8_t *label, double *dist, GridWork w,
-                     hipStream_t st)
+void launch_distance(const Grid &g, double cap, const uint8_t *label, uint8_t zero, double *dist,
+                     GridWork w, long long *sweeps, hipStream_t st)
 {
     int ms = max_distance_sweeps(g, cap);
     launch_fill_u32(w.changed, 0u, ms + 1, st);
     const unsigned ntiles = (unsigned)distance_tiles(g);
     launch_fill_u32(w.tdirty, 0u, 2 * (int64_t)ntiles, st);
-    emit<KDistInit>({g, label, dist, w.tdirty}, grid1(g.G), st);
+    emit<KDistInit>({g, label, dist, w.tdirty, zero}, grid1(g.G), st);
     launch_fill_u32(w.tcur, 0u, 2 * (int64_t)ntiles, st);
     for (int it = 0; it < ms; ++it)
-        emit<KDistTiles>({g, label, dist, w.dist2, cap, w.changed, w.tdirty, w.tcur, it}, ntiles, st);
+        emit<KDistTiles>({g, label, dist, w.dist2, cap, w.changed, w.tdirty, w.tcur, it, zero}, ntiles, st);
     emit<KDistGather>({g, dist, (const double *)w.dist2, w.tcur, w.changed, ms, (int)ntiles}, grid1(g.G), st);
-    emit<KDistFinish>({w.changed, ms, w.stats + 5, w.flags}, 1, st);
+    emit<KDistFinish>({w.changed, ms, sweeps, w.flags}, 1, st);
 }
 
 void launch_cap_copy(const double *dist, double cap, double *out, int64_t G, hipStream_t st)

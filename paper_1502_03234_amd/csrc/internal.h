@@ -85,6 +85,7 @@ struct GridWork {
     uint32_t *tcur;         // [2 * distance_tiles] which distance copy is current per tile
     double *dist2;          // second copy of the distance grid
     uint8_t *ctile;         // [component_tiles] tile kinds of the current component pass
+    double *dist_v;         // box-liquid distances (tail correction only, else NULL)
 };
 
 // ---- launchers (each enqueues on `st`; no synchronization) ------------------------------
@@ -111,8 +112,12 @@ void launch_segment(const Grid &g, const uint32_t *img, const double *km, int32_
 int max_distance_sweeps(const Grid &g, double cap);
 int64_t distance_tiles(const Grid &g);
 int64_t component_tiles(const Grid &g);
-void launch_distance(const Grid &g, double cap, const uint8_t *label, double *dist, GridWork w,
-                     hipStream_t st);
+// Box labels after segmentation (Eq. 11-12).
+constexpr uint8_t kLabelLiquid = 0, kLabelVapor = 1;
+// Distance of every box to the boxes labelled `zero` (which get 0); the sweep count goes to
+// *sweeps.
+void launch_distance(const Grid &g, double cap, const uint8_t *label, uint8_t zero, double *dist,
+                     GridWork w, long long *sweeps, hipStream_t st);
 void launch_cutoffs(const Grid &g, PSet s, int64_t n, const double *dist, double cap,
                     double rc_min, double rc_max, double alpha, double a, double b, int linear, hipStream_t st);
 void launch_cap_copy(const double *dist, double cap, double *out, int64_t G, hipStream_t st);
@@ -140,6 +145,25 @@ struct ForceArgs {
 };
 int force_blocks(int64_t n);
 void launch_forces(const ForceArgs &a, hipStream_t st);
+
+// tail.hip
+struct TailArgs {
+    Grid grid;
+    const double4 *pos;     // storage order, w = r_c
+    const uint32_t *id;
+    int64_t n;
+    const double *dist_l;   // box-interface distances (vapor boxes 0)
+    const double *dist_v;   // box-liquid distances (liquid boxes 0)
+    const double *km;       // two-means centres {vapor, liquid, threshold} of the smoothed image
+    double cap;             // distance band limit
+    double half_edge;       // mean half box edge
+    double inv_norm;        // 1 / (64^passes * box volume): centre -> number density
+    double epsilon, sigma;
+    double *fx, *fy, *fz;   // storage order, added to
+    double *e_out;          // per-atom energy in caller order, added to (optional)
+    Partial *partials;      // [force_blocks(n)] energy partials, added to
+};
+void launch_tail(const TailArgs &a, hipStream_t st);
 
 // exact.hip
 // Upper bound of the box visits of launch_forces_images (work guard).
