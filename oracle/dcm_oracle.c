@@ -672,9 +672,11 @@ double orc_interp_grad(const int32_t d[3], const double h[3], const double *D, c
  * Signed box value: depth into the liquid less half a box edge (the interface is taken
  * midway between the last liquid and the first vapor box centre), and minus the depth into
  * the vapor less half a box edge on vapor boxes; half a box edge is the mean of h / 2.
- * delta and m are the interpolated signed value at x_i and its normalised gradient. Where all
- * eight boxes around x_i lie at the band limit (the capped depth) the particle is deep in its
- * phase: du is the uniform value of that phase and F = 0; a zero gradient gives F = 0.
+ * delta is the interpolated signed value at x_i and m the gradient of the interpolant (a
+ * distance field has a unit gradient; where the field flattens at the band limit the force
+ * fades with it). Where all eight boxes around x_i lie at the band limit (the capped depth,
+ * less a relative 1e-9 so that rounding in the distances cannot move the decision) the
+ * particle is deep in its phase: du is the uniform value of that phase and F = 0.
  * Densities: the two-means centres (km[1] liquid, km[0] vapor) over the box volume, divided by
  * 64 per smoothing pass (each pass multiplies a uniform image by 4 along each axis).
  * Outputs: f [3][n] and du [n] (Eq. 22's du_i; the pair-energy share of i is du_i / 2). */
@@ -696,7 +698,7 @@ void orc_tail(const orc_params *p, const double *Dl, const double *Dv, const dou
         double t[3], g[3];
         interp_corners(d, h, xp, idx, t);
         int deep = 1;
-        for (int q = 0; q < 8; ++q) if (fabs(phi[idx[q]]) < cap - s) deep = 0;
+        for (int q = 0; q < 8; ++q) if (fabs(phi[idx[q]]) < (cap - s) * (1.0 - 1e-9)) deep = 0;
         f[i] = f[n + i] = f[2 * n + i] = 0.0;
         if (deep) {
             double rho = phi[idx[0]] > 0.0 ? rho_l : rho_v;
@@ -705,9 +707,7 @@ void orc_tail(const orc_params *p, const double *Dl, const double *Dv, const dou
         }
         double delta = orc_interp_grad(d, h, phi, xp, g), fn;
         orc_tail_planar(p, rc[i], delta, rho_l, rho_v, &fn, &du[i]);
-        double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-        if (gn > 0.0)
-            for (int k = 0; k < 3; ++k) f[k * n + i] = fn * g[k] / gn;
+        for (int k = 0; k < 3; ++k) f[k * n + i] = fn * g[k];
     }
     free(phi);
 }
