@@ -654,8 +654,11 @@ def speedup_study(equil: int = 5000, nsteps: int = 200):
 
 
 def _detect_kw(args) -> dict:
-    return dict(bin=args.study_bin, smooth_passes=args.study_smooth,
-                min_component=args.study_min_component)
+    kw = dict(bin=args.study_bin, smooth_passes=args.study_smooth,
+              min_component=args.study_min_component)
+    if args.study_tail:
+        kw["tail"] = 1
+    return kw
 
 
 def main():
@@ -666,6 +669,8 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32c"], default="fp64")
     ap.add_argument("--cpu-sample", type=int, default=60000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tail", action="store_true",
+                    help="with the runtime tail correction (Eq. 21-22): its cost on the same workload")
     ap.add_argument("--compare-static", action="store_true",
                     help="also time the same system with a static cutoff r_c = r_c^max")
     ap.add_argument("--forces-only", type=int, default=0, metavar="K",
@@ -693,6 +698,8 @@ def main():
     ap.add_argument("--study-smooth", type=int, default=1, help="studies: smoothing passes")
     ap.add_argument("--study-min-component", type=int, default=27,
                     help="studies: components below this many boxes are removed")
+    ap.add_argument("--study-tail", action="store_true",
+                    help="--accuracy-study / --nvt-study: with the runtime tail correction (Eq. 21-22)")
     ap.add_argument("--save-dir", type=str, default="", help="--nvt-study: write the final states here")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run one plain device copy of BYTES (HBM counter calibration)")
@@ -741,7 +748,7 @@ def main():
     log(f"generating {WORKLOAD}")
     state = synth.named(WORKLOAD)
     prec = dcm.DCM_FP64 if args.precision == "fp64" else dcm.DCM_FP32C
-    p = dcm.params(state.box, precision=prec)
+    p = dcm.params(state.box, precision=prec, tail=1 if args.tail else 0)
     stream = torch.cuda.current_stream()
     sysm = dcm.System(p, state.x, state.v)
     if args.forces_only:
@@ -826,7 +833,8 @@ def main():
         "dtype": "f64" if prec == dcm.DCM_FP64 else "f32-compensated",
         "data": "synthetic",
         "config": {"workload": "LJ liquid/vapor slab, 2,048,000 particles, box 320x320x60, "
-                               "r_c 2.5..6 (exponential), detect every 2nd step, dt 0.005, NVE",
+                               "r_c 2.5..6 (exponential), detect every 2nd step, dt 0.005, NVE"
+                               + (", runtime tail correction" if args.tail else ""),
                    "n_particles": state.n, "grid": list(sysm.dims), "detect_every": 2,
                    "thermo_every_step": True},
         "roofline": {"bound": "alu", "kernel": "KForces (FP64 pair forces, energy, virial)",

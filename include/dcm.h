@@ -92,8 +92,10 @@ typedef struct {
                                centres (Eq. 14), the plane at the interpolated signed distance
                                to the interface with the normal its gradient. The signed
                                distance needs a second distance solve per detection (the
-                               distance of vapor boxes to the liquid). The correction is a mean
-                               field, not conservative, and adds nothing to the virial.     */
+                               distance of vapor boxes to the liquid), and both bands reach
+                               2 r_c^max + max h_k instead of r_c^max + max h_k. The correction
+                               is a mean field, not conservative, and adds nothing to the
+                               virial.                                                       */
 } dcm_params;
 
 /* One thermodynamic record (all FP64 sums in a fixed reduction order).
@@ -116,7 +118,8 @@ typedef struct {
     uint32_t *smooth;  /* smoothed counts                                                */
     uint8_t *raw;      /* threshold labels before component removal (0 liquid, 1 vapor)  */
     uint8_t *label;    /* final labels, Eq. 11-12                                        */
-    double *dist;      /* box-interface distances, Eq. 5, capped at r_c^max + max h_k     */
+    double *dist;      /* box-interface distances, Eq. 5, capped at r_c^max + max h_k
+                          (2 r_c^max + max h_k with the tail correction)                 */
     double *rc;        /* per-particle cutoffs r_c[i], Eq. 7                              */
     double *km;        /* [3] vapor centre, liquid centre, threshold (Eq. 14)             */
     int64_t *stats;    /* [6] Lloyd iterations, vapor / liquid components removed,
@@ -224,12 +227,13 @@ dcm_status dcm_check(dcm_system *s, dcm_stream_t stream);
 
 /* Per-stage timing with HIP events on the system's stream (off by default). Stages:
  * 0 kick/drift/key, 1 sort and cell ranges, 2 smoothing, 3 two-means, 4 labels and
- * components, 5 distance, 6 interpolation and cutoffs, 7 pair forces, 8 reductions.
+ * components, 5 distance (both solves with the tail correction), 6 interpolation and
+ * cutoffs, 7 pair forces, 8 reductions, 9 tail correction.
  * on: 0 off, 1 every stage, 2 the pair-force stage only (two events per force launch).
  * DCM_E_INVALID for another level. dcm_stage_times synchronizes and returns total
  * milliseconds and launch counts per stage (arrays of DCM_NSTAGES) accumulated since
  * profiling was first switched on. */
-#define DCM_NSTAGES 9
+#define DCM_NSTAGES 10
 dcm_status dcm_set_profiling(dcm_system *s, int32_t on);
 dcm_status dcm_stage_times(dcm_system *s, double *h_ms, int64_t *h_counts);
 

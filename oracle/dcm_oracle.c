@@ -332,6 +332,16 @@ double orc_interp(const int32_t d[3], const double h[3], const double *D, const 
     return lerp(c0, c1, t[2]);
 }
 
+/* Depth of the distance band (Section 4.3.2): one box beyond r_c^max, where the cutoff
+ * function has reached r_c^min. The tail correction sees the interface further, to 2 r_c^max
+ * plus a box (the proximity of 2 r_c that Section 7 suggests for its integral): beyond, the
+ * planar force is below a sixteenth of its value at r_c^max. */
+static double band_limit(const orc_params *p, const double h[3])
+{
+    double hmax = fmax(h[0], fmax(h[1], h[2]));
+    return (p->tail ? 2.0 * p->rc_max : p->rc_max) + hmax;
+}
+
 /* Distance of every box to the liquid (the same solve with the roles of the phases swapped):
  * liquid boxes are the zero set. Used by the tail correction to place vapor particles. */
 static int64_t vapor_distance(const int32_t d[3], const double h[3], double cap, const uint8_t *label,
@@ -355,9 +365,9 @@ int orc_detect(const orc_params *p, int64_t n, const double *x, orc_detect_out *
     orc_smooth(d, p->smooth_passes, o->count, o->smooth);
     o->stats[0] = orc_two_means(G, o->smooth, o->km);
     orc_segment(d, o->smooth, o->km[2], p->min_component, o->raw, o->label, o->stats + 1);
-    double hmax = fmax(h[0], fmax(h[1], h[2]));
-    o->stats[5] = orc_distance(d, h, p->rc_max + hmax, o->label, o->dist);
-    if (p->tail && o->dist_v) vapor_distance(d, h, p->rc_max + hmax, o->label, o->dist_v);
+    double cap = band_limit(p, h);
+    o->stats[5] = orc_distance(d, h, cap, o->label, o->dist);
+    if (p->tail && o->dist_v) vapor_distance(d, h, cap, o->label, o->dist_v);
     for (int64_t i = 0; i < n; ++i) {
         double xp[3] = {x[i], x[n + i], x[2 * n + i]};
         o->d[i] = orc_interp(d, h, o->dist, xp);
@@ -686,8 +696,7 @@ void orc_tail(const orc_params *p, const double *Dl, const double *Dv, const dou
     int32_t d[3]; double h[3];
     orc_grid(p, d, h);
     int64_t G = (int64_t)d[0] * d[1] * d[2];
-    double hmax = fmax(h[0], fmax(h[1], h[2]));
-    double cap = p->rc_max + hmax, s = (h[0] + h[1] + h[2]) / 6.0;
+    double cap = band_limit(p, h), s = (h[0] + h[1] + h[2]) / 6.0;
     double *phi = (double *)malloc(sizeof(double) * (size_t)G);
     for (int64_t c = 0; c < G; ++c) phi[c] = Dl[c] > 0.0 ? Dl[c] - s : -(Dv[c] - s);
     double norm = pow(64.0, p->smooth_passes) * h[0] * h[1] * h[2];

@@ -195,7 +195,9 @@ void init_derived(dcm_system *s)
     const dcm_params &p = s->p;
     s->hdt = 0.5 * p.dt / p.mass;
     double hmax = std::max(s->grid.h[0], std::max(s->grid.h[1], s->grid.h[2]));
-    s->cap = p.rc_max + hmax;
+    // the distance band ends a box beyond r_c^max, where the cutoff function is flat; the tail
+    // correction sees the interface to 2 r_c^max and a box
+    s->cap = (p.tail ? 2.0 * p.rc_max : p.rc_max) + hmax;
     if (p.rc_min != p.rc_max && p.cutoff_shape == DCM_CUTOFF_EXP) {
         s->cut_a = (p.rc_max - p.rc_min) / (std::exp2(p.alpha * p.rc_max) - 1.0);
         s->cut_b = p.rc_min - s->cut_a;
@@ -321,7 +323,7 @@ void forces(dcm_system *s, hipStream_t st, double *e_out, double *w_out, uint32_
         t.fz = s->fz;
         t.e_out = e_out;
         t.partials = s->fparts;
-        stage_begin(s, 7, st);
+        stage_begin(s, 9, st);
         launch_tail(t, st);
         stage_end(s, st);
     }

@@ -21,9 +21,9 @@ DCM_FP64, DCM_FP32C = 0, 1
 DCM_PAIR_I, DCM_PAIR_MAX = 0, 1
 DCM_NVE, DCM_NOSE_HOOVER = 0, 1
 DCM_CUTOFF_EXP, DCM_CUTOFF_LINEAR = 0, 1
-DCM_NSTAGES = 9
+DCM_NSTAGES = 10
 STAGES = ["kick_drift_key", "sort", "smooth", "two_means", "segment", "distance", "cutoffs",
-          "forces", "reduce"]
+          "forces", "reduce", "tail"]
 
 
 class DcmError(RuntimeError):

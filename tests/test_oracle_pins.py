@@ -803,20 +803,21 @@ def test_interp_grad_matches_finite_differences(orc):
 
 
 def test_tail_on_a_planar_slab(orc):
-    """Known geometry: liquid boxes k in [6, 14) of a 6 x 6 x 20 grid of unit boxes. The signed
-    value is then the exact distance to the planes z = 6 and z = 14 inside the band, so every
+    """Known geometry: liquid boxes k in [12, 28) of a 6 x 6 x 40 grid of unit boxes. The signed
+    value is then the exact distance to the planes z = 12 and z = 28 inside the band, so every
     particle gets the planar model at its own distance along z, and none in x or y."""
-    dims = np.array([6, 6, 20], np.int32)
-    p = orc.params((6.0, 6.0, 20.0), rc_min=2.5, rc_max=3.0, bin=1.0, smooth_passes=1, tail=1)
+    dims = np.array([6, 6, 40], np.int32)
+    p = orc.params((6.0, 6.0, 40.0), rc_min=2.5, rc_max=3.0, bin=1.0, smooth_passes=1, tail=1)
     _, h = orc.grid(p)
-    label = np.ones((20, 6, 6), np.uint8)
-    label[6:14] = 0
-    cap = p.rc_max + 1.0
+    label = np.ones((40, 6, 6), np.uint8)
+    label[12:28] = 0
+    cap = 2 * p.rc_max + 1.0                        # the band of the tail correction
     dl = orc.distance(dims, h, cap, label.ravel())[0]
     dv = orc.distance(dims, h, cap, (1 - label).ravel())[0]
     rho_l, rho_v = 0.75, 0.05
     km = np.array([rho_v, rho_l, 0.0]) * 64.0       # one smoothing pass, unit boxes
-    z = np.array([0.7, 2.5, 4.9, 5.5, 6.0, 6.4, 8.0, 9.3, 10.0, 12.2, 13.6, 15.1, 17.9])
+    z = np.array([1.0, 5.2, 5.8, 9.0, 11.5, 12.0, 12.4, 14.0, 17.3, 19.9, 22.2, 27.6, 29.1,
+                  33.0, 38.9])
     n = z.size
     x = np.stack([np.full(n, 2.5), np.full(n, 3.5), z])
     rc = np.full(n, 2.75)
@@ -827,16 +828,19 @@ def test_tail_on_a_planar_slab(orc):
     det.dist, det.dist_v, det.km = dl, dv, km
     f, du = orc.tail(p, det, x, rc)
     assert np.all(f[0] == 0.0) and np.all(f[1] == 0.0)
+    ndeep = 0
     for i, zi in enumerate(z):
-        inside = 6.0 <= zi <= 14.0
-        delta = min(zi - 6.0, 14.0 - zi) if inside else -min(abs(zi - 6.0), abs(zi - 14.0),
-                                                               abs(zi - 26.0), abs(zi + 6.0))
+        inside = 12.0 <= zi <= 28.0
+        delta = min(zi - 12.0, 28.0 - zi) if inside else -min(abs(zi - 12.0), abs(zi - 28.0),
+                                                                abs(zi - 52.0), abs(zi + 12.0))
         # the signed values are capped at depth cap - 1/2: a particle whose two boxes along z
         # both lie there is deep in its phase
         if abs(delta) > cap - 0.5:
+            ndeep += 1
             want_f, want_u = 0.0, (rho_l if inside else rho_v) * _bulk_tail(1.0, rc[i])
         else:
             fn, want_u = orc.tail_planar(p, rc[i], delta, rho_l, rho_v)
-            want_f = fn if zi < 10.0 else -fn       # the liquid lies toward z = 10
+            want_f = fn if zi < 20.0 else -fn       # the liquid lies toward z = 20
         assert du[i] == pytest.approx(want_u, rel=1e-12, abs=1e-14), (zi, delta)
         assert f[2, i] == pytest.approx(want_f, rel=1e-12, abs=1e-14), (zi, delta)
+    assert ndeep == 4
