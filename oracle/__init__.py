@@ -43,7 +43,7 @@ class Params(C.Structure):
                 ("min_component", C.c_int32), ("detect_every", C.c_int32),
                 ("pair_rule", C.c_int32), ("energy_shift", C.c_int32), ("dt", C.c_double),
                 ("temperature", C.c_double), ("tdamp", C.c_double), ("thermostat", C.c_int32), ("cutoff_shape", C.c_int32),
-                ("tail", C.c_int32)]
+                ("tail", C.c_int32), ("vapor_cutoff", C.c_int32)]
 
 
 class Thermo(C.Structure):
@@ -104,7 +104,7 @@ def _p(a):
 def params(box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_min=2.5, rc_max=6.0, alpha=-0.5,
            bin=1.0, smooth_passes=1, min_component=27, detect_every=2, pair_rule=0,
            energy_shift=0, dt=0.005, temperature=0.7, tdamp=0.5, thermostat=0,
-           cutoff_shape=0, tail=0) -> Params:
+           cutoff_shape=0, tail=0, vapor_cutoff=0) -> Params:
     p = Params()
     p.box[:] = [float(b) for b in box]
     p.epsilon, p.sigma, p.mass = epsilon, sigma, mass
@@ -115,6 +115,7 @@ def params(box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_min=2.5, rc_max=6.0, alp
     p.temperature, p.tdamp, p.thermostat = temperature, tdamp, thermostat
     p.cutoff_shape = cutoff_shape
     p.tail = tail
+    p.vapor_cutoff = vapor_cutoff
     return p
 
 
@@ -264,10 +265,11 @@ def detect(p: Params, x: np.ndarray) -> Detection:
     n = x.shape[1]
     det = Detection(np.zeros(G, np.uint32), np.zeros(G, np.uint32), np.zeros(G, np.uint8),
                     np.zeros(G, np.uint8), np.zeros(G), np.zeros(n), np.zeros(n),
-                    np.zeros(3), np.zeros(6, np.int64), np.zeros(G) if p.tail else None)
+                    np.zeros(3), np.zeros(6, np.int64),
+                    np.zeros(G) if (p.tail or p.vapor_cutoff) else None)
     o = DetectOut(_p(det.count).value, _p(det.smooth).value, _p(det.raw).value,
                   _p(det.label).value, _p(det.dist).value, _p(det.d).value, _p(det.rc).value)
-    o.dist_v = _p(det.dist_v).value if p.tail else None
+    o.dist_v = _p(det.dist_v).value if det.dist_v is not None else None
     lib().orc_detect(C.byref(p), n, _p(x), C.byref(o))
     det.km[:] = o.km[:]
     det.stats[:] = o.stats[:]

@@ -14,7 +14,8 @@
  *                           until nothing changes; band limited as in Section 4.3.2)
  *   orc_interp              Section 3, Eq. 5-6, Alg. 3.1 (trilinear interpolation)
  *   orc_cutoff              Section 3.1, Eq. 7-8 (exponential cutoff function; or the
- *                           linear ramp that Section 6 compares it with)
+ *                           linear ramp that Section 6 compares it with; optionally applied
+ *                           to vapor particles by their depth into the vapor, Section 3.1)
  *   orc_forces              Section 2.2, Eq. 4 and Section 3.2, Alg. 3.2 (full pair loop,
  *                           the pair is used iff r < r_c[i]; only f_i is updated)
  *   orc_forces_images       the exact forces of Eq. 20's accuracy measure: Eq. 4 with no
@@ -367,11 +368,17 @@ int orc_detect(const orc_params *p, int64_t n, const double *x, orc_detect_out *
     orc_segment(d, o->smooth, o->km[2], p->min_component, o->raw, o->label, o->stats + 1);
     double cap = band_limit(p, h);
     o->stats[5] = orc_distance(d, h, cap, o->label, o->dist);
-    if (p->tail && o->dist_v) vapor_distance(d, h, cap, o->label, o->dist_v);
+    int vapor_side = (p->tail || p->vapor_cutoff) && o->dist_v;
+    if (vapor_side) vapor_distance(d, h, cap, o->label, o->dist_v);
     for (int64_t i = 0; i < n; ++i) {
         double xp[3] = {x[i], x[n + i], x[2 * n + i]};
         o->d[i] = orc_interp(d, h, o->dist, xp);
-        o->rc[i] = orc_cutoff(p, o->d[i]);
+        /* vapor particles too (Section 3.1's extension of Eq. 7 to the low-density phase): the
+         * cutoff of the larger of the two interpolated depths, which mirrors Eq. 7 about the
+         * midplane between the last liquid and the first vapor box centre */
+        double depth = o->d[i];
+        if (p->vapor_cutoff && vapor_side) depth = fmax(depth, orc_interp(d, h, o->dist_v, xp));
+        o->rc[i] = orc_cutoff(p, depth);
     }
     return 0;
 }
@@ -745,7 +752,7 @@ int orc_run(const orc_params *p, int64_t n, double *x, double *v, double *rc, do
     o.label = (uint8_t *)malloc((size_t)G);
     o.dist = (double *)malloc(sizeof(double) * (size_t)G);
     o.d = (double *)malloc(sizeof(double) * (size_t)n);
-    o.dist_v = p->tail ? (double *)malloc(sizeof(double) * (size_t)G) : NULL;
+    o.dist_v = (p->tail || p->vapor_cutoff) ? (double *)malloc(sizeof(double) * (size_t)G) : NULL;
     double *ft = p->tail ? (double *)malloc(sizeof(double) * (size_t)n * 3) : NULL;
     double *du = p->tail ? (double *)malloc(sizeof(double) * (size_t)n) : NULL;
     if (p->tail) {

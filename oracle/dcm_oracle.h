@@ -24,6 +24,7 @@ typedef struct {
     int32_t thermostat;          /* 0: constant energy, 1: Nose-Hoover (constant T)     */
     int32_t cutoff_shape;        /* 0: exponential (Eq. 7-8), 1: linear ramp            */
     int32_t tail;                /* 1: add the runtime tail correction (Eq. 21-22)      */
+    int32_t vapor_cutoff;        /* 1: dynamic cutoffs in the vapor too (Section 3.1)   */
 } orc_params;
 
 typedef struct {
@@ -44,7 +45,8 @@ typedef struct {
     double    km[3];   /* vapor centre, liquid centre, threshold        */
     int64_t   stats[6];/* lloyd iters, vapor comps removed, liquid comps removed,
                           vapor boxes flipped, liquid boxes flipped, distance rounds */
-    double   *dist_v;  /* [G] box-liquid distances (computed only when tail is set), capped */
+    double   *dist_v;  /* [G] box-liquid distances (computed when tail or vapor_cutoff is set),
+                          capped */
 } orc_detect_out;
 
 int     orc_grid(const orc_params *p, int32_t dims[3], double h[3]);

@@ -485,6 +485,30 @@ def test_slab_labels_away_from_planes(orc, slab16k):
     assert det.count.sum() == x.shape[1]
 
 
+def test_vapor_cutoffs_on_slab(orc, slab16k):
+    """Section 3.1's extension of Eq. 7 to the vapor, on the 16k slab (planes z = 17.5, 42.5).
+    Only vapor-side particles change; far in the vapor the cutoff falls to r_c^min; in between
+    it follows the distance to the planes within a box (labels are exact 2 sigma from them)."""
+    p0 = orc.params(slab16k.box)
+    p1 = orc.params(slab16k.box, vapor_cutoff=1)
+    x = orc.wrap(p0, slab16k.x)
+    d0, d1 = orc.detect(p0, x), orc.detect(p1, x)
+    assert np.array_equal(d0.label, d1.label) and np.array_equal(d0.dist, d1.dist)
+    assert np.array_equal(d0.d, d1.d)
+    z = x[2]
+    e = np.abs(z - 30.0) - 12.5                      # analytic depth into the vapor
+    assert np.all(d1.rc <= d0.rc) and np.all(d1.rc >= 2.5)
+    # the liquid keeps its cutoffs
+    assert np.array_equal(d1.rc[e < -1.0], d0.rc[e < -1.0])
+    far = e > 6.0 + 2.0
+    assert far.sum() > 20 and np.all(d1.rc[far] == 2.5) and np.all(d0.rc[far] == 6.0)
+    mid = (e > 2.0) & (e < 6.0)
+    assert mid.sum() > 20
+    lo = np.array([orc.cutoff(p0, q + 1.5) for q in e[mid]])
+    hi = np.array([orc.cutoff(p0, q - 0.5) for q in e[mid]])
+    assert np.all(d1.rc[mid] >= lo - 1e-12) and np.all(d1.rc[mid] <= hi + 1e-12)
+
+
 # ---------------------------------------------------------------- integrator (Eq. 1-2)
 def test_free_flight(orc):
     rng = np.random.default_rng(4)
