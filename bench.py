@@ -658,6 +658,8 @@ def _detect_kw(args) -> dict:
               min_component=args.study_min_component)
     if args.study_tail:
         kw["tail"] = 1
+    if args.study_vapor_cutoffs:
+        kw["vapor_cutoff"] = 1
     return kw
 
 
@@ -671,6 +673,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tail", action="store_true",
                     help="with the runtime tail correction (Eq. 21-22): its cost on the same workload")
+    ap.add_argument("--vapor-cutoffs", action="store_true",
+                    help="vapor particles with dynamic cutoffs too (Section 3.1's extension of Eq. 7)")
     ap.add_argument("--compare-static", action="store_true",
                     help="also time the same system with a static cutoff r_c = r_c^max")
     ap.add_argument("--forces-only", type=int, default=0, metavar="K",
@@ -698,6 +702,8 @@ def main():
     ap.add_argument("--study-smooth", type=int, default=1, help="studies: smoothing passes")
     ap.add_argument("--study-min-component", type=int, default=27,
                     help="studies: components below this many boxes are removed")
+    ap.add_argument("--study-vapor-cutoffs", action="store_true",
+                    help="--accuracy-study / --nvt-study: vapor particles with dynamic cutoffs too")
     ap.add_argument("--study-tail", action="store_true",
                     help="--accuracy-study / --nvt-study: with the runtime tail correction (Eq. 21-22)")
     ap.add_argument("--save-dir", type=str, default="", help="--nvt-study: write the final states here")
@@ -748,7 +754,8 @@ def main():
     log(f"generating {WORKLOAD}")
     state = synth.named(WORKLOAD)
     prec = dcm.DCM_FP64 if args.precision == "fp64" else dcm.DCM_FP32C
-    p = dcm.params(state.box, precision=prec, tail=1 if args.tail else 0)
+    p = dcm.params(state.box, precision=prec, tail=1 if args.tail else 0,
+                   vapor_cutoff=1 if args.vapor_cutoffs else 0)
     stream = torch.cuda.current_stream()
     sysm = dcm.System(p, state.x, state.v)
     if args.forces_only:
@@ -834,7 +841,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "LJ liquid/vapor slab, 2,048,000 particles, box 320x320x60, "
                                "r_c 2.5..6 (exponential), detect every 2nd step, dt 0.005, NVE"
-                               + (", runtime tail correction" if args.tail else ""),
+                               + (", runtime tail correction" if args.tail else "")
+                               + (", vapor cutoffs" if args.vapor_cutoffs else ""),
                    "n_particles": state.n, "grid": list(sysm.dims), "detect_every": 2,
                    "thermo_every_step": True},
         "roofline": {"bound": "alu", "kernel": "KForces (FP64 pair forces, energy, virial)",

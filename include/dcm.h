@@ -96,6 +96,12 @@ typedef struct {
                                2 r_c^max + max h_k instead of r_c^max + max h_k. The correction
                                is a mean field, not conservative, and adds nothing to the
                                virial.                                                       */
+    int32_t vapor_cutoff;   /* 1: dynamic cutoffs in the vapor too, the extension of Eq. 7 that
+                               Section 3.1 suggests [0]: particle i gets the cutoff of the
+                               larger of its interpolated depth into the liquid and into the
+                               vapor, which mirrors Eq. 7 about the interface; a vapor particle
+                               r_c^max or more from the liquid gets r_c^min. Needs the second
+                               distance solve of the tail correction.                         */
 } dcm_params;
 
 /* One thermodynamic record (all FP64 sums in a fixed reduction order).
@@ -125,7 +131,7 @@ typedef struct {
     int64_t *stats;    /* [6] Lloyd iterations, vapor / liquid components removed,
                           vapor / liquid boxes flipped, distance sweeps                  */
     double *dist_v;    /* distances of the boxes to the liquid (liquid boxes 0), capped like
-                          dist; only with tail = 1, else DCM_E_INVALID                   */
+                          dist; only with tail = 1 or vapor_cutoff = 1, else DCM_E_INVALID */
 } dcm_detect_out;
 
 typedef struct dcm_system dcm_system;

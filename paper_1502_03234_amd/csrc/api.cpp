@@ -123,6 +123,7 @@ dcm_status validate(const dcm_params *p, int64_t n, Grid &g)
         return fail(DCM_E_INVALID, "the thermostat needs temperature > 0 and tdamp > 0 (got %g, %g)",
                     p->temperature, p->tdamp);
     if (p->tail != 0 && p->tail != 1) return fail(DCM_E_INVALID, "tail must be 0 or 1");
+    if (p->vapor_cutoff != 0 && p->vapor_cutoff != 1) return fail(DCM_E_INVALID, "vapor_cutoff must be 0 or 1");
     if (p->tail && (p->pair_rule != DCM_PAIR_I || p->energy_shift))
         return fail(DCM_E_INVALID, "the tail correction needs pair_rule DCM_PAIR_I and energy_shift 0");
     return DCM_OK;
@@ -180,7 +181,7 @@ size_t layout(dcm_system *s, void *ws)
     s->gw.tcur = b.take<uint32_t>(2 * distance_tiles(s->grid));
     s->gw.dist2 = b.take<double>(G);
     s->gw.ctile = b.take<uint8_t>(component_tiles(s->grid));
-    s->gw.dist_v = s->p.tail ? b.take<double>(G) : nullptr;
+    s->gw.dist_v = (s->p.tail || s->p.vapor_cutoff) ? b.take<double>(G) : nullptr;
     s->nfb = force_blocks(n);
     s->nkb = stream_blocks(n);
     s->fparts = b.take<Partial>(s->nfb);
@@ -267,11 +268,12 @@ void detect(dcm_system *s, hipStream_t st, bool with_cutoffs = true)
     stage_end(s, st);
     stage_begin(s, 5, st);
     launch_distance(g, s->cap, w.label, kLabelVapor, w.dist, w, w.stats + 5, st);
-    if (s->p.tail) launch_distance(g, s->cap, w.label, kLabelLiquid, w.dist_v, w, w.stats + 6, st);
+    if (w.dist_v) launch_distance(g, s->cap, w.label, kLabelLiquid, w.dist_v, w, w.stats + 6, st);
     stage_end(s, st);
     if (!with_cutoffs) return;
     stage_begin(s, 6, st);
-    launch_cutoffs(g, s->set[s->cur], s->n, w.dist, s->cap, s->p.rc_min, s->p.rc_max, s->p.alpha,
+    launch_cutoffs(g, s->set[s->cur], s->n, w.dist, s->p.vapor_cutoff ? w.dist_v : nullptr, s->cap,
+                   s->p.rc_min, s->p.rc_max, s->p.alpha,
                    s->cut_a, s->cut_b, s->p.cutoff_shape == DCM_CUTOFF_LINEAR ? 1 : 0, st);
     stage_end(s, st);
 }
@@ -480,7 +482,8 @@ dcm_status dcm_set_cutoffs(dcm_system *s, dcm_stream_t stream, const double *d_r
 dcm_status dcm_detect_interface(dcm_system *s, dcm_stream_t stream, const dcm_detect_out *o)
 {
     if (!s) return fail(DCM_E_INVALID, "system is NULL");
-    if (o && o->dist_v && !s->p.tail) return fail(DCM_E_INVALID, "dist_v needs the tail correction (tail = 1)");
+    if (o && o->dist_v && !s->gw.dist_v)
+        return fail(DCM_E_INVALID, "dist_v needs tail = 1 or vapor_cutoff = 1");
     hipStream_t st = (hipStream_t)stream;
     detect(s, st);
     if (o) {

@@ -970,6 +970,7 @@ struct KCutoffs {
         PSet s;
         int64_t n;
         const double *dist;
+        const double *dist_v;   // NULL unless vapor particles get dynamic cutoffs too
         double cap;
         double rc_min;
         double rc_max;
@@ -1010,15 +1011,20 @@ __device__ void KCutoffs::run(const Args &args_, uint32_t blk, uint32_t)
         i0[k] = fi;
         i1[k] = fi + 1 == g.n[k] ? 0 : fi + 1;
     }
-#define DV(ii, jj, kk) fmin(dist[lin(g, ii, jj, kk)], cap)
-    double c00 = lerp(DV(i0[0], i0[1], i0[2]), DV(i1[0], i0[1], i0[2]), t[0]);
-    double c10 = lerp(DV(i0[0], i1[1], i0[2]), DV(i1[0], i1[1], i0[2]), t[0]);
-    double c01 = lerp(DV(i0[0], i0[1], i1[2]), DV(i1[0], i0[1], i1[2]), t[0]);
-    double c11 = lerp(DV(i0[0], i1[1], i1[2]), DV(i1[0], i1[1], i1[2]), t[0]);
+    auto interp = [&](const double *D) {
+#define DV(ii, jj, kk) fmin(D[lin(g, ii, jj, kk)], cap)
+        double c00 = lerp(DV(i0[0], i0[1], i0[2]), DV(i1[0], i0[1], i0[2]), t[0]);
+        double c10 = lerp(DV(i0[0], i1[1], i0[2]), DV(i1[0], i1[1], i0[2]), t[0]);
+        double c01 = lerp(DV(i0[0], i0[1], i1[2]), DV(i1[0], i0[1], i1[2]), t[0]);
+        double c11 = lerp(DV(i0[0], i1[1], i1[2]), DV(i1[0], i1[1], i1[2]), t[0]);
 #undef DV
-    double c0 = lerp(c00, c10, t[1]);
-    double c1 = lerp(c01, c11, t[1]);
-    double d = lerp(c0, c1, t[2]);
+        double c0 = lerp(c00, c10, t[1]);
+        double c1 = lerp(c01, c11, t[1]);
+        return lerp(c0, c1, t[2]);
+    };
+    double d = interp(dist);
+    // vapor particles too: the larger of the two depths mirrors Eq. 7 about the interface
+    if (args_.dist_v) d = fmax(d, interp(args_.dist_v));
     double rc;
     if (rc_min == rc_max || d <= 0.0) rc = rc_max;
     else if (d >= rc_max) rc = rc_min;
@@ -1121,10 +1127,10 @@ void launch_cap_copy(const double *dist, double cap, double *out, int64_t G, hip
     emit<KCapCopy>({dist, cap, out, G}, grid1(G), st);
 }
 
-void launch_cutoffs(const Grid &g, PSet s, int64_t n, const double *dist, double cap, double rc_min,
-                    double rc_max, double alpha, double a, double b, int linear, hipStream_t st)
+void launch_cutoffs(const Grid &g, PSet s, int64_t n, const double *dist, const double *dist_v, double cap,
+                    double rc_min, double rc_max, double alpha, double a, double b, int linear, hipStream_t st)
 {
-    emit<KCutoffs>({g, s, n, dist, cap, rc_min, rc_max, alpha, a, b, linear}, grid1(n), st);
+    emit<KCutoffs>({g, s, n, dist, dist_v, cap, rc_min, rc_max, alpha, a, b, linear}, grid1(n), st);
 }
 
 }  // namespace dcm

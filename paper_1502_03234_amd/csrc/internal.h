@@ -118,7 +118,8 @@ constexpr uint8_t kLabelLiquid = 0, kLabelVapor = 1;
 // *sweeps.
 void launch_distance(const Grid &g, double cap, const uint8_t *label, uint8_t zero, double *dist,
                      GridWork w, long long *sweeps, hipStream_t st);
-void launch_cutoffs(const Grid &g, PSet s, int64_t n, const double *dist, double cap,
+// dist_v (optional): box-liquid distances; the cutoff then takes the larger of the two depths.
+void launch_cutoffs(const Grid &g, PSet s, int64_t n, const double *dist, const double *dist_v, double cap,
                     double rc_min, double rc_max, double alpha, double a, double b, int linear, hipStream_t st);
 void launch_cap_copy(const double *dist, double cap, double *out, int64_t G, hipStream_t st);
 void launch_count_from_ranges(const Grid &g, const uint32_t *cell_start, uint32_t *out, hipStream_t st);

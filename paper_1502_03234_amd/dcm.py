@@ -39,7 +39,8 @@ class Params(C.Structure):
                 ("min_component", C.c_int32), ("detect_every", C.c_int32),
                 ("precision", C.c_int32), ("pair_rule", C.c_int32), ("energy_shift", C.c_int32),
                 ("dt", C.c_double), ("temperature", C.c_double), ("tdamp", C.c_double),
-                ("thermostat", C.c_int32), ("cutoff_shape", C.c_int32), ("tail", C.c_int32)]
+                ("thermostat", C.c_int32), ("cutoff_shape", C.c_int32), ("tail", C.c_int32),
+                ("vapor_cutoff", C.c_int32)]
 
 
 class Thermo(C.Structure):
@@ -129,7 +130,7 @@ def _stream(stream=None) -> int:
 def params(box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_min=2.5, rc_max=6.0, alpha=-0.5, bin=1.0,
            smooth_passes=1, min_component=27, detect_every=2, precision=DCM_FP64,
            pair_rule=DCM_PAIR_I, energy_shift=0, dt=0.005, temperature=0.7, tdamp=0.5,
-           thermostat=DCM_NVE, cutoff_shape=DCM_CUTOFF_EXP, tail=0) -> Params:
+           thermostat=DCM_NVE, cutoff_shape=DCM_CUTOFF_EXP, tail=0, vapor_cutoff=0) -> Params:
     p = Params()
     p.box[:] = [float(b) for b in box]
     p.epsilon, p.sigma, p.mass = epsilon, sigma, mass
@@ -139,6 +140,7 @@ def params(box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_min=2.5, rc_max=6.0, alp
     p.temperature, p.tdamp, p.thermostat = temperature, tdamp, thermostat
     p.cutoff_shape = cutoff_shape
     p.tail = tail
+    p.vapor_cutoff = vapor_cutoff
     return p
 
 
@@ -367,7 +369,7 @@ class System:
                  raw=self._t(self.G, torch.uint8), label=self._t(self.G, torch.uint8),
                  dist=self._t(self.G, torch.float64), rc=self._t(self.n, torch.float64),
                  km=self._t(3, torch.float64), stats=self._t(6, torch.int64))
-        if self.p.tail:
+        if self.p.tail or self.p.vapor_cutoff:
             o["dist_v"] = self._t(self.G, torch.float64)
         dcm_detect_interface(self.h, self.stream, **o)
         return o

@@ -41,13 +41,14 @@ def dist_ulps(cap, hmin):
     return 2 * int(np.ceil(cap / hmin))
 
 
-def rc_close(rc, ref, rc_min=2.5, rc_max=6.0, alpha=-0.5, h=1.0, linear=False):
+def rc_close(rc, ref, rc_min=2.5, rc_max=6.0, alpha=-0.5, h=1.0, linear=False, cap=None):
     """Cutoffs within the propagated bound: box distances may differ by dist_ulps ulp of the
-    band cap, the cutoff function's slope is at most |a alpha ln 2| (Eq. 7-8; (r_c^max -
-    r_c^min) / r_c^max for the linear ramp), plus 4 ulp of r_c itself for the exponential."""
+    band cap (r_c^max + h unless given), the cutoff function's slope is at most |a alpha ln 2|
+    (Eq. 7-8; (r_c^max - r_c^min) / r_c^max for the linear ramp), plus 4 ulp of r_c itself for
+    the exponential."""
     a = (rc_max - rc_min) / (2.0 ** (alpha * rc_max) - 1.0) if rc_min != rc_max else 0.0
     slope = (rc_max - rc_min) / rc_max if linear else abs(a * alpha * np.log(2.0))
-    cap = rc_max + h
+    cap = rc_max + h if cap is None else cap
     tol = slope * dist_ulps(cap, h) * np.spacing(cap) + ULP_TOL * np.spacing(np.maximum(np.abs(rc), np.abs(ref)))
     return np.all(np.abs(np.asarray(rc) - np.asarray(ref)) <= tol)
 
