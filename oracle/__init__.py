@@ -43,7 +43,8 @@ class Params(C.Structure):
                 ("min_component", C.c_int32), ("detect_every", C.c_int32),
                 ("pair_rule", C.c_int32), ("energy_shift", C.c_int32), ("dt", C.c_double),
                 ("temperature", C.c_double), ("tdamp", C.c_double), ("thermostat", C.c_int32), ("cutoff_shape", C.c_int32),
-                ("tail", C.c_int32), ("vapor_cutoff", C.c_int32)]
+                ("tail", C.c_int32), ("vapor_cutoff", C.c_int32), ("ms_nu", C.c_double),
+                ("ms_iters", C.c_int32)]
 
 
 class Thermo(C.Structure):
@@ -93,6 +94,8 @@ def lib():
         L.orc_interp_grad.argtypes = [vp, vp, vp, vp, vp]
         L.orc_interp_grad.restype = d
         L.orc_tail.argtypes = [P, vp, vp, vp, i64, vp, vp, vp, vp]
+        L.orc_ms_solve.argtypes = [vp, vp, vp, i32, vp]
+        L.orc_mumford_shah.argtypes = [vp, vp, d, vp, vp, d, i32, vp, vp]
         _lib = L
     return _lib
 
@@ -104,7 +107,7 @@ def _p(a):
 def params(box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_min=2.5, rc_max=6.0, alpha=-0.5,
            bin=1.0, smooth_passes=1, min_component=27, detect_every=2, pair_rule=0,
            energy_shift=0, dt=0.005, temperature=0.7, tdamp=0.5, thermostat=0,
-           cutoff_shape=0, tail=0, vapor_cutoff=0) -> Params:
+           cutoff_shape=0, tail=0, vapor_cutoff=0, ms_nu=0.0, ms_iters=100) -> Params:
     p = Params()
     p.box[:] = [float(b) for b in box]
     p.epsilon, p.sigma, p.mass = epsilon, sigma, mass
@@ -116,6 +119,7 @@ def params(box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_min=2.5, rc_max=6.0, alp
     p.cutoff_shape = cutoff_shape
     p.tail = tail
     p.vapor_cutoff = vapor_cutoff
+    p.ms_nu, p.ms_iters = ms_nu, ms_iters
     return p
 
 
@@ -205,6 +209,30 @@ def interp(dims, h, D: np.ndarray, xp) -> float:
     D = np.ascontiguousarray(D, np.float64).ravel()
     xp = np.asarray(xp, np.float64)
     return lib().orc_interp(_p(dims), _p(h), _p(D), _p(xp))
+
+
+def ms_solve(dims, r: np.ndarray, w, iters: int, u0: np.ndarray) -> np.ndarray:
+    """Relaxed two-phase segmentation (Eq. 13): minimise sum u r + sum_k w_k |D_k u| over
+    u in [0, 1] by primal-dual iterations from u0; returns u."""
+    dims = np.asarray(dims, np.int32)
+    r = np.ascontiguousarray(r, np.float64).ravel()
+    w = np.asarray(w, np.float64)
+    u = np.ascontiguousarray(u0, np.float64).ravel().copy()
+    lib().orc_ms_solve(_p(dims), _p(r), _p(w), int(iters), _p(u))
+    return u
+
+
+def mumford_shah(dims, h, Lmax: float, g: np.ndarray, km, nu: float, iters: int, raw: np.ndarray):
+    """Eq. 13 on image g from the labels raw (threshold labels): (labels, relaxed u)."""
+    dims = np.asarray(dims, np.int32)
+    h = np.asarray(h, np.float64)
+    g = np.ascontiguousarray(g, np.uint32).ravel()
+    km = np.ascontiguousarray(km, np.float64)
+    lab = np.ascontiguousarray(raw, np.uint8).ravel().copy()
+    u = np.zeros(lab.size)
+    lib().orc_mumford_shah(_p(dims), _p(h), float(Lmax), _p(g), _p(km), float(nu), int(iters),
+                           _p(lab), _p(u))
+    return lab, u
 
 
 def interp_grad(dims, h, D: np.ndarray, xp):

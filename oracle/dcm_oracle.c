@@ -10,6 +10,9 @@
  *   orc_components /
  *   orc_segment             Eq. 11-12 labels; Section 4.2, Alg. 4.1 connected components
  *                           (here a breadth-first flood fill), small-component removal
+ *   orc_mumford_shah /
+ *   orc_ms_solve            Section 4.1, Eq. 13 (two-phase piecewise-constant Mumford-Shah
+ *                           segmentation; convex relaxation solved by a primal-dual method)
  *   orc_distance            Section 4.3, Eq. 15-19, Alg. 4.2 (fast sweeping, repeated
  *                           until nothing changes; band limited as in Section 4.3.2)
  *   orc_interp              Section 3, Eq. 5-6, Alg. 3.1 (trilinear interpolation)
@@ -190,13 +193,23 @@ int64_t orc_components(const int32_t d[3], const uint8_t *s, uint8_t phase, uint
  * min_component boxes become liquid; then, on the updated image, liquid components with
  * fewer than min_component boxes become vapor.
  * stats = {vapor comps removed, liquid comps removed, vapor boxes flipped, liquid flipped} */
+static void remove_small(const int32_t d[3], int32_t min_component, uint8_t *label, int64_t stats[4]);
+
 void orc_segment(const int32_t d[3], const uint32_t *g, double t, int32_t min_component,
                  uint8_t *raw, uint8_t *label, int64_t stats[4])
 {
     int64_t G = (int64_t)d[0] * d[1] * d[2];
+    for (int64_t c = 0; c < G; ++c) { raw[c] = ((double)g[c] > t) ? 0 : 1; label[c] = raw[c]; }
+    remove_small(d, min_component, label, stats);
+}
+
+/* Section 4.2: vapor components smaller than min_component boxes become liquid, then liquid
+ * components smaller than that (on the updated labels) become vapor. */
+static void remove_small(const int32_t d[3], int32_t min_component, uint8_t *label, int64_t stats[4])
+{
+    int64_t G = (int64_t)d[0] * d[1] * d[2];
     uint32_t *comp = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)G);
     uint32_t *size = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)G);
-    for (int64_t c = 0; c < G; ++c) { raw[c] = ((double)g[c] > t) ? 0 : 1; label[c] = raw[c]; }
     for (int pass = 0; pass < 2; ++pass) {
         uint8_t phase = pass == 0 ? 1 : 0;
         orc_components(d, label, phase, comp, size);
@@ -214,6 +227,84 @@ void orc_segment(const int32_t d[3], const uint32_t *g, double t, int32_t min_co
     }
     free(comp);
     free(size);
+}
+
+/* ---- two-phase piecewise-constant Mumford-Shah segmentation (Eq. 13) --------------------
+ * Eq. 13 with its data terms in the intended pairing (the liquid set against rho_l, the vapor
+ * set against rho_v; the print swaps them) and the two densities fixed at the two-means centres
+ * (Section 4.1). The labelling is minimised through its convex relaxation: over u in [0, 1]^G
+ * (u = 1 liquid),
+ *     sum_c u_c r_c + sum_c sum_k w_k |u(c + e_k) - u(c)|,  r_c = (f_c - rho_l)^2 - (f_c - rho_v)^2,
+ * whose perimeter term is the anisotropic total variation (faces of the box grid, periodic);
+ * for it the coarea formula holds, so every level set {u > t}, 0 < t < 1, of a minimiser is a
+ * minimising labelling (Chan, Esedoglu and Nikolova 2006). The minimiser is sought by the
+ * primal-dual algorithm of Chambolle and Pock (2011, Algorithm 1, theta = 1) with steps
+ * sigma = tau = 1 / sqrt(12) (the squared norm of the forward-difference operator is at most
+ * 12): per iteration
+ *     p_k <- clamp(p_k + sigma (ubar(c + e_k) - ubar(c)), -w_k, w_k)        (dual, per axis)
+ *     u'  <- clamp(u - tau (r - div p), 0, 1),  div p = sum_k (p_k(c) - p_k(c - e_k))
+ *     ubar <- 2 u' - u,  u <- u'
+ * from u = ubar = the threshold labelling and p = 0, for a fixed number of iterations; then
+ * liquid iff u > 1/2. The per-element operations are in the order written. */
+void orc_ms_solve(const int32_t d[3], const double *r, const double w[3], int32_t iters, double *u)
+{
+    int64_t G = (int64_t)d[0] * d[1] * d[2];
+    double *ub = (double *)malloc(sizeof(double) * (size_t)G);
+    double *p = (double *)calloc((size_t)G * 3, sizeof(double));
+    const double sigma = 1.0 / sqrt(12.0), tau = sigma;
+    memcpy(ub, u, sizeof(double) * (size_t)G);
+    for (int32_t it = 0; it < iters; ++it) {
+        for (int32_t k = 0; k < d[2]; ++k)
+            for (int32_t j = 0; j < d[1]; ++j)
+                for (int32_t i = 0; i < d[0]; ++i) {
+                    int64_t c = IDX(d, i, j, k);
+                    int64_t nb[3] = {IDX(d, pmod(i + 1, d[0]), j, k), IDX(d, i, pmod(j + 1, d[1]), k),
+                                     IDX(d, i, j, pmod(k + 1, d[2]))};
+                    for (int a = 0; a < 3; ++a) {
+                        double v = p[a * G + c] + sigma * (ub[nb[a]] - ub[c]);
+                        p[a * G + c] = fmin(fmax(v, -w[a]), w[a]);
+                    }
+                }
+        for (int32_t k = 0; k < d[2]; ++k)
+            for (int32_t j = 0; j < d[1]; ++j)
+                for (int32_t i = 0; i < d[0]; ++i) {
+                    int64_t c = IDX(d, i, j, k);
+                    int64_t nb[3] = {IDX(d, pmod(i - 1, d[0]), j, k), IDX(d, i, pmod(j - 1, d[1]), k),
+                                     IDX(d, i, j, pmod(k - 1, d[2]))};
+                    double div = ((p[c] - p[nb[0]]) + (p[G + c] - p[G + nb[1]])) + (p[2 * G + c] - p[2 * G + nb[2]]);
+                    double un = fmin(fmax(u[c] - tau * (r[c] - div), 0.0), 1.0);
+                    ub[c] = 2.0 * un - u[c];
+                    u[c] = un;
+                }
+    }
+    free(ub);
+    free(p);
+}
+
+/* Eq. 13 on the density image g (the image the two-means centres came from), in units where
+ * the liquid centre is 1 and the longest box edge L_max is 1: f = g / rho_l, and per unit box
+ * volume a face normal to axis k weighs nu L_max / h_k. raw holds the threshold labels on entry
+ * and the minimiser's labels (0 liquid, 1 vapor) on exit; u (optional) the relaxed field. */
+void orc_mumford_shah(const int32_t d[3], const double h[3], double Lmax, const uint32_t *g,
+                      const double km[3], double nu, int32_t iters, uint8_t *raw, double *u_out)
+{
+    int64_t G = (int64_t)d[0] * d[1] * d[2];
+    if (!(km[1] > 0.0)) return;                       /* empty image: nothing to segment */
+    double *r = (double *)calloc((size_t)G, sizeof(double));
+    double *u = (double *)calloc((size_t)G, sizeof(double));
+    double cv = km[0] / km[1];
+    for (int64_t c = 0; c < G; ++c) {
+        double f = (double)g[c] / km[1];
+        double fl = f - 1.0, fv = f - cv;
+        r[c] = fl * fl - fv * fv;
+        u[c] = raw[c] == 0 ? 1.0 : 0.0;
+    }
+    double w[3] = {nu * Lmax / h[0], nu * Lmax / h[1], nu * Lmax / h[2]};
+    orc_ms_solve(d, r, w, iters, u);
+    for (int64_t c = 0; c < G; ++c) raw[c] = u[c] > 0.5 ? 0 : 1;
+    if (u_out) memcpy(u_out, u, sizeof(double) * (size_t)G);
+    free(r);
+    free(u);
 }
 
 /* ---- Godunov upwind update (Eq. 16-18, three dimensions, per-axis spacing) -------------
@@ -365,7 +456,16 @@ int orc_detect(const orc_params *p, int64_t n, const double *x, orc_detect_out *
     orc_bin(p, n, x, o->count, NULL);
     orc_smooth(d, p->smooth_passes, o->count, o->smooth);
     o->stats[0] = orc_two_means(G, o->smooth, o->km);
-    orc_segment(d, o->smooth, o->km[2], p->min_component, o->raw, o->label, o->stats + 1);
+    if (p->ms_nu > 0.0) {
+        /* Eq. 13 in place of the plain threshold, then the removal of Section 4.2 */
+        for (int64_t c = 0; c < G; ++c) o->raw[c] = ((double)o->smooth[c] > o->km[2]) ? 0 : 1;
+        double Lmax = fmax(p->box[0], fmax(p->box[1], p->box[2]));
+        orc_mumford_shah(d, h, Lmax, o->smooth, o->km, p->ms_nu, p->ms_iters, o->raw, NULL);
+        memcpy(o->label, o->raw, (size_t)G);
+        remove_small(d, p->min_component, o->label, o->stats + 1);
+    } else {
+        orc_segment(d, o->smooth, o->km[2], p->min_component, o->raw, o->label, o->stats + 1);
+    }
     double cap = band_limit(p, h);
     o->stats[5] = orc_distance(d, h, cap, o->label, o->dist);
     int vapor_side = (p->tail || p->vapor_cutoff) && o->dist_v;

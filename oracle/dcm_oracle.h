@@ -25,6 +25,8 @@ typedef struct {
     int32_t cutoff_shape;        /* 0: exponential (Eq. 7-8), 1: linear ramp            */
     int32_t tail;                /* 1: add the runtime tail correction (Eq. 21-22)      */
     int32_t vapor_cutoff;        /* 1: dynamic cutoffs in the vapor too (Section 3.1)   */
+    double ms_nu;                /* > 0: Mumford-Shah segmentation (Eq. 13), its nu     */
+    int32_t ms_iters;            /* primal-dual iterations of that segmentation         */
 } orc_params;
 
 typedef struct {
@@ -58,6 +60,10 @@ int64_t orc_components(const int32_t dims[3], const uint8_t *s, uint8_t phase,
                        uint32_t *comp, uint32_t *size);
 void    orc_segment(const int32_t dims[3], const uint32_t *g, double t, int32_t min_component,
                     uint8_t *raw, uint8_t *label, int64_t stats[4]);
+void    orc_ms_solve(const int32_t dims[3], const double *r, const double w[3], int32_t iters,
+                     double *u);
+void    orc_mumford_shah(const int32_t dims[3], const double h[3], double Lmax, const uint32_t *g,
+                         const double km[3], double nu, int32_t iters, uint8_t *raw, double *u_out);
 int64_t orc_distance(const int32_t dims[3], const double h[3], double cap, const uint8_t *label,
                      double *dist);
 double  orc_godunov(const double a[3], const double h[3]);

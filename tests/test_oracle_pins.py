@@ -868,3 +868,117 @@ def test_tail_on_a_planar_slab(orc):
         assert du[i] == pytest.approx(want_u, rel=1e-12, abs=1e-14), (zi, delta)
         assert f[2, i] == pytest.approx(want_f, rel=1e-12, abs=1e-14), (zi, delta)
     assert ndeep == 4
+
+
+# ---------------------------------------------------------------- Mumford-Shah segmentation (Eq. 13)
+def _ms_mincut(d, r, w):
+    """Exact minimum of sum_c r_c x_c + sum_k w_k sum_c |x(c + e_k) - x(c)| over x in {0, 1}^G
+    (periodic) by a minimum s-t cut (scipy's maximum flow; integer r and w)."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import maximum_flow
+    G = int(np.prod(d))
+    s, t = G, G + 1
+    rows, cols, caps, off = [], [], [], 0
+    for c in range(G):
+        if r[c] > 0:
+            rows.append(s); cols.append(c); caps.append(int(r[c]))
+        elif r[c] < 0:
+            rows.append(c); cols.append(t); caps.append(int(-r[c])); off += int(r[c])
+    idx = np.arange(G).reshape(d[2], d[1], d[0])
+    for a, ax in enumerate((2, 1, 0)):
+        nb = np.roll(idx, -1, ax).ravel()
+        for c, q in zip(idx.ravel(), nb):
+            rows += [c, q]; cols += [q, c]; caps += [int(w[a]), int(w[a])]
+    m = sp.coo_matrix((caps, (rows, cols)), shape=(G + 2, G + 2)).tocsr()
+    m.sum_duplicates()
+    return maximum_flow(m.astype(np.int32), s, t).flow_value + off
+
+
+def _ms_energy(d, r, w, x):
+    x3 = x.reshape(d[2], d[1], d[0]).astype(np.int64)
+    e = float(np.sum(r * x))
+    for a, ax in enumerate((2, 1, 0)):
+        e += w[a] * np.abs(np.roll(x3, -1, ax) - x3).sum()
+    return e
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_ms_solve_reaches_the_minimum_cut(orc, seed):
+    """The relaxation thresholded at 1/2 attains the exact binary minimum (coarea formula),
+    which a minimum s-t cut computes independently."""
+    rng = np.random.default_rng(seed)
+    d = np.array(rng.integers(3, 7, 3), np.int32)
+    G = int(np.prod(d))
+    r = rng.integers(-100, 101, G).astype(np.float64)
+    w = rng.integers(2, 14, 3).astype(np.float64)
+    u = orc.ms_solve(d, r, w, 1000, (r < 0).astype(np.float64))
+    assert np.all((u >= 0.0) & (u <= 1.0))
+    assert _ms_energy(d, r, w, (u > 0.5).astype(np.int64)) == _ms_mincut(d, r, w)
+
+
+def test_ms_solve_limits(orc):
+    rng = np.random.default_rng(9)
+    d = np.array([5, 4, 6], np.int32)
+    G = int(np.prod(d))
+    r = rng.uniform(-1, 1, G)
+    # no perimeter weight: each box takes its cheaper phase
+    u = orc.ms_solve(d, r, [0.0, 0.0, 0.0], 200, np.full(G, 0.5))
+    assert np.array_equal(u > 0.5, r < 0)
+    # a perimeter weight above every data term: one phase everywhere, the cheaper in total
+    u = orc.ms_solve(d, r, [10.0, 10.0, 10.0], 2000, (r < 0).astype(np.float64))
+    lab = u > 0.5
+    assert lab.all() or (~lab).all()
+    assert lab.all() == (r.sum() < 0)
+
+
+def test_mumford_shah_removes_a_planted_bubble(orc):
+    """A slab image with one liquid box planted in the vapor and one vapor box in the liquid:
+    a perimeter weight above the data gain of a single box (6 faces) removes both, nu = 0 keeps
+    them. Scaling the image, or the box and its edges together, changes nothing."""
+    dims = np.array([8, 8, 16], np.int32)
+    h = np.array([1.0, 1.0, 1.0])
+    g = np.full((16, 8, 8), 2, np.uint32)
+    g[4:12] = 50
+    g[1, 3, 3] = 50             # liquid box in the vapor
+    g[8, 5, 2] = 2              # vapor box in the liquid
+    km = np.array([2.0, 50.0, 26.0])
+    raw = np.where(g.ravel() > km[2], 0, 1).astype(np.uint8)
+    keep, _ = orc.mumford_shah(dims, h, 16.0, g, km, 0.0, 300, raw)
+    assert np.array_equal(keep, raw)
+    # data gain of flipping one planted box: (1 - 0.04)^2 = 0.92 in units of rho_l; a face
+    # weighs nu * L_max / h = nu * 16
+    gone, u = orc.mumford_shah(dims, h, 16.0, g, km, 0.2 / 16, 2000, raw)
+    want = raw.copy().reshape(16, 8, 8)
+    want[1, 3, 3] = 1
+    want[8, 5, 2] = 0
+    assert np.array_equal(gone, want.ravel())
+    lab2, _ = orc.mumford_shah(dims, h, 16.0, 3 * g, 3 * km, 0.2 / 16, 2000, raw)
+    assert np.array_equal(lab2, gone)
+    lab3, _ = orc.mumford_shah(dims, 2 * h, 32.0, g, km, 0.2 / 16, 2000, raw)
+    assert np.array_equal(lab3, gone)
+    # a weight below 0.92 / 6 per face keeps them
+    kept, _ = orc.mumford_shah(dims, h, 16.0, g, km, 0.1 / 16, 2000, raw)
+    assert np.array_equal(kept, raw)
+
+
+def test_mumford_shah_detection_on_slab(orc, slab16k):
+    """Eq. 13 inside the detection on the 16k slab (planes z = 17.5, 42.5), at the thesis's
+    nu = 0.005: with 1-sigma boxes and one smoothing pass, and with the thesis's ~2.6-sigma boxes
+    and no smoothing, the segmentation is the two flat planes (2 x N_x x N_y faces), every box
+    more than 2 sigma from them labelled right. The plain threshold leaves rough planes and,
+    with the coarse boxes, mislabelled boxes deep in the liquid."""
+    for kw in (dict(smooth_passes=1), dict(smooth_passes=0, bin=2.6, min_component=5)):
+        p0 = orc.params(slab16k.box, **kw)
+        p1 = orc.params(slab16k.box, ms_nu=0.005, ms_iters=200, **kw)
+        x = orc.wrap(p0, slab16k.x)
+        d0, d1 = orc.detect(p0, x), orc.detect(p1, x)
+        dims, h = orc.grid(p1)
+        assert np.array_equal(d0.km, d1.km) and np.array_equal(d0.smooth, d1.smooth)
+        lab = d1.label.reshape(orc.grid_shape(dims))
+        zc = (np.arange(dims[2]) + 0.5) * h[2]
+        assert np.all(lab[np.abs(zc - 30.0) < 10.5] == 0) and np.all(lab[np.abs(zc - 30.0) > 14.5] == 1)
+
+        def faces(a):
+            a = a.reshape(orc.grid_shape(dims)).astype(np.int64)
+            return sum(int(np.abs(np.roll(a, -1, ax) - a).sum()) for ax in range(3))
+        assert faces(d1.raw) == 2 * dims[0] * dims[1] < faces(d0.raw)
