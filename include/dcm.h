@@ -102,6 +102,14 @@ typedef struct {
                                vapor, which mirrors Eq. 7 about the interface; a vapor particle
                                r_c^max or more from the liquid gets r_c^min. Needs the second
                                distance solve of the tail correction.                         */
+    double ms_nu;           /* > 0: the segmentation of Eq. 13 (two-phase piecewise-constant
+                               Mumford-Shah) replaces the plain threshold, with this perimeter
+                               weight [0]; densities are the two-means centres, the image is
+                               scaled so that the liquid centre is 1 and lengths so that the
+                               longest box edge is 1 (the thesis uses nu = 0.005). Solved by
+                               ms_iters primal-dual iterations of its convex relaxation from the
+                               threshold labels; components are removed afterwards as before. */
+    int32_t ms_iters;       /* iterations of that solver, 1..100000 [100]; ignored if ms_nu = 0 */
 } dcm_params;
 
 /* One thermodynamic record (all FP64 sums in a fixed reduction order).

@@ -85,6 +85,9 @@ bool grid_of(const dcm_params *p, Grid &g)
     return true;
 }
 
+// Upper bound on the segmentation's iterations (two launches each per detection).
+constexpr int32_t kMaxMsIters = 100000;
+
 dcm_status validate(const dcm_params *p, int64_t n, Grid &g)
 {
     if (!p) return fail(DCM_E_INVALID, "params is NULL");
@@ -124,6 +127,9 @@ dcm_status validate(const dcm_params *p, int64_t n, Grid &g)
                     p->temperature, p->tdamp);
     if (p->tail != 0 && p->tail != 1) return fail(DCM_E_INVALID, "tail must be 0 or 1");
     if (p->vapor_cutoff != 0 && p->vapor_cutoff != 1) return fail(DCM_E_INVALID, "vapor_cutoff must be 0 or 1");
+    if (!(p->ms_nu >= 0.0) || !std::isfinite(p->ms_nu)) return fail(DCM_E_INVALID, "ms_nu must be finite and >= 0");
+    if (p->ms_nu > 0.0 && (p->ms_iters < 1 || p->ms_iters > kMaxMsIters))
+        return fail(DCM_E_INVALID, "ms_iters must be in [1, %d] (got %d)", kMaxMsIters, p->ms_iters);
     if (p->tail && (p->pair_rule != DCM_PAIR_I || p->energy_shift))
         return fail(DCM_E_INVALID, "the tail correction needs pair_rule DCM_PAIR_I and energy_shift 0");
     return DCM_OK;
@@ -182,6 +188,13 @@ size_t layout(dcm_system *s, void *ws)
     s->gw.dist2 = b.take<double>(G);
     s->gw.ctile = b.take<uint8_t>(component_tiles(s->grid));
     s->gw.dist_v = (s->p.tail || s->p.vapor_cutoff) ? b.take<double>(G) : nullptr;
+    s->gw.ms = MsWork{nullptr, nullptr, nullptr, nullptr};
+    if (s->p.ms_nu > 0.0) {
+        s->gw.ms.u = b.take<double>(G);
+        s->gw.ms.ub = b.take<double>(G);
+        s->gw.ms.p = b.take<double>(3 * G);
+        s->gw.ms.r = b.take<double>(G);
+    }
     s->nfb = force_blocks(n);
     s->nkb = stream_blocks(n);
     s->fparts = b.take<Partial>(s->nfb);
@@ -264,7 +277,8 @@ void detect(dcm_system *s, hipStream_t st, bool with_cutoffs = true)
     launch_two_means(g, w.g, w, w.stats, st);
     stage_end(s, st);
     stage_begin(s, 4, st);
-    launch_segment(g, w.g, w.km, s->p.min_component, w, st);
+    MsParams ms = {s->p.ms_nu, std::max(s->p.box[0], std::max(s->p.box[1], s->p.box[2])), s->p.ms_iters};
+    launch_segment(g, w.g, w.km, s->p.min_component, ms, w, st);
     stage_end(s, st);
     stage_begin(s, 5, st);
     launch_distance(g, s->cap, w.label, kLabelVapor, w.dist, w, w.stats + 5, st);
@@ -681,6 +695,7 @@ static size_t grid_layout(const Grid &g, GridWork &w, void *ws, double cap)
     w.dist2 = b.take<double>(G);
     w.ctile = b.take<uint8_t>(component_tiles(g));
     w.dist_v = nullptr;
+    w.ms = MsWork{nullptr, nullptr, nullptr, nullptr};
     return b.off + 256;
 }
 
@@ -766,7 +781,7 @@ dcm_status dcm_grid_segment(const int32_t dims[3], const uint32_t *d_g, const do
     w.raw = d_raw;
     w.label = d_label;
     launch_fill_u32((uint32_t *)w.stats, 0u, 16, st);
-    launch_segment(g, d_g, d_km, min_component, w, st);
+    launch_segment(g, d_g, d_km, min_component, MsParams{0.0, 1.0, 0}, w, st);
     if (d_stats) launch_copy_bytes(d_stats, w.stats + 1, 4 * sizeof(long long), st);
     return hip_status("dcm_grid_segment");
 }

@@ -1072,9 +1072,10 @@ void launch_two_means(const Grid &g, const uint32_t *img, GridWork w, long long 
 }
 
 void launch_segment(const Grid &g, const uint32_t *img, const double *km, int32_t min_component,
-                    GridWork w, hipStream_t st)
+                    const MsParams &ms, GridWork w, hipStream_t st)
 {
     emit<KThreshold>({img, km, g.G, w.raw, w.label}, grid1(g.G), st);
+    if (ms.nu > 0.0) launch_mumford_shah(g, img, km, ms, w.raw, w.label, w.ms, st);
     if (min_component <= 1) return;                 // no component can be smaller
     for (int pass = 0; pass < 2; ++pass) {
         uint8_t phase = pass == 0 ? 1 : 0;

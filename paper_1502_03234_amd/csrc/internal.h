@@ -67,6 +67,19 @@ struct NhConst {
 enum { kNhNone = 0, kNhStart = 1, kNhEnd = 2 };
 
 // Scratch of the grid pipeline (interface detection), G entries each unless noted.
+// Box labels after segmentation (Eq. 11-12).
+constexpr uint8_t kLabelLiquid = 0, kLabelVapor = 1;
+
+// Working arrays of the Mumford-Shah segmentation (G boxes each; p holds 3 G).
+struct MsWork {
+    double *u, *ub, *p, *r;
+};
+struct MsParams {
+    double nu;       // perimeter weight of Eq. 13 (0: plain threshold)
+    double Lmax;     // longest box edge (the length unit of nu)
+    int32_t iters;   // primal-dual iterations
+};
+
 struct GridWork {
     uint32_t *cell_start;   // [G + 1] first sorted slot of each box (Eq. 9 counts = differences)
     uint32_t *g;            // smoothed image
@@ -86,6 +99,7 @@ struct GridWork {
     double *dist2;          // second copy of the distance grid
     uint8_t *ctile;         // [component_tiles] tile kinds of the current component pass
     double *dist_v;         // box-liquid distances (tail correction only, else NULL)
+    MsWork ms;              // Mumford-Shah segmentation (all NULL unless it is on)
 };
 
 // ---- launchers (each enqueues on `st`; no synchronization) ------------------------------
@@ -107,13 +121,16 @@ void launch_smooth(const Grid &g, int passes, const uint32_t *cell_start, const 
                    uint32_t *out, uint32_t *tmp, hipStream_t st);
 void launch_two_means(const Grid &g, const uint32_t *img, GridWork w, long long *stats_out,
                       hipStream_t st);
+// ms.nu > 0: Eq. 13's segmentation between the threshold and the component removal.
 void launch_segment(const Grid &g, const uint32_t *img, const double *km, int32_t min_component,
-                    GridWork w, hipStream_t st);
+                    const MsParams &ms, GridWork w, hipStream_t st);
+// mumford_shah.hip: raw holds the threshold labels on entry; raw and label the segmentation's.
+void launch_mumford_shah(const Grid &g, const uint32_t *img, const double *km, const MsParams &ms,
+                         uint8_t *raw, uint8_t *label, MsWork m, hipStream_t st);
 int max_distance_sweeps(const Grid &g, double cap);
 int64_t distance_tiles(const Grid &g);
 int64_t component_tiles(const Grid &g);
-// Box labels after segmentation (Eq. 11-12).
-constexpr uint8_t kLabelLiquid = 0, kLabelVapor = 1;
+
 // Distance of every box to the boxes labelled `zero` (which get 0); the sweep count goes to
 // *sweeps.
 void launch_distance(const Grid &g, double cap, const uint8_t *label, uint8_t zero, double *dist,

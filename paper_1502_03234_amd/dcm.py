@@ -40,7 +40,7 @@ class Params(C.Structure):
                 ("precision", C.c_int32), ("pair_rule", C.c_int32), ("energy_shift", C.c_int32),
                 ("dt", C.c_double), ("temperature", C.c_double), ("tdamp", C.c_double),
                 ("thermostat", C.c_int32), ("cutoff_shape", C.c_int32), ("tail", C.c_int32),
-                ("vapor_cutoff", C.c_int32)]
+                ("vapor_cutoff", C.c_int32), ("ms_nu", C.c_double), ("ms_iters", C.c_int32)]
 
 
 class Thermo(C.Structure):
@@ -130,7 +130,8 @@ def _stream(stream=None) -> int:
 def params(box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_min=2.5, rc_max=6.0, alpha=-0.5, bin=1.0,
            smooth_passes=1, min_component=27, detect_every=2, precision=DCM_FP64,
            pair_rule=DCM_PAIR_I, energy_shift=0, dt=0.005, temperature=0.7, tdamp=0.5,
-           thermostat=DCM_NVE, cutoff_shape=DCM_CUTOFF_EXP, tail=0, vapor_cutoff=0) -> Params:
+           thermostat=DCM_NVE, cutoff_shape=DCM_CUTOFF_EXP, tail=0, vapor_cutoff=0, ms_nu=0.0,
+           ms_iters=100) -> Params:
     p = Params()
     p.box[:] = [float(b) for b in box]
     p.epsilon, p.sigma, p.mass = epsilon, sigma, mass
@@ -141,6 +142,7 @@ def params(box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_min=2.5, rc_max=6.0, alp
     p.cutoff_shape = cutoff_shape
     p.tail = tail
     p.vapor_cutoff = vapor_cutoff
+    p.ms_nu, p.ms_iters = ms_nu, ms_iters
     return p
 
 
