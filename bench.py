@@ -660,6 +660,9 @@ def _detect_kw(args) -> dict:
         kw["tail"] = 1
     if args.study_vapor_cutoffs:
         kw["vapor_cutoff"] = 1
+    if args.study_ms_nu > 0:
+        kw["ms_nu"] = args.study_ms_nu
+        kw["ms_iters"] = args.study_ms_iters
     return kw
 
 
@@ -673,6 +676,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tail", action="store_true",
                     help="with the runtime tail correction (Eq. 21-22): its cost on the same workload")
+    ap.add_argument("--ms-nu", type=float, default=0.0,
+                    help="segment by Eq. 13 (Mumford-Shah) with this nu instead of the threshold")
+    ap.add_argument("--ms-iters", type=int, default=100, help="primal-dual iterations of --ms-nu")
     ap.add_argument("--vapor-cutoffs", action="store_true",
                     help="vapor particles with dynamic cutoffs too (Section 3.1's extension of Eq. 7)")
     ap.add_argument("--compare-static", action="store_true",
@@ -702,6 +708,9 @@ def main():
     ap.add_argument("--study-smooth", type=int, default=1, help="studies: smoothing passes")
     ap.add_argument("--study-min-component", type=int, default=27,
                     help="studies: components below this many boxes are removed")
+    ap.add_argument("--study-ms-nu", type=float, default=0.0,
+                    help="--accuracy-study / --nvt-study: Mumford-Shah segmentation (Eq. 13) with this nu")
+    ap.add_argument("--study-ms-iters", type=int, default=100, help="iterations of --study-ms-nu")
     ap.add_argument("--study-vapor-cutoffs", action="store_true",
                     help="--accuracy-study / --nvt-study: vapor particles with dynamic cutoffs too")
     ap.add_argument("--study-tail", action="store_true",
@@ -755,7 +764,7 @@ def main():
     state = synth.named(WORKLOAD)
     prec = dcm.DCM_FP64 if args.precision == "fp64" else dcm.DCM_FP32C
     p = dcm.params(state.box, precision=prec, tail=1 if args.tail else 0,
-                   vapor_cutoff=1 if args.vapor_cutoffs else 0)
+                   vapor_cutoff=1 if args.vapor_cutoffs else 0, ms_nu=args.ms_nu, ms_iters=args.ms_iters)
     stream = torch.cuda.current_stream()
     sysm = dcm.System(p, state.x, state.v)
     if args.forces_only:
@@ -842,7 +851,8 @@ def main():
         "config": {"workload": "LJ liquid/vapor slab, 2,048,000 particles, box 320x320x60, "
                                "r_c 2.5..6 (exponential), detect every 2nd step, dt 0.005, NVE"
                                + (", runtime tail correction" if args.tail else "")
-                               + (", vapor cutoffs" if args.vapor_cutoffs else ""),
+                               + (", vapor cutoffs" if args.vapor_cutoffs else "")
+                               + (f", Mumford-Shah nu {args.ms_nu} x {args.ms_iters}" if args.ms_nu > 0 else ""),
                    "n_particles": state.n, "grid": list(sysm.dims), "detect_every": 2,
                    "thermo_every_step": True},
         "roofline": {"bound": "alu", "kernel": "KForces (FP64 pair forces, energy, virial)",
