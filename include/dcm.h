@@ -110,6 +110,18 @@ typedef struct {
                                ms_iters primal-dual iterations of its convex relaxation from the
                                threshold labels; components are removed afterwards as before. */
     int32_t ms_iters;       /* iterations of that solver, 1..100000 [100]; ignored if ms_nu = 0 */
+    int32_t neighbor_list;  /* 1: forces from Verlet neighbour lists (Alg. 3.3) instead of the
+                               direct cell traversal [0]. Each list holds the slots within
+                               r_c[i] + skin at its build; it is rebuilt (with a re-sort) when
+                               twice the largest displacement since the build plus the largest
+                               growth of a cutoff exceeds the skin, which the host checks once
+                               per step (a stream synchronization). Particles keep their
+                               storage order between builds. Needs DCM_PAIR_I; not for the
+                               server. The same pairs as the traversal, summed in list order. */
+    double skin;            /* list skin r_s > 0 [0.3]; r_c^max + skin must pass the checks
+                               that r_c^max does (half the box, stencil boxes)                */
+    int32_t list_capacity;  /* slots per list; 0: 1.25 (4/3) pi (r_c^max + skin)^3 (a density
+                               of 1.25 sigma^-3) [0]. A longer list fails with DCM_E_INVALID. */
 } dcm_params;
 
 /* One thermodynamic record (all FP64 sums in a fixed reduction order).
@@ -242,12 +254,16 @@ dcm_status dcm_check(dcm_system *s, dcm_stream_t stream);
 /* Per-stage timing with HIP events on the system's stream (off by default). Stages:
  * 0 kick/drift/key, 1 sort and cell ranges, 2 smoothing, 3 two-means, 4 labels and
  * components, 5 distance (both solves with the tail correction), 6 interpolation and
- * cutoffs, 7 pair forces, 8 reductions, 9 tail correction.
+ * cutoffs, 7 pair forces, 8 reductions, 9 tail correction, 10 neighbour-list checks and
+ * builds.
  * on: 0 off, 1 every stage, 2 the pair-force stage only (two events per force launch).
  * DCM_E_INVALID for another level. dcm_stage_times synchronizes and returns total
  * milliseconds and launch counts per stage (arrays of DCM_NSTAGES) accumulated since
  * profiling was first switched on. */
-#define DCM_NSTAGES 10
+#define DCM_NSTAGES 11
+
+/* Number of neighbour-list builds since creation (0 without neighbor_list), host value. */
+dcm_status dcm_list_builds(dcm_system *s, int64_t *h_builds);
 dcm_status dcm_set_profiling(dcm_system *s, int32_t on);
 dcm_status dcm_stage_times(dcm_system *s, double *h_ms, int64_t *h_counts);
 

@@ -97,17 +97,26 @@ dcm_status validate(const dcm_params *p, int64_t n, Grid &g)
     if (g.G >= ((int64_t)1 << 31)) return fail(DCM_E_INVALID, "grid of %lld boxes is too large", (long long)g.G);
     if (!(p->rc_min > 0.0) || !(p->rc_min <= p->rc_max))
         return fail(DCM_E_INVALID, "need 0 < rc_min <= rc_max (got %g, %g)", p->rc_min, p->rc_max);
+    if (p->neighbor_list != 0 && p->neighbor_list != 1) return fail(DCM_E_INVALID, "neighbor_list must be 0 or 1");
+    if (p->neighbor_list && (!(p->skin > 0.0) || !std::isfinite(p->skin)))
+        return fail(DCM_E_INVALID, "skin must be positive and finite (got %g)", p->skin);
+    if (p->neighbor_list && p->pair_rule != DCM_PAIR_I)
+        return fail(DCM_E_INVALID, "neighbour lists need pair_rule DCM_PAIR_I");
+    if (p->neighbor_list && p->list_capacity < 0) return fail(DCM_E_INVALID, "list_capacity must be >= 0");
+    // the largest search radius: r_c^max, or r_c^max + skin when lists are built
+    const double reach = p->rc_max + (p->neighbor_list ? p->skin : 0.0);
     for (int k = 0; k < 3; ++k) {
-        if (!(p->rc_max < 0.5 * p->box[k]))
-            return fail(DCM_E_INVALID, "rc_max = %g must be below half the box edge %g", p->rc_max, p->box[k]);
-        int need = 2 * (int)std::ceil(p->rc_max / g.h[k]) + 2;
+        if (!(reach < 0.5 * p->box[k]))
+            return fail(DCM_E_INVALID, "search radius %g (rc_max, plus the skin with lists) must be below half the box edge %g",
+                        reach, p->box[k]);
+        int need = 2 * (int)std::ceil(reach / g.h[k]) + 2;
         if (g.n[k] < need)
             return fail(DCM_E_INVALID, "axis %d has %d boxes; the cutoff stencil needs %d", k, g.n[k], need);
     }
     // force rows of two boxes in y and in z where the axis has an even box count and room for
     // the stencil in units of two boxes (a lane's rows then never meet the same storage row twice)
-    g.sy = (g.n[1] % 2 == 0 && g.n[1] >= 2 * (int)std::ceil(p->rc_max / g.h[1]) + 6) ? 1 : 0;
-    g.sz = (g.n[2] % 2 == 0 && g.n[2] >= 2 * (int)std::ceil(p->rc_max / g.h[2]) + 6) ? 1 : 0;
+    g.sy = (g.n[1] % 2 == 0 && g.n[1] >= 2 * (int)std::ceil(reach / g.h[1]) + 6) ? 1 : 0;
+    g.sz = (g.n[2] % 2 == 0 && g.n[2] >= 2 * (int)std::ceil(reach / g.h[2]) + 6) ? 1 : 0;
     if (p->cutoff_shape != DCM_CUTOFF_EXP && p->cutoff_shape != DCM_CUTOFF_LINEAR)
         return fail(DCM_E_INVALID, "unknown cutoff_shape");
     if (p->cutoff_shape == DCM_CUTOFF_EXP && p->alpha == 0.0 && p->rc_min != p->rc_max)
@@ -195,6 +204,21 @@ size_t layout(dcm_system *s, void *ws)
         s->gw.ms.p = b.take<double>(3 * G);
         s->gw.ms.r = b.take<double>(G);
     }
+    s->list = s->nlist = nullptr;
+    s->pos_build = nullptr;
+    s->box_count = nullptr;
+    s->check = nullptr;
+    s->list_cap = 0;
+    if (s->p.neighbor_list) {
+        const double R = s->p.rc_max + s->p.skin;
+        s->list_cap = s->p.list_capacity > 0 ? (uint32_t)s->p.list_capacity
+                                             : (uint32_t)std::ceil(1.25 * 4.0 / 3.0 * M_PI * R * R * R);
+        s->list = b.take<uint32_t>((int64_t)s->list_cap * n);
+        s->nlist = b.take<uint32_t>(n);
+        s->pos_build = b.take<double4>(n);
+        s->box_count = b.take<uint32_t>(G);
+        s->check = b.take<unsigned long long>(2);
+    }
     s->nfb = force_blocks(n);
     s->nkb = stream_blocks(n);
     s->fparts = b.take<Partial>(s->nfb);
@@ -270,7 +294,13 @@ void detect(dcm_system *s, hipStream_t st, bool with_cutoffs = true)
     const Grid &g = s->grid;
     GridWork w = s->gw;
     stage_begin(s, 2, st);
-    launch_smooth(g, s->p.smooth_passes, w.cell_start, nullptr, w.g, w.gtmp, st);
+    if (s->p.neighbor_list) {
+        // particles keep their storage order between list builds: count the current positions
+        launch_count_boxes(g, s->set[s->cur].pos, s->n, s->box_count, st);
+        launch_smooth(g, s->p.smooth_passes, nullptr, s->box_count, w.g, w.gtmp, st);
+    } else {
+        launch_smooth(g, s->p.smooth_passes, w.cell_start, nullptr, w.g, w.gtmp, st);
+    }
     stage_end(s, st);
     stage_begin(s, 3, st);
     launch_fill_u32((uint32_t *)w.stats, 0u, 16, st);
@@ -317,6 +347,10 @@ void forces(dcm_system *s, hipStream_t st, double *e_out, double *w_out, uint32_
     a.pairs_out = pairs_out;
     a.partials = s->fparts;
     a.flags = s->gw.flags;
+    a.list_mode = s->p.neighbor_list;
+    a.list = s->list;
+    a.nlist = s->nlist;
+    a.list_cap = s->list_cap;
     stage_begin(s, 7, st);
     launch_forces(a, st);
     stage_end(s, st);
@@ -343,6 +377,57 @@ void forces(dcm_system *s, hipStream_t st, double *e_out, double *w_out, uint32_
         launch_tail(t, st);
         stage_end(s, st);
     }
+}
+
+// Neighbour lists (Alg. 3.3 with a skin r_s). A list holds every slot within r_c[i] + r_s of
+// slot i at its build. A pair within r_c[i] now was within r_c[i] + 2 D at the build (D = the
+// largest displacement since), so every list still holds all its pairs while
+// 2 D + max_i (r_c[i] - r_c[i] at the build) <= r_s. The host reads the two maxima once per
+// step; a rebuild re-sorts the particles by box (the traversal reads box ranges) and records
+// the positions and cutoffs it was built from.
+dcm_status list_update(dcm_system *s, hipStream_t st, bool force_rebuild)
+{
+    stage_begin(s, 10, st);
+    bool rebuild = force_rebuild || !s->list_valid;
+    if (!rebuild) {
+        launch_list_check(s->grid, s->set[s->cur].pos, s->pos_build, s->n, s->check, st);
+        unsigned long long h[2] = {0, 0};
+        (void)hipMemcpyAsync(h, s->check, sizeof h, hipMemcpyDeviceToHost, st);
+        if (hipStreamSynchronize(st) != hipSuccess) { stage_end(s, st); return hip_status("neighbour-list check"); }
+        double d2, grow;
+        std::memcpy(&d2, &h[0], sizeof d2);
+        std::memcpy(&grow, &h[1], sizeof grow);
+        rebuild = !(2.0 * std::sqrt(d2) + grow <= s->p.skin);
+    }
+    if (rebuild) {
+        launch_wrap_key(s->grid, s->set[s->cur], s->n, s->key, s->val, st);
+        rebin_sorted(s, st);
+        ForceArgs a;
+        a.grid = s->grid;
+        a.pos = s->set[s->cur].pos;
+        a.cell_start = s->gw.cell_start;
+        a.id = s->set[s->cur].id;
+        a.n = s->n;
+        a.rc_max = s->p.rc_max;
+        a.flags = s->gw.flags;
+        a.list = s->list;
+        a.nlist = s->nlist;
+        a.list_cap = s->list_cap;
+        launch_build_list(a, s->p.skin, st);
+        launch_copy_bytes(s->pos_build, s->set[s->cur].pos, sizeof(double4) * (size_t)s->n, st);
+        s->list_valid = true;
+        s->list_builds += 1;
+        uint32_t flags = 0;
+        (void)hipMemcpyAsync(&flags, s->gw.flags, sizeof flags, hipMemcpyDeviceToHost, st);
+        if (hipStreamSynchronize(st) != hipSuccess) { stage_end(s, st); return hip_status("neighbour-list build"); }
+        if (flags & kFlagListOverflow) {
+            s->list_valid = false;
+            stage_end(s, st);
+            return fail(DCM_E_INVALID, "a neighbour list exceeds list_capacity = %u slots", s->list_cap);
+        }
+    }
+    stage_end(s, st);
+    return DCM_OK;
 }
 
 dcm_status create_impl(const dcm_params *p, int64_t n, void *d_ws, size_t ws_bytes, const double *d_x,
@@ -382,6 +467,12 @@ dcm_status create_impl(const dcm_params *p, int64_t n, void *d_ws, size_t ws_byt
     bool redetect = !from_state || (p->detect_every > 0 && step % p->detect_every == 0);
     if (redetect) detect(s, st);
     else if (p->tail) detect(s, st, false);
+    s->list_valid = false;
+    s->list_builds = 0;
+    if (p->neighbor_list) {
+        dcm_status lr = list_update(s, st, true);
+        if (lr != DCM_OK) { delete s; return lr; }
+    }
     forces(s, st, nullptr, nullptr, nullptr);
     uint32_t flags = 0;
     (void)hipMemcpyAsync(&flags, s->gw.flags, sizeof flags, hipMemcpyDeviceToHost, st);
@@ -408,7 +499,7 @@ dcm_status create_impl(const dcm_params *p, int64_t n, void *d_ws, size_t ws_byt
 // The opening half uses the kinetic energy of the velocities in memory (a pass of its own on the
 // first step of a call, else the one fused into the previous step's closing scaling), so a run
 // split over several calls, or resumed from a checkpoint, takes the same bits as one call.
-void step_nose_hoover(dcm_system *s, int32_t nsteps, hipStream_t st, dcm_thermo *d_th)
+dcm_status step_nose_hoover(dcm_system *s, int32_t nsteps, hipStream_t st, dcm_thermo *d_th)
 {
     for (int32_t q = 1; q <= nsteps; ++q) {
         s->k += 1;
@@ -421,10 +512,16 @@ void step_nose_hoover(dcm_system *s, int32_t nsteps, hipStream_t st, dcm_thermo 
         launch_kick_drift_key(s->grid, s->set[s->cur], s->fx, s->fy, s->fz, s->n, s->hdt, s->p.dt, 0,
                               s->nh + 2, s->key, s->val, s->kparts, st);
         stage_end(s, st);
-        stage_begin(s, 1, st);
-        rebin_sorted(s, st);
-        stage_end(s, st);
+        if (!s->p.neighbor_list) {
+            stage_begin(s, 1, st);
+            rebin_sorted(s, st);
+            stage_end(s, st);
+        }
         if (s->p.detect_every > 0 && s->k % s->p.detect_every == 0) detect(s, st);
+        if (s->p.neighbor_list) {
+            dcm_status lr = list_update(s, st, false);
+            if (lr != DCM_OK) return lr;
+        }
         forces(s, st, nullptr, nullptr, nullptr);
         stage_begin(s, 0, st);
         launch_kick(s->set[s->cur], s->fx, s->fy, s->fz, s->n, s->hdt, s->kparts, st);
@@ -437,6 +534,7 @@ void step_nose_hoover(dcm_system *s, int32_t nsteps, hipStream_t st, dcm_thermo 
         launch_scale(s->set[s->cur], s->n, s->nh + 2, s->kparts, st);
         stage_end(s, st);
     }
+    return DCM_OK;
 }
 
 }  // namespace
@@ -489,6 +587,10 @@ dcm_status dcm_set_cutoffs(dcm_system *s, dcm_stream_t stream, const double *d_r
     if (!s || !d_rc) return fail(DCM_E_INVALID, "NULL argument");
     hipStream_t st = (hipStream_t)stream;
     launch_scatter_rc(s->set[s->cur], d_rc, s->n, s->p.rc_min, s->p.rc_max, s->gw.flags, st);
+    if (s->p.neighbor_list) {
+        dcm_status lr = list_update(s, st, false);
+        if (lr != DCM_OK) return lr;
+    }
     forces(s, st, nullptr, nullptr, nullptr);
     return hip_status("dcm_set_cutoffs");
 }
@@ -500,9 +602,17 @@ dcm_status dcm_detect_interface(dcm_system *s, dcm_stream_t stream, const dcm_de
         return fail(DCM_E_INVALID, "dist_v needs tail = 1 or vapor_cutoff = 1");
     hipStream_t st = (hipStream_t)stream;
     detect(s, st);
+    if (s->p.neighbor_list) {
+        // the new cutoffs may have outgrown the lists
+        dcm_status lr = list_update(s, st, false);
+        if (lr != DCM_OK) return lr;
+    }
     if (o) {
         const int64_t G = s->grid.G;
-        if (o->count) launch_count_from_ranges(s->grid, s->gw.cell_start, o->count, st);
+        if (o->count) {
+            if (s->p.neighbor_list) launch_copy_bytes(o->count, s->box_count, sizeof(uint32_t) * (size_t)G, st);
+            else launch_count_from_ranges(s->grid, s->gw.cell_start, o->count, st);
+        }
         if (o->smooth) launch_copy_bytes(o->smooth, s->gw.g, sizeof(uint32_t) * G, st);
         if (o->raw) launch_copy_bytes(o->raw, s->gw.raw, (size_t)G, st);
         if (o->label) launch_copy_bytes(o->label, s->gw.label, (size_t)G, st);
@@ -549,7 +659,8 @@ dcm_status dcm_step(dcm_system *s, int32_t nsteps, dcm_stream_t stream, dcm_ther
     if (nsteps < 0) return fail(DCM_E_INVALID, "nsteps must be >= 0");
     hipStream_t st = (hipStream_t)stream;
     if (s->p.thermostat == DCM_NOSE_HOOVER) {
-        step_nose_hoover(s, nsteps, st, d_th);
+        dcm_status rs = step_nose_hoover(s, nsteps, st, d_th);
+        if (rs != DCM_OK) return rs;
         return hip_status("dcm_step");
     }
     for (int32_t q = 1; q <= nsteps; ++q) {
@@ -564,10 +675,16 @@ dcm_status dcm_step(dcm_system *s, int32_t nsteps, dcm_stream_t stream, dcm_ther
                                  s->rparts, s->nh, kNhNone, s->nhc, st);
             stage_end(s, st);
         }
-        stage_begin(s, 1, st);
-        rebin_sorted(s, st);
-        stage_end(s, st);
+        if (!s->p.neighbor_list) {
+            stage_begin(s, 1, st);
+            rebin_sorted(s, st);
+            stage_end(s, st);
+        }
         if (s->p.detect_every > 0 && s->k % s->p.detect_every == 0) detect(s, st);
+        if (s->p.neighbor_list) {
+            dcm_status lr = list_update(s, st, false);
+            if (lr != DCM_OK) return lr;
+        }
         forces(s, st, nullptr, nullptr, nullptr);
     }
     if (nsteps > 0) {
@@ -633,6 +750,7 @@ dcm_status dcm_check(dcm_system *s, dcm_stream_t stream)
     if (flags & kFlagNotConverged) return fail(DCM_E_NOT_CONVERGED, "distance sweeps hit their limit");
     if (flags & kFlagHistOverflow) return fail(DCM_E_INVALID, "smoothed counts exceed the histogram range");
     if (flags & kFlagBadCutoff) return fail(DCM_E_INVALID, "a cutoff lies outside [rc_min, rc_max]");
+    if (flags & kFlagListOverflow) return fail(DCM_E_INVALID, "a neighbour list exceeded list_capacity");
     return DCM_OK;
 }
 
@@ -660,6 +778,13 @@ dcm_status dcm_stage_times(dcm_system *s, double *h_ms, int64_t *h_counts)
         if (h_ms) h_ms[q] = s->ms[q];
         if (h_counts) h_counts[q] = s->counts[q];
     }
+    return DCM_OK;
+}
+
+dcm_status dcm_list_builds(dcm_system *s, int64_t *h_builds)
+{
+    if (!s || !h_builds) return fail(DCM_E_INVALID, "NULL argument");
+    *h_builds = s->list_builds;
     return DCM_OK;
 }
 

@@ -77,7 +77,7 @@ __device__ __forceinline__ float rcp_f32(float a)
 template <int PAIR, bool SHIFT, bool IMAGE>
 __device__ __forceinline__ void interact(const ForceArgs &a, const double4 pj, bool valid,
                                          double xi, double yi, double zi, double rci, double rc2,
-                                         double sx, double sy, double sz, Acc &c)
+                                         double sx, double sy, double sz, Acc &c, uint32_t)
 {
     // x_j moved to the periodic image of its interval (adding 0 is exact, so the no-image
     // variant gives the same bits without the three additions)
@@ -118,7 +118,7 @@ __device__ __forceinline__ void interact(const ForceArgs &a, const double4 pj, b
 template <int PAIR, bool SHIFT, bool IMAGE>
 __device__ __forceinline__ void interact(const ForceArgs &a, const double4 pj, bool valid,
                                          double xi, double yi, double zi, double rci, double rc2,
-                                         double sx, double sy, double sz, Acc32 &c)
+                                         double sx, double sy, double sz, Acc32 &c, uint32_t)
 {
     // displacement, r^2 and the cutoff test stay FP64: the pair set is the FP64 one
     double dx = IMAGE ? xi - (pj.x + sx) : xi - pj.x;
@@ -153,6 +153,29 @@ __device__ __forceinline__ void interact(const ForceArgs &a, const double4 pj, b
             const float s6 = s2 * s2 * s2;
             c.eshift += fmaf(s6, s6, -s6);
         }
+    }
+}
+
+// List building: appends the slots within the list radius (rc2 holds its square) to
+// list[count * n + i]; counts past the capacity are kept to flag the overflow.
+struct AccList {
+    uint32_t *list;
+    int64_t n, i;
+    uint32_t cap, count;
+};
+
+template <int PAIR, bool SHIFT, bool IMAGE>
+__device__ __forceinline__ void interact(const ForceArgs &, const double4 pj, bool valid,
+                                         double xi, double yi, double zi, double, double rl2,
+                                         double sx, double sy, double sz, AccList &c, uint32_t j)
+{
+    double dx = IMAGE ? xi - (pj.x + sx) : xi - pj.x;
+    double dy = IMAGE ? yi - (pj.y + sy) : yi - pj.y;
+    double dz = IMAGE ? zi - (pj.z + sz) : zi - pj.z;
+    double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    if (valid && r2 < rl2) {
+        if (c.count < c.cap) c.list[(int64_t)c.count * c.n + c.i] = j;
+        c.count += 1;
     }
 }
 
@@ -198,7 +221,7 @@ __device__ __forceinline__ void scan(const ForceArgs &a, __amdgpu_buffer_rsrc_t 
 #pragma unroll
         for (int u = 0; u < U; ++u)
             interact<PAIR, SHIFT, IMAGE>(a, p[u], t + u < len && jb + t + u != (uint32_t)q.i, q.x, q.y, q.z, q.rc,
-                                         q.rc2, sx, sy, sz, c);
+                                         q.rc2, sx, sy, sz, c, jb + t + u);
     }
 }
 
@@ -303,8 +326,41 @@ __device__ __forceinline__ void traverse(const ForceArgs &a, bool live, const Pa
     }
 }
 
+// The candidates of lane i's list, U at a time, until the wave's longest list is done. The
+// periodic image of x_j is the one nearest x_i (shift +L where x_i - x_j > L / 2, -L below
+// -L / 2), so dx = x_i - (x_j + shift) is the number the cell traversal and the minimum-image
+// convention give for every pair within r_c < L / 2.
+template <bool SHIFT, int U, typename A>
+__device__ __forceinline__ void list_scan(const ForceArgs &a, bool live, const Particle &q, A &c)
+{
+    const Grid &g = a.grid;
+    const uint32_t cnt = live ? a.nlist[q.i] : 0u;
+    const int kmax = wave_max((int)cnt);
+    const __amdgpu_buffer_rsrc_t pb =
+        __builtin_amdgcn_make_buffer_rsrc((void *)a.pos, 0, (int)((uint32_t)a.n * 32u), 0x00020000);
+    const double hx = 0.5 * g.L[0], hy = 0.5 * g.L[1], hz = 0.5 * g.L[2];
+    for (int k = 0; k < kmax; k += U) {
+        uint32_t jj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            jj[u] = (uint32_t)(k + u) < cnt ? a.list[(int64_t)(k + u) * a.n + q.i] : (uint32_t)q.i;
+        double4 p[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) p[u] = load_pos<DCM_PAIR_I>(pb, jj[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double ex = q.x - p[u].x, ey = q.y - p[u].y, ez = q.z - p[u].z;
+            const double sx = ex > hx ? g.L[0] : (ex < -hx ? -g.L[0] : 0.0);
+            const double sy = ey > hy ? g.L[1] : (ey < -hy ? -g.L[1] : 0.0);
+            const double sz = ez > hz ? g.L[2] : (ez < -hz ? -g.L[2] : 0.0);
+            interact<DCM_PAIR_I, SHIFT, true>(a, p[u], (uint32_t)(k + u) < cnt, q.x, q.y, q.z, q.rc, q.rc2, sx, sy,
+                                              sz, c, jj[u]);
+        }
+    }
+}
+
 // Compiled for 4 waves per SIMD (128 VGPRs per lane).
-template <int PAIR, bool SHIFT, int U, int PREC>
+template <int PAIR, bool SHIFT, int U, int PREC, bool LIST = false>
 struct KForces {
     static constexpr int kThreads = kForceBlock, kWaves = 4;
     struct Args {
@@ -314,8 +370,8 @@ struct KForces {
     static __device__ void run(const Args &args_, uint32_t blk, uint32_t);
 };
 
-template <int PAIR, bool SHIFT, int U, int PREC>
-__device__ void KForces<PAIR, SHIFT, U, PREC>::run(const Args &args_, uint32_t blk, uint32_t)
+template <int PAIR, bool SHIFT, int U, int PREC, bool LIST>
+__device__ void KForces<PAIR, SHIFT, U, PREC, LIST>::run(const Args &args_, uint32_t blk, uint32_t)
 {
     const ForceArgs &a = args_.a;
     const double rc_max = args_.rc_max;
@@ -339,10 +395,12 @@ __device__ void KForces<PAIR, SHIFT, U, PREC>::run(const Args &args_, uint32_t b
     // every lane of the wave takes part in the (wave-uniform) traversal
     Acc c = {};
     if (PREC == DCM_FP64) {
-        traverse<PAIR, SHIFT, U, Acc>(a, live, q, rc_max, c);
+        if (LIST) list_scan<SHIFT, U, Acc>(a, live, q, c);
+        else traverse<PAIR, SHIFT, U, Acc>(a, live, q, rc_max, c);
     } else {
         Acc32 c32 = {};
-        traverse<PAIR, SHIFT, U, Acc32>(a, live, q, rc_max, c32);
+        if (LIST) list_scan<SHIFT, U, Acc32>(a, live, q, c32);
+        else traverse<PAIR, SHIFT, U, Acc32>(a, live, q, rc_max, c32);
         // FP32 sums and their compensation terms, combined in FP64
         c.fx = (double)c32.fx + (double)c32.cfx;
         c.fy = (double)c32.fy + (double)c32.cfy;
@@ -413,6 +471,39 @@ __device__ void KForces<PAIR, SHIFT, U, PREC>::run(const Args &args_, uint32_t b
     }
 }
 
+// Neighbour lists: the force kernel's traversal with the search radius r_c[i] + skin, each
+// slot within it recorded (Alg. 3.3's list of the pairs within r_c + r_s).
+struct KBuildList {
+    static constexpr int kThreads = kForceBlock, kWaves = 4;
+    struct Args {
+        ForceArgs a;
+        double skin;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t);
+};
+
+__device__ void KBuildList::run(const Args &args_, uint32_t blk, uint32_t)
+{
+    const ForceArgs &a = args_.a;
+    const int64_t i = (int64_t)blk * kForceBlock + threadIdx.x;
+    const bool have = i < a.n;
+    Particle q;
+    q.i = have ? i : 0;
+    const double4 pi = a.pos[q.i];
+    q.x = pi.x;
+    q.y = pi.y;
+    q.z = pi.z;
+    q.rc = pi.w + args_.skin;
+    q.rc2 = q.rc * q.rc;
+    const bool sane = isfinite(q.x) && isfinite(q.y) && isfinite(q.z) && pi.w > 0.0 && pi.w <= a.rc_max;
+    AccList c = {a.list, a.n, i, a.list_cap, 0u};
+    traverse<DCM_PAIR_I, false, 4, AccList>(a, have && sane, q, a.rc_max, c);
+    if (have) {
+        a.nlist[i] = c.count < a.list_cap ? c.count : a.list_cap;
+        if (c.count > a.list_cap) atomicOr(a.flags, kFlagListOverflow);
+    }
+}
+
 }  // namespace
 
 int force_blocks(int64_t n) { return (int)((n + kForceBlock - 1) / kForceBlock); }
@@ -422,6 +513,11 @@ static void launch_prec(const ForceArgs &a, int nb, hipStream_t st)
 {
     constexpr int U = 4;
     const uint32_t blocks = (uint32_t)nb;
+    if (a.list_mode) {
+        if (a.energy_shift) emit<KForces<DCM_PAIR_I, true, U, PREC, true>>({a, a.rc_max}, blocks, st);
+        else emit<KForces<DCM_PAIR_I, false, U, PREC, true>>({a, a.rc_max}, blocks, st);
+        return;
+    }
     if (a.pair_rule == DCM_PAIR_MAX) {
         if (a.energy_shift) emit<KForces<DCM_PAIR_MAX, true, U, PREC>>({a, a.rc_max}, blocks, st);
         else emit<KForces<DCM_PAIR_MAX, false, U, PREC>>({a, a.rc_max}, blocks, st);
@@ -429,6 +525,11 @@ static void launch_prec(const ForceArgs &a, int nb, hipStream_t st)
         if (a.energy_shift) emit<KForces<DCM_PAIR_I, true, U, PREC>>({a, a.rc_max}, blocks, st);
         else emit<KForces<DCM_PAIR_I, false, U, PREC>>({a, a.rc_max}, blocks, st);
     }
+}
+
+void launch_build_list(const ForceArgs &a, double skin, hipStream_t st)
+{
+    emit<KBuildList>({a, skin}, (uint32_t)force_blocks(a.n), st);
 }
 
 void launch_forces(const ForceArgs &a, hipStream_t st)

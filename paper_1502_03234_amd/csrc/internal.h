@@ -23,6 +23,7 @@ constexpr uint32_t kFlagNonFinite = 1u;
 constexpr uint32_t kFlagHistOverflow = 2u;
 constexpr uint32_t kFlagNotConverged = 4u;
 constexpr uint32_t kFlagBadCutoff = 8u;
+constexpr uint32_t kFlagListOverflow = 16u;
 
 // Grid geometry shared by every kernel that maps positions to boxes (Eq. 10).
 struct Grid {
@@ -107,6 +108,12 @@ struct GridWork {
 size_t sort_scratch_bytes(int64_t n, int64_t G);
 void launch_wrap_key(const Grid &g, PSet s, int64_t n, uint32_t *key, uint32_t *val, hipStream_t st);
 void launch_init_ids(PSet s, int64_t n, hipStream_t st);
+// Box counts of the current positions into count (linear box index); clears count first.
+void launch_count_boxes(const Grid &g, const double4 *pos, int64_t n, uint32_t *count, hipStream_t st);
+// out[0] = max squared displacement since pos_build (minimum image), out[1] = max cutoff growth,
+// as double bit patterns.
+void launch_list_check(const Grid &g, const double4 *pos, const double4 *pos_build, int64_t n,
+                       unsigned long long *out, hipStream_t st);
 // Returns true when the sorted keys and values end in key_alt / val_alt.
 bool launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key_alt, uint32_t *val_alt,
                        void *scratch, int64_t n, int bits, hipStream_t st);
@@ -160,9 +167,18 @@ struct ForceArgs {
     uint32_t *pairs_out;    // per-atom pair count in caller order (optional)
     Partial *partials;      // [force_blocks(n)]
     uint32_t *flags;
+    // neighbour lists (Verlet lists with a skin): list[k * n + i] is the k-th candidate slot
+    // of slot i, nlist[i] their number; list_mode 1 evaluates forces from them
+    int list_mode;
+    uint32_t *list;
+    uint32_t *nlist;
+    uint32_t list_cap;
 };
 int force_blocks(int64_t n);
 void launch_forces(const ForceArgs &a, hipStream_t st);
+// Lists of every slot within r_c[i] + skin, built by the force kernel's traversal (cell_start
+// must describe the current positions); sets kFlagListOverflow if a list exceeds list_cap.
+void launch_build_list(const ForceArgs &a, double skin, hipStream_t st);
 
 // tail.hip
 struct TailArgs {
@@ -247,4 +263,11 @@ struct dcm_system {
     std::vector<dcm::Event> events, spare;
     double ms[DCM_NSTAGES];
     int64_t counts[DCM_NSTAGES];
+    // neighbour-list mode
+    uint32_t *list, *nlist, list_cap;
+    double4 *pos_build;          // positions and cutoffs at the last list build (storage order)
+    uint32_t *box_count;         // box counts of the current positions
+    unsigned long long *check;   // [2] list check results
+    bool list_valid;
+    int64_t list_builds;
 };

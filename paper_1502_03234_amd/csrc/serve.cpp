@@ -485,6 +485,9 @@ dcm_status dcm_submit(dcm_server *sv, const dcm_params *p, int64_t n, const doub
                       int32_t nsteps, uint64_t *ticket)
 {
     if (!sv || !p || !h_x || !h_v || !ticket || nsteps < 0) return DCM_E_INVALID;
+    // neighbour lists decide their rebuilds on the host between launches, which a recorded
+    // batch cannot do
+    if (p->neighbor_list) return DCM_E_INVALID;
     size_t ws = 0;
     dcm_status s = dcm_workspace_bytes(p, n, &ws);
     if (s != DCM_OK) return s;

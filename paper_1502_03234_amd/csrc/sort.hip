@@ -60,6 +60,57 @@ __device__ void KWrapKey::run(const Args &args, uint32_t blk, uint32_t)
     args.val[i] = (uint32_t)i;
 }
 
+// Box counts of Eq. 9 from the current positions (neighbour-list mode, where particles keep
+// their storage order between list builds): count[(c N_y + b) N_x + a] += 1, integer atomics,
+// so the counts do not depend on the order of the additions.
+struct KCountBoxes {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args { Grid g; const double4 *pos; int64_t n; uint32_t *count; };
+    static __device__ void run(const Args &args, uint32_t blk, uint32_t)
+    {
+        const Grid &g = args.g;
+        int64_t i = (int64_t)blk * kThreads + threadIdx.x;
+        if (i >= args.n) return;
+        const double4 p = args.pos[i];
+        const int32_t a = box_of(p.x, g.h[0], g.n[0]);
+        const int32_t b = box_of(p.y, g.h[1], g.n[1]);
+        const int32_t c = box_of(p.z, g.h[2], g.n[2]);
+        atomicAdd(args.count + ((int64_t)c * g.n[1] + b) * g.n[0] + a, 1u);
+    }
+};
+
+// Validity of the neighbour lists: the largest squared displacement since the build (minimum
+// image) and the largest growth of a cutoff, as the bit patterns of non-negative doubles
+// (ordered like the values) in out[0] and out[1].
+struct KListCheck {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args { Grid g; const double4 *pos; const double4 *pos_build; int64_t n; unsigned long long *out; };
+    static __device__ void run(const Args &args, uint32_t blk, uint32_t)
+    {
+        const Grid &g = args.g;
+        int64_t i = (int64_t)blk * kThreads + threadIdx.x;
+        double d2 = 0.0, grow = 0.0;
+        if (i < args.n) {
+            const double4 p = args.pos[i], b = args.pos_build[i];
+            double dx = p.x - b.x, dy = p.y - b.y, dz = p.z - b.z;
+            dx -= g.L[0] * rint(dx / g.L[0]);
+            dy -= g.L[1] * rint(dy / g.L[1]);
+            dz -= g.L[2] * rint(dz / g.L[2]);
+            d2 = dx * dx + dy * dy + dz * dz;
+            grow = fmax(p.w - b.w, 0.0);
+            if (!(d2 >= 0.0) || !(p.w == p.w)) d2 = INFINITY;   // a non-finite state rebuilds
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            d2 = fmax(d2, __shfl_xor(d2, off, 64));
+            grow = fmax(grow, __shfl_xor(grow, off, 64));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicMax(args.out, (unsigned long long)__double_as_longlong(d2));
+            atomicMax(args.out + 1, (unsigned long long)__double_as_longlong(grow));
+        }
+    }
+};
+
 struct KInitIds {
     static constexpr int kThreads = kBlock, kWaves = 0;
     struct Args { PSet s; int64_t n; };
@@ -383,6 +434,19 @@ size_t sort_scratch_bytes(int64_t n, int64_t G)
 void launch_wrap_key(const Grid &g, PSet s, int64_t n, uint32_t *key, uint32_t *val, hipStream_t st)
 {
     emit<KWrapKey>({g, s, n, key, val}, grid1(n), st);
+}
+
+void launch_count_boxes(const Grid &g, const double4 *pos, int64_t n, uint32_t *count, hipStream_t st)
+{
+    launch_fill_u32(count, 0u, g.G, st);
+    emit<KCountBoxes>({g, pos, n, count}, grid1(n), st);
+}
+
+void launch_list_check(const Grid &g, const double4 *pos, const double4 *pos_build, int64_t n,
+                       unsigned long long *out, hipStream_t st)
+{
+    launch_fill_u32((uint32_t *)out, 0u, 4, st);
+    emit<KListCheck>({g, pos, pos_build, n, out}, grid1(n), st);
 }
 
 void launch_init_ids(PSet s, int64_t n, hipStream_t st)

@@ -21,9 +21,9 @@ DCM_FP64, DCM_FP32C = 0, 1
 DCM_PAIR_I, DCM_PAIR_MAX = 0, 1
 DCM_NVE, DCM_NOSE_HOOVER = 0, 1
 DCM_CUTOFF_EXP, DCM_CUTOFF_LINEAR = 0, 1
-DCM_NSTAGES = 10
+DCM_NSTAGES = 11
 STAGES = ["kick_drift_key", "sort", "smooth", "two_means", "segment", "distance", "cutoffs",
-          "forces", "reduce", "tail"]
+          "forces", "reduce", "tail", "list"]
 
 
 class DcmError(RuntimeError):
@@ -40,7 +40,8 @@ class Params(C.Structure):
                 ("precision", C.c_int32), ("pair_rule", C.c_int32), ("energy_shift", C.c_int32),
                 ("dt", C.c_double), ("temperature", C.c_double), ("tdamp", C.c_double),
                 ("thermostat", C.c_int32), ("cutoff_shape", C.c_int32), ("tail", C.c_int32),
-                ("vapor_cutoff", C.c_int32), ("ms_nu", C.c_double), ("ms_iters", C.c_int32)]
+                ("vapor_cutoff", C.c_int32), ("ms_nu", C.c_double), ("ms_iters", C.c_int32),
+                ("neighbor_list", C.c_int32), ("skin", C.c_double), ("list_capacity", C.c_int32)]
 
 
 class Thermo(C.Structure):
@@ -89,6 +90,7 @@ _SIGS = {
     "dcm_set_profiling": ([_vp, _i32], _i32),
     "dcm_stage_times": ([_vp, _vp, _vp], _i32),
     "dcm_destroy": ([_vp], _i32),
+    "dcm_list_builds": ([_vp, C.POINTER(_i64)], _i32),
     "dcm_grid_workspace_bytes": ([_vp, C.POINTER(_sz)], _i32),
     "dcm_grid_smooth": ([_vp, _i32, _vp, _vp, _vp, _sz, _vp], _i32),
     "dcm_grid_two_means": ([_vp, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
@@ -131,7 +133,7 @@ def params(box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_min=2.5, rc_max=6.0, alp
            smooth_passes=1, min_component=27, detect_every=2, precision=DCM_FP64,
            pair_rule=DCM_PAIR_I, energy_shift=0, dt=0.005, temperature=0.7, tdamp=0.5,
            thermostat=DCM_NVE, cutoff_shape=DCM_CUTOFF_EXP, tail=0, vapor_cutoff=0, ms_nu=0.0,
-           ms_iters=100) -> Params:
+           ms_iters=100, neighbor_list=0, skin=0.3, list_capacity=0) -> Params:
     p = Params()
     p.box[:] = [float(b) for b in box]
     p.epsilon, p.sigma, p.mass = epsilon, sigma, mass
@@ -143,6 +145,7 @@ def params(box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_min=2.5, rc_max=6.0, alp
     p.tail = tail
     p.vapor_cutoff = vapor_cutoff
     p.ms_nu, p.ms_iters = ms_nu, ms_iters
+    p.neighbor_list, p.skin, p.list_capacity = neighbor_list, skin, list_capacity
     return p
 
 
@@ -235,6 +238,12 @@ def dcm_stage_times(h: int):
     cnt = (C.c_int64 * DCM_NSTAGES)()
     _check(_lib.dcm_stage_times(h, ms, cnt))
     return {STAGES[q]: (ms[q], cnt[q]) for q in range(DCM_NSTAGES)}
+
+
+def dcm_list_builds(h: int) -> int:
+    b = C.c_int64(0)
+    _check(_lib.dcm_list_builds(h, C.byref(b)))
+    return b.value
 
 
 def dcm_destroy(h: int):

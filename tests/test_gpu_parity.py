@@ -63,9 +63,13 @@ def sum_close(got, terms, tol=1e-12):
     return abs(got - ref) <= tol * np.sum(np.abs(terms)) + 1e-300
 
 
+# parameters of the HIP path that do not change what is computed (the oracle has no counterpart)
+_PATH_ONLY = ("precision", "neighbor_list", "skin", "list_capacity")
+
+
 def make(state, **kw):
     p = dcm.params(state.box, **kw)
-    po = O.params(state.box, **{k: v for k, v in kw.items() if k != "precision"})
+    po = O.params(state.box, **{k: v for k, v in kw.items() if k not in _PATH_ONLY})
     return p, po
 
 
