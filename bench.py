@@ -676,6 +676,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tail", action="store_true",
                     help="with the runtime tail correction (Eq. 21-22): its cost on the same workload")
+    ap.add_argument("--skin", type=float, default=0.0,
+                    help="> 0: forces from Verlet neighbour lists with this skin (Alg. 3.3)")
+    ap.add_argument("--detect-every", type=int, default=2, help="re-detect the interface every k steps")
     ap.add_argument("--ms-nu", type=float, default=0.0,
                     help="segment by Eq. 13 (Mumford-Shah) with this nu instead of the threshold")
     ap.add_argument("--ms-iters", type=int, default=100, help="primal-dual iterations of --ms-nu")
@@ -764,7 +767,9 @@ def main():
     state = synth.named(WORKLOAD)
     prec = dcm.DCM_FP64 if args.precision == "fp64" else dcm.DCM_FP32C
     p = dcm.params(state.box, precision=prec, tail=1 if args.tail else 0,
-                   vapor_cutoff=1 if args.vapor_cutoffs else 0, ms_nu=args.ms_nu, ms_iters=args.ms_iters)
+                   vapor_cutoff=1 if args.vapor_cutoffs else 0, ms_nu=args.ms_nu, ms_iters=args.ms_iters,
+                   neighbor_list=1 if args.skin > 0 else 0, skin=args.skin if args.skin > 0 else 0.3,
+                   detect_every=args.detect_every)
     stream = torch.cuda.current_stream()
     sysm = dcm.System(p, state.x, state.v)
     if args.forces_only:
@@ -797,6 +802,7 @@ def main():
     dcm.dcm_step(sysm.h, nb, stream, thb)
     after = dcm.dcm_stage_times(sysm.h)
     dcm.dcm_set_profiling(sysm.h, 0)
+    list_builds = dcm.dcm_list_builds(sysm.h)
     rec = dcm.thermo_records(th[: args.steps * dcm.THERMO_DOUBLES])
     pairs = sum(r["pairs"] for r in rec) / len(rec)
     ms_step = elapsed / args.steps * 1e3
@@ -849,11 +855,14 @@ def main():
         "dtype": "f64" if prec == dcm.DCM_FP64 else "f32-compensated",
         "data": "synthetic",
         "config": {"workload": "LJ liquid/vapor slab, 2,048,000 particles, box 320x320x60, "
-                               "r_c 2.5..6 (exponential), detect every 2nd step, dt 0.005, NVE"
+                               "r_c 2.5..6 (exponential), "
+                               + ("detect every 2nd step" if args.detect_every == 2 else f"detect every {args.detect_every} steps")
+                               + ", dt 0.005, NVE"
                                + (", runtime tail correction" if args.tail else "")
                                + (", vapor cutoffs" if args.vapor_cutoffs else "")
-                               + (f", Mumford-Shah nu {args.ms_nu} x {args.ms_iters}" if args.ms_nu > 0 else ""),
-                   "n_particles": state.n, "grid": list(sysm.dims), "detect_every": 2,
+                               + (f", Mumford-Shah nu {args.ms_nu} x {args.ms_iters}" if args.ms_nu > 0 else "")
+                               + (f", neighbour lists skin {args.skin}" if args.skin > 0 else ""),
+                   "n_particles": state.n, "grid": list(sysm.dims), "detect_every": args.detect_every,
                    "thermo_every_step": True},
         "roofline": {"bound": "alu", "kernel": "KForces (FP64 pair forces, energy, virial)",
                      "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -866,6 +875,9 @@ def main():
         "energy_drift_per_atom": (e1 - e0) / state.n,
         "static_cutoff_6": static,
     }
+    if args.skin > 0:
+        out["neighbour_lists"] = {"skin": args.skin, "builds": list_builds,
+                                  "steps_run": args.warmup + args.steps + nb}
     print(json.dumps(out), flush=True)
 
 
