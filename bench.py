@@ -671,6 +671,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed runs of STEPS steps each; value and ms_per_step are the median run's")
     ap.add_argument("--precision", choices=["fp64", "fp32c"], default="fp64")
     ap.add_argument("--cpu-sample", type=int, default=60000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -771,29 +773,43 @@ def main():
                    neighbor_list=1 if args.skin > 0 else 0, skin=args.skin if args.skin > 0 else 0.3,
                    detect_every=args.detect_every)
     stream = torch.cuda.current_stream()
-    sysm = dcm.System(p, state.x, state.v)
     if args.forces_only:
+        sysm = dcm.System(p, state.x, state.v)
         for _ in range(args.forces_only):
             dcm.dcm_compute_forces(sysm.h, stream)
         torch.cuda.synchronize()
         log(f"{args.forces_only} force evaluations done")
         return
     th = torch.empty(max(args.steps, args.warmup, 1) * dcm.THERMO_DOUBLES, dtype=torch.float64, device=dev)
-    log(f"n={state.n} grid={sysm.dims} warmup={args.warmup}")
-    if args.warmup:
-        dcm.dcm_step(sysm.h, args.warmup, stream, th)
-    torch.cuda.synchronize()
-    sysm.check()
-    # the timed steps record HIP events around the force launches only (the roofline's kernel
-    # time); the per-stage breakdown comes from a separate profiled run afterwards
-    dcm.dcm_set_profiling(sysm.h, 2)
-    base = dcm.dcm_stage_times(sysm.h)                   # cumulative timers, zero here
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    dcm.dcm_step(sysm.h, args.steps, stream, th)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    stages = dcm.dcm_stage_times(sysm.h)
+    # `repeats` timed runs of exactly K steps, each from the same initial state after the same
+    # W warmup steps (the slab's pair count grows as it evolves, so every run must cover the
+    # same steps); value and ms/step are the median run's. The timed steps record HIP events
+    # around the force launches only (the roofline's kernel time); the per-stage breakdown comes
+    # from a separate profiled run afterwards.
+    runs = []
+    f_ms = 0.0
+    f_cnt = 0
+    sysm = None
+    for r in range(max(1, args.repeats)):
+        if sysm is not None:
+            sysm.close()
+        sysm = dcm.System(p, state.x, state.v)
+        if r == 0:
+            log(f"n={state.n} grid={sysm.dims} warmup={args.warmup} repeats={args.repeats}")
+        if args.warmup:
+            dcm.dcm_step(sysm.h, args.warmup, stream, th)
+        torch.cuda.synchronize()
+        sysm.check()
+        dcm.dcm_set_profiling(sysm.h, 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dcm.dcm_step(sysm.h, args.steps, stream, th)
+        torch.cuda.synchronize()
+        runs.append(time.perf_counter() - t0)
+        fst = dcm.dcm_stage_times(sysm.h)["forces"]
+        f_ms += fst[0]
+        f_cnt += fst[1]
+    elapsed = sorted(runs)[len(runs) // 2]
     sysm.check()
     nb = max(10, args.steps // 10)
     dcm.dcm_set_profiling(sysm.h, 1)
@@ -807,7 +823,6 @@ def main():
     pairs = sum(r["pairs"] for r in rec) / len(rec)
     ms_step = elapsed / args.steps * 1e3
     value = state.n * args.steps / elapsed
-    f_ms, f_cnt = stages["forces"][0] - base["forces"][0], stages["forces"][1] - base["forces"][1]
     f_avg_s = f_ms / f_cnt * 1e-3
     achieved = FLOPS_PER_PAIR * pairs / f_avg_s / 1e12
     breakdown = {k: round((v[0] - before[k][0]) / nb, 5) for k, v in after.items()}
@@ -874,6 +889,8 @@ def main():
         "breakdown_ms_per_step": breakdown,
         "energy_drift_per_atom": (e1 - e0) / state.n,
         "static_cutoff_6": static,
+        "timing": {"repeats": len(runs), "of_steps": args.steps, "statistic": "median",
+                   "ms_per_step_runs": [round(r / args.steps * 1e3, 4) for r in runs]},
     }
     if args.skin > 0:
         out["neighbour_lists"] = {"skin": args.skin, "builds": list_builds,
