@@ -97,3 +97,71 @@ def test_other_detection_schedules(slab16k, de, detections):
 def test_smoothing_and_removal_settings(slab16k, kw):
     p, po = make(slab16k, **kw)
     check_system(slab16k, p, po, f"slab16k {kw}").close()
+
+
+@pytest.mark.parametrize("kw", [dict(vapor_cutoff=1), dict(ms_nu=0.005, ms_iters=20),
+                                dict(neighbor_list=1, skin=0.3)])
+def test_options_without_an_interface(kw):
+    """The options on a density image with no interface: vapor cutoffs, the Mumford-Shah
+    segmentation (a constant image has nothing to segment) and neighbour lists all reduce to the
+    plain path's labels and cutoffs."""
+    st = synth.lattice(16, 16.0, seed=5)
+    p, po = make(st, **kw)
+    s = check_system(st, p, po, f"lattice 16^3 {kw}")
+    det = s.detect()
+    torch.cuda.synchronize()
+    assert not det["label"].cpu().numpy().any()
+    assert np.all(det["rc"].cpu().numpy() == p.rc_min)
+    s.close()
+
+
+def test_tail_without_an_interface():
+    """No interface: every particle is deep in the liquid, so the tail force is zero and the
+    tail energy is the uniform one, (8/3) pi rho [(1/3) r_c^-9 - r_c^-3] per particle with the
+    two-means density."""
+    st = synth.lattice(16, 16.0, seed=5)
+    p, po = make(st, tail=1)
+    s = dcm.System(p, st.x, st.v)
+    fo = s.forces()
+    x, _, rc, _ = s.state()
+    torch.cuda.synchronize()
+    xw, rcg = x.cpu().numpy(), rc.cpu().numpy()
+    pair = O.forces(po, xw, rcg)
+    assert np.max(np.abs(fo["f"].cpu().numpy() - pair.f)) <= FORCE_TOL * np.sqrt(np.mean(np.sum(pair.f ** 2, axis=0))) + 1e-13
+    rho = 1.0                                      # one particle per unit box
+    share = (8.0 / 3.0) * np.pi * rho * (rcg ** -9 / 3.0 - rcg ** -3)
+    e = fo["e"].cpu().numpy()
+    assert np.all(np.abs(e - (pair.e + share)) <= 1e-12 * np.maximum(np.abs(pair.e + share), 1.0))
+    s.close()
+
+
+def test_options_on_a_dilute_gas():
+    """A gas with no liquid (every box vapor after removal) with the tail correction, vapor
+    cutoffs and the Mumford-Shah segmentation at once."""
+    st = synth.gas(500, (20.0, 20.0, 20.0), seed=6)
+    p, po = make(st, tail=1, vapor_cutoff=1, ms_nu=0.005, ms_iters=20)
+    s = dcm.System(p, st.x, st.v)
+    det = s.detect()
+    fo = s.forces(per_atom=False, thermo=False)
+    x, _, rc, _ = s.state()
+    torch.cuda.synchronize()
+    xw, rcg = x.cpu().numpy(), rc.cpu().numpy()
+    od = O.detect(po, xw)
+    assert np.array_equal(det["label"].cpu().numpy(), od.label)
+    assert rc_close(rcg, od.rc, p.rc_min, p.rc_max, p.alpha, cap=2 * p.rc_max + 1.0)
+    ref = O.forces(po, xw, rcg).f + O.tail(po, od, xw, rcg)[0]
+    frms = np.sqrt(np.mean(np.sum(ref ** 2, axis=0)))
+    err = np.linalg.norm(fo["f"].cpu().numpy() - ref, axis=0) / np.maximum(np.linalg.norm(ref, axis=0), frms)
+    assert err.max() <= FORCE_TOL
+    s.close()
+
+
+def test_two_particles_with_lists():
+    r = 1.5
+    st = synth.pair(r, 14.0)
+    p, po = make(st, neighbor_list=1, skin=0.5, rc_max=5.0)    # r_c^max + skin fits the 14-box axis
+    s = check_system(st, p, po, "pair with lists")
+    f = s.forces()["f"].cpu().numpy()
+    mag = 24.0 * (2.0 * r ** -12 - r ** -6) / r
+    assert abs(f[0, 0] - (-mag)) <= 1e-12 * abs(mag) and abs(f[0, 1] - mag) <= 1e-12 * abs(mag)
+    s.close()
