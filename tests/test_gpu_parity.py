@@ -440,6 +440,74 @@ def test_slab2m_sampled_parity():
     s.close()
 
 
+@pytest.mark.slow
+def test_slab2m_options_sampled_parity():
+    """The 2M slab with the Mumford-Shah segmentation, vapor cutoffs and the tail correction at
+    once: labels bit-exact, both distance fields and the cutoffs within their bars (bands to
+    2 r_c^max + h), sampled forces (pair + tail) within the force bar."""
+    st = synth.named("slab2m")
+    p, po = make(st, ms_nu=0.005, ms_iters=60, vapor_cutoff=1, tail=1)
+    say("slab2m options: create + detect")
+    s = dcm.System(p, st.x, st.v)
+    det = s.detect()
+    fo = s.forces(per_atom=True, thermo=False)
+    x, v, rc, k = s.state()
+    torch.cuda.synchronize()
+    s.check()
+    xw = x.cpu().numpy()
+    say("slab2m options: oracle detect")
+    od = O.detect(po, xw)
+    assert np.array_equal(det["raw"].cpu().numpy(), od.raw), "Mumford-Shah labels"
+    assert np.array_equal(det["label"].cpu().numpy(), od.label)
+    cap = 2 * p.rc_max + 1.0
+    assert ulp_close(det["dist"].cpu().numpy(), od.dist, dist_ulps(cap, 1.0)), "distances"
+    assert ulp_close(det["dist_v"].cpu().numpy(), od.dist_v, dist_ulps(cap, 1.0)), "vapor-side distances"
+    rc_gpu = rc.cpu().numpy()
+    assert rc_close(rc_gpu, od.rc, cap=cap), "cutoffs"
+    idx = np.unique(np.random.default_rng(10).choice(st.n, 3000, replace=False))
+    say(f"slab2m options: oracle forces and tail on {idx.size} particles")
+    ref = O.forces(po, xw, rc_gpu, subset=idx)
+    ft, du = O.tail(po, od, np.ascontiguousarray(xw[:, idx]), rc_gpu[idx])
+    want = ref.f + ft
+    f = fo["f"].cpu().numpy()[:, idx]
+    frms = np.sqrt(np.mean(np.sum(want ** 2, axis=0)))
+    err = np.linalg.norm(f - want, axis=0) / np.maximum(np.linalg.norm(want, axis=0), frms)
+    say(f"slab2m options: max sampled force error {err.max():.2e}")
+    assert err.max() <= FORCE_TOL
+    e = fo["e"].cpu().numpy()[idx]
+    assert np.all(np.abs(e - (ref.e + 0.5 * du)) <= 1e-12 * np.maximum(np.abs(ref.e + 0.5 * du), 1.0))
+    s.step(2)
+    s.check()
+    s.close()
+
+
+@pytest.mark.slow
+def test_slab2m_lists_sampled_parity():
+    """Neighbour lists on the 2M slab: sampled forces and exact pair counts after steps that
+    cross list rebuilds."""
+    st = synth.named("slab2m")
+    p, po = make(st, neighbor_list=1, skin=0.3)
+    s = dcm.System(p, st.x, st.v)
+    s.step(5)
+    fo = s.forces(per_atom=True, thermo=False)
+    x, v, rc, k = s.state()
+    torch.cuda.synchronize()
+    s.check()
+    builds = dcm.dcm_list_builds(s.h)
+    say(f"slab2m lists: {builds} builds in 5 steps")
+    assert builds >= 2
+    xw, rc_gpu = x.cpu().numpy(), rc.cpu().numpy()
+    idx = np.unique(np.random.default_rng(11).choice(st.n, 3000, replace=False))
+    ref = O.forces(po, xw, rc_gpu, subset=idx)
+    f = fo["f"].cpu().numpy()[:, idx]
+    frms = np.sqrt(np.mean(np.sum(f ** 2, axis=0)))
+    err = np.linalg.norm(f - ref.f, axis=0) / np.maximum(np.linalg.norm(ref.f, axis=0), frms)
+    say(f"slab2m lists: max sampled force error {err.max():.2e}")
+    assert err.max() <= FORCE_TOL
+    assert np.array_equal(fo["pairs"].cpu().numpy()[idx].astype(np.int64), ref.pairs)
+    s.close()
+
+
 # ---- precision form: FP32 pair math, compensated FP32 per-particle sums --------------------
 FP32_FORCE_TOL = 1e-5
 
