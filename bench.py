@@ -39,6 +39,32 @@ def force_traffic():
     return FORCE_TRAFFIC_BYTES if h == FORCE_TRAFFIC_SRC else None
 
 
+def stage_bandwidth(breakdown: dict, n: int, G: int, detect_every: int) -> dict:
+    """Achieved bandwidth of the HBM-bound stages: algorithmic bytes per step / stage time.
+    Per particle: kick/drift/key 144 B (read x, v, F; write x, v, key, value); binning 196 B
+    (three radix passes of 24 B, box starts 4 B, gather 120 B) plus 4 B per box. Per box and
+    detection: smoothing 24 B (three axis passes of 8 B), two-means 4 B (histogram read),
+    labels and components 66 B (threshold 6 B, two component passes of about 30 B). Per particle
+    and detection: cutoffs 96 B (eight 8-byte box values, the 32-byte position record read).
+    Detection stages count once per detect_every steps. The distance solve is bound by its LDS
+    relaxations, not by HBM, and is left out."""
+    per_det = 1.0 / detect_every if detect_every > 0 else 0.0
+    bytes_per_step = {
+        "kick_drift_key": 144.0 * n,
+        "sort": 196.0 * n + 4.0 * G,
+        "smooth": 24.0 * G * per_det,
+        "two_means": 4.0 * G * per_det,
+        "segment": 66.0 * G * per_det,
+        "cutoffs": 96.0 * n * per_det,
+    }
+    out = {}
+    for k, b in bytes_per_step.items():
+        ms = breakdown.get(k, 0.0)
+        if ms > 0 and b > 0:
+            out[k] = {"bytes_per_step": b, "GB_per_s": round(b / (ms * 1e-3) / 1e9, 1)}
+    return out
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -828,6 +854,7 @@ def main():
     breakdown = {k: round((v[0] - before[k][0]) / nb, 5) for k, v in after.items()}
     log(f"{ms_step:.4f} ms/step, force kernel {f_avg_s * 1e3:.4f} ms, pairs/step {pairs:.4e}, "
         f"breakdown ms/step {breakdown}")
+    G_boxes = int(sysm.dims[0]) * int(sysm.dims[1]) * int(sysm.dims[2])
     e0 = rec[0]["ke"] + rec[0]["pe"]
     e1 = rec[-1]["ke"] + rec[-1]["pe"]
 
@@ -887,6 +914,7 @@ def main():
         "cpu_baseline": cpu and {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
         "cpu_baseline_all_cores": cpu_all,
         "breakdown_ms_per_step": breakdown,
+        "stage_bandwidth": stage_bandwidth(breakdown, state.n, G_boxes, args.detect_every),
         "energy_drift_per_atom": (e1 - e0) / state.n,
         "static_cutoff_6": static,
         "timing": {"repeats": len(runs), "of_steps": args.steps, "statistic": "median",
