@@ -191,7 +191,11 @@ dcm_status dcm_create(const dcm_params *p, int64_t n, void *d_ws, size_t ws_byte
 /* As dcm_create, but resumes a saved state: d_rc [n] holds the cutoffs carried by each
  * particle and step the index k of the force evaluation that state belongs to. The
  * interface is re-detected only if k % detect_every == 0 (Section 3: cutoffs are
- * carried between detections), so a resumed run repeats the original bit for bit. */
+ * carried between detections), so a resumed run repeats the original bit for bit. Two
+ * options break that: with tail = 1 a state resumed between detections recomputes the
+ * distance fields from its own positions (the original kept those of its last detection),
+ * and with neighbor_list = 1 the storage order, and with it the order of the force sums,
+ * depends on when the lists were last rebuilt. */
 dcm_status dcm_create_from_state(const dcm_params *p, int64_t n, void *d_ws, size_t ws_bytes,
                                  const double *d_x, const double *d_v, const double *d_rc,
                                  int64_t step, dcm_stream_t stream, dcm_system **out);
