@@ -322,7 +322,8 @@ void detect(dcm_system *s, hipStream_t st, bool with_cutoffs = true)
     stage_end(s, st);
 }
 
-void forces(dcm_system *s, hipStream_t st, double *e_out, double *w_out, uint32_t *pairs_out)
+// Arguments of the pair-force kernels (and the list build) for the current set.
+ForceArgs force_args(const dcm_system *s, double *e_out, double *w_out, uint32_t *pairs_out)
 {
     ForceArgs a;
     a.grid = s->grid;
@@ -351,6 +352,12 @@ void forces(dcm_system *s, hipStream_t st, double *e_out, double *w_out, uint32_
     a.list = s->list;
     a.nlist = s->nlist;
     a.list_cap = s->list_cap;
+    return a;
+}
+
+void forces(dcm_system *s, hipStream_t st, double *e_out, double *w_out, uint32_t *pairs_out)
+{
+    const ForceArgs a = force_args(s, e_out, w_out, pairs_out);
     stage_begin(s, 7, st);
     launch_forces(a, st);
     stage_end(s, st);
@@ -402,18 +409,7 @@ dcm_status list_update(dcm_system *s, hipStream_t st, bool force_rebuild)
     if (rebuild) {
         launch_wrap_key(s->grid, s->set[s->cur], s->n, s->key, s->val, st);
         rebin_sorted(s, st);
-        ForceArgs a;
-        a.grid = s->grid;
-        a.pos = s->set[s->cur].pos;
-        a.cell_start = s->gw.cell_start;
-        a.id = s->set[s->cur].id;
-        a.n = s->n;
-        a.rc_max = s->p.rc_max;
-        a.flags = s->gw.flags;
-        a.list = s->list;
-        a.nlist = s->nlist;
-        a.list_cap = s->list_cap;
-        launch_build_list(a, s->p.skin, st);
+        launch_build_list(force_args(s, nullptr, nullptr, nullptr), s->p.skin, st);
         launch_copy_bytes(s->pos_build, s->set[s->cur].pos, sizeof(double4) * (size_t)s->n, st);
         s->list_valid = true;
         s->list_builds += 1;
