@@ -580,6 +580,59 @@ def accuracy_study(equil: int, R: float = 20.0, time_steps: int = 200, detect_kw
     print(json.dumps(out), flush=True)
 
 
+def oracle_study(steps16k: int = 100, steps256k: int = 5):
+    """The single-threaded CPU oracle against the HIP path on the smaller configurations, whole
+    runs rather than samples: the 16,000-particle slab for `steps16k` steps and the
+    256,000-particle slab for `steps256k` steps (each from the generated state, detection every
+    2nd step, FP64, NVE). Per configuration: seconds per step on each side and the ratio."""
+    import numpy as np
+    import torch
+    import oracle as O
+    from paper_1502_03234_amd import dcm, synth
+
+    rows = []
+    for name, k in (("slab16k", steps16k), ("slab256k", steps256k)):
+        st = synth.named(name)
+        p = dcm.params(st.box)
+        s = dcm.System(p, st.x, st.v)
+        s.step(2, thermo=False)
+        torch.cuda.synchronize()
+        s.close()
+        s = dcm.System(p, st.x, st.v)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(k, thermo=False)
+        torch.cuda.synchronize()
+        gpu = (time.perf_counter() - t0) / k
+        s.check()
+        s.close()
+        po = O.params(st.box)
+        t0 = time.perf_counter()
+        rs = O.prepare(po, st.x, st.v)
+        t_prep = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        O.run(po, rs, k)
+        cpu = (time.perf_counter() - t0) / k
+        rows.append({"config": name, "n": st.n, "steps": k, "gpu_s_per_step": gpu, "oracle_s_per_step": cpu,
+                     "oracle_setup_s": t_prep, "ratio": cpu / gpu,
+                     "gpu_atom_steps_per_s": st.n / gpu, "oracle_atom_steps_per_s": st.n / cpu})
+        log(f"oracle study: {name}: GPU {gpu * 1e3:.3f} ms/step, oracle {cpu:.3f} s/step, ratio {cpu / gpu:.0f}")
+    out = {"study": "oracle_timing", "oracle": "dcm_oracle.c, gcc -O2, one thread", "cores": 1,
+           "host_cpu": _host_cpu(), "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
+def _host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def profile_study(nsteps: int = 100):
     """Cutoff profile over the density profile (Figure 33 analogue): the 16,000-particle slab
     (28 x 28 x 60) after `nsteps` NVE steps, for the default cutoffs (2.5 / 6.0) and the
@@ -732,6 +785,8 @@ def main():
                          "exact image sum, on the thesis slab after EQUIL NVT steps")
     ap.add_argument("--speedup-study", type=int, default=0, metavar="EQUIL",
                     help="DCM vs static r_c^max on the thesis's 192,000-particle slab after EQUIL steps")
+    ap.add_argument("--oracle-study", action="store_true",
+                    help="whole-run timing of the CPU oracle against the HIP path on the 16k and 256k slabs")
     ap.add_argument("--profile-study", type=int, default=0, metavar="STEPS",
                     help="cutoff profile over the density profile of the 16k slab after STEPS steps")
     ap.add_argument("--study-bin", type=float, default=1.0,
@@ -773,6 +828,9 @@ def main():
         return
     if args.profile_study:
         profile_study(args.profile_study)
+        return
+    if args.oracle_study:
+        oracle_study()
         return
     if args.accuracy_study >= 0:
         accuracy_study(args.accuracy_study, detect_kw=_detect_kw(args))
