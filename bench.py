@@ -732,6 +732,54 @@ def speedup_study(equil: int = 5000, nsteps: int = 200):
     print(json.dumps(out), flush=True)
 
 
+def tail_cost_study(equil: int = 100000, nsteps: int = 200):
+    """Step time at matched force accuracy, with and without the runtime tail correction, on the
+    thesis's geometry at 192,000 particles (the speedup study's state: NVT-equilibrated `equil`
+    steps at static r_c = 5.0). The configurations pair up by their Eq. 20 error on the thesis's
+    16,000-particle slab (`--accuracy-study`, 1-sigma boxes): about 0.0013-0.0015 (static 3.0
+    with the correction, DCM 3.0/4.0 with it, DCM 3.0/5.0 without), about 0.0004-0.0005 (static
+    4.0 and DCM 3.5/5.0 with it, DCM 3.5/5.0 without is 0.0007), and about 0.0001-0.0003 (static
+    5.0, DCM 4.0/5.0 and DCM 4.5/8.0 with it; DCM 4.0/7.0 and 4.5/8.0 without). Static cutoffs
+    with the correction keep the interface detection (the correction needs its fields)."""
+    import numpy as np
+    import torch
+    from paper_1502_03234_amd import dcm, synth
+
+    st = synth.named("thesis192k")
+    s = dcm.System(dcm.params(st.box, rc_min=5.0, rc_max=5.0, thermostat=dcm.DCM_NOSE_HOOVER,
+                              temperature=0.7, tdamp=0.5), st.x, st.v)
+    for k in range(0, equil, 10000):
+        s.step(min(10000, equil - k), thermo=False)
+        torch.cuda.synchronize()
+        log(f"tail cost study: equilibrated {min(k + 10000, equil)}/{equil} steps")
+    s.check()
+    x, v, _, _ = s.state()
+    torch.cuda.synchronize()
+    s.close()
+    rows = []
+    for rmin, rmax, tail in ((3.0, 3.0, 1), (3.0, 4.0, 1), (3.0, 5.0, 0), (4.0, 4.0, 1), (3.5, 5.0, 1),
+                             (3.5, 5.0, 0), (5.0, 5.0, 1), (4.0, 5.0, 1), (4.0, 7.0, 0), (4.5, 8.0, 1),
+                             (4.5, 8.0, 0)):
+        de = 0 if (rmin == rmax and not tail) else 2
+        sysm = dcm.System(dcm.params(st.box, rc_min=rmin, rc_max=rmax, detect_every=de, tail=tail), x, v)
+        sysm.step(10, thermo=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        th = dcm.thermo_records(sysm.step(nsteps))
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3 / nsteps
+        sysm.check()
+        sysm.close()
+        name = ("static %.1f" % rmax if rmin == rmax else "DCM %.1f/%.1f" % (rmin, rmax)) + (" + tail" if tail else "")
+        pp = float(np.mean([r["pairs"] for r in th])) / st.n
+        rows.append({"config": name, "ms_per_step": ms, "pairs_per_particle": pp})
+        log(f"tail cost study: {name}: {ms:.3f} ms/step, {pp:.0f} pairs per particle")
+    out = {"study": "tail_cost", "workload": "192,000 LJ particles, 76 x 76 x 44 block in 76 x 76 x 88, "
+           f"NVT-equilibrated {equil} steps, then {nsteps} timed NVE steps per configuration, FP64",
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def _detect_kw(args) -> dict:
     kw = dict(bin=args.study_bin, smooth_passes=args.study_smooth,
               min_component=args.study_min_component)
@@ -785,6 +833,8 @@ def main():
                          "exact image sum, on the thesis slab after EQUIL NVT steps")
     ap.add_argument("--speedup-study", type=int, default=0, metavar="EQUIL",
                     help="DCM vs static r_c^max on the thesis's 192,000-particle slab after EQUIL steps")
+    ap.add_argument("--tail-cost-study", type=int, default=0, metavar="EQUIL",
+                    help="step time at matched accuracy with and without the tail correction (192k slab)")
     ap.add_argument("--oracle-study", action="store_true",
                     help="whole-run timing of the CPU oracle against the HIP path on the 16k and 256k slabs")
     ap.add_argument("--profile-study", type=int, default=0, metavar="STEPS",
@@ -831,6 +881,9 @@ def main():
         return
     if args.oracle_study:
         oracle_study()
+        return
+    if args.tail_cost_study:
+        tail_cost_study(args.tail_cost_study)
         return
     if args.accuracy_study >= 0:
         accuracy_study(args.accuracy_study, detect_kw=_detect_kw(args))
