@@ -38,7 +38,7 @@ namespace dcm {
 
 namespace {
 
-constexpr int kTailBlock = 256;   // the pair-force kernel's block, so that partial b is shared
+constexpr int kTailBlock = 64;   // the pair-force kernel's block, so that partial b is shared
 
 __device__ __forceinline__ double lerp(double a, double b, double t) { return a + t * (b - a); }
 
