@@ -72,6 +72,20 @@ def test_grid_dims_and_workspace(dcm):
     dict(thermostat=1, temperature=0.0),
     dict(thermostat=1, tdamp=-1.0),
     dict(thermostat=1, tdamp=float("inf")),
+    dict(tail=2),                                      # options: flags are 0 or 1
+    dict(tail=1, pair_rule=1),                         # the tail needs the r_c[i] rule
+    dict(tail=1, energy_shift=1),                      # ... and unshifted energies
+    dict(vapor_cutoff=3),
+    dict(ms_nu=-0.1),
+    dict(ms_nu=float("nan")),
+    dict(ms_nu=0.005, ms_iters=0),
+    dict(ms_nu=0.005, ms_iters=100001),
+    dict(neighbor_list=2),
+    dict(neighbor_list=1, skin=0.0),
+    dict(neighbor_list=1, skin=float("inf")),
+    dict(neighbor_list=1, pair_rule=1),
+    dict(neighbor_list=1, list_capacity=-1),
+    dict(neighbor_list=1, skin=1.5, box=(14.0, 14.0, 60.0), rc_max=5.0),   # r_c^max + skin >= L/2
 ])
 def test_invalid_parameters_rejected(dcm, bad):
     kw = dict(box=(28.0, 28.0, 60.0))
@@ -82,6 +96,26 @@ def test_invalid_parameters_rejected(dcm, bad):
         dcm.dcm_workspace_bytes(p, 1000)
     assert e.value.status == dcm.DCM_E_INVALID
     assert dcm.dcm_last_error()
+
+
+def test_option_workspaces(dcm):
+    """Each option adds its arrays to the workspace: the vapor-side distance field (8 B per box),
+    the Mumford-Shah fields (48 B per box), the neighbour lists (a slot capacity per particle,
+    default 1.25 (4/3) pi (r_c^max + skin)^3, plus positions at the build and box counts)."""
+    box, n = (28.0, 28.0, 60.0), 16000
+    G = 28 * 28 * 60
+    base = dcm.dcm_workspace_bytes(dcm.params(box), n)
+    tail = dcm.dcm_workspace_bytes(dcm.params(box, tail=1), n)
+    vap = dcm.dcm_workspace_bytes(dcm.params(box, vapor_cutoff=1), n)
+    ms = dcm.dcm_workspace_bytes(dcm.params(box, ms_nu=0.005), n)
+    lists = dcm.dcm_workspace_bytes(dcm.params(box, neighbor_list=1, skin=0.3), n)
+    small = dcm.dcm_workspace_bytes(dcm.params(box, neighbor_list=1, skin=0.3, list_capacity=100), n)
+    assert tail >= base + 8 * G and vap >= base + 8 * G
+    assert ms >= base + 48 * G
+    import math
+    cap = math.ceil(1.25 * 4.0 / 3.0 * math.pi * 6.3 ** 3)
+    assert lists >= base + 4 * cap * n + 4 * n + 32 * n + 4 * G
+    assert small < lists and small >= base + 4 * 100 * n
 
 
 def test_invalid_n_and_workspace(dcm):
