@@ -165,3 +165,43 @@ def test_two_particles_with_lists():
     mag = 24.0 * (2.0 * r ** -12 - r ** -6) / r
     assert abs(f[0, 0] - (-mag)) <= 1e-12 * abs(mag) and abs(f[0, 1] - mag) <= 1e-12 * abs(mag)
     s.close()
+
+
+@pytest.mark.slow
+def test_largest_system_sampled_parity():
+    """The largest system the ABI accepts, near n = 2^26 (406^3 = 66,923,416 particles, one per
+    box of a density-0.80 lattice): positions are addressed with 32-bit byte offsets, which reach
+    within 0.3 % of 2^31 here. Forces under seeded per-particle cutoffs (the detection of a
+    uniform lattice finds no interface) are checked against the oracle for particles at the
+    highest storage offsets (the top force rows in y and z), the lowest, and a random sample."""
+    m = 406
+    assert m ** 3 < 1 << 26
+    st = synth.lattice(m, 437.0, seed=11)
+    p, po = make(st, rc_min=2.5, rc_max=4.0)
+    say(f"largest: n={st.n}, workspace {dcm.dcm_workspace_bytes(p, st.n) / 2**30:.1f} GiB")
+    s = dcm.System(p, st.x, st.v)
+    rc = np.random.default_rng(12).uniform(2.5, 4.0, st.n)
+    s.set_cutoffs(rc)
+    fo = s.forces()
+    x, _, rcg, _ = s.state()
+    torch.cuda.synchronize()
+    s.check()
+    xw = x.cpu().numpy()
+    assert np.array_equal(rcg.cpu().numpy(), rc)
+    L = st.box[0]
+    top = np.nonzero((xw[2] > L - 2.0) & (xw[1] > L - 2.0))[0]
+    low = np.nonzero((xw[2] < 2.0) & (xw[1] < 2.0))[0]
+    rng = np.random.default_rng(13)
+    idx = np.unique(np.concatenate([rng.choice(top, 400, replace=False), rng.choice(low, 200, replace=False),
+                                    rng.choice(st.n, 400, replace=False)]))
+    say(f"largest: oracle forces on {idx.size} particles")
+    ref = O.forces(po, xw, rc, subset=idx)
+    f = fo["f"].cpu().numpy()[:, idx]
+    frms = np.sqrt(np.mean(np.sum(ref.f ** 2, axis=0)))
+    err = np.linalg.norm(f - ref.f, axis=0) / np.maximum(np.linalg.norm(ref.f, axis=0), frms)
+    say(f"largest: max sampled force error {err.max():.2e}")
+    assert err.max() <= FORCE_TOL
+    assert np.array_equal(fo["pairs"].cpu().numpy()[idx].astype(np.int64), ref.pairs)
+    s.close()
+    del s, fo, x, rcg
+    torch.cuda.empty_cache()
