@@ -222,6 +222,8 @@ size_t layout(dcm_system *s, void *ws)
     s->nfb = force_blocks(n);
     s->nkb = stream_blocks(n);
     s->fparts = b.take<Partial>(s->nfb);
+    s->order = b.take<uint32_t>(s->nfb);
+    s->wave_time = b.take<uint32_t>(s->nfb);
     s->kparts = b.take<Partial>(s->nkb);
     s->rparts = b.take<Partial>(reduce_stage_partials());
     s->nh = b.take<double>(4);
@@ -352,6 +354,8 @@ ForceArgs force_args(const dcm_system *s, double *e_out, double *w_out, uint32_t
     a.list = s->list;
     a.nlist = s->nlist;
     a.list_cap = s->list_cap;
+    a.order = s->order;
+    a.wave_time = s->wave_time;
     return a;
 }
 
@@ -454,6 +458,8 @@ dcm_status create_impl(const dcm_params *p, int64_t n, void *d_ws, size_t ws_byt
     hipStream_t st = (hipStream_t)stream;
     launch_fill_u32(s->gw.flags, 0u, 1, st);
     launch_fill_u32((uint32_t *)s->nh, 0u, 8, st);
+    launch_fill_u32(s->wave_time, 0u, s->nfb, st);
+    launch_wave_order(s->wave_time, s->order, s->nfb, st);
     launch_check_finite(d_x, 3 * n, s->gw.flags, st);
     launch_check_finite(d_v, 3 * n, s->gw.flags, st);
     launch_load_state(s->set[0], d_x, d_v, from_state ? d_rc : nullptr, n, p->rc_max, st);

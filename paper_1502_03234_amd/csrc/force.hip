@@ -374,13 +374,15 @@ struct KForces {
 };
 
 template <int PAIR, bool SHIFT, int U, int PREC, bool LIST>
-__device__ void KForces<PAIR, SHIFT, U, PREC, LIST>::run(const Args &args_, uint32_t blk, uint32_t)
+__device__ void KForces<PAIR, SHIFT, U, PREC, LIST>::run(const Args &args_, uint32_t blk, uint32_t nblk)
 {
     const ForceArgs &a = args_.a;
     const double rc_max = args_.rc_max;
-    // hardware (round-robin over XCDs) block order: the cost per particle varies strongly
-    // with z through the cutoffs, and interleaving keeps every XCD's share of it even
-    const int64_t b = blk;
+    // the wave this workgroup takes: longest (in the last launch) first, so that the waves
+    // still running at the end are short ones; the hardware deals workgroups round-robin over
+    // the XCDs, which spreads every duration class over all of them
+    const int64_t b = a.order ? (int64_t)min(a.order[blk], nblk - 1u) : (int64_t)blk;
+    const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
     const int64_t i = b * kForceBlock + threadIdx.x;
     const bool have = i < a.n;
     Particle q;
@@ -471,6 +473,68 @@ __device__ void KForces<PAIR, SHIFT, U, PREC, LIST>::run(const Args &args_, uint
             p.pairs += ldp[q];
         }
         a.partials[b] = p;
+        if (a.wave_time) {
+            const uint64_t dt = __builtin_amdgcn_s_memrealtime() - t_start;
+            a.wave_time[b] = dt < 0xffffffffull ? (uint32_t)dt : 0xffffffffu;
+        }
+    }
+}
+
+// Duration class, 16 per octave (monotone in t), numbered from the longest: 0 .. 511.
+__device__ __forceinline__ uint32_t duration_class(uint32_t t)
+{
+    const uint32_t v = t < 0xffffffffu ? t + 1u : t;
+    const int e = 31 - __clz(v);
+    const uint32_t c = e < 4 ? v : ((uint32_t)(e - 3) << 4) | ((v >> (e - 4)) & 15u);
+    return 511u - (c < 511u ? c : 511u);
+}
+
+// Counting sort of the waves by duration class, longest first, in one workgroup. Waves of one
+// class take no fixed order among themselves.
+struct KWaveOrder {
+    static constexpr int kThreads = 1024, kWaves = 0;
+    static constexpr int kClasses = 512, kLoads = 8;
+    struct Args {
+        const uint32_t *t;
+        uint32_t *order;
+        uint32_t nb;
+    };
+    static __device__ void run(const Args &a, uint32_t, uint32_t);
+};
+
+__device__ void KWaveOrder::run(const Args &a, uint32_t, uint32_t)
+{
+    __shared__ uint32_t cnt[kClasses], next[kClasses];
+    for (int k = threadIdx.x; k < kClasses; k += kThreads) cnt[k] = 0u;
+    __syncthreads();
+    for (uint32_t k0 = 0; k0 < a.nb; k0 += kLoads * kThreads) {
+        uint32_t c[kLoads];
+#pragma unroll
+        for (int u = 0; u < kLoads; ++u) {
+            const uint32_t k = k0 + (uint32_t)(u * kThreads) + threadIdx.x;
+            c[u] = k < a.nb ? duration_class(a.t[k]) : (uint32_t)kClasses;
+        }
+#pragma unroll
+        for (int u = 0; u < kLoads; ++u)
+            if (c[u] < (uint32_t)kClasses) atomicAdd(&cnt[c[u]], 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kClasses; k += kThreads) {
+        uint32_t s = 0;
+        for (int q = 0; q < k; ++q) s += cnt[q];
+        next[k] = s;
+    }
+    __syncthreads();
+    for (uint32_t k0 = 0; k0 < a.nb; k0 += kLoads * kThreads) {
+        uint32_t c[kLoads];
+#pragma unroll
+        for (int u = 0; u < kLoads; ++u) {
+            const uint32_t k = k0 + (uint32_t)(u * kThreads) + threadIdx.x;
+            c[u] = k < a.nb ? duration_class(a.t[k]) : (uint32_t)kClasses;
+        }
+#pragma unroll
+        for (int u = 0; u < kLoads; ++u)
+            if (c[u] < (uint32_t)kClasses) a.order[atomicAdd(&next[c[u]], 1u)] = k0 + (uint32_t)(u * kThreads) + threadIdx.x;
     }
 }
 
@@ -535,11 +599,17 @@ void launch_build_list(const ForceArgs &a, double skin, hipStream_t st)
     emit<KBuildList>({a, skin}, (uint32_t)force_blocks(a.n), st);
 }
 
+void launch_wave_order(const uint32_t *wave_time, uint32_t *order, int64_t nb, hipStream_t st)
+{
+    emit<KWaveOrder>({wave_time, order, (uint32_t)nb}, 1, st);
+}
+
 void launch_forces(const ForceArgs &a, hipStream_t st)
 {
     const int nb = force_blocks(a.n);
     if (a.precision == DCM_FP32C) launch_prec<DCM_FP32C>(a, nb, st);
     else launch_prec<DCM_FP64>(a, nb, st);
+    if (a.order && a.wave_time) launch_wave_order(a.wave_time, a.order, nb, st);
 }
 
 }  // namespace dcm

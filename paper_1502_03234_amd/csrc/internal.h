@@ -173,9 +173,16 @@ struct ForceArgs {
     uint32_t *list;
     uint32_t *nlist;
     uint32_t list_cap;
+    // launch order of the force waves (a permutation of the workgroups, longest last duration
+    // first) and each wave's duration in its last launch (constant-rate clock ticks); the
+    // forces do not depend on the order
+    uint32_t *order;
+    uint32_t *wave_time;
 };
 int force_blocks(int64_t n);
 void launch_forces(const ForceArgs &a, hipStream_t st);
+// Longest-first order of nb force waves from their recorded durations.
+void launch_wave_order(const uint32_t *wave_time, uint32_t *order, int64_t nb, hipStream_t st);
 // Lists of every slot within r_c[i] + skin, built by the force kernel's traversal (cell_start
 // must describe the current positions); sets kFlagListOverflow if a list exceeds list_cap.
 void launch_build_list(const ForceArgs &a, double skin, hipStream_t st);
@@ -254,6 +261,7 @@ struct dcm_system {
     void *sort_scratch;
     dcm::GridWork gw;
     dcm::Partial *fparts, *kparts, *rparts;
+    uint32_t *order, *wave_time;  // [nfb] force-wave launch order and last durations
     double *nh;             // Nose-Hoover state {xi, eta, velocity scale of the last half step}
     dcm::NhConst nhc;
     int nfb, nkb;
