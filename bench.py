@@ -27,8 +27,8 @@ WORKLOAD = "slab2m"
 # HBM-side bytes per force-kernel launch from FETCH_SIZE/WRITE_SIZE counter runs, scaled by a plain
 # 1 GiB copy (profiles/KForces_slab2m_traffic.md). Valid only for the kernel source it was
 # taken on: reported as null once csrc/force.hip no longer hashes to this value.
-FORCE_TRAFFIC_BYTES = 2.379e9
-FORCE_TRAFFIC_SRC = "e11b1df1bd2d3575"
+FORCE_TRAFFIC_BYTES = 2.745e9
+FORCE_TRAFFIC_SRC = "f97f4fc5d169dabd"
 
 
 def force_traffic():
