@@ -69,11 +69,13 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(state, sample: int, seed: int = 12345):
+def cpu_baseline(state, sample: int, seed: int = 12345, total_pairs: float | None = None):
     """Time the CPU oracle on a bounded sample of the same workload: one interface detection
     on the full state (charged at 1/2 per step: detection every other step), forces for a
-    seeded random sample of particles (per-particle cost scaled to all particles), and one
-    full velocity-Verlet position/velocity update."""
+    seeded random sample of particles, and one full velocity-Verlet position/velocity update.
+    The sample's force time is scaled to all particles by their number; with total_pairs (the
+    whole system's in-range pair count) it is also scaled by pairs, and the two estimates are
+    reported side by side (their spread bounds the sampling error of the extrapolation)."""
     import numpy as np
     import oracle as O
 
@@ -84,8 +86,10 @@ def cpu_baseline(state, sample: int, seed: int = 12345):
     t_det = time.perf_counter() - t0
     idx = np.sort(np.random.default_rng(seed).choice(state.n, sample, replace=False))
     t0 = time.perf_counter()
-    O.forces(p, x, det.rc, subset=idx)
-    t_f = (time.perf_counter() - t0) / sample * state.n
+    fr = O.forces(p, x, det.rc, subset=idx)
+    t_sample = time.perf_counter() - t0
+    t_f = t_sample / sample * state.n
+    sample_pairs = float(fr.pairs.sum())
     v = state.v.copy()
     f = np.zeros_like(v)
     t0 = time.perf_counter()
@@ -95,41 +99,95 @@ def cpu_baseline(state, sample: int, seed: int = 12345):
     v += 0.0025 * f
     t_int = time.perf_counter() - t0
     per_step = t_f + 0.5 * t_det + t_int
-    return dict(value=state.n / per_step, unit="atom-steps/s", cores=1, kind="oracle",
-                sample=(f"slab2m: detection on all {state.n} particles (x1/2 per step), forces "
-                        f"for {sample} seeded random particles scaled to {state.n}, one full "
-                        f"integration update; {per_step:.1f} s per step"),
-                seconds=dict(detect=t_det, forces_scaled=t_f, integrate=t_int))
+    out = dict(value=state.n / per_step, unit="atom-steps/s", cores=1, kind="oracle",
+               sample=(f"slab2m: detection on all {state.n} particles (x1/2 per step), forces "
+                       f"for {sample} seeded random particles scaled to {state.n}, one full "
+                       f"integration update; {per_step:.1f} s per step"),
+               seconds=dict(detect=t_det, forces_sample=t_sample, forces_scaled=t_f, integrate=t_int))
+    if total_pairs:
+        t_fp = t_sample * total_pairs / sample_pairs
+        per_step_p = t_fp + 0.5 * t_det + t_int
+        out["by_pairs"] = dict(value=state.n / per_step_p, sample_pairs_per_particle=sample_pairs / sample,
+                               pairs_per_particle=total_pairs / state.n,
+                               rel_diff=per_step_p / per_step - 1.0)
+    return out
 
 
-def _cpu_worker(args):
-    """One oracle copy of the bounded sample (a separate interpreter; the state comes from a
-    file so that no process that touched the GPU is forked)."""
-    path, box, sample, seed = args
+def under_profiler() -> bool:
+    """True when a profiler tool is loaded into this process (rocprofv3 announces itself through
+    ROCPROF_* variables). Child processes would inherit the tool."""
+    return any(k.startswith("ROCPROF") for k in os.environ)
+
+
+def host_cpu() -> dict:
+    """CPU model, logical CPUs of the host and CPUs this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return {"model": model, "nproc": os.cpu_count() or 1, "usable": usable}
+
+
+def cpu_workers_start(state, sample: int, procs: int):
+    """Starts `procs` oracle processes (bench.py --cpu-worker) before this process touches the
+    GPU, so that no process holding a GPU context forks. Each loads the state from a file and
+    then waits on its stdin; cpu_workers_collect releases them once the GPU timing is over, so
+    that they do not compete with it for host cores."""
+    import subprocess
+    import tempfile
+    import numpy as np
+    fd, path = tempfile.mkstemp(suffix=".npz", dir="/dev/shm" if os.path.isdir("/dev/shm") else None)
+    os.close(fd)
+    np.savez(path, x=state.x, v=state.v, box=np.array(state.box))
+    workers = []
+    for k in range(procs):
+        workers.append(subprocess.Popen(
+            [sys.executable, os.path.abspath(__file__), "--cpu-worker", path, "--cpu-sample", str(sample),
+             "--cpu-seed", str(12345 + k)],
+            stdin=subprocess.PIPE, stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True))
+    return {"path": path, "workers": workers}
+
+
+def cpu_workers_collect(handle, timeout_s: float = 600.0):
+    """Releases the workers at once and sums their throughput: the host's aggregate figure."""
+    ws = handle["workers"]
+    try:
+        for w in ws:
+            w.stdin.write("go\n")
+            w.stdin.flush()
+        vals = []
+        for w in ws:
+            out, _ = w.communicate(timeout=timeout_s)
+            vals.append(float(json.loads(out.strip().splitlines()[-1])["value"]))
+    finally:
+        for w in ws:
+            if w.poll() is None:
+                w.kill()
+                w.wait()
+        os.unlink(handle["path"])
+    return dict(value=float(sum(vals)), unit="atom-steps/s", cores=len(ws), kind="oracle",
+                sample=f"{len(ws)} independent oracle processes at once, each on the single-core sample")
+
+
+def cpu_worker_main(path: str, sample: int, seed: int):
+    """One oracle copy of the bounded sample, started by cpu_workers_start; it never touches
+    the GPU. Waits for the go line, runs, prints one JSON line."""
     import numpy as np
     from types import SimpleNamespace
     d = np.load(path)
-    st = SimpleNamespace(x=d["x"], v=d["v"], box=tuple(box), n=d["x"].shape[1])
-    return cpu_baseline(st, sample, seed)["value"]
-
-
-def cpu_baseline_aggregate(state, sample: int, procs: int):
-    """The same bounded sample run by `procs` independent oracle processes at once (one per
-    host core): their summed throughput is the host's aggregate figure."""
-    import multiprocessing as mp
-    import numpy as np
-    import tempfile
-    fd, path = tempfile.mkstemp(suffix=".npz", dir="/dev/shm" if os.path.isdir("/dev/shm") else None)
-    os.close(fd)
-    try:
-        np.savez(path, x=state.x, v=state.v)
-        ctx = mp.get_context("spawn")
-        with ctx.Pool(procs) as pool:
-            vals = pool.map(_cpu_worker, [(path, state.box, sample, 12345 + k) for k in range(procs)])
-    finally:
-        os.unlink(path)
-    return dict(value=float(sum(vals)), unit="atom-steps/s", cores=procs, kind="oracle",
-                sample=f"{procs} independent oracle processes, each on the single-core sample")
+    st = SimpleNamespace(x=d["x"], v=d["v"], box=tuple(float(b) for b in d["box"]), n=d["x"].shape[1])
+    if sys.stdin.readline().strip() != "go":
+        return
+    print(json.dumps({"value": cpu_baseline(st, sample, seed)["value"]}), flush=True)
 
 
 def _fp64_forces_of(p, x, v, rc, k):
@@ -253,7 +311,7 @@ def droplet_study(nsteps: int):
 
 
 def serving_study(nseeds: int, nsys: int = 64, nsteps: int = 100, load: float = 0.8,
-                  droplets: bool = False):
+                  droplets: bool = False, emit: bool = True):
     """Serving form against one-system-at-a-time solves on the same Poisson traces.
 
     Systems: 64 slabs (with `droplets`, every 4th system a droplet of the same size in vapor),
@@ -273,7 +331,12 @@ def serving_study(nseeds: int, nsys: int = 64, nsteps: int = 100, load: float = 
     params = [dcm.params(s.box) for s in systems]
     sizes = np.array([s.n for s in systems])
     log(f"serving: {nsys} systems, {sizes.sum()} particles, sizes {sizes.min()}..{sizes.max()}")
-    # sequential service times
+    # sequential service times, after one untimed solve of the first system (library and
+    # allocator warm-up would otherwise be charged to it)
+    warm = dcm.System(params[0], torch.from_numpy(systems[0].x).cuda(), torch.from_numpy(systems[0].v).cuda())
+    warm.step(nsteps, thermo=True)
+    torch.cuda.synchronize()
+    warm.close()
     svc = np.zeros(nsys)
     for j, (s, p) in enumerate(zip(systems, params)):
         torch.cuda.synchronize()
@@ -287,7 +350,6 @@ def serving_study(nseeds: int, nsys: int = 64, nsteps: int = 100, load: float = 
         torch.cuda.synchronize()
         svc[j] = time.perf_counter() - t0
         sysm.close()
-    # warm the sequential path once more for the first (cold) system
     cap = nsys / svc.sum()
     rate = load * cap
     foot = [dcm.dcm_workspace_bytes(p, s.n) + 48 * s.n + 4096 for s, p in zip(systems, params)]
@@ -361,7 +423,9 @@ def serving_study(nseeds: int, nsys: int = 64, nsteps: int = 100, load: float = 
                          "makespan_s": makespan, "server_stats": sat_stats},
            "server_stats_per_seed": srv_stats,
            "samples": len(srv_lat)}
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 # Total energy per particle printed by the thesis (Section 6, Table 1) for its 16,000-particle
@@ -793,6 +857,52 @@ def _detect_kw(args) -> dict:
     return kw
 
 
+def run_study(args):
+    """The studies (one per flag); each prints its own JSON line."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {src.numel() * 8} bytes")
+        return
+    if args.speedup_study:
+        speedup_study(args.speedup_study)
+        return
+    if args.profile_study:
+        profile_study(args.profile_study)
+        return
+    if args.oracle_study:
+        oracle_study()
+        return
+    if args.tail_cost_study:
+        tail_cost_study(args.tail_cost_study)
+        return
+    if args.accuracy_study >= 0:
+        accuracy_study(args.accuracy_study, detect_kw=_detect_kw(args))
+        return
+    if args.nvt_study:
+        vals = [int(v) for v in args.nvt_study.split(",")]
+        nvt_study(vals[0], vals[1], set(vals[2:]) or None, save_dir=args.save_dir or None,
+                  detect_kw=_detect_kw(args))
+        return
+    if args.precision_study:
+        precision_study(args.precision_study)
+        return
+    if args.serve:
+        serving_study(args.serve, droplets=args.serve_droplets)
+        return
+    if args.droplet_study:
+        droplet_study(args.droplet_study)
+        return
+
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -813,8 +923,14 @@ def main():
     ap.add_argument("--ms-iters", type=int, default=100, help="primal-dual iterations of --ms-nu")
     ap.add_argument("--vapor-cutoffs", action="store_true",
                     help="vapor particles with dynamic cutoffs too (Section 3.1's extension of Eq. 7)")
-    ap.add_argument("--compare-static", action="store_true",
-                    help="also time the same system with a static cutoff r_c = r_c^max")
+    ap.add_argument("--no-compare-static", action="store_true",
+                    help="skip timing the same system with a static cutoff r_c = r_c^max")
+    ap.add_argument("--equilibrate", type=int, default=1000,
+                    help="untimed steps from the lattice start before the timed runs (steady state)")
+    ap.add_argument("--serve-seeds", type=int, default=1,
+                    help="serving leg of the headline line: this many Poisson traces (0: none)")
+    ap.add_argument("--cpu-worker", type=str, default="", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-seed", type=int, default=12345, help=argparse.SUPPRESS)
     ap.add_argument("--forces-only", type=int, default=0, metavar="K",
                     help="only create the system and run K force evaluations (counter passes)")
     ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
@@ -859,51 +975,32 @@ def main():
         print("bench.py measures one GPU only: the DCM path here has no multi-GPU "
               "decomposition; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.cpu_worker:
+        cpu_worker_main(args.cpu_worker, args.cpu_sample, args.cpu_seed)
+        return
+    from paper_1502_03234_amd import synth
 
-    import torch
-    from paper_1502_03234_amd import dcm, synth
-
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    if args.calibrate_copy:
-        src = torch.ones(args.calibrate_copy // 8, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"copied {src.numel() * 8} bytes")
-        return
-    if args.speedup_study:
-        speedup_study(args.speedup_study)
-        return
-    if args.profile_study:
-        profile_study(args.profile_study)
-        return
-    if args.oracle_study:
-        oracle_study()
-        return
-    if args.tail_cost_study:
-        tail_cost_study(args.tail_cost_study)
-        return
-    if args.accuracy_study >= 0:
-        accuracy_study(args.accuracy_study, detect_kw=_detect_kw(args))
-        return
-    if args.nvt_study:
-        vals = [int(v) for v in args.nvt_study.split(",")]
-        nvt_study(vals[0], vals[1], set(vals[2:]) or None, save_dir=args.save_dir or None,
-                  detect_kw=_detect_kw(args))
-        return
-    if args.precision_study:
-        precision_study(args.precision_study)
-        return
-    if args.serve:
-        serving_study(args.serve, droplets=args.serve_droplets)
-        return
-    if args.droplet_study:
-        droplet_study(args.droplet_study)
+    studies = (args.calibrate_copy or args.speedup_study or args.profile_study or args.oracle_study
+               or args.tail_cost_study or args.accuracy_study >= 0 or args.nvt_study or args.precision_study
+               or args.serve or args.droplet_study)
+    if studies:
+        run_study(args)
         return
     log(f"generating {WORKLOAD}")
     state = synth.named(WORKLOAD)
+    host = host_cpu()
+    share = min(16, host["usable"])       # one GPU's share of the machine's host cores
+    profiled = under_profiler()
+    workers = None
+    if not args.no_cpu_baseline and not profiled and share > 1:
+        log(f"cpu baseline: starting {share} oracle processes (released after the GPU timing)")
+        workers = cpu_workers_start(state, args.cpu_sample, share)
+
+    import torch
+    from paper_1502_03234_amd import dcm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
     prec = dcm.DCM_FP64 if args.precision == "fp64" else dcm.DCM_FP32C
     p = dcm.params(state.box, precision=prec, tail=1 if args.tail else 0,
                    vapor_cutoff=1 if args.vapor_cutoffs else 0, ms_nu=args.ms_nu, ms_iters=args.ms_iters,
@@ -917,12 +1014,23 @@ def main():
         torch.cuda.synchronize()
         log(f"{args.forces_only} force evaluations done")
         return
-    th = torch.empty(max(args.steps, args.warmup, 1) * dcm.THERMO_DOUBLES, dtype=torch.float64, device=dev)
-    # `repeats` timed runs of exactly K steps, each from the same initial state after the same
-    # W warmup steps (the slab's pair count grows as it evolves, so every run must cover the
-    # same steps); value and ms/step are the median run's. The timed steps record HIP events
-    # around the force launches only (the roofline's kernel time); the per-stage breakdown comes
-    # from a separate profiled run afterwards.
+    th = torch.empty(max(args.steps, args.warmup, args.equilibrate, 1) * dcm.THERMO_DOUBLES,
+                     dtype=torch.float64, device=dev)
+    # The lattice start roughens and its pair count grows for about a thousand steps; an untimed
+    # equilibration brings the slab to that state first. Every timed run then starts from the
+    # equilibrated state (positions, velocities, cutoffs, step count), takes the same W warmup
+    # steps and is timed over exactly K steps; value and ms/step are the median run's. The timed
+    # steps record HIP events around the force launches only (the roofline's kernel time); the
+    # per-stage breakdown comes from a separate profiled run afterwards.
+    eq = dcm.System(p, state.x, state.v)
+    if args.equilibrate:
+        log(f"equilibrating {args.equilibrate} untimed steps")
+        dcm.dcm_step(eq.h, args.equilibrate, stream, th)
+        torch.cuda.synchronize()
+        eq.check()
+    ex, ev, erc, ek = eq.state()
+    torch.cuda.synchronize()
+    eq.close()
     runs = []
     f_ms = 0.0
     f_cnt = 0
@@ -930,9 +1038,9 @@ def main():
     for r in range(max(1, args.repeats)):
         if sysm is not None:
             sysm.close()
-        sysm = dcm.System(p, state.x, state.v)
+        sysm = dcm.System(p, ex, ev, rc=erc, step=ek)
         if r == 0:
-            log(f"n={state.n} grid={sysm.dims} warmup={args.warmup} repeats={args.repeats}")
+            log(f"n={state.n} grid={sysm.dims} equilibrated={ek} warmup={args.warmup} repeats={args.repeats}")
         if args.warmup:
             dcm.dcm_step(sysm.h, args.warmup, stream, th)
         torch.cuda.synchronize()
@@ -968,34 +1076,51 @@ def main():
     G_boxes = int(sysm.dims[0]) * int(sysm.dims[1]) * int(sysm.dims[2])
     e0 = rec[0]["ke"] + rec[0]["pe"]
     e1 = rec[-1]["ke"] + rec[-1]["pe"]
+    sysm.close()
 
     static = None
-    if args.compare_static:
-        sysm.close()
-        ps = dcm.params(state.box, rc_min=6.0, rc_max=6.0, precision=prec, detect_every=0)
-        ss = dcm.System(ps, state.x, state.v)
-        dcm.dcm_step(ss.h, 3, stream, th)
+    if not args.no_compare_static:
+        # the static cutoff method (r_c = r_c^max for every particle, no interface detection)
+        # from the same equilibrated state, over the same number of steps
+        ps = dcm.params(state.box, rc_min=p.rc_max, rc_max=p.rc_max, precision=prec, detect_every=0)
+        ss = dcm.System(ps, ex, ev, step=ek)
+        dcm.dcm_step(ss.h, max(3, args.warmup), stream, th)
         torch.cuda.synchronize()
-        ks = max(10, args.steps // 10)
+        dcm.dcm_set_profiling(ss.h, 2)
         t0 = time.perf_counter()
-        dcm.dcm_step(ss.h, ks, stream, th)
+        dcm.dcm_step(ss.h, args.steps, stream, th)
         torch.cuda.synchronize()
-        st_ms = (time.perf_counter() - t0) / ks * 1e3
-        static = dict(ms_per_step=round(st_ms, 4), dcm_speedup=round(st_ms / ms_step, 3))
+        st_ms = (time.perf_counter() - t0) / args.steps * 1e3
+        sf_ms, sf_cnt = dcm.dcm_stage_times(ss.h)["forces"]
+        srec = dcm.thermo_records(th[: args.steps * dcm.THERMO_DOUBLES])
+        spairs = sum(r["pairs"] for r in srec) / len(srec)
+        ss.check()
         ss.close()
-    else:
-        sysm.close()
+        static = dict(r_c=p.rc_max, ms_per_step=round(st_ms, 4), dcm_speedup=round(st_ms / ms_step, 3),
+                      force_ms=round(sf_ms / max(sf_cnt, 1), 4),
+                      force_speedup=round(sf_ms / max(sf_cnt, 1) / (f_avg_s * 1e3), 3),
+                      pairs_per_particle=round(spairs / state.n, 2),
+                      pair_ratio=round(spairs / pairs, 3))
+        log(f"static r_c = {p.rc_max}: {st_ms:.3f} ms/step, DCM speedup {static['dcm_speedup']}x "
+            f"(forces {static['force_speedup']}x, pairs {static['pair_ratio']}x)")
+
+    serving = None
+    if args.serve_seeds > 0:
+        serving = serving_study(args.serve_seeds, emit=False)
 
     cpu = cpu_all = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on a sample of {args.cpu_sample} particles")
-        cpu = cpu_baseline(state, args.cpu_sample)
-        procs = min(16, os.cpu_count() or 1)
-        log(f"cpu baseline: {procs} oracle processes at once")
-        cpu_all = cpu_baseline_aggregate(state, args.cpu_sample, procs)
+        cpu = cpu_baseline(state, args.cpu_sample, total_pairs=pairs)
+        if workers is not None:
+            log(f"cpu baseline: releasing {share} oracle processes at once")
+            cpu_all = cpu_workers_collect(workers)
+        elif profiled:
+            cpu_all = {"skipped": "a profiler tool is loaded into this process; child processes "
+                                  "would inherit it"}
 
     out = {
-        "metric": "atom-steps/s/GPU at 2M-atom LJ slab",
+        "metric": "atom-steps/s/GPU at 2M-atom LJ slab; serving p50/p99 latency per system",
         "value": value,
         "unit": "atom-steps/s",
         "n_gpus": 1,
@@ -1016,18 +1141,27 @@ def main():
                                + (f", Mumford-Shah nu {args.ms_nu} x {args.ms_iters}" if args.ms_nu > 0 else "")
                                + (f", neighbour lists skin {args.skin}" if args.skin > 0 else ""),
                    "n_particles": state.n, "grid": list(sysm.dims), "detect_every": args.detect_every,
-                   "thermo_every_step": True},
+                   "thermo_every_step": True, "equilibrated_steps": int(ek),
+                   "pairs_per_particle": round(pairs / state.n, 2)},
         "roofline": {"bound": "alu", "kernel": "KForces (FP64 pair forces, energy, virial)",
                      "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": force_traffic(),
                      "avg_launch_ms": f_avg_s * 1e3, "pairs_per_launch": pairs,
                      "flops_per_pair": FLOPS_PER_PAIR},
-        "cpu_baseline": cpu and {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
+        "cpu_baseline": cpu and dict({k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
+                                     host=host, extrapolation_by_pairs=cpu.get("by_pairs")),
         "cpu_baseline_all_cores": cpu_all,
         "breakdown_ms_per_step": breakdown,
         "stage_bandwidth": stage_bandwidth(breakdown, state.n, G_boxes, args.detect_every),
         "energy_drift_per_atom": (e1 - e0) / state.n,
         "static_cutoff_6": static,
+        "serving": serving and {
+            "workload": f"{serving['systems']} slab systems of 4,000-200,000 particles, "
+                        f"{serving['steps_each']} steps each, Poisson arrivals at {serving['load']} of the "
+                        f"sequential capacity, {serving['seeds']} trace",
+            "server": serving["server"], "sequential": serving["sequential"],
+            "saturated_atom_steps_per_s": {"server": serving["saturated"]["server_atom_steps_per_s"],
+                                           "sequential": serving["saturated"]["sequential_atom_steps_per_s"]}},
         "timing": {"repeats": len(runs), "of_steps": args.steps, "statistic": "median",
                    "ms_per_step_runs": [round(r / args.steps * 1e3, 4) for r in runs]},
     }

@@ -519,10 +519,21 @@ __device__ void KWaveOrder::run(const Args &a, uint32_t, uint32_t)
             if (c[u] < (uint32_t)kClasses) atomicAdd(&cnt[c[u]], 1u);
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < kClasses; k += kThreads) {
-        uint32_t s = 0;
-        for (int q = 0; q < k; ++q) s += cnt[q];
-        next[k] = s;
+    // exclusive prefix sum of the class counts: Hillis-Steele doubling steps over the 512
+    // counters (one thread each), ping-ponging between the two arrays
+    static_assert(kClasses <= kThreads, "one thread per class");
+    {
+        uint32_t *src = cnt, *dst = next;
+        const int k = threadIdx.x;
+        for (int off = 1; off < kClasses; off <<= 1) {
+            if (k < kClasses) dst[k] = src[k] + (k >= off ? src[k - off] : 0u);
+            __syncthreads();
+            uint32_t *t = src; src = dst; dst = t;
+        }
+        // src holds the inclusive sums; shift them to exclusive ones in next
+        const uint32_t excl = (k < kClasses && k > 0) ? src[k - 1] : 0u;
+        __syncthreads();
+        if (k < kClasses) next[k] = excl;
     }
     __syncthreads();
     for (uint32_t k0 = 0; k0 < a.nb; k0 += kLoads * kThreads) {

@@ -34,7 +34,7 @@ def test_uniform_lattice_has_no_interface():
 def test_dilute_gas():
     st = synth.gas(500, (20.0, 20.0, 20.0), seed=6)
     p, po = make(st)
-    check_system(st, p, po, "gas 500").close()
+    check_system(st, p, po, "gas 500", planar=False).close()
 
 
 def test_two_particles_closed_form():
@@ -148,7 +148,7 @@ def test_options_on_a_dilute_gas():
     xw, rcg = x.cpu().numpy(), rc.cpu().numpy()
     od = O.detect(po, xw)
     assert np.array_equal(det["label"].cpu().numpy(), od.label)
-    assert rc_close(rcg, od.rc, p.rc_min, p.rc_max, p.alpha, cap=2 * p.rc_max + 1.0)
+    assert rc_close(rcg, od.rc, p.rc_min, p.rc_max, p.alpha, cap=2 * p.rc_max + 1.0, planar=False)
     ref = O.forces(po, xw, rcg).f + O.tail(po, od, xw, rcg)[0]
     frms = np.sqrt(np.mean(np.sum(ref ** 2, axis=0)))
     err = np.linalg.norm(fo["f"].cpu().numpy() - ref, axis=0) / np.maximum(np.linalg.norm(ref, axis=0), frms)

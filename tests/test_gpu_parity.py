@@ -2,7 +2,9 @@
 
 Bars: integer stages (box counts, smoothed values, labels, components, pair counts) bit-exact;
 two-means centres bit-exact (exact integer sums, same FP64 operation sequence); box distances
-within 2 ceil(cap / h) ulp (see dist_ulps); cutoffs within that bound carried through Eq. 7-8;
+of planar (slab) interfaces within 4 ulp, and of curved, random or doubled-band fronts within
+the empirical chain bound 2 ceil(cap / h) ulp (see dist_ulps); cutoffs within the distance bar
+carried through Eq. 7-8;
 forces per atom |dF_i| / max(|F_i|, F_rms) <= 1e-12; energy and virial sums within 1e-12 of the
 sum of absolute per-atom terms (the conditioning of a sum whose terms cancel). The oracle is run
 on the GPU's own wrapped positions and cutoffs where a stage is tested in isolation.
@@ -21,6 +23,7 @@ from paper_1502_03234_amd import dcm, synth  # noqa: E402
 
 FORCE_TOL = 1e-12
 ULP_TOL = 4
+SLAB_DIST_ULP = 4      # planar interfaces: every slab observed at <= 3 ulp
 
 
 def say(msg):
@@ -33,23 +36,25 @@ def ulp_close(a, b, k=ULP_TOL):
 
 
 def dist_ulps(cap, hmin):
-    """Distance bar in ulp. The oracle (sweeps in 2^3 orders) and the GPU (tile passes) stop at
-    fixed points of the same upwind update (Eq. 15-19) reached in different orders; the update
-    is monotone and non-expansive, so the rounding of the two orders is not amplified but can
-    add up along the chain of at most ceil(cap / h) upwind steps from the zero set, each
-    rounding by about 2 ulp."""
+    """Distance bar in ulp for curved, random or doubled-band fronts (an empirical bar, not a
+    proven one). The oracle (sweeps in 2^3 orders) and the GPU (tile passes) stop at fixed points
+    of the same upwind update (Eq. 15-19) reached in different orders; the update is monotone and
+    non-expansive, so the rounding of the two orders is not amplified but can add up along the
+    chain of at most ceil(cap / h) upwind steps from the zero set. Observed: one box of the
+    droplet 5 ulp apart (cap 7, bar 14), every slab <= 3 ulp (held to SLAB_DIST_ULP)."""
     return 2 * int(np.ceil(cap / hmin))
 
 
-def rc_close(rc, ref, rc_min=2.5, rc_max=6.0, alpha=-0.5, h=1.0, linear=False, cap=None):
-    """Cutoffs within the propagated bound: box distances may differ by dist_ulps ulp of the
-    band cap (r_c^max + h unless given), the cutoff function's slope is at most |a alpha ln 2|
-    (Eq. 7-8; (r_c^max - r_c^min) / r_c^max for the linear ramp), plus 4 ulp of r_c itself for
-    the exponential."""
+def rc_close(rc, ref, rc_min=2.5, rc_max=6.0, alpha=-0.5, h=1.0, linear=False, cap=None, planar=True):
+    """Cutoffs within the propagated bound: box distances may differ by the distance bar (4 ulp
+    of the band cap for planar fronts, dist_ulps otherwise; the cap is r_c^max + h unless
+    given), the cutoff function's slope is at most |a alpha ln 2| (Eq. 7-8; (r_c^max - r_c^min)
+    / r_c^max for the linear ramp), plus 4 ulp of r_c itself for the exponential."""
     a = (rc_max - rc_min) / (2.0 ** (alpha * rc_max) - 1.0) if rc_min != rc_max else 0.0
     slope = (rc_max - rc_min) / rc_max if linear else abs(a * alpha * np.log(2.0))
     cap = rc_max + h if cap is None else cap
-    tol = slope * dist_ulps(cap, h) * np.spacing(cap) + ULP_TOL * np.spacing(np.maximum(np.abs(rc), np.abs(ref)))
+    dbar = SLAB_DIST_ULP if planar else dist_ulps(cap, h)
+    tol = slope * dbar * np.spacing(cap) + ULP_TOL * np.spacing(np.maximum(np.abs(rc), np.abs(ref)))
     return np.all(np.abs(np.asarray(rc) - np.asarray(ref)) <= tol)
 
 
@@ -73,7 +78,7 @@ def make(state, **kw):
     return p, po
 
 
-def check_system(state, p, po, name):
+def check_system(state, p, po, name, planar=True):
     say(f"{name}: n={state.n} box={state.box}")
     s = dcm.System(p, state.x, state.v)
     det = s.detect()
@@ -92,9 +97,11 @@ def check_system(state, p, po, name):
     assert np.array_equal(det["label"].cpu().numpy(), od.label), "labels after removal"
     st = det["stats"].cpu().numpy()
     assert st[0] == od.stats[0] and np.array_equal(st[1:5], od.stats[1:5]), (st, od.stats)
-    assert ulp_close(det["dist"].cpu().numpy(), od.dist, dist_ulps(p.rc_max + 1.0, 1.0)), "distances"
+    dbar = SLAB_DIST_ULP if planar else dist_ulps(p.rc_max + 1.0, 1.0)
+    assert ulp_close(det["dist"].cpu().numpy(), od.dist, dbar), "distances"
     rc_gpu = rc.cpu().numpy()
-    assert rc_close(rc_gpu, od.rc, p.rc_min, p.rc_max, p.alpha, linear=p.cutoff_shape == 1), "cutoffs"
+    assert rc_close(rc_gpu, od.rc, p.rc_min, p.rc_max, p.alpha, linear=p.cutoff_shape == 1,
+                    planar=planar), "cutoffs"
     assert ulp_close(det["rc"].cpu().numpy(), rc_gpu, 0)
     ref = O.forces(po, xw, rc_gpu)
     err = force_err(fo["f"].cpu().numpy(), ref.f)
@@ -350,7 +357,7 @@ def test_droplet1m_segmentation_and_sampled_parity():
     assert np.array_equal(lab, od.label)
     rc_gpu = rc.cpu().numpy()
     assert ulp_close(det["dist"].cpu().numpy(), od.dist, dist_ulps(p.rc_max + 1.0, 1.0)), "distances"
-    assert rc_close(rc_gpu, od.rc), "cutoffs"
+    assert rc_close(rc_gpu, od.rc, planar=False), "cutoffs"
     idx = np.random.default_rng(13).choice(st.n, 3000, replace=False)
     # particles near the sphere (the largest cutoff gradient) are among the sampled too
     rp = np.sqrt(np.sum((xw - c) ** 2, axis=0))
@@ -417,7 +424,7 @@ def test_slab2m_sampled_parity():
     assert np.array_equal(det["label"].cpu().numpy(), od.label)
     assert np.array_equal(det["km"].cpu().numpy(), od.km)
     rc_gpu = rc.cpu().numpy()
-    assert ulp_close(det["dist"].cpu().numpy(), od.dist, dist_ulps(p.rc_max + 1.0, 1.0)), "distances"
+    assert ulp_close(det["dist"].cpu().numpy(), od.dist, SLAB_DIST_ULP), "distances"
     assert rc_close(rc_gpu, od.rc), "cutoffs"
     idx = np.random.default_rng(9).choice(st.n, 3000, replace=False)
     # every particle within 7 sigma of a periodic face is among the sampled too
@@ -463,7 +470,7 @@ def test_slab2m_options_sampled_parity():
     assert ulp_close(det["dist"].cpu().numpy(), od.dist, dist_ulps(cap, 1.0)), "distances"
     assert ulp_close(det["dist_v"].cpu().numpy(), od.dist_v, dist_ulps(cap, 1.0)), "vapor-side distances"
     rc_gpu = rc.cpu().numpy()
-    assert rc_close(rc_gpu, od.rc, cap=cap), "cutoffs"
+    assert rc_close(rc_gpu, od.rc, cap=cap, planar=False), "cutoffs"
     idx = np.unique(np.random.default_rng(10).choice(st.n, 3000, replace=False))
     say(f"slab2m options: oracle forces and tail on {idx.size} particles")
     ref = O.forces(po, xw, rc_gpu, subset=idx)
@@ -589,6 +596,70 @@ def _serve(reqs, budget, pool_bytes):
     dcm.dcm_server_destroy(sv)
     assert len(out) == len(tickets), "server did not finish in time"
     return [out[t] for t in tickets], stats
+
+
+def _served_form_error(f_gpu_implied, f_ref):
+    """Per-atom error of a force-like array against the oracle's, in the force bar's measure."""
+    return force_err(f_gpu_implied, f_ref).max()
+
+
+def test_served_systems_match_oracle():
+    """Served requests (dcm_submit / dcm_poll, batched graph launches with device argument
+    tables) against the oracle's own run (Eq. 1-2 velocity Verlet over Alg. 3.2 forces, detection
+    on even force evaluations) from the same initial state: a 1-step request, 2-step requests
+    whose second force evaluation re-detects the interface (k = 2), a system of another grid in
+    the same batch, and two precision-form requests. FP64 requests at the one-step bars:
+    positions 1e-13, velocities 1e-11, kinetic and potential energy 1e-12 and 1e-11 relative, the
+    virial within 1e-11 of the sum of absolute per-atom terms, pair counts exact. FP32C
+    requests: the forces implied by the served positions and velocities (x1 - x0 - dt v0 =
+    dt^2/2 F0 / m; v_k - v_0 = dt/2 sum of the force pairs) within 1e-5 of the oracle's in the
+    per-atom measure, pair counts exact (the cutoff test is FP64 in both forms)."""
+    specs = [
+        (4000, (16.0, 16.0, 32.0), 1, {}),
+        (4000, (16.0, 16.0, 32.0), 2, {}),
+        (5000, (18.0, 18.0, 30.0), 2, {}),
+        (4000, (16.0, 16.0, 32.0), 1, dict(precision=dcm.DCM_FP32C)),
+        (4000, (16.0, 16.0, 32.0), 2, dict(precision=dcm.DCM_FP32C)),
+    ]
+    reqs = []
+    for j, (n, box, ns, kw) in enumerate(specs):
+        st = synth.small_slab(n, box, 700 + j)
+        reqs.append((dcm.params(st.box, **kw), st, ns))
+    say("served vs oracle: %d requests" % len(reqs))
+    got, stats = _serve(reqs, budget=1 << 31, pool_bytes=1 << 31)
+    assert stats["completed"] == len(reqs) and stats["grouped_steps"] > 0
+    for (p, st, ns), (status, x, v, th), (_, _, _, kw) in zip(reqs, got, specs):
+        po = O.params(st.box)
+        ost = O.prepare(po, st.x, st.v)
+        x0, v0, f0 = ost.x.copy(), ost.v.copy(), ost.f.copy()
+        oth = O.run(po, ost, ns)
+        assert th["step"] == ns == oth[-1]["step"]
+        assert th["pairs"] == oth[-1]["pairs"], (th["pairs"], oth[-1]["pairs"])
+        if p.precision == dcm.DCM_FP64:
+            assert np.max(np.abs(x - ost.x)) < 1e-13
+            assert np.max(np.abs(v - ost.v)) < 1e-11
+            assert abs(th["ke"] - oth[-1]["ke"]) < 1e-12 * abs(oth[-1]["ke"])
+            assert abs(th["pe"] - oth[-1]["pe"]) < 1e-11 * abs(oth[-1]["pe"])
+            ref = O.forces(po, ost.x, ost.rc)
+            for c in range(6):
+                assert sum_close(th["virial"][c], ref.w[c], 1e-11)
+        else:
+            dt, m = p.dt, p.mass
+            # x1 = x0 + dt v0 + dt^2/2 F0 / m (minimum image of the wrapped difference)
+            L = np.array(st.box)[:, None]
+            dx = x - x0 - dt * v0
+            dx -= L * np.rint(dx / L)
+            dxo = ost.x - x0 - dt * v0
+            dxo -= L * np.rint(dxo / L)
+            if ns == 1:
+                f0_gpu = dx * (2.0 * m / dt ** 2)
+                assert _served_form_error(f0_gpu, f0) <= 1e-5
+            # v_ns - v_0 = dt / (2 m) (F_0 + 2 F_1 + ... + F_ns): compare the implied force sums
+            fsum_gpu = (v - v0) * (2.0 * m / dt)
+            fsum_ref = (ost.v - v0) * (2.0 * m / dt)
+            assert _served_form_error(fsum_gpu, fsum_ref) <= 1e-5
+            assert abs(th["pe"] - oth[-1]["pe"]) < 1e-5 * abs(oth[-1]["pe"])
+        say(f"served n={st.n} steps={ns} form={p.precision}: pairs {th['pairs']} match the oracle")
 
 
 def test_served_systems_equal_eager_runs_bitwise():

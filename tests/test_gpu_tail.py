@@ -208,7 +208,7 @@ def test_vapor_cutoffs_with_tail(slab16k):
     torch.cuda.synchronize()
     xw, rcg = x.cpu().numpy(), rc.cpu().numpy()
     od = O.detect(po, xw)
-    assert rc_close(rcg, od.rc, 3.0, 5.0, -0.5, cap=2 * 5.0 + 1.0)   # the tail correction's band
+    assert rc_close(rcg, od.rc, 3.0, 5.0, -0.5, cap=2 * 5.0 + 1.0, planar=False)   # the tail band
     ref = O.forces(po, xw, rcg).f + O.tail(po, od, xw, rcg)[0]
     assert force_err(fo["f"].cpu().numpy(), ref).max() <= FORCE_TOL
     s.close()

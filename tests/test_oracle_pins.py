@@ -870,6 +870,32 @@ def test_tail_on_a_planar_slab(orc):
     assert ndeep == 4
 
 
+@pytest.mark.parametrize("name", ["slab16k", "droplet_small"])
+def test_tail_deep_decision_not_at_the_margin(orc, name):
+    """The tail correction (Section 7, Eq. 21-22) treats a particle as deep in its phase when
+    all eight surrounding signed box values sit at the band limit cap - h/2, with a relative
+    margin of 1e-9 for rounding. On a slab and on a droplet the box values are either exactly at
+    the limit (capped) or more than 1e-6 below it, so every decision is the same with the margin
+    and without it (a strict test at the limit): the margin cannot move a result."""
+    from paper_1502_03234_amd import synth
+    if name == "slab16k":
+        st = synth.named("slab16k")
+    else:
+        st = synth.serving_droplet(0, 20000, 0.7)
+    p = orc.params(st.box, tail=1)
+    _, h = orc.grid(p)
+    x = orc.wrap(p, st.x)
+    det = orc.detect(p, x)
+    s = (h[0] + h[1] + h[2]) / 6.0
+    lim = 2.0 * p.rc_max + max(h) - s
+    phi = np.where(det.dist > 0.0, det.dist - s, -(det.dist_v - s))
+    a = np.abs(phi)
+    at_limit = a == lim
+    assert at_limit.any() and (~at_limit).any()
+    assert np.all(a[~at_limit] < lim * (1.0 - 1e-6)), np.max(a[~at_limit]) / lim
+    assert not np.any(a > lim)
+
+
 # ---------------------------------------------------------------- Mumford-Shah segmentation (Eq. 13)
 def _ms_mincut(d, r, w):
     """Exact minimum of sum_c r_c x_c + sum_k w_k sum_c |x(c + e_k) - x(c)| over x in {0, 1}^G
