@@ -100,7 +100,7 @@ def cpu_baseline(state, sample: int, seed: int = 12345, total_pairs: float | Non
     t_int = time.perf_counter() - t0
     per_step = t_f + 0.5 * t_det + t_int
     out = dict(value=state.n / per_step, unit="atom-steps/s", cores=1, kind="oracle",
-               sample=(f"slab2m: detection on all {state.n} particles (x1/2 per step), forces "
+               sample=(f"slab2m, the state the GPU timing starts from: detection on all {state.n} particles (x1/2 per step), forces "
                        f"for {sample} seeded random particles scaled to {state.n}, one full "
                        f"integration update; {per_step:.1f} s per step"),
                seconds=dict(detect=t_det, forces_sample=t_sample, forces_scaled=t_f, integrate=t_int))
@@ -137,32 +137,38 @@ def host_cpu() -> dict:
     return {"model": model, "nproc": os.cpu_count() or 1, "usable": usable}
 
 
-def cpu_workers_start(state, sample: int, procs: int):
-    """Starts `procs` oracle processes (bench.py --cpu-worker) before this process touches the
-    GPU, so that no process holding a GPU context forks. Each loads the state from a file and
-    then waits on its stdin; cpu_workers_collect releases them once the GPU timing is over, so
-    that they do not compete with it for host cores."""
-    import subprocess
+def save_state(state, x, v):
+    """Writes a state (positions and velocities in caller order) for the oracle workers."""
     import tempfile
     import numpy as np
     fd, path = tempfile.mkstemp(suffix=".npz", dir="/dev/shm" if os.path.isdir("/dev/shm") else None)
     os.close(fd)
-    np.savez(path, x=state.x, v=state.v, box=np.array(state.box))
+    np.savez(path, x=x, v=v, box=np.array(state.box))
+    return path
+
+
+def cpu_workers_start(sample: int, procs: int):
+    """Starts `procs` oracle processes (bench.py --cpu-worker) before this process touches the
+    GPU, so that no process holding a GPU context forks. Each waits on its stdin for the path of
+    the state to run on; cpu_workers_collect sends it once the GPU timing is over, so that they
+    do not compete with it for host cores and work on the state the GPU timing measured."""
+    import subprocess
     workers = []
     for k in range(procs):
         workers.append(subprocess.Popen(
-            [sys.executable, os.path.abspath(__file__), "--cpu-worker", path, "--cpu-sample", str(sample),
+            [sys.executable, os.path.abspath(__file__), "--cpu-worker", "stdin", "--cpu-sample", str(sample),
              "--cpu-seed", str(12345 + k)],
             stdin=subprocess.PIPE, stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True))
-    return {"path": path, "workers": workers}
+    return {"workers": workers}
 
 
-def cpu_workers_collect(handle, timeout_s: float = 600.0):
-    """Releases the workers at once and sums their throughput: the host's aggregate figure."""
+def cpu_workers_collect(handle, path: str, timeout_s: float = 600.0):
+    """Releases the workers at once on the state in `path` and sums their throughput: the
+    host's aggregate figure."""
     ws = handle["workers"]
     try:
         for w in ws:
-            w.stdin.write("go\n")
+            w.stdin.write(path + "\n")
             w.stdin.flush()
         vals = []
         for w in ws:
@@ -173,20 +179,20 @@ def cpu_workers_collect(handle, timeout_s: float = 600.0):
             if w.poll() is None:
                 w.kill()
                 w.wait()
-        os.unlink(handle["path"])
     return dict(value=float(sum(vals)), unit="atom-steps/s", cores=len(ws), kind="oracle",
                 sample=f"{len(ws)} independent oracle processes at once, each on the single-core sample")
 
 
-def cpu_worker_main(path: str, sample: int, seed: int):
+def cpu_worker_main(sample: int, seed: int):
     """One oracle copy of the bounded sample, started by cpu_workers_start; it never touches
-    the GPU. Waits for the go line, runs, prints one JSON line."""
+    the GPU. Waits for the path of the state on its stdin, runs, prints one JSON line."""
     import numpy as np
     from types import SimpleNamespace
+    path = sys.stdin.readline().strip()
+    if not path:
+        return
     d = np.load(path)
     st = SimpleNamespace(x=d["x"], v=d["v"], box=tuple(float(b) for b in d["box"]), n=d["x"].shape[1])
-    if sys.stdin.readline().strip() != "go":
-        return
     print(json.dumps({"value": cpu_baseline(st, sample, seed)["value"]}), flush=True)
 
 
@@ -976,7 +982,7 @@ def main():
               "decomposition; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.cpu_worker:
-        cpu_worker_main(args.cpu_worker, args.cpu_sample, args.cpu_seed)
+        cpu_worker_main(args.cpu_sample, args.cpu_seed)
         return
     from paper_1502_03234_amd import synth
 
@@ -994,7 +1000,7 @@ def main():
     workers = None
     if not args.no_cpu_baseline and not profiled and share > 1:
         log(f"cpu baseline: starting {share} oracle processes (released after the GPU timing)")
-        workers = cpu_workers_start(state, args.cpu_sample, share)
+        workers = cpu_workers_start(args.cpu_sample, share)
 
     import torch
     from paper_1502_03234_amd import dcm
@@ -1031,6 +1037,9 @@ def main():
     ex, ev, erc, ek = eq.state()
     torch.cuda.synchronize()
     eq.close()
+    from types import SimpleNamespace
+    # the state the timed runs start from, for the oracle's CPU baseline
+    cpu_state = SimpleNamespace(x=ex.cpu().numpy(), v=ev.cpu().numpy(), box=state.box, n=state.n)
     runs = []
     f_ms = 0.0
     f_cnt = 0
@@ -1111,10 +1120,14 @@ def main():
     cpu = cpu_all = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on a sample of {args.cpu_sample} particles")
-        cpu = cpu_baseline(state, args.cpu_sample, total_pairs=pairs)
+        cpu = cpu_baseline(cpu_state, args.cpu_sample, total_pairs=pairs)
         if workers is not None:
             log(f"cpu baseline: releasing {share} oracle processes at once")
-            cpu_all = cpu_workers_collect(workers)
+            path = save_state(state, cpu_state.x, cpu_state.v)
+            try:
+                cpu_all = cpu_workers_collect(workers, path)
+            finally:
+                os.unlink(path)
         elif profiled:
             cpu_all = {"skipped": "a profiler tool is loaded into this process; child processes "
                                   "would inherit it"}
