@@ -240,6 +240,83 @@ __device__ __forceinline__ void scan_interval(const ForceArgs &a, __amdgpu_buffe
         scan<PAIR, SHIFT, false, U, A>(a, rs, q, jb, je, sx, sy, sz, c);
 }
 
+// The slots of one force row that a wave's lanes scan, staged in LDS. Reading candidate
+// positions lane by lane from global memory costs the vector-memory data path a cache line per
+// lane and candidate (the lanes' windows are offset from each other), and that path, not the
+// arithmetic, bounds the traversal. The wave instead loads the union of its lanes' x-intervals of
+// a row once, coalesced, into LDS (coordinates in separate arrays, so that neighbouring lanes
+// read neighbouring words), and the lanes read their candidates from there.
+constexpr uint32_t kStageSlots = 192;
+struct Stage {
+    double x[kStageSlots], y[kStageSlots], z[kStageSlots], w[kStageSlots];
+};
+
+template <int PAIR, bool SHIFT, bool IMAGE, int U, typename A>
+__device__ __forceinline__ void scan_staged(const ForceArgs &a, const Stage &sg, uint32_t lo, const Particle &q,
+                                            uint32_t jb, uint32_t je, double sx, double sy, double sz, A &c)
+{
+    const uint32_t len = je - jb;
+    const uint32_t o = len ? jb - lo : 0u;
+    for (uint32_t t = 0; __any(t < len); t += U) {
+        double4 p[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t k = min(o + t + (uint32_t)u, kStageSlots - 1u);
+            p[u].x = sg.x[k];
+            p[u].y = sg.y[k];
+            p[u].z = sg.z[k];
+            p[u].w = PAIR == DCM_PAIR_MAX ? sg.w[k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            interact<PAIR, SHIFT, IMAGE>(a, p[u], t + u < len && jb + t + u != (uint32_t)q.i, q.x, q.y, q.z, q.rc,
+                                         q.rc2, sx, sy, sz, c, jb + t + u);
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_min_u(uint32_t v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ uint32_t wave_max_u(uint32_t v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Slot range [jb, je) of every lane, from LDS when the lanes' ranges lie in one window of at
+// most kStageSlots slots (the usual case: the wave's lanes share a force row), else directly.
+template <int PAIR, bool SHIFT, int U, typename A>
+__device__ __forceinline__ void scan_row(const ForceArgs &a, __amdgpu_buffer_rsrc_t rs, Stage &sg, const Particle &q,
+                                         uint32_t jb, uint32_t je, double sx, double sy, double sz, A &c)
+{
+    const bool has = jb < je;
+    const uint32_t lo = wave_min_u(has ? jb : 0xFFFFFFFFu);
+    const uint32_t hi = wave_max_u(has ? je : 0u);
+    if (hi <= lo) return;
+    if (hi - lo > kStageSlots) {
+        scan_interval<PAIR, SHIFT, U, A>(a, rs, q, jb, je, sx, sy, sz, c);
+        return;
+    }
+    const uint32_t lane = threadIdx.x & 63u;
+    for (uint32_t k = lane; k < hi - lo; k += 64u) {
+        const double4 p = load_pos<PAIR>(rs, lo + k);
+        sg.x[k] = p.x;
+        sg.y[k] = p.y;
+        sg.z[k] = p.z;
+        if (PAIR == DCM_PAIR_MAX) sg.w[k] = p.w;
+    }
+    __syncthreads();
+    const bool image = has && (sx != 0.0 || sy != 0.0 || sz != 0.0);
+    if (__any(image))
+        scan_staged<PAIR, SHIFT, true, U, A>(a, sg, lo, q, jb, je, sx, sy, sz, c);
+    else
+        scan_staged<PAIR, SHIFT, false, U, A>(a, sg, lo, q, jb, je, sx, sy, sz, c);
+    __syncthreads();
+}
+
 __device__ __forceinline__ int wave_min(int v)
 {
     for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
@@ -259,7 +336,8 @@ __device__ __forceinline__ int wave_max(int v)
 // together and their windows overlap. Each lane visits exactly its own rows, in increasing z,
 // then y, then x.
 template <int PAIR, bool SHIFT, int U, typename A>
-__device__ __forceinline__ void traverse(const ForceArgs &a, bool live, const Particle &q, double rc_max, A &c)
+__device__ __forceinline__ void traverse(const ForceArgs &a, bool live, const Particle &q, double rc_max, A &c,
+                                         Stage *sg = nullptr)
 {
     const Grid &g = a.grid;
     // search radius (slightly enlarged so that rounding in the box bounds never drops a box
@@ -323,7 +401,8 @@ __device__ __forceinline__ void traverse(const ForceArgs &a, bool live, const Pa
                     e1 = a.cell_start[(row + (uint32_t)hi1 + 1u) << gs];
                 }
             }
-            scan_interval<PAIR, SHIFT, U, A>(a, pb, q, b0, e0, sx0, sy, sz, c);
+            if (sg) scan_row<PAIR, SHIFT, U, A>(a, pb, *sg, q, b0, e0, sx0, sy, sz, c);
+            else scan_interval<PAIR, SHIFT, U, A>(a, pb, q, b0, e0, sx0, sy, sz, c);
             if (__any(b1 < e1)) scan_interval<PAIR, SHIFT, U, A>(a, pb, q, b1, e1, sx1, sy, sz, c);
         }
     }
@@ -399,13 +478,18 @@ __device__ void KForces<PAIR, SHIFT, U, PREC, LIST>::run(const Args &args_, uint
     const bool live = have && sane;
     // every lane of the wave takes part in the (wave-uniform) traversal
     Acc c = {};
+    Stage *stage = nullptr;
+    if constexpr (!LIST) {
+        __shared__ Stage st;
+        stage = &st;
+    }
     if (PREC == DCM_FP64) {
         if (LIST) list_scan<SHIFT, U, Acc>(a, live, q, c);
-        else traverse<PAIR, SHIFT, U, Acc>(a, live, q, rc_max, c);
+        else traverse<PAIR, SHIFT, U, Acc>(a, live, q, rc_max, c, stage);
     } else {
         Acc32 c32 = {};
         if (LIST) list_scan<SHIFT, U, Acc32>(a, live, q, c32);
-        else traverse<PAIR, SHIFT, U, Acc32>(a, live, q, rc_max, c32);
+        else traverse<PAIR, SHIFT, U, Acc32>(a, live, q, rc_max, c32, stage);
         // FP32 sums and their compensation terms, combined in FP64
         c.fx = (double)c32.fx + (double)c32.cfx;
         c.fy = (double)c32.fy + (double)c32.cfy;
