@@ -23,6 +23,7 @@
 // accumulated per particle, reduced per workgroup in a fixed order, and the workgroup partials
 // are summed in a fixed order by the reduction kernel.
 #include <climits>
+#include <type_traits>
 
 #include "internal.h"
 #include "launch.h"
@@ -48,9 +49,20 @@ __device__ __forceinline__ int floor_mul(double v, double inv_h) { return (int)f
 // Conservative square root for box bounds: the hardware estimate, enlarged well past its error.
 __device__ __forceinline__ double sqrt_up(double v) { return __builtin_amdgcn_sqrt(v) * (1.0 + 1e-6) + 1e-9; }
 
+// FP64 form. The pair loop accumulates the force and the virial in units of 24 eps (the factor
+// is applied once per particle) and, in place of the energy, the sum of (sigma/r)^6: with
+// u = (sigma/r)^6 (2 (sigma/r)^6 - 1) the force scalar is 24 eps u / r^2, so the trace of the
+// virial sum is sum u (up to rounding), and sum ((sigma/r)^12 - (sigma/r)^6) = (sum u - sum
+// (sigma/r)^6) / 2 gives the energy without a per-pair term of its own.
 struct Acc {
     double fx, fy, fz, e, wxx, wyy, wzz, wxy, wxz, wyz, eshift;
     uint32_t pairs;
+};
+
+// The same, counting pairs per wave (a scalar) instead of per lane: used when no per-particle
+// pair count is needed (no per-particle outputs, no per-pair energy shift of the r_c[i] rule).
+struct AccLean : Acc {
+    uint32_t wave_pairs;
 };
 
 // Precision form: FP32 running sums with their TwoSum error terms (force, energy), plain FP32
@@ -97,12 +109,12 @@ __device__ __forceinline__ void interact(const ForceArgs &a, const double4 pj, b
         double inv = rcp_refined(r2);
         double sr2 = a.sigma2 * inv;
         double sr6 = sr2 * sr2 * sr2;
-        double fr = a.eps24 * sr6 * fma(2.0, sr6, -1.0) * inv;
+        double fr = sr6 * fma(2.0, sr6, -1.0) * inv;     // force scalar / (24 eps)
         double fxp = fr * dx, fyp = fr * dy, fzp = fr * dz;
         c.fx += fxp;
         c.fy += fyp;
         c.fz += fzp;
-        c.e += fma(sr6, sr6, -sr6);
+        c.e += sr6;
         c.wxx = fma(dx, fxp, c.wxx);
         c.wyy = fma(dy, fyp, c.wyy);
         c.wzz = fma(dz, fzp, c.wzz);
@@ -110,6 +122,46 @@ __device__ __forceinline__ void interact(const ForceArgs &a, const double4 pj, b
         c.wxz = fma(dx, fzp, c.wxz);
         c.wyz = fma(dy, fzp, c.wyz);
         c.pairs += 1;
+        if (SHIFT && PAIR == DCM_PAIR_MAX) {
+            double s2 = a.sigma2 / lim2;
+            double s6 = s2 * s2 * s2;
+            c.eshift += fma(s6, s6, -s6);
+        }
+    }
+}
+
+template <int PAIR, bool SHIFT, bool IMAGE>
+__device__ __forceinline__ void interact(const ForceArgs &a, const double4 pj, bool valid,
+                                         double xi, double yi, double zi, double rci, double rc2,
+                                         double sx, double sy, double sz, AccLean &c, uint32_t)
+{
+    double dx = IMAGE ? xi - (pj.x + sx) : xi - pj.x;
+    double dy = IMAGE ? yi - (pj.y + sy) : yi - pj.y;
+    double dz = IMAGE ? zi - (pj.z + sz) : zi - pj.z;
+    double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    double lim2 = rc2;
+    if (PAIR == DCM_PAIR_MAX) {
+        double rcp = pj.w > rci ? pj.w : rci;
+        lim2 = rcp * rcp;
+    }
+    const bool in = valid && r2 < lim2;
+    c.wave_pairs += (uint32_t)__builtin_popcountll(__ballot(in));
+    if (in) {
+        double inv = rcp_refined(r2);
+        double sr2 = a.sigma2 * inv;
+        double sr6 = sr2 * sr2 * sr2;
+        double fr = sr6 * fma(2.0, sr6, -1.0) * inv;     // force scalar / (24 eps)
+        double fxp = fr * dx, fyp = fr * dy, fzp = fr * dz;
+        c.fx += fxp;
+        c.fy += fyp;
+        c.fz += fzp;
+        c.e += sr6;
+        c.wxx = fma(dx, fxp, c.wxx);
+        c.wyy = fma(dy, fyp, c.wyy);
+        c.wzz = fma(dz, fzp, c.wzz);
+        c.wxy = fma(dx, fyp, c.wxy);
+        c.wxz = fma(dx, fzp, c.wxz);
+        c.wyz = fma(dy, fzp, c.wyz);
         if (SHIFT && PAIR == DCM_PAIR_MAX) {
             double s2 = a.sigma2 / lim2;
             double s6 = s2 * s2 * s2;
@@ -247,8 +299,10 @@ __device__ __forceinline__ void scan_interval(const ForceArgs &a, __amdgpu_buffe
 // a row once, coalesced, into LDS (coordinates in separate arrays, so that neighbouring lanes
 // read neighbouring words), and the lanes read their candidates from there.
 constexpr uint32_t kStageSlots = 192;
+constexpr uint32_t kStagePad = 4;          // the candidate unroll reads up to U - 1 slots past
 struct Stage {
-    double x[kStageSlots], y[kStageSlots], z[kStageSlots], w[kStageSlots];
+    double x[kStageSlots + kStagePad], y[kStageSlots + kStagePad], z[kStageSlots + kStagePad],
+        w[kStageSlots + kStagePad];
 };
 
 template <int PAIR, bool SHIFT, bool IMAGE, int U, typename A>
@@ -257,34 +311,44 @@ __device__ __forceinline__ void scan_staged(const ForceArgs &a, const Stage &sg,
 {
     const uint32_t len = je - jb;
     const uint32_t o = len ? jb - lo : 0u;
+    // the particle's own slot as an offset into the interval (past its end if not in it)
+    const uint32_t self = (uint32_t)q.i - jb;
     for (uint32_t t = 0; __any(t < len); t += U) {
+        // one clamped index per iteration; the stage has U - 1 slots of padding
+        const uint32_t k = min(o + t, kStageSlots);
         double4 p[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint32_t k = min(o + t + (uint32_t)u, kStageSlots - 1u);
-            p[u].x = sg.x[k];
-            p[u].y = sg.y[k];
-            p[u].z = sg.z[k];
-            p[u].w = PAIR == DCM_PAIR_MAX ? sg.w[k] : 0.0;
+            p[u].x = sg.x[k + u];
+            p[u].y = sg.y[k + u];
+            p[u].z = sg.z[k + u];
+            p[u].w = PAIR == DCM_PAIR_MAX ? sg.w[k + u] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            interact<PAIR, SHIFT, IMAGE>(a, p[u], t + u < len && jb + t + u != (uint32_t)q.i, q.x, q.y, q.z, q.rc,
-                                         q.rc2, sx, sy, sz, c, jb + t + u);
+            interact<PAIR, SHIFT, IMAGE>(a, p[u], t + u < len && t + u != self, q.x, q.y, q.z, q.rc, q.rc2, sx, sy,
+                                         sz, c, jb + t + u);
     }
 }
 
-__device__ __forceinline__ uint32_t wave_min_u(uint32_t v)
+// Wave-wide minimum / maximum with DPP lane moves (rows of 16 lanes by shifts, then row
+// broadcasts; lane 63 ends with the result). Every lane of the wave must be active.
+template <bool MAX>
+__device__ __forceinline__ uint32_t wave_reduce_u(uint32_t v)
 {
-    for (int off = 32; off > 0; off >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off, 64));
-    return __builtin_amdgcn_readfirstlane(v);
+    const uint32_t id = MAX ? 0u : 0xFFFFFFFFu;
+    auto op = [](uint32_t x, uint32_t y) { return MAX ? max(x, y) : min(x, y); };
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)v, 0x111, 0xf, 0xf, false));   // row_shr:1
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)v, 0x112, 0xf, 0xf, false));   // row_shr:2
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)v, 0x114, 0xf, 0xf, false));   // row_shr:4
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)v, 0x118, 0xf, 0xf, false));   // row_shr:8
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)v, 0x142, 0xa, 0xf, false));   // row_bcast:15
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)v, 0x143, 0xc, 0xf, false));   // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-__device__ __forceinline__ uint32_t wave_max_u(uint32_t v)
-{
-    for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
-    return __builtin_amdgcn_readfirstlane(v);
-}
+__device__ __forceinline__ uint32_t wave_min_u(uint32_t v) { return wave_reduce_u<false>(v); }
+__device__ __forceinline__ uint32_t wave_max_u(uint32_t v) { return wave_reduce_u<true>(v); }
 
 // Slot range [jb, je) of every lane, from LDS when the lanes' ranges lie in one window of at
 // most kStageSlots slots (the usual case: the wave's lanes share a force row), else directly.
@@ -441,8 +505,16 @@ __device__ __forceinline__ void list_scan(const ForceArgs &a, bool live, const P
     }
 }
 
-// Compiled for 4 waves per SIMD (128 VGPRs per lane).
-template <int PAIR, bool SHIFT, int U, int PREC, bool LIST = false>
+template <typename A>
+__device__ __forceinline__ long long wave_pairs_of(const A &c)
+{
+    if constexpr (std::is_same<A, AccLean>::value) return (long long)c.wave_pairs;
+    else return 0;
+}
+
+// Compiled for 4 waves per SIMD (128 VGPRs per lane). LEAN counts pairs per wave (no per-particle
+// outputs and no per-pair energy shift of the r_c[i] rule may be asked for).
+template <int PAIR, bool SHIFT, int U, int PREC, bool LIST = false, bool LEAN = false>
 struct KForces {
     static constexpr int kThreads = kForceBlock, kWaves = 4;
     struct Args {
@@ -452,9 +524,10 @@ struct KForces {
     static __device__ void run(const Args &args_, uint32_t blk, uint32_t);
 };
 
-template <int PAIR, bool SHIFT, int U, int PREC, bool LIST>
-__device__ void KForces<PAIR, SHIFT, U, PREC, LIST>::run(const Args &args_, uint32_t blk, uint32_t nblk)
+template <int PAIR, bool SHIFT, int U, int PREC, bool LIST, bool LEAN>
+__device__ void KForces<PAIR, SHIFT, U, PREC, LIST, LEAN>::run(const Args &args_, uint32_t blk, uint32_t nblk)
 {
+    static_assert(!LEAN || (PREC == DCM_FP64 && !(SHIFT && PAIR == DCM_PAIR_I)), "lean variant");
     const ForceArgs &a = args_.a;
     const double rc_max = args_.rc_max;
     // the wave this workgroup takes: longest (in the last launch) first, so that the waves
@@ -477,15 +550,23 @@ __device__ void KForces<PAIR, SHIFT, U, PREC, LIST>::run(const Args &args_, uint
     const bool sane = isfinite(q.x) && isfinite(q.y) && isfinite(q.z) && q.rc > 0.0 && q.rc <= rc_max;
     const bool live = have && sane;
     // every lane of the wave takes part in the (wave-uniform) traversal
-    Acc c = {};
+    typedef typename std::conditional<LEAN, AccLean, Acc>::type AccT;
+    AccT c = {};
     Stage *stage = nullptr;
     if constexpr (!LIST) {
         __shared__ Stage st;
         stage = &st;
     }
     if (PREC == DCM_FP64) {
-        if (LIST) list_scan<SHIFT, U, Acc>(a, live, q, c);
-        else traverse<PAIR, SHIFT, U, Acc>(a, live, q, rc_max, c, stage);
+        if (LIST) list_scan<SHIFT, U, AccT>(a, live, q, c);
+        else traverse<PAIR, SHIFT, U, AccT>(a, live, q, rc_max, c, stage);
+        // the pair loop's units (see Acc): forces and virial times 24 eps; sum ((sigma/r)^12 -
+        // (sigma/r)^6) from the virial trace and the sum of (sigma/r)^6
+        const double esum = 0.5 * ((c.wxx + c.wyy + c.wzz) - c.e);
+        c.fx *= a.eps24; c.fy *= a.eps24; c.fz *= a.eps24;
+        c.wxx *= a.eps24; c.wyy *= a.eps24; c.wzz *= a.eps24;
+        c.wxy *= a.eps24; c.wxz *= a.eps24; c.wyz *= a.eps24;
+        c.e = esum;
     } else {
         Acc32 c32 = {};
         if (LIST) list_scan<SHIFT, U, Acc32>(a, live, q, c32);
@@ -540,7 +621,9 @@ __device__ void KForces<PAIR, SHIFT, U, PREC, LIST>::run(const Args &args_, uint
 #pragma unroll
     for (int q = 0; q < 7; ++q)
         for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
-    for (int off = 32; off > 0; off >>= 1) pc += __shfl_xor(pc, off, 64);
+    if constexpr (LEAN) pc = wave_pairs_of(c);
+    else
+        for (int off = 32; off > 0; off >>= 1) pc += __shfl_xor(pc, off, 64);
     __shared__ double lds[kForceBlock / 64][8];
     __shared__ long long ldp[kForceBlock / 64];
     const int w = threadIdx.x >> 6;
@@ -680,11 +763,14 @@ static void launch_prec(const ForceArgs &a, int nb, hipStream_t st)
         else emit<KForces<DCM_PAIR_I, false, U, PREC, true>>({a, a.rc_max}, blocks, st);
         return;
     }
+    const bool per_particle = a.e_out || a.w_out || a.pairs_out;
     if (a.pair_rule == DCM_PAIR_MAX) {
         if (a.energy_shift) emit<KForces<DCM_PAIR_MAX, true, U, PREC>>({a, a.rc_max}, blocks, st);
         else emit<KForces<DCM_PAIR_MAX, false, U, PREC>>({a, a.rc_max}, blocks, st);
     } else {
         if (a.energy_shift) emit<KForces<DCM_PAIR_I, true, U, PREC>>({a, a.rc_max}, blocks, st);
+        else if (PREC == DCM_FP64 && !per_particle)
+            emit<KForces<DCM_PAIR_I, false, U, DCM_FP64, false, true>>({a, a.rc_max}, blocks, st);
         else emit<KForces<DCM_PAIR_I, false, U, PREC>>({a, a.rc_max}, blocks, st);
     }
 }
