@@ -59,11 +59,6 @@ struct Acc {
     uint32_t pairs;
 };
 
-// The same, counting pairs per wave (a scalar) instead of per lane: used when no per-particle
-// pair count is needed (no per-particle outputs, no per-pair energy shift of the r_c[i] rule).
-struct AccLean : Acc {
-    uint32_t wave_pairs;
-};
 
 // Precision form: FP32 running sums with their TwoSum error terms (force, energy), plain FP32
 // virial sums.
@@ -122,46 +117,6 @@ __device__ __forceinline__ void interact(const ForceArgs &a, const double4 pj, b
         c.wxz = fma(dx, fzp, c.wxz);
         c.wyz = fma(dy, fzp, c.wyz);
         c.pairs += 1;
-        if (SHIFT && PAIR == DCM_PAIR_MAX) {
-            double s2 = a.sigma2 / lim2;
-            double s6 = s2 * s2 * s2;
-            c.eshift += fma(s6, s6, -s6);
-        }
-    }
-}
-
-template <int PAIR, bool SHIFT, bool IMAGE>
-__device__ __forceinline__ void interact(const ForceArgs &a, const double4 pj, bool valid,
-                                         double xi, double yi, double zi, double rci, double rc2,
-                                         double sx, double sy, double sz, AccLean &c, uint32_t)
-{
-    double dx = IMAGE ? xi - (pj.x + sx) : xi - pj.x;
-    double dy = IMAGE ? yi - (pj.y + sy) : yi - pj.y;
-    double dz = IMAGE ? zi - (pj.z + sz) : zi - pj.z;
-    double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    double lim2 = rc2;
-    if (PAIR == DCM_PAIR_MAX) {
-        double rcp = pj.w > rci ? pj.w : rci;
-        lim2 = rcp * rcp;
-    }
-    const bool in = valid && r2 < lim2;
-    c.wave_pairs += (uint32_t)__builtin_popcountll(__ballot(in));
-    if (in) {
-        double inv = rcp_refined(r2);
-        double sr2 = a.sigma2 * inv;
-        double sr6 = sr2 * sr2 * sr2;
-        double fr = sr6 * fma(2.0, sr6, -1.0) * inv;     // force scalar / (24 eps)
-        double fxp = fr * dx, fyp = fr * dy, fzp = fr * dz;
-        c.fx += fxp;
-        c.fy += fyp;
-        c.fz += fzp;
-        c.e += sr6;
-        c.wxx = fma(dx, fxp, c.wxx);
-        c.wyy = fma(dy, fyp, c.wyy);
-        c.wzz = fma(dz, fzp, c.wzz);
-        c.wxy = fma(dx, fyp, c.wxy);
-        c.wxz = fma(dx, fzp, c.wxz);
-        c.wyz = fma(dy, fzp, c.wyz);
         if (SHIFT && PAIR == DCM_PAIR_MAX) {
             double s2 = a.sigma2 / lim2;
             double s6 = s2 * s2 * s2;
@@ -505,16 +460,8 @@ __device__ __forceinline__ void list_scan(const ForceArgs &a, bool live, const P
     }
 }
 
-template <typename A>
-__device__ __forceinline__ long long wave_pairs_of(const A &c)
-{
-    if constexpr (std::is_same<A, AccLean>::value) return (long long)c.wave_pairs;
-    else return 0;
-}
-
-// Compiled for 4 waves per SIMD (128 VGPRs per lane). LEAN counts pairs per wave (no per-particle
-// outputs and no per-pair energy shift of the r_c[i] rule may be asked for).
-template <int PAIR, bool SHIFT, int U, int PREC, bool LIST = false, bool LEAN = false>
+// Compiled for 4 waves per SIMD (128 VGPRs per lane).
+template <int PAIR, bool SHIFT, int U, int PREC, bool LIST = false>
 struct KForces {
     static constexpr int kThreads = kForceBlock, kWaves = 4;
     struct Args {
@@ -524,10 +471,9 @@ struct KForces {
     static __device__ void run(const Args &args_, uint32_t blk, uint32_t);
 };
 
-template <int PAIR, bool SHIFT, int U, int PREC, bool LIST, bool LEAN>
-__device__ void KForces<PAIR, SHIFT, U, PREC, LIST, LEAN>::run(const Args &args_, uint32_t blk, uint32_t nblk)
+template <int PAIR, bool SHIFT, int U, int PREC, bool LIST>
+__device__ void KForces<PAIR, SHIFT, U, PREC, LIST>::run(const Args &args_, uint32_t blk, uint32_t nblk)
 {
-    static_assert(!LEAN || (PREC == DCM_FP64 && !(SHIFT && PAIR == DCM_PAIR_I)), "lean variant");
     const ForceArgs &a = args_.a;
     const double rc_max = args_.rc_max;
     // the wave this workgroup takes: longest (in the last launch) first, so that the waves
@@ -550,7 +496,7 @@ __device__ void KForces<PAIR, SHIFT, U, PREC, LIST, LEAN>::run(const Args &args_
     const bool sane = isfinite(q.x) && isfinite(q.y) && isfinite(q.z) && q.rc > 0.0 && q.rc <= rc_max;
     const bool live = have && sane;
     // every lane of the wave takes part in the (wave-uniform) traversal
-    typedef typename std::conditional<LEAN, AccLean, Acc>::type AccT;
+    typedef Acc AccT;
     AccT c = {};
     Stage *stage = nullptr;
     if constexpr (!LIST) {
@@ -621,9 +567,7 @@ __device__ void KForces<PAIR, SHIFT, U, PREC, LIST, LEAN>::run(const Args &args_
 #pragma unroll
     for (int q = 0; q < 7; ++q)
         for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
-    if constexpr (LEAN) pc = wave_pairs_of(c);
-    else
-        for (int off = 32; off > 0; off >>= 1) pc += __shfl_xor(pc, off, 64);
+    for (int off = 32; off > 0; off >>= 1) pc += __shfl_xor(pc, off, 64);
     __shared__ double lds[kForceBlock / 64][8];
     __shared__ long long ldp[kForceBlock / 64];
     const int w = threadIdx.x >> 6;
@@ -763,14 +707,11 @@ static void launch_prec(const ForceArgs &a, int nb, hipStream_t st)
         else emit<KForces<DCM_PAIR_I, false, U, PREC, true>>({a, a.rc_max}, blocks, st);
         return;
     }
-    const bool per_particle = a.e_out || a.w_out || a.pairs_out;
     if (a.pair_rule == DCM_PAIR_MAX) {
         if (a.energy_shift) emit<KForces<DCM_PAIR_MAX, true, U, PREC>>({a, a.rc_max}, blocks, st);
         else emit<KForces<DCM_PAIR_MAX, false, U, PREC>>({a, a.rc_max}, blocks, st);
     } else {
         if (a.energy_shift) emit<KForces<DCM_PAIR_I, true, U, PREC>>({a, a.rc_max}, blocks, st);
-        else if (PREC == DCM_FP64 && !per_particle)
-            emit<KForces<DCM_PAIR_I, false, U, DCM_FP64, false, true>>({a, a.rc_max}, blocks, st);
         else emit<KForces<DCM_PAIR_I, false, U, PREC>>({a, a.rc_max}, blocks, st);
     }
 }
