@@ -260,7 +260,8 @@ struct Stage {
         w[kStageSlots + kStagePad];
 };
 
-template <int PAIR, bool SHIFT, bool IMAGE, int U, typename A>
+// SELF: some lane's own slot lies in its interval (only then is j != i tested).
+template <int PAIR, bool SHIFT, bool IMAGE, bool SELF, int U, typename A>
 __device__ __forceinline__ void scan_staged(const ForceArgs &a, const Stage &sg, uint32_t lo, const Particle &q,
                                             uint32_t jb, uint32_t je, double sx, double sy, double sz, A &c)
 {
@@ -281,8 +282,8 @@ __device__ __forceinline__ void scan_staged(const ForceArgs &a, const Stage &sg,
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            interact<PAIR, SHIFT, IMAGE>(a, p[u], t + u < len && t + u != self, q.x, q.y, q.z, q.rc, q.rc2, sx, sy,
-                                         sz, c, jb + t + u);
+            interact<PAIR, SHIFT, IMAGE>(a, p[u], t + u < len && (!SELF || t + u != self), q.x, q.y, q.z, q.rc,
+                                         q.rc2, sx, sy, sz, c, jb + t + u);
     }
 }
 
@@ -329,10 +330,13 @@ __device__ __forceinline__ void scan_row(const ForceArgs &a, __amdgpu_buffer_rsr
     }
     __syncthreads();
     const bool image = has && (sx != 0.0 || sy != 0.0 || sz != 0.0);
+    const bool self = (uint32_t)q.i - jb < je - jb;
     if (__any(image))
-        scan_staged<PAIR, SHIFT, true, U, A>(a, sg, lo, q, jb, je, sx, sy, sz, c);
+        scan_staged<PAIR, SHIFT, true, true, U, A>(a, sg, lo, q, jb, je, sx, sy, sz, c);
+    else if (__any(self))
+        scan_staged<PAIR, SHIFT, false, true, U, A>(a, sg, lo, q, jb, je, sx, sy, sz, c);
     else
-        scan_staged<PAIR, SHIFT, false, U, A>(a, sg, lo, q, jb, je, sx, sy, sz, c);
+        scan_staged<PAIR, SHIFT, false, false, U, A>(a, sg, lo, q, jb, je, sx, sy, sz, c);
     __syncthreads();
 }
 
