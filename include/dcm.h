@@ -298,6 +298,16 @@ dcm_status dcm_grid_segment(const int32_t dims[3], const uint32_t *d_g, const do
                             int32_t min_component, uint8_t *d_raw, uint8_t *d_label,
                             int64_t *d_stats, void *d_ws, size_t ws_bytes, dcm_stream_t stream);
 
+/* dcm_grid_smooth without a workspace, for callers that cannot allocate device memory
+ * (code under graph capture, tight serving loops, hosts that forbid allocation). The
+ * intermediate image of the passes lives in a device array of the library (8,388,608 boxes,
+ * 32 MiB per device, held until the process ends), so dims must give at most 8,388,608 boxes
+ * (DCM_E_INVALID otherwise). Allocates nothing and copies nothing to or from the host. All
+ * calls on one device share that array: calls that overlap on one device (other streams, other
+ * threads) race. Same result as dcm_grid_smooth, bit for bit. */
+dcm_status dcm_grid_smooth_noalloc(const int32_t dims[3], int32_t passes, const uint32_t *d_in,
+                                   uint32_t *d_out, dcm_stream_t stream);
+
 /* Distance of liquid boxes (label 0) to the vapor set (label 1): the fixed point of the
  * Godunov upwind update (Eq. 16-19) restricted to values <= cap, all other values set to
  * cap (Section 4.3.2). h = box edges. *d_sweeps (optional, device) = sweeps used. */

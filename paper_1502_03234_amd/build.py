@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdcm.so")
-SOURCES = ["sort.hip", "detect.hip", "force.hip", "tail.hip", "mumford_shah.hip", "exact.hip", "integrate.hip", "api.cpp", "serve.cpp"]
+SOURCES = ["sort.hip", "detect.hip", "force.hip", "tail.hip", "mumford_shah.hip", "exact.hip", "integrate.hip", "noalloc.hip", "api.cpp", "serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -46,6 +46,21 @@ dcm_status fail(dcm_status s, const char *fmt, ...)
     return s;
 }
 
+}  // namespace
+
+dcm_status dcm::report_error(dcm_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+namespace {
+
 dcm_status hip_status(const char *where)
 {
     hipError_t e = hipGetLastError();

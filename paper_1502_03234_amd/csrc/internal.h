@@ -103,6 +103,9 @@ struct GridWork {
     MsWork ms;              // Mumford-Shah segmentation (all NULL unless it is on)
 };
 
+// Records a message for dcm_last_error (printf format) and returns s.
+dcm_status report_error(dcm_status s, const char *fmt, ...);
+
 // ---- launchers (each enqueues on `st`; no synchronization) ------------------------------
 // sort.hip
 size_t sort_scratch_bytes(int64_t n, int64_t G);

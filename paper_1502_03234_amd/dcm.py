@@ -93,6 +93,7 @@ _SIGS = {
     "dcm_list_builds": ([_vp, C.POINTER(_i64)], _i32),
     "dcm_grid_workspace_bytes": ([_vp, C.POINTER(_sz)], _i32),
     "dcm_grid_smooth": ([_vp, _i32, _vp, _vp, _vp, _sz, _vp], _i32),
+    "dcm_grid_smooth_noalloc": ([_vp, _i32, _vp, _vp, _vp], _i32),
     "dcm_grid_two_means": ([_vp, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
     "dcm_grid_segment": ([_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
     "dcm_grid_distance": ([_vp, _vp, C.c_double, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
@@ -261,6 +262,11 @@ def dcm_grid_smooth(dims, passes: int, img, out, ws, stream=None):
     d = (C.c_int32 * 3)(*dims)
     _check(_lib.dcm_grid_smooth(d, int(passes), _ptr(img), _ptr(out), _ptr(ws),
                                 ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def dcm_grid_smooth_noalloc(dims, passes: int, img, out, stream=None):
+    d = (C.c_int32 * 3)(*dims)
+    _check(_lib.dcm_grid_smooth_noalloc(d, int(passes), _ptr(img), _ptr(out), _stream(stream)))
 
 
 def dcm_grid_two_means(dims, img, km, stats, ws, stream=None):
