@@ -96,7 +96,7 @@ bool grid_of(const dcm_params *p, Grid &g)
         g.L[k] = p->box[k];
     }
     g.G = (int64_t)g.n[0] * g.n[1] * g.n[2];
-    g.sy = g.sz = 0;
+    g.sy = g.sz = g.sx = 0;
     return true;
 }
 
@@ -132,6 +132,9 @@ dcm_status validate(const dcm_params *p, int64_t n, Grid &g)
     // the stencil in units of two boxes (a lane's rows then never meet the same storage row twice)
     g.sy = (g.n[1] % 2 == 0 && g.n[1] >= 2 * (int)std::ceil(reach / g.h[1]) + 6) ? 1 : 0;
     g.sz = (g.n[2] % 2 == 0 && g.n[2] >= 2 * (int)std::ceil(reach / g.h[2]) + 6) ? 1 : 0;
+    // storage cells of half a box along x (the force kernel's x-intervals end at half boxes),
+    // while the cell keys fit 31 bits
+    g.sx = (g.G << 1) < ((int64_t)1 << 31) ? 1 : 0;
     if (p->cutoff_shape != DCM_CUTOFF_EXP && p->cutoff_shape != DCM_CUTOFF_LINEAR)
         return fail(DCM_E_INVALID, "unknown cutoff_shape");
     if (p->cutoff_shape == DCM_CUTOFF_EXP && p->alpha == 0.0 && p->rc_min != p->rc_max)
@@ -193,8 +196,8 @@ size_t layout(dcm_system *s, void *ws)
     s->val = b.take<uint32_t>(n);
     s->key_alt = b.take<uint32_t>(n);
     s->val_alt = b.take<uint32_t>(n);
-    s->sort_scratch = b.take<uint8_t>(sort_scratch_bytes(n, G));
-    s->gw.cell_start = b.take<uint32_t>(G + 1);
+    s->sort_scratch = b.take<uint8_t>(sort_scratch_bytes(n, key_count(s->grid)));
+    s->gw.cell_start = b.take<uint32_t>(key_count(s->grid) + 1);
     s->gw.g = b.take<uint32_t>(G);
     s->gw.gtmp = b.take<uint32_t>(G);
     s->gw.raw = b.take<uint8_t>(G);
@@ -260,7 +263,7 @@ void init_derived(dcm_system *s)
         s->cut_a = 0.0;
         s->cut_b = p.rc_max;
     }
-    s->bits = key_bits(s->grid.G);
+    s->bits = key_bits(key_count(s->grid));
     // g = 3n - 3: the thermostat leaves the total momentum unchanged (it scales it), so the
     // centre-of-mass degrees of freedom are not thermalised
     const double g = 3.0 * (double)s->n - 3.0;
@@ -298,8 +301,8 @@ void rebin_sorted(dcm_system *s, hipStream_t st)
         std::swap(s->key, s->key_alt);
         std::swap(s->val, s->val_alt);
     }
-    launch_cell_ranges(s->key, s->n, s->grid.G, s->gw.cell_start, s->sort_scratch, st);
-    launch_cell_fixup(s->gw.cell_start, s->grid.G, s->val, from.id, st);
+    launch_cell_ranges(s->key, s->n, key_count(s->grid), s->gw.cell_start, s->sort_scratch, st);
+    launch_cell_fixup(s->gw.cell_start, key_count(s->grid), s->val, from.id, st);
     launch_gather(from, to, s->val, s->n, st);
     s->cur = 1 - s->cur;
 }
@@ -851,6 +854,7 @@ static dcm_status grid_from_dims(const int32_t dims[3], Grid &g)
         g.L[k] = dims[k];
     }
     g.G = (int64_t)dims[0] * dims[1] * dims[2];
+    g.sx = g.sy = g.sz = 0;
     if (g.G >= ((int64_t)1 << 31)) return fail(DCM_E_INVALID, "grid too large");
     return DCM_OK;
 }

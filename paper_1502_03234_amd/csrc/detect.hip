@@ -70,12 +70,9 @@ __device__ void KSmoothAxis::run(const Args &args_, uint32_t blk, uint32_t)
     int64_t cl = lin(g, lo[0], lo[1], lo[2]), ch = lin(g, hi[0], hi[1], hi[2]);
     uint32_t a, b, d;
     if (cell_start) {
-        const uint32_t kl = box_key(g, (int32_t)lo[0], (int32_t)lo[1], (int32_t)lo[2]);
-        const uint32_t kc = box_key(g, (int32_t)i, (int32_t)j, (int32_t)k);
-        const uint32_t kh = box_key(g, (int32_t)hi[0], (int32_t)hi[1], (int32_t)hi[2]);
-        a = cell_start[kl + 1] - cell_start[kl];
-        b = cell_start[kc + 1] - cell_start[kc];
-        d = cell_start[kh + 1] - cell_start[kh];
+        a = box_count(g, cell_start, (int32_t)lo[0], (int32_t)lo[1], (int32_t)lo[2]);
+        b = box_count(g, cell_start, (int32_t)i, (int32_t)j, (int32_t)k);
+        d = box_count(g, cell_start, (int32_t)hi[0], (int32_t)hi[1], (int32_t)hi[2]);
     } else {
         a = in[cl];
         b = in[c];
@@ -103,8 +100,7 @@ __device__ void KCountFromRanges::run(const Args &args_, uint32_t blk, uint32_t)
     if (c >= g.G) return;
     int64_t i, j, k;
     coords(g, c, i, j, k);
-    const uint32_t q = box_key(g, (int32_t)i, (int32_t)j, (int32_t)k);
-    out[c] = cell_start[q + 1] - cell_start[q];
+    out[c] = box_count(g, cell_start, (int32_t)i, (int32_t)j, (int32_t)k);
 }
 
 // ---- histogram and two-means ----------------------------------------------------------

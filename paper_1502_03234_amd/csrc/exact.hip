@@ -16,15 +16,6 @@ namespace {
 
 inline unsigned grid1(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-__device__ __forceinline__ int32_t box_of(double x, double h, int32_t N)
-{
-    double f = floor(x / h);
-    int32_t i = (int32_t)f;
-    if (f > (double)(N - 1)) i = N - 1;
-    if (i < 0) i = 0;
-    return i;
-}
-
 // floor division and remainder of an unwrapped box index
 __device__ __forceinline__ void unwrap(int32_t u, int32_t N, int32_t &w, int32_t &img)
 {
@@ -77,9 +68,9 @@ __device__ void KForcesImages::run(const Args &args_, uint32_t blk, uint32_t)
     const int64_t p = (int64_t)blk * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const double4 q = s.pos[p];
-    const int32_t a = box_of(q.x, g.h[0], g.n[0]);
-    const int32_t b = box_of(q.y, g.h[1], g.n[1]);
-    const int32_t c = box_of(q.z, g.h[2], g.n[2]);
+    const int32_t a = box_index(q.x, g.h[0], g.n[0]);
+    const int32_t b = box_index(q.y, g.h[1], g.n[1]);
+    const int32_t c = box_index(q.z, g.h[2], g.n[2]);
     const double R2 = R * R;
     double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
     for (int32_t oz = -mz; oz <= mz; ++oz) {
@@ -99,23 +90,25 @@ __device__ void KForcesImages::run(const Args &args_, uint32_t blk, uint32_t)
                 unwrap(a + ox, g.n[0], wa, ix);
                 const double sx = (double)ix * g.L[0], sy = (double)iy * g.L[1], sz = (double)iz * g.L[2];
                 const bool home = ix == 0 && iy == 0 && iz == 0;
-                const uint32_t key = box_key(g, wa, wb, wc);
-                const uint32_t j0 = cell_start[key], j1 = cell_start[key + 1];
-                for (uint32_t j = j0; j < j1; ++j) {
-                    if (home && (int64_t)j == p) continue;
-                    const double4 o = s.pos[j];
-                    const double dx = q.x - (o.x + sx), dy = q.y - (o.y + sy), dz = q.z - (o.z + sz);
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    if (!(r2 < R2)) continue;
-                    const double ir2 = 1.0 / r2;
-                    const double s2 = sig2 * ir2;
-                    const double s6 = s2 * s2 * s2;
-                    const double s12 = s6 * s6;
-                    const double fr = eps24 * (2.0 * s12 - s6) * ir2;
-                    fx += fr * dx;
-                    fy += fr * dy;
-                    fz += fr * dz;
-                    e += eps4 * (s12 - s6);
+                for (int32_t cq = 0; cq < (1 << g.sx); ++cq) {
+                    const uint32_t key = cell_key(g, (wa << g.sx) + cq, wb, wc);
+                    const uint32_t j0 = cell_start[key], j1 = cell_start[key + 1];
+                    for (uint32_t j = j0; j < j1; ++j) {
+                        if (home && (int64_t)j == p) continue;
+                        const double4 o = s.pos[j];
+                        const double dx = q.x - (o.x + sx), dy = q.y - (o.y + sy), dz = q.z - (o.z + sz);
+                        const double r2 = dx * dx + dy * dy + dz * dz;
+                        if (!(r2 < R2)) continue;
+                        const double ir2 = 1.0 / r2;
+                        const double s2 = sig2 * ir2;
+                        const double s6 = s2 * s2 * s2;
+                        const double s12 = s6 * s6;
+                        const double fr = eps24 * (2.0 * s12 - s6) * ir2;
+                        fx += fr * dx;
+                        fy += fr * dy;
+                        fz += fr * dz;
+                        e += eps4 * (s12 - s6);
+                    }
                 }
             }
         }

@@ -4,7 +4,7 @@
 //
 // One lane per particle, particles in storage (sort-key) order, so a wavefront holds a run of
 // neighbouring boxes along x inside one force row. A force row is a block of 2 x 2 boxes in y
-// and z (1 x 1 where an axis is too short or odd; see box_key), and storage order keeps the boxes
+// and z (1 x 1 where an axis is too short or odd; see cell_key), and storage order keeps the boxes
 // of a force row and any x-interval in one contiguous slot range. Lane i walks the force rows
 // whose y-z rectangle comes within r_c[i] of it and, in each, scans the slot range of the
 // x-interval the sphere cuts: the small-bin stencil of Fig. 13b with single-box resolution in
@@ -352,7 +352,7 @@ __device__ __forceinline__ int wave_max(int v)
     return __builtin_amdgcn_readfirstlane(v);
 }
 
-// Walks the force rows (2^sz x 2^sy boxes in z and y, see box_key) that come within particle
+// Walks the force rows (2^sz x 2^sy boxes in z and y, see cell_key) that come within particle
 // i's search radius and scans, in each, the slot range of the x-interval the sphere cuts. The
 // row loops are uniform over the wave: they run over the union of the lanes' row offsets
 // relative to each lane's own force row, so lanes of one row look at the same neighbour rows
@@ -370,7 +370,9 @@ __device__ __forceinline__ void traverse(const ForceArgs &a, bool live, const Pa
     const double rs2 = rs * rs;
     const int nY = g.n[1] >> g.sy, nZ = g.n[2] >> g.sz, gs = g.sy + g.sz;
     const double Hy = g.h[1] * (double)(1 << g.sy), Hz = g.h[2] * (double)(1 << g.sz);
-    const double iHy = 1.0 / Hy, iHz = 1.0 / Hz, ihx = 1.0 / g.h[0];
+    // x-intervals are resolved in storage cells of h_x / 2^sx
+    const double iHy = 1.0 / Hy, iHz = 1.0 / Hz, ihx = (double)(1 << g.sx) / g.h[0];
+    const int ncx = g.n[0] << g.sx;
     const int Yi = live ? floor_mul(q.y, iHy) : 0, Zi = live ? floor_mul(q.z, iHz) : 0;
     const int zlo_r = live ? floor_mul(q.z - rs, iHz) - Zi : INT_MAX;
     const int zhi_r = live ? floor_mul(q.z + rs, iHz) - Zi : INT_MIN;
@@ -408,14 +410,14 @@ __device__ __forceinline__ void traverse(const ForceArgs &a, bool live, const Pa
             if (yok) {
                 const double rx = sqrt_up(rem);
                 const int ixlo = floor_mul(q.x - rx, ihx), ixhi = floor_mul(q.x + rx, ihx);
-                const uint32_t row = (uint32_t)(wZ * nY + wY) * (uint32_t)g.n[0];
+                const uint32_t row = (uint32_t)(wZ * nY + wY) * (uint32_t)ncx;
                 int lo0 = ixlo, hi0 = ixhi, lo1 = 0, hi1 = -1;
                 if (ixlo < 0) {
-                    lo0 = ixlo + g.n[0]; hi0 = g.n[0] - 1; sx0 = -g.L[0];
+                    lo0 = ixlo + ncx; hi0 = ncx - 1; sx0 = -g.L[0];
                     lo1 = 0; hi1 = ixhi;
-                } else if (ixhi >= g.n[0]) {
-                    hi0 = g.n[0] - 1;
-                    lo1 = 0; hi1 = ixhi - g.n[0]; sx1 = g.L[0];
+                } else if (ixhi >= ncx) {
+                    hi0 = ncx - 1;
+                    lo1 = 0; hi1 = ixhi - ncx; sx1 = g.L[0];
                 }
                 b0 = a.cell_start[(row + (uint32_t)lo0) << gs];
                 e0 = a.cell_start[(row + (uint32_t)hi0 + 1u) << gs];

@@ -29,15 +29,6 @@ __device__ __forceinline__ double wrap1(double x, double L)
     return t;
 }
 
-__device__ __forceinline__ int32_t box_of(double x, double h, int32_t N)
-{
-    double f = floor(x / h);
-    int32_t i = (int32_t)f;
-    if (f > (double)(N - 1)) i = N - 1;
-    if (i < 0) i = 0;
-    return i;
-}
-
 __device__ double block_sum(double v)
 {
     __shared__ double lds[kBlock / 64];
@@ -126,10 +117,7 @@ __device__ void KKickDriftKey::run(const Args &a, uint32_t blk, uint32_t)
         s.vx[i] = vx;
         s.vy[i] = vy;
         s.vz[i] = vz;
-        const int32_t ba = box_of(p.x, g.h[0], g.n[0]);
-        const int32_t bb = box_of(p.y, g.h[1], g.n[1]);
-        const int32_t bc = box_of(p.z, g.h[2], g.n[2]);
-        a.key[i] = box_key(g, ba, bb, bc);
+        a.key[i] = pos_key(g, p.x, p.y, p.z);
         a.val[i] = (uint32_t)i;
     }
     if (second_kick) {

@@ -31,19 +31,62 @@ struct Grid {
     double h[3];        // box edges L_k / N_k
     double L[3];        // periodic box
     int64_t G;          // N_x N_y N_z
-    int32_t sy, sz;     // log2 of the y and z extent of a force row (0 or 1; see box_key)
+    int32_t sy, sz;     // log2 of the y and z extent of a force row (0 or 1; see cell_key)
+    int32_t sx;         // log2 of the storage cells per box along x (0 or 1; see cell_key)
 };
 
-// Sort key (storage order) of box (a, b, c). Boxes are grouped into force rows of 2^sy x 2^sz
-// boxes in y and z; keys run over force rows, then x, then the box's place inside its force
-// row. The boxes of one force row and an x-interval are therefore one contiguous key range, and
-// with sy = sz = 0 the key is the plain linear index (c N_y + b) N_x + a. Every box keeps its own
-// contiguous key, so per-box counts are key-range lengths in either order.
-__host__ __device__ inline uint32_t box_key(const Grid &g, int32_t a, int32_t b, int32_t c)
+// Sort key (storage order) of storage cell (ax, b, c), where ax counts cells of h_x / 2^sx along
+// x (box a holds cells a 2^sx .. a 2^sx + 2^sx - 1). Boxes are grouped into force rows of 2^sy x
+// 2^sz boxes in y and z; keys run over force rows, then x cells, then the box's place inside its
+// force row. The boxes of one force row and an x-interval (in cells) are therefore one
+// contiguous key range; with sx = sy = sz = 0 the key is the plain linear box index
+// (c N_y + b) N_x + a. The particles of box (a, b, c) are the 2^sx key ranges of its cells.
+__host__ __device__ inline uint32_t cell_key(const Grid &g, int32_t ax, int32_t b, int32_t c)
 {
     const uint32_t row = (uint32_t)(c >> g.sz) * (uint32_t)(g.n[1] >> g.sy) + (uint32_t)(b >> g.sy);
     const uint32_t sub = ((uint32_t)(c & ((1 << g.sz) - 1)) << g.sy) | (uint32_t)(b & ((1 << g.sy) - 1));
-    return ((row * (uint32_t)g.n[0] + (uint32_t)a) << (g.sy + g.sz)) | sub;
+    return ((row * ((uint32_t)g.n[0] << g.sx) + (uint32_t)ax) << (g.sy + g.sz)) | sub;
+}
+
+// Number of storage keys (cells).
+__host__ __device__ inline int64_t key_count(const Grid &g) { return g.G << g.sx; }
+
+// Particles in box (a, b, c) (Eq. 9): the lengths of its cells' key ranges.
+__device__ inline uint32_t box_count(const Grid &g, const uint32_t *cell_start, int32_t a, int32_t b, int32_t c)
+{
+    uint32_t cnt = 0u;
+    for (int q = 0; q < (1 << g.sx); ++q) {
+        const uint32_t k = cell_key(g, (a << g.sx) + q, b, c);
+        cnt += cell_start[k + 1] - cell_start[k];
+    }
+    return cnt;
+}
+
+// Box index of a wrapped coordinate along an axis of N boxes of edge h (Eq. 10: floor(x / h),
+// clamped to 0 .. N - 1).
+__host__ __device__ inline int32_t box_index(double x, double h, int32_t N)
+{
+    const double f = floor(x / h);
+    int32_t i = (int32_t)f;
+    if (f > (double)(N - 1)) i = N - 1;
+    if (i < 0) i = 0;
+    return i;
+}
+
+// Storage key of a wrapped position: its box (Eq. 10) and, inside the box, its x cell (used
+// only to narrow the force kernel's x-intervals; the box alone decides the counts).
+__host__ __device__ inline uint32_t pos_key(const Grid &g, double x, double y, double z)
+{
+    const int32_t a = box_index(x, g.h[0], g.n[0]);
+    const int32_t b = box_index(y, g.h[1], g.n[1]);
+    const int32_t c = box_index(z, g.h[2], g.n[2]);
+    int32_t q = 0;
+    if (g.sx) {
+        const int32_t S = 1 << g.sx;
+        const double f = floor(x * ((double)S / g.h[0])) - (double)a * S;
+        q = f < 0.0 ? 0 : (f > (double)(S - 1) ? S - 1 : (int32_t)f);
+    }
+    return cell_key(g, (a << g.sx) + q, b, c);
 }
 
 // One copy of the per-particle state in cell-sorted order.

@@ -27,15 +27,6 @@ __device__ __forceinline__ double wrap1(double x, double L)
     return t;
 }
 
-__device__ __forceinline__ int32_t box_of(double x, double h, int32_t N)
-{
-    double f = floor(x / h);
-    int32_t i = (int32_t)f;
-    if (f > (double)(N - 1)) i = N - 1;
-    if (i < 0) i = 0;
-    return i;
-}
-
 struct KWrapKey {
     static constexpr int kThreads = kBlock, kWaves = 0;
     struct Args { Grid g; PSet s; int64_t n; uint32_t *key, *val; };
@@ -53,10 +44,7 @@ __device__ void KWrapKey::run(const Args &args, uint32_t blk, uint32_t)
     p.y = wrap1(p.y, g.L[1]);
     p.z = wrap1(p.z, g.L[2]);
     s.pos[i] = p;
-    int32_t a = box_of(p.x, g.h[0], g.n[0]);
-    int32_t b = box_of(p.y, g.h[1], g.n[1]);
-    int32_t c = box_of(p.z, g.h[2], g.n[2]);
-    args.key[i] = box_key(g, a, b, c);
+    args.key[i] = pos_key(g, p.x, p.y, p.z);
     args.val[i] = (uint32_t)i;
 }
 
@@ -72,9 +60,9 @@ struct KCountBoxes {
         int64_t i = (int64_t)blk * kThreads + threadIdx.x;
         if (i >= args.n) return;
         const double4 p = args.pos[i];
-        const int32_t a = box_of(p.x, g.h[0], g.n[0]);
-        const int32_t b = box_of(p.y, g.h[1], g.n[1]);
-        const int32_t c = box_of(p.z, g.h[2], g.n[2]);
+        const int32_t a = box_index(p.x, g.h[0], g.n[0]);
+        const int32_t b = box_index(p.y, g.h[1], g.n[1]);
+        const int32_t c = box_index(p.z, g.h[2], g.n[2]);
         atomicAdd(args.count + ((int64_t)c * g.n[1] + b) * g.n[0] + a, 1u);
     }
 };
