@@ -358,22 +358,20 @@ __device__ __forceinline__ int wave_max(int v)
 // relative to each lane's own force row, so lanes of one row look at the same neighbour rows
 // together and their windows overlap. Each lane visits exactly its own rows, in increasing z,
 // then y, then x.
-template <int PAIR, bool SHIFT, int U, typename A>
-__device__ __forceinline__ void traverse(const ForceArgs &a, bool live, const Particle &q, double rc_max, A &c,
-                                         Stage *sg = nullptr)
+// UNI: every live lane of the wave lies in one force row and no lane's x-interval can wrap
+// around x, so row indices, their periodic wraps and image shifts are uniform over the wave
+// (scalar) and each row is one slot range per lane.
+template <int PAIR, bool SHIFT, int U, typename A, bool UNI>
+__device__ __forceinline__ void traverse_rows(const ForceArgs &a, bool live, const Particle &q, double rs, int Yi,
+                                              int Zi, A &c, Stage *sg)
 {
     const Grid &g = a.grid;
-    // search radius (slightly enlarged so that rounding in the box bounds never drops a box
-    // that holds an in-range particle; the pair test itself is exact)
-    double rs = PAIR == DCM_PAIR_MAX ? rc_max : q.rc;
-    rs = rs * (1.0 + 1e-12) + 1e-9;
     const double rs2 = rs * rs;
     const int nY = g.n[1] >> g.sy, nZ = g.n[2] >> g.sz, gs = g.sy + g.sz;
     const double Hy = g.h[1] * (double)(1 << g.sy), Hz = g.h[2] * (double)(1 << g.sz);
     // x-intervals are resolved in storage cells of h_x / 2^sx
     const double iHy = 1.0 / Hy, iHz = 1.0 / Hz, ihx = (double)(1 << g.sx) / g.h[0];
     const int ncx = g.n[0] << g.sx;
-    const int Yi = live ? floor_mul(q.y, iHy) : 0, Zi = live ? floor_mul(q.z, iHz) : 0;
     const int zlo_r = live ? floor_mul(q.z - rs, iHz) - Zi : INT_MAX;
     const int zhi_r = live ? floor_mul(q.z + rs, iHz) - Zi : INT_MIN;
     const int zb = wave_min(zlo_r), ze = wave_max(zhi_r);
@@ -404,33 +402,56 @@ __device__ __forceinline__ void traverse(const ForceArgs &a, bool live, const Pa
             double sy = 0.0;
             if (Y < 0) { wY += nY; sy = -g.L[1]; }
             else if (Y >= nY) { wY -= nY; sy = g.L[1]; }
+            const uint32_t row = (uint32_t)(wZ * nY + wY) * (uint32_t)ncx;
             // up to two contiguous slot ranges (the second one wraps around x)
             uint32_t b0 = 0, e0 = 0, b1 = 0, e1 = 0;
             double sx0 = 0.0, sx1 = 0.0;
             if (yok) {
                 const double rx = sqrt_up(rem);
                 const int ixlo = floor_mul(q.x - rx, ihx), ixhi = floor_mul(q.x + rx, ihx);
-                const uint32_t row = (uint32_t)(wZ * nY + wY) * (uint32_t)ncx;
                 int lo0 = ixlo, hi0 = ixhi, lo1 = 0, hi1 = -1;
-                if (ixlo < 0) {
-                    lo0 = ixlo + ncx; hi0 = ncx - 1; sx0 = -g.L[0];
-                    lo1 = 0; hi1 = ixhi;
-                } else if (ixhi >= ncx) {
-                    hi0 = ncx - 1;
-                    lo1 = 0; hi1 = ixhi - ncx; sx1 = g.L[0];
+                if (!UNI) {
+                    if (ixlo < 0) {
+                        lo0 = ixlo + ncx; hi0 = ncx - 1; sx0 = -g.L[0];
+                        lo1 = 0; hi1 = ixhi;
+                    } else if (ixhi >= ncx) {
+                        hi0 = ncx - 1;
+                        lo1 = 0; hi1 = ixhi - ncx; sx1 = g.L[0];
+                    }
                 }
                 b0 = a.cell_start[(row + (uint32_t)lo0) << gs];
                 e0 = a.cell_start[(row + (uint32_t)hi0 + 1u) << gs];
-                if (hi1 >= lo1) {
+                if (!UNI && hi1 >= lo1) {
                     b1 = a.cell_start[(row + (uint32_t)lo1) << gs];
                     e1 = a.cell_start[(row + (uint32_t)hi1 + 1u) << gs];
                 }
             }
             if (sg) scan_row<PAIR, SHIFT, U, A>(a, pb, *sg, q, b0, e0, sx0, sy, sz, c);
             else scan_interval<PAIR, SHIFT, U, A>(a, pb, q, b0, e0, sx0, sy, sz, c);
-            if (__any(b1 < e1)) scan_interval<PAIR, SHIFT, U, A>(a, pb, q, b1, e1, sx1, sy, sz, c);
+            if (!UNI && __any(b1 < e1)) scan_interval<PAIR, SHIFT, U, A>(a, pb, q, b1, e1, sx1, sy, sz, c);
         }
     }
+}
+
+template <int PAIR, bool SHIFT, int U, typename A>
+__device__ __forceinline__ void traverse(const ForceArgs &a, bool live, const Particle &q, double rc_max, A &c,
+                                         Stage *sg = nullptr)
+{
+    const Grid &g = a.grid;
+    // search radius (slightly enlarged so that rounding in the box bounds never drops a box
+    // that holds an in-range particle; the pair test itself is exact)
+    double rs = PAIR == DCM_PAIR_MAX ? rc_max : q.rc;
+    rs = rs * (1.0 + 1e-12) + 1e-9;
+    const double iHy = 1.0 / (g.h[1] * (double)(1 << g.sy)), iHz = 1.0 / (g.h[2] * (double)(1 << g.sz));
+    const int Yi = live ? floor_mul(q.y, iHy) : 0, Zi = live ? floor_mul(q.z, iHz) : 0;
+    // one force row for every live lane, and every x-interval inside [0, L_x)
+    const int ylo = wave_min(live ? Yi : INT_MAX), yhi = wave_max(live ? Yi : INT_MIN);
+    const int zlo = wave_min(live ? Zi : INT_MAX), zhi = wave_max(live ? Zi : INT_MIN);
+    const bool inside = !live || (q.x - rs >= 0.0 && q.x + rs < g.L[0]);
+    if (ylo == yhi && zlo == zhi && __all(inside))
+        traverse_rows<PAIR, SHIFT, U, A, true>(a, live, q, rs, ylo, zlo, c, sg);
+    else
+        traverse_rows<PAIR, SHIFT, U, A, false>(a, live, q, rs, Yi, Zi, c, sg);
 }
 
 // The candidates of lane i's list, U at a time, until the wave's longest list is done. The
