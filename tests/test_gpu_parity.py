@@ -407,6 +407,44 @@ def test_slab256k_both_forms_after_steps(prec, tol):
 
 
 @pytest.mark.slow
+def test_slab256k_precision_form_against_oracle_over_1000_steps():
+    """The precision form's force error against the oracle along a long FP64 trajectory of the
+    256,000-particle slab: the FP64 form runs 1,000 steps; at steps 0, 500 and 1,000 the
+    precision form evaluates the forces of that FP64 state with its cutoffs, and the oracle
+    those of 2,000 sampled particles on the same state. Per-atom error within 1e-5 and pair
+    counts exact at every checkpoint (the cutoff test is FP64 in both forms)."""
+    st = synth.named("slab256k")
+    p, po = make(st)
+    s = dcm.System(p, st.x, st.v)
+    q = dcm.Params.from_buffer_copy(p)
+    q.precision, q.detect_every = dcm.DCM_FP32C, 0
+    rng = np.random.default_rng(31)
+    done = 0
+    for k_target in (0, 500, 1000):
+        if k_target > done:
+            s.step(k_target - done, thermo=False)
+            done = k_target
+        x, v, rc, k = s.state()
+        torch.cuda.synchronize()
+        assert k == k_target
+        f32 = dcm.System(q, x, v, rc=rc, step=k)
+        fo = f32.forces(per_atom=True, thermo=False)
+        torch.cuda.synchronize()
+        f32.check()
+        xw, rcw = x.cpu().numpy(), rc.cpu().numpy()
+        idx = np.sort(rng.choice(st.n, 2000, replace=False))
+        ref = O.forces(po, xw, rcw, subset=idx)
+        err = force_err(fo["f"].cpu().numpy()[:, idx], ref.f)
+        say(f"slab256k precision form vs oracle at step {k}: max {err.max():.3e}, "
+            f"rms {np.sqrt(np.mean(err ** 2)):.3e} over {idx.size} particles")
+        assert err.max() <= 1e-5
+        assert np.array_equal(fo["pairs"].cpu().numpy()[idx].astype(np.int64), ref.pairs)
+        f32.close()
+    s.check()
+    s.close()
+
+
+@pytest.mark.slow
 def test_slab2m_sampled_parity():
     st = synth.named("slab2m")
     p, po = make(st)
