@@ -45,7 +45,6 @@ struct KSmoothAxis {
     struct Args {
         Grid g;
         const uint32_t *in;
-        const uint32_t *cell_start;
         uint32_t *out;
         int axis;
     };
@@ -56,7 +55,6 @@ __device__ void KSmoothAxis::run(const Args &args_, uint32_t blk, uint32_t)
 {
     Grid g = args_.g;
     const uint32_t *in = args_.in;
-    const uint32_t *cell_start = args_.cell_start;
     uint32_t *out = args_.out;
     int axis = args_.axis;
     int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
@@ -68,17 +66,7 @@ __device__ void KSmoothAxis::run(const Args &args_, uint32_t blk, uint32_t)
     lo[axis] = q[axis] == 0 ? g.n[axis] - 1 : q[axis] - 1;
     hi[axis] = q[axis] == g.n[axis] - 1 ? 0 : q[axis] + 1;
     int64_t cl = lin(g, lo[0], lo[1], lo[2]), ch = lin(g, hi[0], hi[1], hi[2]);
-    uint32_t a, b, d;
-    if (cell_start) {
-        a = box_count(g, cell_start, (int32_t)lo[0], (int32_t)lo[1], (int32_t)lo[2]);
-        b = box_count(g, cell_start, (int32_t)i, (int32_t)j, (int32_t)k);
-        d = box_count(g, cell_start, (int32_t)hi[0], (int32_t)hi[1], (int32_t)hi[2]);
-    } else {
-        a = in[cl];
-        b = in[c];
-        d = in[ch];
-    }
-    out[c] = a + 2u * b + d;
+    out[c] = in[cl] + 2u * in[c] + in[ch];
 }
 
 struct KCountFromRanges {
@@ -1037,8 +1025,8 @@ void launch_count_from_ranges(const Grid &g, const uint32_t *cell_start, uint32_
     emit<KCountFromRanges>({g, cell_start, out}, grid1(g.G), st);
 }
 
-// `passes` rounds of x, y, z [1,2,1] passes; the first reads counts from cell ranges when
-// cell_start is given (else from `in`); the result always ends in `out`.
+// `passes` rounds of x, y, z [1,2,1] passes over the box counts taken from the cell ranges
+// when cell_start is given (else over `in`); the result always ends in `out`.
 void launch_smooth(const Grid &g, int passes, const uint32_t *cell_start, const uint32_t *in,
                    uint32_t *out, uint32_t *tmp, hipStream_t st)
 {
@@ -1049,12 +1037,16 @@ void launch_smooth(const Grid &g, int passes, const uint32_t *cell_start, const 
     }
     int total = 3 * passes;
     const uint32_t *src = in;
-    const uint32_t *cs = cell_start;
+    if (cell_start) {
+        // the box counts (Eq. 9) as an image first, in the buffer the first pass does not write
+        uint32_t *counts = (total % 2 == 1) ? tmp : out;
+        launch_count_from_ranges(g, cell_start, counts, st);
+        src = counts;
+    }
     for (int s = 0; s < total; ++s) {
         uint32_t *dst = ((total - 1 - s) % 2 == 0) ? out : tmp;
-        emit<KSmoothAxis>({g, src, cs, dst, s % 3}, grid1(g.G), st);
+        emit<KSmoothAxis>({g, src, dst, s % 3}, grid1(g.G), st);
         src = dst;
-        cs = nullptr;
     }
 }
 

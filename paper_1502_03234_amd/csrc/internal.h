@@ -54,10 +54,12 @@ __host__ __device__ inline int64_t key_count(const Grid &g) { return g.G << g.sx
 // Particles in box (a, b, c) (Eq. 9): the lengths of its cells' key ranges.
 __device__ inline uint32_t box_count(const Grid &g, const uint32_t *cell_start, int32_t a, int32_t b, int32_t c)
 {
-    uint32_t cnt = 0u;
-    for (int q = 0; q < (1 << g.sx); ++q) {
-        const uint32_t k = cell_key(g, (a << g.sx) + q, b, c);
-        cnt += cell_start[k + 1] - cell_start[k];
+    // the box's first cell, and its second one a force row of keys further on (sx = 1)
+    const uint32_t k = cell_key(g, a << g.sx, b, c);
+    uint32_t cnt = cell_start[k + 1] - cell_start[k];
+    if (g.sx) {
+        const uint32_t k2 = k + (1u << (g.sy + g.sz));
+        cnt += cell_start[k2 + 1] - cell_start[k2];
     }
     return cnt;
 }
