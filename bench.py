@@ -24,11 +24,12 @@ sys.path.insert(0, ROOT)
 FP64_VALU_PEAK_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 FLOPS_PER_PAIR = 41              # algorithmic FP64 flops per in-range ordered pair
 WORKLOAD = "slab2m"
-# HBM-side bytes per force-kernel launch from FETCH_SIZE/WRITE_SIZE counter runs, scaled by a plain
-# 1 GiB copy (profiles/KForces_slab2m_traffic.md). Valid only for the kernel source it was
-# taken on: reported as null once csrc/force.hip no longer hashes to this value.
-FORCE_TRAFFIC_BYTES = 2.745e9
-FORCE_TRAFFIC_SRC = "f97f4fc5d169dabd"
+# HBM-side bytes per force-kernel launch from FETCH_SIZE/WRITE_SIZE counter runs on the slab's
+# lattice start (--forces-only), scaled by a plain 1 GiB copy (profiles/KForces_slab2m_traffic.md).
+# Valid only for the kernel source it was taken on: reported as null once csrc/force.hip no longer
+# hashes to this value.
+FORCE_TRAFFIC_BYTES = 3.09e9
+FORCE_TRAFFIC_SRC = "abbfeac1d0af6162"
 
 
 def force_traffic():
