@@ -798,6 +798,12 @@ __device__ void KDistTiles::run(const Args &args_, uint32_t blk, uint32_t nblk)
     double init[2][2];
     for (int p = 0; p < 2; ++p)
         for (int m = 0; m < 2; ++m) init[p][m] = t[bzs[p][m]][bys[p][m]][bxs[p][m]];
+    // the upwind neighbour values each box was last updated from (NaN: not yet). An update
+    // from the same values gives the same candidate, which cannot lower the box again, so it
+    // is skipped; only boxes next to a change redo the quadratic solve.
+    double seen[2][2][3];
+    for (int p = 0; p < 2; ++p)
+        for (int m = 0; m < 2; ++m) seen[p][m][0] = seen[p][m][1] = seen[p][m][2] = NAN;
     bool local_done = false;
     for (int sweep = 0; sweep < kLocalMax; ++sweep) {
         bool ch = false;
@@ -805,11 +811,13 @@ __device__ void KDistTiles::run(const Args &args_, uint32_t blk, uint32_t nblk)
             for (int m = 0; m < 2; ++m) {
                 if (!liq[p][m]) continue;
                 const int hx = bxs[p][m], hy = bys[p][m], hz = bzs[p][m];
-                const double old = t[hz][hy][hx];
                 const double ax = fmin(t[hz][hy][hx - 1], t[hz][hy][hx + 1]);
                 const double ay = fmin(t[hz][hy - 1][hx], t[hz][hy + 1][hx]);
                 const double az = fmin(t[hz - 1][hy][hx], t[hz + 1][hy][hx]);
+                if (ax == seen[p][m][0] && ay == seen[p][m][1] && az == seen[p][m][2]) continue;
+                seen[p][m][0] = ax; seen[p][m][1] = ay; seen[p][m][2] = az;
                 if (isinf(ax) && isinf(ay) && isinf(az)) continue;
+                const double old = t[hz][hy][hx];
                 const double db = godunov(ax, ay, az, g.h[0], g.h[1], g.h[2], wx, wy, wz);
                 if (db <= cap && db < old) { t[hz][hy][hx] = db; ch = true; }
             }
