@@ -242,6 +242,7 @@ size_t layout(dcm_system *s, void *ws)
     s->fparts = b.take<Partial>(s->nfb);
     s->order = b.take<uint32_t>(s->nfb);
     s->wave_time = b.take<uint32_t>(s->nfb);
+    s->wave_hist = b.take<uint32_t>((int64_t)wave_order_scratch_words());
     s->kparts = b.take<Partial>(s->nkb);
     s->rparts = b.take<Partial>(reduce_stage_partials());
     s->nh = b.take<double>(4);
@@ -302,7 +303,7 @@ void rebin_sorted(dcm_system *s, hipStream_t st)
         std::swap(s->val, s->val_alt);
     }
     launch_cell_ranges(s->key, s->n, key_count(s->grid), s->gw.cell_start, s->sort_scratch, st);
-    launch_cell_fixup(s->gw.cell_start, key_count(s->grid), s->val, from.id, st);
+    launch_cell_fixup(s->key, s->n, s->val, from.id, st);
     launch_gather(from, to, s->val, s->n, st);
     s->cur = 1 - s->cur;
 }
@@ -374,6 +375,7 @@ ForceArgs force_args(const dcm_system *s, double *e_out, double *w_out, uint32_t
     a.list_cap = s->list_cap;
     a.order = s->order;
     a.wave_time = s->wave_time;
+    a.wave_hist = s->wave_hist;
     return a;
 }
 
@@ -477,7 +479,7 @@ dcm_status create_impl(const dcm_params *p, int64_t n, void *d_ws, size_t ws_byt
     launch_fill_u32(s->gw.flags, 0u, 1, st);
     launch_fill_u32((uint32_t *)s->nh, 0u, 8, st);
     launch_fill_u32(s->wave_time, 0u, s->nfb, st);
-    launch_wave_order(s->wave_time, s->order, s->nfb, st);
+    launch_wave_order(s->wave_time, s->order, s->wave_hist, s->nfb, st);
     launch_check_finite(d_x, 3 * n, s->gw.flags, st);
     launch_check_finite(d_v, 3 * n, s->gw.flags, st);
     launch_load_state(s->set[0], d_x, d_v, from_state ? d_rc : nullptr, n, p->rc_max, st);

@@ -627,65 +627,88 @@ __device__ __forceinline__ uint32_t duration_class(uint32_t t)
     return 511u - (c < 511u ? c : 511u);
 }
 
-// Counting sort of the waves by duration class, longest first, in one workgroup. Waves of one
-// class take no fixed order among themselves.
-struct KWaveOrder {
-    static constexpr int kThreads = 1024, kWaves = 0;
-    static constexpr int kClasses = 512, kLoads = 8;
+// Counting sort of the waves by duration class, longest first, in three launches over
+// kWaveGroups workgroups that each own a contiguous chunk of waves: per-chunk class counts,
+// the start of every (class, chunk) pair, and the scatter. Waves of one class and chunk take
+// no fixed order among themselves.
+constexpr int kWaveClasses = 512;
+constexpr int kWaveGroups = 64;
+
+__device__ __forceinline__ void wave_chunk(uint32_t nb, uint32_t w, uint32_t &lo, uint32_t &hi)
+{
+    const uint32_t per = (nb + kWaveGroups - 1) / kWaveGroups;
+    lo = min(nb, w * per);
+    hi = min(nb, lo + per);
+}
+
+struct KWaveCount {
+    static constexpr int kThreads = 256, kWaves = 0;
     struct Args {
         const uint32_t *t;
+        uint32_t *hist;     // [kWaveGroups][kWaveClasses]
+        uint32_t nb;
+    };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t)
+    {
+        __shared__ uint32_t cnt[kWaveClasses];
+        for (int k = threadIdx.x; k < kWaveClasses; k += kThreads) cnt[k] = 0u;
+        __syncthreads();
+        uint32_t lo, hi;
+        wave_chunk(a.nb, blk, lo, hi);
+        for (uint32_t k = lo + threadIdx.x; k < hi; k += kThreads) atomicAdd(&cnt[duration_class(a.t[k])], 1u);
+        __syncthreads();
+        for (int k = threadIdx.x; k < kWaveClasses; k += kThreads) a.hist[blk * kWaveClasses + k] = cnt[k];
+    }
+};
+
+// hist[w][c] becomes the first slot of class c's waves from chunk w: the waves of all longer
+// classes, then those of class c in earlier chunks.
+struct KWaveStarts {
+    static constexpr int kThreads = kWaveClasses, kWaves = 0;
+    struct Args { uint32_t *hist; };
+    static __device__ void run(const Args &a, uint32_t, uint32_t)
+    {
+        __shared__ uint32_t tot[2][kWaveClasses];
+        const int c = threadIdx.x;
+        uint32_t sum = 0u;
+        for (int w = 0; w < kWaveGroups; ++w) sum += a.hist[w * kWaveClasses + c];
+        tot[0][c] = sum;
+        __syncthreads();
+        // inclusive sums over the classes: Hillis-Steele doubling steps, ping-ponging
+        int src = 0;
+        for (int off = 1; off < kWaveClasses; off <<= 1) {
+            tot[1 - src][c] = tot[src][c] + (c >= off ? tot[src][c - off] : 0u);
+            __syncthreads();
+            src = 1 - src;
+        }
+        uint32_t base = c > 0 ? tot[src][c - 1] : 0u;
+        for (int w = 0; w < kWaveGroups; ++w) {
+            const uint32_t h = a.hist[w * kWaveClasses + c];
+            a.hist[w * kWaveClasses + c] = base;
+            base += h;
+        }
+    }
+};
+
+struct KWaveScatter {
+    static constexpr int kThreads = 256, kWaves = 0;
+    struct Args {
+        const uint32_t *t;
+        const uint32_t *hist;
         uint32_t *order;
         uint32_t nb;
     };
-    static __device__ void run(const Args &a, uint32_t, uint32_t);
-};
-
-__device__ void KWaveOrder::run(const Args &a, uint32_t, uint32_t)
-{
-    __shared__ uint32_t cnt[kClasses], next[kClasses];
-    for (int k = threadIdx.x; k < kClasses; k += kThreads) cnt[k] = 0u;
-    __syncthreads();
-    for (uint32_t k0 = 0; k0 < a.nb; k0 += kLoads * kThreads) {
-        uint32_t c[kLoads];
-#pragma unroll
-        for (int u = 0; u < kLoads; ++u) {
-            const uint32_t k = k0 + (uint32_t)(u * kThreads) + threadIdx.x;
-            c[u] = k < a.nb ? duration_class(a.t[k]) : (uint32_t)kClasses;
-        }
-#pragma unroll
-        for (int u = 0; u < kLoads; ++u)
-            if (c[u] < (uint32_t)kClasses) atomicAdd(&cnt[c[u]], 1u);
-    }
-    __syncthreads();
-    // exclusive prefix sum of the class counts: Hillis-Steele doubling steps over the 512
-    // counters (one thread each), ping-ponging between the two arrays
-    static_assert(kClasses <= kThreads, "one thread per class");
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t)
     {
-        uint32_t *src = cnt, *dst = next;
-        const int k = threadIdx.x;
-        for (int off = 1; off < kClasses; off <<= 1) {
-            if (k < kClasses) dst[k] = src[k] + (k >= off ? src[k - off] : 0u);
-            __syncthreads();
-            uint32_t *t = src; src = dst; dst = t;
-        }
-        // src holds the inclusive sums; shift them to exclusive ones in next
-        const uint32_t excl = (k < kClasses && k > 0) ? src[k - 1] : 0u;
+        __shared__ uint32_t next[kWaveClasses];
+        for (int k = threadIdx.x; k < kWaveClasses; k += kThreads) next[k] = a.hist[blk * kWaveClasses + k];
         __syncthreads();
-        if (k < kClasses) next[k] = excl;
+        uint32_t lo, hi;
+        wave_chunk(a.nb, blk, lo, hi);
+        for (uint32_t k = lo + threadIdx.x; k < hi; k += kThreads)
+            a.order[atomicAdd(&next[duration_class(a.t[k])], 1u)] = k;
     }
-    __syncthreads();
-    for (uint32_t k0 = 0; k0 < a.nb; k0 += kLoads * kThreads) {
-        uint32_t c[kLoads];
-#pragma unroll
-        for (int u = 0; u < kLoads; ++u) {
-            const uint32_t k = k0 + (uint32_t)(u * kThreads) + threadIdx.x;
-            c[u] = k < a.nb ? duration_class(a.t[k]) : (uint32_t)kClasses;
-        }
-#pragma unroll
-        for (int u = 0; u < kLoads; ++u)
-            if (c[u] < (uint32_t)kClasses) a.order[atomicAdd(&next[c[u]], 1u)] = k0 + (uint32_t)(u * kThreads) + threadIdx.x;
-    }
-}
+};
 
 // Neighbour lists: the force kernel's traversal with the search radius r_c[i] + skin, each
 // slot within it recorded (Alg. 3.3's list of the pairs within r_c + r_s).
@@ -748,9 +771,13 @@ void launch_build_list(const ForceArgs &a, double skin, hipStream_t st)
     emit<KBuildList>({a, skin}, (uint32_t)force_blocks(a.n), st);
 }
 
-void launch_wave_order(const uint32_t *wave_time, uint32_t *order, int64_t nb, hipStream_t st)
+size_t wave_order_scratch_words() { return (size_t)kWaveGroups * kWaveClasses; }
+
+void launch_wave_order(const uint32_t *wave_time, uint32_t *order, uint32_t *hist, int64_t nb, hipStream_t st)
 {
-    emit<KWaveOrder>({wave_time, order, (uint32_t)nb}, 1, st);
+    emit<KWaveCount>({wave_time, hist, (uint32_t)nb}, kWaveGroups, st);
+    emit<KWaveStarts>({hist}, 1, st);
+    emit<KWaveScatter>({wave_time, hist, order, (uint32_t)nb}, kWaveGroups, st);
 }
 
 void launch_forces(const ForceArgs &a, hipStream_t st)
@@ -758,7 +785,7 @@ void launch_forces(const ForceArgs &a, hipStream_t st)
     const int nb = force_blocks(a.n);
     if (a.precision == DCM_FP32C) launch_prec<DCM_FP32C>(a, nb, st);
     else launch_prec<DCM_FP64>(a, nb, st);
-    if (a.order && a.wave_time) launch_wave_order(a.wave_time, a.order, nb, st);
+    if (a.order && a.wave_time) launch_wave_order(a.wave_time, a.order, a.wave_hist, nb, st);
 }
 
 }  // namespace dcm

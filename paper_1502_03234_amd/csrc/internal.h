@@ -167,7 +167,7 @@ bool launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key_alt, uint32_t
                        void *scratch, int64_t n, int bits, hipStream_t st);
 void launch_cell_ranges(const uint32_t *key_sorted, int64_t n, int64_t G, uint32_t *cell_start,
                         void *sort_scratch, hipStream_t st);
-void launch_cell_fixup(const uint32_t *cell_start, int64_t G, uint32_t *val, const uint32_t *id_old,
+void launch_cell_fixup(const uint32_t *key_sorted, int64_t n, uint32_t *val, const uint32_t *id_old,
                        hipStream_t st);
 void launch_gather(PSet from, PSet to, const uint32_t *perm, int64_t n, hipStream_t st);
 
@@ -226,11 +226,13 @@ struct ForceArgs {
     // forces do not depend on the order
     uint32_t *order;
     uint32_t *wave_time;
+    uint32_t *wave_hist;    // wave_order_scratch_words() words for the ordering
 };
 int force_blocks(int64_t n);
 void launch_forces(const ForceArgs &a, hipStream_t st);
 // Longest-first order of nb force waves from their recorded durations.
-void launch_wave_order(const uint32_t *wave_time, uint32_t *order, int64_t nb, hipStream_t st);
+size_t wave_order_scratch_words();
+void launch_wave_order(const uint32_t *wave_time, uint32_t *order, uint32_t *hist, int64_t nb, hipStream_t st);
 // Lists of every slot within r_c[i] + skin, built by the force kernel's traversal (cell_start
 // must describe the current positions); sets kFlagListOverflow if a list exceeds list_cap.
 void launch_build_list(const ForceArgs &a, double skin, hipStream_t st);
@@ -310,6 +312,7 @@ struct dcm_system {
     dcm::GridWork gw;
     dcm::Partial *fparts, *kparts, *rparts;
     uint32_t *order, *wave_time;  // [nfb] force-wave launch order and last durations
+    uint32_t *wave_hist;          // scratch of the wave ordering
     double *nh;             // Nose-Hoover state {xi, eta, velocity scale of the last half step}
     dcm::NhConst nhc;
     int nfb, nkb;

@@ -359,25 +359,28 @@ __device__ void KCellRanges::run(const Args &args, uint32_t blk, uint32_t)
     }
 }
 
-// Inside each box, order slots by particle id (insertion sort; boxes hold a few particles).
+// Inside each storage cell, order slots by particle id (insertion sort; cells hold a few
+// particles). One thread per sorted slot: the first slot of a run of equal keys sorts the run.
 struct KCellFixup {
     static constexpr int kThreads = kBlock, kWaves = 0;
-    struct Args { const uint32_t *cell_start; int64_t G; uint32_t *val; const uint32_t *id; };
+    struct Args { const uint32_t *key; int64_t n; uint32_t *val; const uint32_t *id; };
     static __device__ void run(const Args &a, uint32_t blk, uint32_t);
 };
 
 __device__ void KCellFixup::run(const Args &a, uint32_t blk, uint32_t)
 {
-    const uint32_t *cell_start = a.cell_start, *id = a.id;
+    const uint32_t *key = a.key, *id = a.id;
     uint32_t *val = a.val;
-    int64_t c = (int64_t)blk * kThreads + threadIdx.x;
-    if (c >= a.G) return;
-    uint32_t s = cell_start[c], e = cell_start[c + 1];
-    if (e - s < 2) return;
-    for (uint32_t q = s + 1; q < e; ++q) {
+    const int64_t s = (int64_t)blk * kThreads + threadIdx.x;
+    if (s + 1 >= a.n) return;
+    const uint32_t k = key[s];
+    if ((s > 0 && key[s - 1] == k) || key[s + 1] != k) return;
+    int64_t e = s + 2;
+    while (e < a.n && key[e] == k) ++e;
+    for (int64_t q = s + 1; q < e; ++q) {
         uint32_t vq = val[q];
         uint32_t iq = id[vq];
-        uint32_t j = q;
+        int64_t j = q;
         while (j > s) {
             uint32_t vp = val[j - 1];
             if (id[vp] <= iq) break;
@@ -474,10 +477,10 @@ void launch_cell_ranges(const uint32_t *key_sorted, int64_t n, int64_t G, uint32
     emit<KCellRanges>({key_sorted, G, run_start, cell_start}, (uint32_t)nruns, st);
 }
 
-void launch_cell_fixup(const uint32_t *cell_start, int64_t G, uint32_t *val, const uint32_t *id_old,
+void launch_cell_fixup(const uint32_t *key_sorted, int64_t n, uint32_t *val, const uint32_t *id_old,
                        hipStream_t st)
 {
-    emit<KCellFixup>({cell_start, G, val, id_old}, grid1(G), st);
+    emit<KCellFixup>({key_sorted, n, val, id_old}, grid1(n), st);
 }
 
 void launch_gather(PSet from, PSet to, const uint32_t *perm, int64_t n, hipStream_t st)
