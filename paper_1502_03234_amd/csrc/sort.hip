@@ -337,25 +337,63 @@ __device__ void KCellRanges::run(const Args &args, uint32_t blk, uint32_t)
     const int64_t G = args.G;
     uint32_t *cell_start = args.cell_start;
     __shared__ uint32_t sk[kRangeKeys];
+    __shared__ uint32_t first[kRangeBoxes];
+    __shared__ uint32_t wmin[kBlock / 64];
+    constexpr int kPer = kRangeBoxes / kBlock;
     const int64_t c0 = (int64_t)blk * kRangeBoxes;
     const uint32_t lo = args.run_start[blk], hi = args.run_start[blk + 1];
     const uint32_t m = hi - lo;
-    const bool staged = m <= (uint32_t)kRangeKeys;
-    if (staged)
-        for (uint32_t q = threadIdx.x; q < m; q += kBlock) sk[q] = key[lo + q];
-    __syncthreads();
-    for (int r = 0; r < kRangeBoxes / kBlock; ++r) {
-        const int64_t c = c0 + r * kBlock + threadIdx.x;
-        if (c > G) break;
-        // first position in [0, m) whose key is >= c
-        uint32_t a = 0, b = m;
-        while (a < b) {
-            const uint32_t mid = (a + b) >> 1;
-            const uint32_t km = staged ? sk[mid] : key[lo + mid];
-            if ((int64_t)km < c) a = mid + 1;
-            else b = mid;
+    if (m > (uint32_t)kRangeKeys) {
+        // too many keys to stage: every box finds its start by binary search in global memory
+        for (int r = 0; r < kPer; ++r) {
+            const int64_t c = c0 + r * kBlock + threadIdx.x;
+            if (c > G) break;
+            uint32_t a = 0, b = m;
+            while (a < b) {
+                const uint32_t mid = (a + b) >> 1;
+                if ((int64_t)key[lo + mid] < c) a = mid + 1;
+                else b = mid;
+            }
+            cell_start[c] = lo + a;
         }
-        cell_start[c] = lo + a;
+        return;
+    }
+    // every key of this run lies in [c0, c0 + kRangeBoxes): the first slot of each key is its
+    // box's start; an empty box starts where the next non-empty box of the run does, or at hi
+    for (int q = threadIdx.x; q < kRangeBoxes; q += kBlock) first[q] = hi;
+    for (uint32_t q = threadIdx.x; q < m; q += kBlock) sk[q] = key[lo + q];
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < m; q += kBlock)
+        if (q == 0 || sk[q - 1] != sk[q]) first[sk[q] - (uint32_t)c0] = lo + q;
+    __syncthreads();
+    // suffix minimum over the boxes: kPer consecutive boxes per thread, then over the threads
+    uint32_t v[kPer];
+    uint32_t run = 0xffffffffu;
+#pragma unroll
+    for (int r = kPer - 1; r >= 0; --r) {
+        run = min(run, first[threadIdx.x * kPer + r]);
+        v[r] = run;
+    }
+    // inclusive suffix minimum of the per-thread minima within the wave (lanes above)
+    const unsigned lane = lane_id();
+    uint32_t suf = run;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_down(suf, off, 64);
+        if (lane + off < 64u) suf = min(suf, t);
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane == 0) wmin[w] = suf;
+    __syncthreads();
+    // minimum over the later waves and over the later lanes of this wave
+    uint32_t after = 0xffffffffu;
+    for (int q = w + 1; q < kBlock / 64; ++q) after = min(after, wmin[q]);
+    const uint32_t later_lanes = __shfl_down(suf, 1, 64);
+    if (lane < 63u) after = min(after, later_lanes);
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const int64_t c = c0 + threadIdx.x * kPer + r;
+        if (c <= G) cell_start[c] = min(v[r], after);
     }
 }
 
