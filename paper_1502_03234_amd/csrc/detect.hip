@@ -699,6 +699,27 @@ __device__ void KDistInit::run(const Args &args_, uint32_t blk, uint32_t)
     if (front) dirty[tile_of(g, i, j, k)] = 1u;
 }
 
+__host__ __device__ inline int64_t distance_tile_count(const Grid &g)
+{
+    return (int64_t)((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY) * ((g.n[2] + TZ - 1) / TZ);
+}
+
+// The first kDistFullPasses passes launch one workgroup per tile. Later passes, where few tiles
+// are dirty or the solve has converged, launch fewer workgroups: each takes every nblk-th tile
+// (at most kDistListMax of them), reads their dirty flags at once and relaxes only the dirty
+// ones.
+constexpr int kDistFullPasses = 8;
+constexpr int kDistListMax = 1024;
+constexpr int64_t kDistLateGroups = 256;
+
+inline unsigned distance_groups(int64_t ntiles, int it)
+{
+    if (it < kDistFullPasses) return (unsigned)ntiles;
+    int64_t gr = ntiles < kDistLateGroups ? ntiles : kDistLateGroups;
+    const int64_t need = (ntiles + kDistListMax - 1) / kDistListMax;
+    return (unsigned)(gr > need ? gr : need);
+}
+
 struct KDistTiles {
     static constexpr int kThreads = kTileThreads, kWaves = 0;
     struct Args {
@@ -716,7 +737,42 @@ struct KDistTiles {
     static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
 };
 
+// One tile of one pass (b uniform over the workgroup).
+__device__ __forceinline__ void dist_tile(const KDistTiles::Args &args_, int b, int ntiles);
+
 __device__ void KDistTiles::run(const Args &args_, uint32_t blk, uint32_t nblk)
+{
+    const int it = args_.it;
+    // once a pass has changed nothing, later passes leave every array as it is (the gather
+    // takes the copy flags of the last pass that ran)
+    if (it > 0 && __hip_atomic_load(args_.changed + it - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        return;
+    const int ntiles = (int)distance_tile_count(args_.g);
+    if ((int)nblk >= ntiles) {
+        dist_tile(args_, (int)blk, ntiles);
+        return;
+    }
+    uint32_t *dflag = args_.dirty + (it & 1) * ntiles;
+    const uint32_t *cprev = args_.cur + (it & 1) * ntiles;
+    uint32_t *cnext = args_.cur + ((it + 1) & 1) * ntiles;
+    __shared__ int list[kDistListMax];
+    __shared__ uint32_t count;
+    if (threadIdx.x == 0) count = 0u;
+    __syncthreads();
+    // clean tiles carry their copy flag over; dirty ones are listed
+    for (int64_t b = blk + (int64_t)threadIdx.x * nblk; b < ntiles; b += (int64_t)kTileThreads * nblk) {
+        if (dflag[b]) list[atomicAdd(&count, 1u)] = (int)b;
+        else cnext[b] = cprev[b];
+    }
+    __syncthreads();
+    const uint32_t m = count;
+    for (uint32_t q = 0; q < m; ++q) {
+        __syncthreads();
+        dist_tile(args_, list[q], ntiles);
+    }
+}
+
+__device__ __forceinline__ void dist_tile(const KDistTiles::Args &args_, int b, int ntiles)
 {
     Grid g = args_.g;
     const uint8_t *label = args_.label;
@@ -728,17 +784,10 @@ __device__ void KDistTiles::run(const Args &args_, uint32_t blk, uint32_t nblk)
     uint32_t *cur = args_.cur;
     int it = args_.it;
     const uint8_t zero = args_.zero;
-    const int b = blk;
-    const int ntiles = nblk;
     uint32_t *dflag = dirty + (it & 1) * ntiles, *dnext = dirty + ((it + 1) & 1) * ntiles;
     const uint32_t *cprev = cur + (it & 1) * ntiles;
     uint32_t *cnext = cur + ((it + 1) & 1) * ntiles;
-    const bool converged = it > 0 &&
-        __hip_atomic_load(changed + it - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
     const uint32_t mycur = cprev[b];
-    // once a pass has changed nothing, later passes leave every array as it is (the gather
-    // takes the copy flags of the last pass that ran)
-    if (converged) return;
     if (dflag[b] == 0) {
         if (threadIdx.x == 0) { cnext[b] = mycur; dflag[b] = 0u; }
         return;
@@ -1091,10 +1140,7 @@ int64_t component_tiles(const Grid &g)
     return (int64_t)((g.n[0] + CT - 1) / CT) * ((g.n[1] + CT - 1) / CT) * ((g.n[2] + CT - 1) / CT);
 }
 
-int64_t distance_tiles(const Grid &g)
-{
-    return (int64_t)((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY) * ((g.n[2] + TZ - 1) / TZ);
-}
+int64_t distance_tiles(const Grid &g) { return distance_tile_count(g); }
 
 // Global passes needed: the band depth in tiles plus slack; reaching the bound is reported.
 int max_distance_sweeps(const Grid &g, double cap)
@@ -1114,7 +1160,8 @@ void launch_distance(const Grid &g, double cap, const uint8_t *label, uint8_t ze
     emit<KDistInit>({g, label, dist, w.tdirty, zero}, grid1(g.G), st);
     launch_fill_u32(w.tcur, 0u, 2 * (int64_t)ntiles, st);
     for (int it = 0; it < ms; ++it)
-        emit<KDistTiles>({g, label, dist, w.dist2, cap, w.changed, w.tdirty, w.tcur, it, zero}, ntiles, st);
+        emit<KDistTiles>({g, label, dist, w.dist2, cap, w.changed, w.tdirty, w.tcur, it, zero},
+                         distance_groups(ntiles, it), st);
     emit<KDistGather>({g, dist, (const double *)w.dist2, w.tcur, w.changed, ms, (int)ntiles}, grid1(g.G), st);
     emit<KDistFinish>({w.changed, ms, sweeps, w.flags}, 1, st);
 }
