@@ -638,6 +638,36 @@ __device__ double godunov(double a0, double a1, double a2, double h0, double h1,
     return d;
 }
 
+// The same root when every axis has the same edge h (w = 1 / h^2): the a_k are sorted by
+// minimum and maximum alone (equal edges and weights need not travel with them), then the
+// operations above run in the same order on the same operands, so the result is the same to
+// the bit.
+__device__ double godunov_uniform(double a0, double a1, double a2, double h, double w)
+{
+    const double lo = fmin(a0, a1), hi = fmax(a0, a1);
+    const double b0 = fmin(lo, a2), mid = fmax(lo, a2);
+    const double b1 = fmin(mid, hi), b2 = fmax(mid, hi);
+    if (isinf(b0)) return INFINITY;
+    double d = b0 + h;
+    if (d > b1) {
+        double sw = w + w;
+        double swa = w * b0 + w * b1;
+        double dd = b0 - b1;
+        double disc = sw - w * w * (dd * dd);
+        if (disc < 0.0) disc = 0.0;
+        d = (swa + sqrt(disc)) / sw;
+        if (d > b2) {
+            sw = w + w + w;
+            swa = w * b0 + w * b1 + w * b2;
+            double d01 = b0 - b1, d02 = b0 - b2, d12 = b1 - b2;
+            disc = sw - (w * w * (d01 * d01) + w * w * (d02 * d02) + w * w * (d12 * d12));
+            if (disc < 0.0) disc = 0.0;
+            d = (swa + sqrt(disc)) / sw;
+        }
+    }
+    return d;
+}
+
 // One global relaxation pass over LDS tiles. Two copies of the distance grid alternate;
 // cur[t] says which copy holds tile t's values as of the end of the previous pass. A tile
 // marked dirty loads its boxes and a one-box halo (each from the copy current for the tile that
@@ -842,6 +872,7 @@ __device__ __forceinline__ void dist_tile(const KDistTiles::Args &args_, int b, 
             liq[p][m] = gx < g.n[0] && gy < g.n[1] && gz < g.n[2] && label[lin(g, gx, gy, gz)] != zero;
         }
     const double wx = 1.0 / (g.h[0] * g.h[0]), wy = 1.0 / (g.h[1] * g.h[1]), wz = 1.0 / (g.h[2] * g.h[2]);
+    const bool uniform = g.h[0] == g.h[1] && g.h[1] == g.h[2];
     __syncthreads();
     // the loaded values of this thread's boxes (the tile's own copy), to detect changes
     double init[2][2];
@@ -867,7 +898,8 @@ __device__ __forceinline__ void dist_tile(const KDistTiles::Args &args_, int b, 
                 seen[p][m][0] = ax; seen[p][m][1] = ay; seen[p][m][2] = az;
                 if (isinf(ax) && isinf(ay) && isinf(az)) continue;
                 const double old = t[hz][hy][hx];
-                const double db = godunov(ax, ay, az, g.h[0], g.h[1], g.h[2], wx, wy, wz);
+                const double db = uniform ? godunov_uniform(ax, ay, az, g.h[0], wx)
+                                          : godunov(ax, ay, az, g.h[0], g.h[1], g.h[2], wx, wy, wz);
                 if (db <= cap && db < old) { t[hz][hy][hx] = db; ch = true; }
             }
             if (p == 0) __syncthreads();
