@@ -332,8 +332,8 @@ void detect(dcm_system *s, hipStream_t st, bool with_cutoffs = true)
     launch_segment(g, w.g, w.km, s->p.min_component, ms, w, st);
     stage_end(s, st);
     stage_begin(s, 5, st);
-    launch_distance(g, s->cap, w.label, kLabelVapor, w.dist, w, w.stats + 5, st);
-    if (w.dist_v) launch_distance(g, s->cap, w.label, kLabelLiquid, w.dist_v, w, w.stats + 6, st);
+    launch_distance(g, s->cap, w.label, kLabelVapor, w.dist, w, w.stats + 5, true, st);
+    if (w.dist_v) launch_distance(g, s->cap, w.label, kLabelLiquid, w.dist_v, w, w.stats + 6, true, st);
     stage_end(s, st);
     if (!with_cutoffs) return;
     stage_begin(s, 6, st);
@@ -477,9 +477,10 @@ dcm_status create_impl(const dcm_params *p, int64_t n, void *d_ws, size_t ws_byt
     s->k = from_state ? step : 0;
     hipStream_t st = (hipStream_t)stream;
     launch_fill_u32(s->gw.flags, 0u, 1, st);
+    launch_distance_flags_zero(s->grid, s->cap, s->gw, st);
     launch_fill_u32((uint32_t *)s->nh, 0u, 8, st);
     launch_fill_u32(s->wave_time, 0u, s->nfb, st);
-    launch_wave_order(s->wave_time, s->order, s->wave_hist, s->nfb, st);
+    launch_wave_order(s->wave_time, s->order, s->wave_hist, s->nfb, false, st);
     launch_check_finite(d_x, 3 * n, s->gw.flags, st);
     launch_check_finite(d_v, 3 * n, s->gw.flags, st);
     launch_load_state(s->set[0], d_x, d_v, from_state ? d_rc : nullptr, n, p->rc_max, st);
@@ -957,7 +958,7 @@ dcm_status dcm_grid_distance(const int32_t dims[3], const double h[3], double ca
     hipStream_t st = (hipStream_t)stream;
     launch_fill_u32(w.flags, 0u, 1, st);
     launch_fill_u32((uint32_t *)w.stats, 0u, 16, st);
-    launch_distance(g, cap, d_label, kLabelVapor, d_dist, w, w.stats + 5, st);
+    launch_distance(g, cap, d_label, kLabelVapor, d_dist, w, w.stats + 5, false, st);
     launch_cap_copy(d_dist, cap, d_dist, g.G, st);
     if (d_sweeps) launch_copy_bytes(d_sweeps, w.stats + 5, sizeof(long long), st);
     return hip_status("dcm_grid_distance");

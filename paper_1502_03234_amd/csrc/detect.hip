@@ -987,29 +987,41 @@ __device__ void KDistGather::run(const Args &args_, uint32_t blk, uint32_t)
     if (cur_final[owner]) d0[c] = d1[c];
 }
 
+// Sweep count and the not-converged flag; then the per-pass change flags, tile dirty flags and
+// tile copy flags go back to zero, as the next solve expects them.
 struct KDistFinish {
-    static constexpr int kThreads = 64, kWaves = 0;
+    static constexpr int kThreads = kBlock, kWaves = 0;
     struct Args {
-        const uint32_t *changed;
+        uint32_t *changed;
         int max_sweeps;
         long long *sweeps;
         uint32_t *flags;
+        uint32_t *dirty;   // [2][tiles]
+        uint32_t *cur;     // [2][tiles]
+        int64_t ntiles;
     };
     static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
 };
 
-__device__ void KDistFinish::run(const Args &args_, uint32_t blk, uint32_t)
+__device__ void KDistFinish::run(const Args &args_, uint32_t blk, uint32_t nblk)
 {
-    const uint32_t *changed = args_.changed;
-    int max_sweeps = args_.max_sweeps;
-    long long *sweeps = args_.sweeps;
-    uint32_t *flags = args_.flags;
-    if (threadIdx.x != 0 || blk != 0) return;
-    int used = max_sweeps;
-    for (int s = 0; s < max_sweeps; ++s)
-        if (changed[s] == 0) { used = s + 1; break; }
-    if (sweeps) *sweeps = used;
-    if (changed[max_sweeps - 1] != 0) atomicOr(flags, kFlagNotConverged);
+    uint32_t *changed = args_.changed;
+    const int max_sweeps = args_.max_sweeps;
+    if (blk == 0) {
+        if (threadIdx.x == 0) {
+            int used = max_sweeps;
+            for (int s = 0; s < max_sweeps; ++s)
+                if (changed[s] == 0) { used = s + 1; break; }
+            if (args_.sweeps) *args_.sweeps = used;
+            if (changed[max_sweeps - 1] != 0) atomicOr(args_.flags, kFlagNotConverged);
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q <= max_sweeps; q += kThreads) changed[q] = 0u;
+    }
+    for (int64_t q = (int64_t)blk * kThreads + threadIdx.x; q < 2 * args_.ntiles; q += (int64_t)nblk * kThreads) {
+        args_.dirty[q] = 0u;
+        args_.cur[q] = 0u;
+    }
 }
 
 struct KCapCopy {
@@ -1183,19 +1195,30 @@ int max_distance_sweeps(const Grid &g, double cap)
 }
 
 void launch_distance(const Grid &g, double cap, const uint8_t *label, uint8_t zero, double *dist,
-                     GridWork w, long long *sweeps, hipStream_t st)
+                     GridWork w, long long *sweeps, bool flags_zero, hipStream_t st)
 {
     int ms = max_distance_sweeps(g, cap);
-    launch_fill_u32(w.changed, 0u, ms + 1, st);
     const unsigned ntiles = (unsigned)distance_tiles(g);
-    launch_fill_u32(w.tdirty, 0u, 2 * (int64_t)ntiles, st);
+    if (!flags_zero) {
+        launch_fill_u32(w.changed, 0u, ms + 1, st);
+        launch_fill_u32(w.tdirty, 0u, 2 * (int64_t)ntiles, st);
+        launch_fill_u32(w.tcur, 0u, 2 * (int64_t)ntiles, st);
+    }
     emit<KDistInit>({g, label, dist, w.tdirty, zero}, grid1(g.G), st);
-    launch_fill_u32(w.tcur, 0u, 2 * (int64_t)ntiles, st);
     for (int it = 0; it < ms; ++it)
         emit<KDistTiles>({g, label, dist, w.dist2, cap, w.changed, w.tdirty, w.tcur, it, zero},
                          distance_groups(ntiles, it), st);
     emit<KDistGather>({g, dist, (const double *)w.dist2, w.tcur, w.changed, ms, (int)ntiles}, grid1(g.G), st);
-    emit<KDistFinish>({w.changed, ms, sweeps, w.flags}, 1, st);
+    const unsigned fb = grid1(2 * (int64_t)ntiles);
+    emit<KDistFinish>({w.changed, ms, sweeps, w.flags, w.tdirty, w.tcur, (int64_t)ntiles}, fb < 256u ? fb : 256u, st);
+}
+
+void launch_distance_flags_zero(const Grid &g, double cap, GridWork w, hipStream_t st)
+{
+    launch_fill_u32(w.changed, 0u, max_distance_sweeps(g, cap) + 1, st);
+    const int64_t ntiles = distance_tiles(g);
+    launch_fill_u32(w.tdirty, 0u, 2 * ntiles, st);
+    launch_fill_u32(w.tcur, 0u, 2 * ntiles, st);
 }
 
 void launch_cap_copy(const double *dist, double cap, double *out, int64_t G, hipStream_t st)

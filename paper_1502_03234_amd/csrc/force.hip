@@ -487,6 +487,25 @@ __device__ __forceinline__ void list_scan(const ForceArgs &a, bool live, const P
     }
 }
 
+// Duration class, 16 per octave (monotone in t), numbered from the longest: 0 .. 511.
+__device__ __forceinline__ uint32_t duration_class(uint32_t t)
+{
+    const uint32_t v = t < 0xffffffffu ? t + 1u : t;
+    const int e = 31 - __clz(v);
+    const uint32_t c = e < 4 ? v : ((uint32_t)(e - 3) << 4) | ((v >> (e - 4)) & 15u);
+    return 511u - (c < 511u ? c : 511u);
+}
+
+constexpr int kWaveClasses = 512;
+constexpr int kWaveGroups = 64;
+
+__device__ __forceinline__ void wave_chunk(uint32_t nb, uint32_t w, uint32_t &lo, uint32_t &hi)
+{
+    const uint32_t per = (nb + kWaveGroups - 1) / kWaveGroups;
+    lo = min(nb, w * per);
+    hi = min(nb, lo + per);
+}
+
 // Compiled for 4 waves per SIMD (128 VGPRs per lane).
 template <int PAIR, bool SHIFT, int U, int PREC, bool LIST = false>
 struct KForces {
@@ -613,34 +632,22 @@ __device__ void KForces<PAIR, SHIFT, U, PREC, LIST>::run(const Args &args_, uint
         a.partials[b] = p;
         if (a.wave_time) {
             const uint64_t dt = __builtin_amdgcn_s_memrealtime() - t_start;
-            a.wave_time[b] = dt < 0xffffffffull ? (uint32_t)dt : 0xffffffffu;
+            const uint32_t t32 = dt < 0xffffffffull ? (uint32_t)dt : 0xffffffffu;
+            a.wave_time[b] = t32;
+            // the count of the ordering's counting sort: chunk of this wave, duration class
+            if (a.wave_hist) {
+                const uint32_t per = (nblk + kWaveGroups - 1) / kWaveGroups;
+                atomicAdd(&a.wave_hist[(uint32_t)b / per * kWaveClasses + duration_class(t32)], 1u);
+            }
         }
     }
 }
 
-// Duration class, 16 per octave (monotone in t), numbered from the longest: 0 .. 511.
-__device__ __forceinline__ uint32_t duration_class(uint32_t t)
-{
-    const uint32_t v = t < 0xffffffffu ? t + 1u : t;
-    const int e = 31 - __clz(v);
-    const uint32_t c = e < 4 ? v : ((uint32_t)(e - 3) << 4) | ((v >> (e - 4)) & 15u);
-    return 511u - (c < 511u ? c : 511u);
-}
-
-// Counting sort of the waves by duration class, longest first, in three launches over
-// kWaveGroups workgroups that each own a contiguous chunk of waves: per-chunk class counts,
-// the start of every (class, chunk) pair, and the scatter. Waves of one class and chunk take
-// no fixed order among themselves.
-constexpr int kWaveClasses = 512;
-constexpr int kWaveGroups = 64;
-
-__device__ __forceinline__ void wave_chunk(uint32_t nb, uint32_t w, uint32_t &lo, uint32_t &hi)
-{
-    const uint32_t per = (nb + kWaveGroups - 1) / kWaveGroups;
-    lo = min(nb, w * per);
-    hi = min(nb, lo + per);
-}
-
+// Counting sort of the waves by duration class, longest first, over kWaveGroups chunks of
+// consecutive waves: per-chunk class counts (taken by the force kernel's waves as they finish,
+// or by KWaveCount), the start of every (class, chunk) pair, and the scatter, which leaves the
+// counts at zero for the next force launch. Waves of one class and chunk take no fixed order
+// among themselves.
 struct KWaveCount {
     static constexpr int kThreads = 256, kWaves = 0;
     struct Args {
@@ -694,14 +701,17 @@ struct KWaveScatter {
     static constexpr int kThreads = 256, kWaves = 0;
     struct Args {
         const uint32_t *t;
-        const uint32_t *hist;
+        uint32_t *hist;
         uint32_t *order;
         uint32_t nb;
     };
     static __device__ void run(const Args &a, uint32_t blk, uint32_t)
     {
         __shared__ uint32_t next[kWaveClasses];
-        for (int k = threadIdx.x; k < kWaveClasses; k += kThreads) next[k] = a.hist[blk * kWaveClasses + k];
+        for (int k = threadIdx.x; k < kWaveClasses; k += kThreads) {
+            next[k] = a.hist[blk * kWaveClasses + k];
+            a.hist[blk * kWaveClasses + k] = 0u;
+        }
         __syncthreads();
         uint32_t lo, hi;
         wave_chunk(a.nb, blk, lo, hi);
@@ -773,9 +783,10 @@ void launch_build_list(const ForceArgs &a, double skin, hipStream_t st)
 
 size_t wave_order_scratch_words() { return (size_t)kWaveGroups * kWaveClasses; }
 
-void launch_wave_order(const uint32_t *wave_time, uint32_t *order, uint32_t *hist, int64_t nb, hipStream_t st)
+void launch_wave_order(const uint32_t *wave_time, uint32_t *order, uint32_t *hist, int64_t nb, bool counted,
+                       hipStream_t st)
 {
-    emit<KWaveCount>({wave_time, hist, (uint32_t)nb}, kWaveGroups, st);
+    if (!counted) emit<KWaveCount>({wave_time, hist, (uint32_t)nb}, kWaveGroups, st);
     emit<KWaveStarts>({hist}, 1, st);
     emit<KWaveScatter>({wave_time, hist, order, (uint32_t)nb}, kWaveGroups, st);
 }
@@ -785,7 +796,7 @@ void launch_forces(const ForceArgs &a, hipStream_t st)
     const int nb = force_blocks(a.n);
     if (a.precision == DCM_FP32C) launch_prec<DCM_FP32C>(a, nb, st);
     else launch_prec<DCM_FP64>(a, nb, st);
-    if (a.order && a.wave_time) launch_wave_order(a.wave_time, a.order, a.wave_hist, nb, st);
+    if (a.order && a.wave_time) launch_wave_order(a.wave_time, a.order, a.wave_hist, nb, true, st);
 }
 
 }  // namespace dcm

@@ -187,9 +187,12 @@ int64_t distance_tiles(const Grid &g);
 int64_t component_tiles(const Grid &g);
 
 // Distance of every box to the boxes labelled `zero` (which get 0); the sweep count goes to
-// *sweeps.
+// *sweeps. The solve leaves its pass and tile flags at zero; flags_zero = true says they are
+// zero already (a previous solve on this workspace, or launch_distance_flags_zero), so they
+// are not cleared first.
 void launch_distance(const Grid &g, double cap, const uint8_t *label, uint8_t zero, double *dist,
-                     GridWork w, long long *sweeps, hipStream_t st);
+                     GridWork w, long long *sweeps, bool flags_zero, hipStream_t st);
+void launch_distance_flags_zero(const Grid &g, double cap, GridWork w, hipStream_t st);
 // dist_v (optional): box-liquid distances; the cutoff then takes the larger of the two depths.
 void launch_cutoffs(const Grid &g, PSet s, int64_t n, const double *dist, const double *dist_v, double cap,
                     double rc_min, double rc_max, double alpha, double a, double b, int linear, hipStream_t st);
@@ -232,7 +235,10 @@ int force_blocks(int64_t n);
 void launch_forces(const ForceArgs &a, hipStream_t st);
 // Longest-first order of nb force waves from their recorded durations.
 size_t wave_order_scratch_words();
-void launch_wave_order(const uint32_t *wave_time, uint32_t *order, uint32_t *hist, int64_t nb, hipStream_t st);
+// counted = true: the force launch has already counted its waves into hist (which the
+// ordering leaves at zero); false: count them from wave_time first (hist may hold anything).
+void launch_wave_order(const uint32_t *wave_time, uint32_t *order, uint32_t *hist, int64_t nb, bool counted,
+                       hipStream_t st);
 // Lists of every slot within r_c[i] + skin, built by the force kernel's traversal (cell_start
 // must describe the current positions); sets kFlagListOverflow if a list exceeds list_cap.
 void launch_build_list(const ForceArgs &a, double skin, hipStream_t st);
