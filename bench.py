@@ -29,7 +29,7 @@ WORKLOAD = "slab2m"
 # Valid only for the kernel source it was taken on: reported as null once csrc/force.hip no longer
 # hashes to this value.
 FORCE_TRAFFIC_BYTES = 3.09e9
-FORCE_TRAFFIC_SRC = "abbfeac1d0af6162"
+FORCE_TRAFFIC_SRC = "83a2adb96acc3d5a"
 
 
 def force_traffic():
