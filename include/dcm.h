@@ -258,8 +258,8 @@ dcm_status dcm_check(dcm_system *s, dcm_stream_t stream);
 /* Per-stage timing with HIP events on the system's stream (off by default). Stages:
  * 0 kick/drift/key, 1 sort and cell ranges, 2 smoothing, 3 two-means, 4 labels and
  * components, 5 distance (both solves with the tail correction), 6 interpolation and
- * cutoffs, 7 pair forces, 8 reductions, 9 tail correction, 10 neighbour-list checks and
- * builds.
+ * cutoffs, 7 pair forces (the force kernel alone), 8 reductions and the ordering of the force
+ * waves for the next launch, 9 tail correction, 10 neighbour-list checks and builds.
  * on: 0 off, 1 every stage, 2 the pair-force stage only (two events per force launch).
  * DCM_E_INVALID for another level. dcm_stage_times synchronizes and returns total
  * milliseconds and launch counts per stage (arrays of DCM_NSTAGES) accumulated since

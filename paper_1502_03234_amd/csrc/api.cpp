@@ -385,6 +385,9 @@ void forces(dcm_system *s, hipStream_t st, double *e_out, double *w_out, uint32_
     stage_begin(s, 7, st);
     launch_forces(a, st);
     stage_end(s, st);
+    stage_begin(s, 8, st);
+    launch_force_wave_order(a, st);
+    stage_end(s, st);
     if (s->p.tail) {
         TailArgs t;
         t.grid = s->grid;

@@ -796,7 +796,11 @@ void launch_forces(const ForceArgs &a, hipStream_t st)
     const int nb = force_blocks(a.n);
     if (a.precision == DCM_FP32C) launch_prec<DCM_FP32C>(a, nb, st);
     else launch_prec<DCM_FP64>(a, nb, st);
-    if (a.order && a.wave_time) launch_wave_order(a.wave_time, a.order, a.wave_hist, nb, true, st);
+}
+
+void launch_force_wave_order(const ForceArgs &a, hipStream_t st)
+{
+    if (a.order && a.wave_time) launch_wave_order(a.wave_time, a.order, a.wave_hist, force_blocks(a.n), true, st);
 }
 
 }  // namespace dcm

@@ -232,7 +232,10 @@ struct ForceArgs {
     uint32_t *wave_hist;    // wave_order_scratch_words() words for the ordering
 };
 int force_blocks(int64_t n);
+// The pair-force kernel alone; launch_force_wave_order then orders the waves for the next
+// launch from the durations this one recorded (every force launch is followed by it).
 void launch_forces(const ForceArgs &a, hipStream_t st);
+void launch_force_wave_order(const ForceArgs &a, hipStream_t st);
 // Longest-first order of nb force waves from their recorded durations.
 size_t wave_order_scratch_words();
 // counted = true: the force launch has already counted its waves into hist (which the
