@@ -42,9 +42,10 @@ def force_traffic():
 
 def stage_bandwidth(breakdown: dict, n: int, G: int, detect_every: int) -> dict:
     """Achieved bandwidth of the HBM-bound stages: algorithmic bytes per step / stage time.
-    Per particle: kick/drift/key 144 B (read x, v, F; write x, v, key, value); binning 196 B
-    (three radix passes of 24 B, in-cell order 4 B, gather 120 B) plus 8 B per box (the starts
-    of its two storage cells). Per box and
+    Per particle: kick/drift/key 144 B (read x, v, F; write x, v, key, value); binning 152 B
+    (count: key read, rank written, 8 B; scatter: key, rank and cell start read, key and source
+    slot written, 20 B; in-cell order 4 B; gather 120 B) plus 24 B per box (its two storage
+    cells' counts read, starts written and counts cleared). Per box and
     detection: smoothing 24 B (three axis passes of 8 B), two-means 4 B (histogram read),
     labels and components 66 B (threshold 6 B, two component passes of about 30 B). Per particle
     and detection: cutoffs 96 B (eight 8-byte box values, the 32-byte position record read).
@@ -55,7 +56,7 @@ def stage_bandwidth(breakdown: dict, n: int, G: int, detect_every: int) -> dict:
     per_det = 1.0 / detect_every if detect_every > 0 else 0.0
     bytes_per_step = {
         "kick_drift_key": 144.0 * n,
-        "sort": 196.0 * n + 8.0 * G,
+        "sort": 152.0 * n + 24.0 * G,
         "smooth": 24.0 * G * per_det,
         "two_means": 4.0 * G * per_det,
         "segment": 66.0 * G * per_det,

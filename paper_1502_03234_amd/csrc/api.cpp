@@ -162,15 +162,6 @@ dcm_status validate(const dcm_params *p, int64_t n, Grid &g)
     return DCM_OK;
 }
 
-int key_bits(int64_t G)
-{
-    int b = 1;
-    while (((int64_t)1 << b) < G) ++b;
-    return b;
-}
-
-
-
 }  // namespace
 
 
@@ -264,7 +255,6 @@ void init_derived(dcm_system *s)
         s->cut_a = 0.0;
         s->cut_b = p.rc_max;
     }
-    s->bits = key_bits(key_count(s->grid));
     // g = 3n - 3: the thermostat leaves the total momentum unchanged (it scales it), so the
     // centre-of-mass degrees of freedom are not thermalised
     const double g = 3.0 * (double)s->n - 3.0;
@@ -298,11 +288,9 @@ void stage_end(dcm_system *s, hipStream_t st)
 void rebin_sorted(dcm_system *s, hipStream_t st)
 {
     PSet from = s->set[s->cur], to = s->set[1 - s->cur];
-    if (launch_radix_sort(s->key, s->val, s->key_alt, s->val_alt, s->sort_scratch, s->n, s->bits, st)) {
-        std::swap(s->key, s->key_alt);
-        std::swap(s->val, s->val_alt);
-    }
-    launch_cell_ranges(s->key, s->n, key_count(s->grid), s->gw.cell_start, s->sort_scratch, st);
+    launch_cell_sort(s->key, s->key_alt, s->val_alt, s->gw.cell_start, s->sort_scratch, s->n, key_count(s->grid), st);
+    std::swap(s->key, s->key_alt);
+    std::swap(s->val, s->val_alt);
     launch_cell_fixup(s->key, s->n, s->val, from.id, st);
     launch_gather(from, to, s->val, s->n, st);
     s->cur = 1 - s->cur;
@@ -481,6 +469,7 @@ dcm_status create_impl(const dcm_params *p, int64_t n, void *d_ws, size_t ws_byt
     hipStream_t st = (hipStream_t)stream;
     launch_fill_u32(s->gw.flags, 0u, 1, st);
     launch_distance_flags_zero(s->grid, s->cap, s->gw, st);
+    launch_cell_sort_init(s->sort_scratch, n, key_count(s->grid), st);
     launch_fill_u32((uint32_t *)s->nh, 0u, 8, st);
     launch_fill_u32(s->wave_time, 0u, s->nfb, st);
     launch_wave_order(s->wave_time, s->order, s->wave_hist, s->nfb, false, st);

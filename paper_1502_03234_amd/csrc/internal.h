@@ -153,7 +153,7 @@ dcm_status report_error(dcm_status s, const char *fmt, ...);
 
 // ---- launchers (each enqueues on `st`; no synchronization) ------------------------------
 // sort.hip
-size_t sort_scratch_bytes(int64_t n, int64_t G);
+size_t sort_scratch_bytes(int64_t n, int64_t K);
 void launch_wrap_key(const Grid &g, PSet s, int64_t n, uint32_t *key, uint32_t *val, hipStream_t st);
 void launch_init_ids(PSet s, int64_t n, hipStream_t st);
 // Box counts of the current positions into count (linear box index); clears count first.
@@ -162,11 +162,13 @@ void launch_count_boxes(const Grid &g, const double4 *pos, int64_t n, uint32_t *
 // as double bit patterns.
 void launch_list_check(const Grid &g, const double4 *pos, const double4 *pos_build, int64_t n,
                        unsigned long long *out, hipStream_t st);
-// Returns true when the sorted keys and values end in key_alt / val_alt.
-bool launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key_alt, uint32_t *val_alt,
-                       void *scratch, int64_t n, int bits, hipStream_t st);
-void launch_cell_ranges(const uint32_t *key_sorted, int64_t n, int64_t G, uint32_t *cell_start,
-                        void *sort_scratch, hipStream_t st);
+// Counting sort of the particles by storage-cell key (K = key_count cells): key_out / val_out
+// get the keys in cell order and the source slot of each, cell_start [K + 1] the first slot of
+// every cell. The sort's scratch holds per-cell counts that must be zero on entry: the sort
+// leaves them zero, and launch_cell_sort_init zeroes them once for a new workspace.
+void launch_cell_sort_init(void *scratch, int64_t n, int64_t K, hipStream_t st);
+void launch_cell_sort(const uint32_t *key, uint32_t *key_out, uint32_t *val_out, uint32_t *cell_start,
+                      void *scratch, int64_t n, int64_t K, hipStream_t st);
 void launch_cell_fixup(const uint32_t *key_sorted, int64_t n, uint32_t *val, const uint32_t *id_old,
                        hipStream_t st);
 void launch_gather(PSet from, PSet to, const uint32_t *perm, int64_t n, hipStream_t st);
@@ -311,7 +313,6 @@ struct dcm_system {
     dcm_params p;
     int64_t n;
     dcm::Grid grid;
-    int bits;
     double hdt, cut_a, cut_b, cap;
     dcm::PSet set[2];
     int cur;

@@ -219,15 +219,8 @@ void regroup(dcm_server *sv)
     std::vector<Recorder> recs;
     std::vector<std::vector<size_t>> members;   // indices into recs / cand
     std::vector<Req *> cand;
-    // One radix-sort length for all: a pass over key bits that are zero for a smaller grid
-    // leaves the (stable) order unchanged, and equal pass counts let systems of different grid
-    // sizes share one launch sequence.
-    int bits = 0;
-    for (Req *r : sv->running)
-        if (r->nsteps - r->done_steps >= r->period) bits = std::max(bits, r->sys->bits);
     for (Req *r : sv->running) {
         if (r->nsteps - r->done_steps < r->period) continue;
-        r->sys->bits = bits;
         Recorder rec;
         if (record_period(r, rec) != DCM_OK) continue;
         size_t gi = 0;

@@ -1,11 +1,12 @@
-// sort.hip -- binning of particles into boxes by sort-and-segment (Section 4, Eq. 9-10).
+// sort.hip -- binning of particles into storage cells by a counting sort (Section 4, Eq. 9-10).
 //
-// Each particle gets the linear index of the box containing it (x fastest). The particles
-// are then sorted by that key with a stable LSD radix sort whose per-tile ranks come from
-// wavefront ballots (no atomics anywhere), the first slot of every box is found where the
-// sorted key changes, and slots inside a box are ordered by particle id so that the
-// internal order -- and with it every summation order -- is a function of the state alone.
-// The box counts b_ijk of Eq. 9 are differences of consecutive box starts.
+// Each particle gets the key of its storage cell (its box, and the half of it along x; see
+// cell_key). Particles are counted per cell with integer atomics, which also hand each one its
+// rank among the particles of its cell; an exclusive scan of the counts gives the first slot of
+// every cell, and each particle goes to its cell's first slot plus its rank. The ranks depend on
+// the order in which the atomics land, so slots inside a cell are then ordered by particle id:
+// the internal order -- and with it every summation order -- is a function of the state alone.
+// The box counts b_ijk of Eq. 9 are sums of the differences of consecutive cell starts.
 #include "internal.h"
 #include "launch.h"
 
@@ -13,11 +14,9 @@ namespace dcm {
 
 namespace {
 
-constexpr int kRadixBits = 8;
-constexpr int kDigits = 1 << kRadixBits;
-constexpr int kItems = 8;                          // keys per thread per tile
 constexpr int kBlockWaves = kBlock / 64;
-constexpr int kTile = kBlock * kItems;             // 2048 keys per tile
+constexpr int kScanPer = 16;                        // cells per thread of the cell scan
+constexpr int kScanCells = kBlock * kScanPer;       // cells per scan block
 
 __device__ __forceinline__ double wrap1(double x, double L)
 {
@@ -111,53 +110,6 @@ struct KInitIds {
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
-// Lanes of the current wave (among `valid` ones) whose digit equals this lane's.
-__device__ __forceinline__ unsigned long long peer_mask(uint32_t digit, bool valid)
-{
-    unsigned long long peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
-        bool bit = (digit >> b) & 1u;
-        unsigned long long bal = __ballot(bit);
-        peers &= bit ? bal : ~bal;
-    }
-    return peers;
-}
-
-// Per-tile digit counts: tile_counts[d * ntiles + t].
-struct KRadixCount {
-    static constexpr int kThreads = kBlock, kWaves = 0;
-    struct Args { const uint32_t *key; int64_t n; int shift; uint32_t *tile_counts; int64_t ntiles; };
-    static __device__ void run(const Args &a, uint32_t blk, uint32_t);
-};
-
-__device__ void KRadixCount::run(const Args &a, uint32_t blk, uint32_t)
-{
-    const uint32_t *key = a.key;
-    const int64_t n = a.n;
-    const int shift = a.shift;
-    __shared__ uint32_t whist[kBlockWaves][kDigits];
-    const int tid = threadIdx.x, w = tid >> 6;
-    const unsigned lane = lane_id();
-    for (int d = tid; d < kBlockWaves * kDigits; d += kBlock) (&whist[0][0])[d] = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)blk * kTile + (int64_t)w * 64 * kItems;
-    for (int r = 0; r < kItems; ++r) {
-        int64_t i = base + r * 64 + lane;
-        bool valid = i < n;
-        uint32_t digit = valid ? (key[i] >> shift) & (kDigits - 1) : 0u;
-        unsigned long long peers = peer_mask(digit, valid);
-        unsigned long long lower = peers & ((1ull << lane) - 1ull);
-        if (valid && lower == 0ull) whist[w][digit] += (uint32_t)__popcll(peers);
-    }
-    __syncthreads();
-    for (int d = tid; d < kDigits; d += kBlock) {
-        uint32_t c = 0;
-        for (int q = 0; q < kBlockWaves; ++q) c += whist[q][d];
-        a.tile_counts[(int64_t)d * a.ntiles + blk] = c;
-    }
-}
-
 // Exclusive scan of 256 values held one per thread (blockDim == 256); returns the total.
 __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *out_excl, uint32_t *lds /*[kBlockWaves]*/)
 {
@@ -181,221 +133,178 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *out_excl, uint32_
     return total;
 }
 
-// One block per digit: exclusive scan of its per-tile counts (in place) and the digit total.
-struct KDigitScan {
-    static constexpr int kThreads = kBlock, kWaves = 0;
-    struct Args { uint32_t *tile_counts; int64_t ntiles; uint32_t *digit_total; };
-    static __device__ void run(const Args &a, uint32_t blk, uint32_t);
-};
+// Per-cell counts (cnt, zero on entry) and each particle's rank in its cell; bsum gets the
+// number of particles in every block of kScanCells cells (one atomic per block present in a
+// wave: the lanes of a wave that fall in one block are counted together). A workgroup takes
+// kCountChunks consecutive chunks of kBlock particles, so that each wave has that many
+// independent load-atomic-store chains in flight.
+constexpr int kCountChunks = 4;
 
-__device__ void KDigitScan::run(const Args &a, uint32_t blk, uint32_t)
-{
-    __shared__ uint32_t lds[kBlockWaves];
-    const int64_t ntiles = a.ntiles;
-    uint32_t *row = a.tile_counts + (int64_t)blk * ntiles;
-    uint32_t carry = 0;
-    for (int64_t start = 0; start < ntiles; start += kBlock * 4) {
-        uint32_t v[4], s = 0;
-        for (int q = 0; q < 4; ++q) {
-            int64_t t = start + (int64_t)threadIdx.x * 4 + q;
-            v[q] = t < ntiles ? row[t] : 0u;
-            s += v[q];
-        }
-        uint32_t excl;
-        uint32_t total = block_exclusive_scan(s, &excl, lds);
-        uint32_t run = carry + excl;
-        for (int q = 0; q < 4; ++q) {
-            int64_t t = start + (int64_t)threadIdx.x * 4 + q;
-            if (t < ntiles) row[t] = run;
-            run += v[q];
-        }
-        carry += total;
-    }
-    if (threadIdx.x == 0) a.digit_total[blk] = carry;
-}
-
-// Stable scatter of one radix pass. The tile's keys are first placed in LDS in tile-local digit
-// order, then written out in that order, so consecutive threads write consecutive slots of a
-// digit's run in the output.
-struct KRadixScatter {
+struct KCellCount {
     static constexpr int kThreads = kBlock, kWaves = 0;
     struct Args {
-        const uint32_t *key, *val;
-        uint32_t *key_out, *val_out;
+        const uint32_t *key;
         int64_t n;
-        int shift;
-        const uint32_t *tile_prefix;
-        int64_t ntiles;
-        const uint32_t *digit_total;
+        uint32_t *cnt;
+        uint32_t *rank;
+        uint32_t *bsum;
     };
-    static __device__ void run(const Args &a, uint32_t blk, uint32_t);
-};
-
-__device__ void KRadixScatter::run(const Args &a, uint32_t blk, uint32_t)
-{
-    const uint32_t *key = a.key, *val = a.val;
-    uint32_t *key_out = a.key_out, *val_out = a.val_out;
-    const int64_t n = a.n;
-    const int shift = a.shift;
-    const uint32_t *tile_prefix = a.tile_prefix, *digit_total = a.digit_total;
-    const int64_t ntiles = a.ntiles;
-    __shared__ uint32_t whist[kBlockWaves][kDigits];
-    __shared__ uint32_t gbase[kDigits];
-    __shared__ uint32_t tbase[kDigits];
-    __shared__ uint32_t lds[kBlockWaves];
-    __shared__ uint32_t sk[kTile], sv[kTile];
-    const int tid = threadIdx.x, w = tid >> 6;
-    const unsigned lane = lane_id();
-    for (int d = tid; d < kBlockWaves * kDigits; d += kBlock) (&whist[0][0])[d] = 0;
-    __syncthreads();
-    const int64_t tile0 = (int64_t)blk * kTile;
-    const int64_t base = tile0 + (int64_t)w * 64 * kItems;
-    uint32_t k[kItems], v[kItems], dg[kItems], rk[kItems];
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        int64_t i = base + r * 64 + lane;
-        bool valid = i < n;
-        k[r] = valid ? key[i] : 0u;
-        v[r] = valid ? val[i] : 0u;
-        uint32_t digit = (k[r] >> shift) & (kDigits - 1);
-        dg[r] = digit;
-        unsigned long long peers = peer_mask(digit, valid);
-        unsigned long long lower = peers & ((1ull << lane) - 1ull);
-        rk[r] = whist[w][digit] + (uint32_t)__popcll(lower);
-        if (valid && lower == 0ull) whist[w][digit] += (uint32_t)__popcll(peers);
-    }
-    __syncthreads();
-    {
-        // global digit base = exclusive scan over digit totals + this tile's prefix for the
-        // digit; tile-local digit base = exclusive scan over the tile's digit counts; per-wave
-        // bases = exclusive scan over the waves of the tile
-        uint32_t excl;
-        block_exclusive_scan(digit_total[tid], &excl, lds);
-        uint32_t acc = 0;
-        for (int q = 0; q < kBlockWaves; ++q) {
-            uint32_t c = whist[q][tid];
-            whist[q][tid] = acc;
-            acc += c;
-        }
-        uint32_t texcl;
-        block_exclusive_scan(acc, &texcl, lds);
-        tbase[tid] = texcl;
-        gbase[tid] = excl + tile_prefix[(int64_t)tid * ntiles + blk];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        int64_t i = base + r * 64 + lane;
-        if (i < n) {
-            const uint32_t p = tbase[dg[r]] + whist[w][dg[r]] + rk[r];
-            sk[p] = k[r];
-            sv[p] = v[r];
-        }
-    }
-    __syncthreads();
-    const int64_t left = n - tile0;
-    const int cnt = left < kTile ? (int)left : kTile;
-    for (int q = tid; q < cnt; q += kBlock) {
-        const uint32_t kk = sk[q];
-        const uint32_t d = (kk >> shift) & (kDigits - 1);
-        const uint32_t dst = gbase[d] + ((uint32_t)q - tbase[d]);
-        key_out[dst] = kk;
-        val_out[dst] = sv[q];
-    }
-}
-
-// Box starts from sorted keys, cell_start[c] = number of keys below c, in two steps. First the
-// start of every run of kRangeBoxes keys: the slot where the key changes from a to b starts
-// every run whose first key lies in (a, b] (runs before the first key start at 0, after the
-// last at n). Then one workgroup per run stages the run's keys in LDS and every box of the run
-// finds its start by binary search, so the box starts are written in order.
-constexpr int kRangeBoxes = 1024;                   // boxes per run (4 per thread)
-constexpr int kRangeKeys = 4096;                    // keys a run can stage in LDS
-
-struct KRunStarts {
-    static constexpr int kThreads = kBlock, kWaves = 0;
-    struct Args { const uint32_t *key; int64_t n, nruns; uint32_t *run_start; };
     static __device__ void run(const Args &a, uint32_t blk, uint32_t)
     {
-        int64_t i = (int64_t)blk * kThreads + threadIdx.x;
-        if (i > a.n) return;
-        int64_t lo = (i == 0) ? 0 : (int64_t)(a.key[i - 1] / kRangeBoxes) + 1;
-        int64_t hi = (i == a.n) ? a.nruns : (int64_t)(a.key[i] / kRangeBoxes);
-        for (int64_t r = lo; r <= hi; ++r) a.run_start[r] = (uint32_t)i;
-    }
-};
-
-struct KCellRanges {
-    static constexpr int kThreads = kBlock, kWaves = 0;
-    struct Args { const uint32_t *key; int64_t G; const uint32_t *run_start; uint32_t *cell_start; };
-    static __device__ void run(const Args &a, uint32_t blk, uint32_t);
-};
-
-__device__ void KCellRanges::run(const Args &args, uint32_t blk, uint32_t)
-{
-    const uint32_t *key = args.key;
-    const int64_t G = args.G;
-    uint32_t *cell_start = args.cell_start;
-    __shared__ uint32_t sk[kRangeKeys];
-    __shared__ uint32_t first[kRangeBoxes];
-    __shared__ uint32_t wmin[kBlock / 64];
-    constexpr int kPer = kRangeBoxes / kBlock;
-    const int64_t c0 = (int64_t)blk * kRangeBoxes;
-    const uint32_t lo = args.run_start[blk], hi = args.run_start[blk + 1];
-    const uint32_t m = hi - lo;
-    if (m > (uint32_t)kRangeKeys) {
-        // too many keys to stage: every box finds its start by binary search in global memory
-        for (int r = 0; r < kPer; ++r) {
-            const int64_t c = c0 + r * kBlock + threadIdx.x;
-            if (c > G) break;
-            uint32_t a = 0, b = m;
-            while (a < b) {
-                const uint32_t mid = (a + b) >> 1;
-                if ((int64_t)key[lo + mid] < c) a = mid + 1;
-                else b = mid;
-            }
-            cell_start[c] = lo + a;
+        const unsigned lane = lane_id();
+        const int64_t i0 = (int64_t)blk * (kThreads * kCountChunks) + threadIdx.x;
+        uint32_t k[kCountChunks], base[kCountChunks];
+        int leader[kCountChunks];
+        bool valid[kCountChunks];
+#pragma unroll
+        for (int u = 0; u < kCountChunks; ++u) {
+            const int64_t i = i0 + (int64_t)u * kThreads;
+            valid[u] = i < a.n;
+            k[u] = valid[u] ? a.key[i] : 0u;
         }
-        return;
-    }
-    // every key of this run lies in [c0, c0 + kRangeBoxes): the first slot of each key is its
-    // box's start; an empty box starts where the next non-empty box of the run does, or at hi
-    for (int q = threadIdx.x; q < kRangeBoxes; q += kBlock) first[q] = hi;
-    for (uint32_t q = threadIdx.x; q < m; q += kBlock) sk[q] = key[lo + q];
-    __syncthreads();
-    for (uint32_t q = threadIdx.x; q < m; q += kBlock)
-        if (q == 0 || sk[q - 1] != sk[q]) first[sk[q] - (uint32_t)c0] = lo + q;
-    __syncthreads();
-    // suffix minimum over the boxes: kPer consecutive boxes per thread, then over the threads
-    uint32_t v[kPer];
-    uint32_t run = 0xffffffffu;
 #pragma unroll
-    for (int r = kPer - 1; r >= 0; --r) {
-        run = min(run, first[threadIdx.x * kPer + r]);
-        v[r] = run;
-    }
-    // inclusive suffix minimum of the per-thread minima within the wave (lanes above)
-    const unsigned lane = lane_id();
-    uint32_t suf = run;
+        for (int u = 0; u < kCountChunks; ++u) {
+            // particles arrive nearly in cell order: a run of neighbouring lanes with one key
+            // takes its ranks with one atomic of its first lane (valid lanes are a prefix)
+            const uint32_t prev = __shfl_up(k[u], 1, 64);
+            const unsigned long long vmask = __ballot(valid[u]);
+            const unsigned long long starts = __ballot(valid[u] && (lane == 0 || prev != k[u]));
+            // this lane's run starts at the highest start at or below it, and ends at the next
+            // start or the first invalid lane above that
+            const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+            const unsigned long long mine = starts & upto;
+            leader[u] = mine ? 63 - __clzll((long long)mine) : (int)lane;
+            const unsigned long long later = leader[u] == 63 ? 0ull : ~((2ull << leader[u]) - 1ull);
+            const unsigned long long ends = (starts | ~vmask) & later;
+            const int next = ends ? __ffsll((long long)ends) - 1 : 64;
+            base[u] = 0u;
+            if (valid[u] && lane == (unsigned)leader[u]) base[u] = atomicAdd(&a.cnt[k[u]], (uint32_t)(next - leader[u]));
+        }
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t t = __shfl_down(suf, off, 64);
-        if (lane + off < 64u) suf = min(suf, t);
+        for (int u = 0; u < kCountChunks; ++u) {
+            const uint32_t b = __shfl(base[u], valid[u] ? leader[u] : (int)lane, 64);
+            const int64_t i = i0 + (int64_t)u * kThreads;
+            if (valid[u]) a.rank[i] = b + (lane - (unsigned)leader[u]);
+            const uint32_t sb = k[u] / (uint32_t)kScanCells;
+            unsigned long long todo = __ballot(valid[u]);
+            while (todo) {
+                const int first = __ffsll((long long)todo) - 1;
+                const uint32_t lb = __shfl(sb, first, 64);
+                const unsigned long long peers = __ballot(valid[u] && sb == lb) & todo;
+                if (lane == (unsigned)first) atomicAdd(&a.bsum[lb], (uint32_t)__popcll(peers));
+                todo &= ~peers;
+            }
+        }
     }
-    const int w = threadIdx.x >> 6;
-    if (lane == 0) wmin[w] = suf;
-    __syncthreads();
-    // minimum over the later waves and over the later lanes of this wave
-    uint32_t after = 0xffffffffu;
-    for (int q = w + 1; q < kBlock / 64; ++q) after = min(after, wmin[q]);
-    const uint32_t later_lanes = __shfl_down(suf, 1, 64);
-    if (lane < 63u) after = min(after, later_lanes);
+};
+
+// One workgroup: boff = exclusive scan of the block counts, which go back to zero.
+struct KCellBlockScan {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        uint32_t *bsum;
+        uint32_t *boff;
+        int64_t nb;
+    };
+    static __device__ void run(const Args &a, uint32_t, uint32_t)
+    {
+        __shared__ uint32_t lds[kBlockWaves];
+        uint32_t carry = 0;
+        for (int64_t start = 0; start < a.nb; start += kBlock * 4) {
+            uint32_t v[4], s = 0;
+            for (int q = 0; q < 4; ++q) {
+                const int64_t t = start + (int64_t)threadIdx.x * 4 + q;
+                v[q] = t < a.nb ? a.bsum[t] : 0u;
+                s += v[q];
+            }
+            uint32_t excl;
+            const uint32_t total = block_exclusive_scan(s, &excl, lds);
+            uint32_t run = carry + excl;
+            for (int q = 0; q < 4; ++q) {
+                const int64_t t = start + (int64_t)threadIdx.x * 4 + q;
+                if (t < a.nb) {
+                    a.boff[t] = run;
+                    a.bsum[t] = 0u;
+                }
+                run += v[q];
+            }
+            carry += total;
+        }
+    }
+};
+
+// cell_start[c] = particles in cells below c: each block scans its kScanCells counts and adds
+// the particles of the blocks before it; the counts go back to zero. The block's counts pass
+// through LDS so that global reads and writes are coalesced while each thread scans a run of
+// kScanPer consecutive cells (rows padded by one word against bank conflicts).
+struct KCellScan {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        uint32_t *cnt;
+        uint32_t *cell_start;
+        const uint32_t *boff;
+        int64_t ncells;     // key_count + 1 (the last start is the particle count)
+    };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t)
+    {
+        __shared__ uint32_t lds[kBlockWaves];
+        __shared__ uint32_t tile[kBlock * (kScanPer + 1)];
+        const int64_t base = (int64_t)blk * kScanCells;
+        // coalesced load: element e of the block goes to row e / kScanPer, column e % kScanPer
 #pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-        const int64_t c = c0 + threadIdx.x * kPer + r;
-        if (c <= G) cell_start[c] = min(v[r], after);
+        for (int q = 0; q < kScanPer; ++q) {
+            const int e = q * kBlock + threadIdx.x;
+            const int64_t c = base + e;
+            tile[(e / kScanPer) * (kScanPer + 1) + e % kScanPer] = c < a.ncells ? a.cnt[c] : 0u;
+        }
+        __syncthreads();
+        uint32_t *row = tile + threadIdx.x * (kScanPer + 1);
+        uint32_t s = 0;
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) s += row[q];
+        uint32_t excl;
+        block_exclusive_scan(s, &excl, lds);
+        uint32_t run = a.boff[blk] + excl;
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) {
+            const uint32_t v = row[q];
+            row[q] = run;
+            run += v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) {
+            const int e = q * kBlock + threadIdx.x;
+            const int64_t c = base + e;
+            if (c < a.ncells) {
+                a.cell_start[c] = tile[(e / kScanPer) * (kScanPer + 1) + e % kScanPer];
+                a.cnt[c] = 0u;
+            }
+        }
     }
-}
+};
+
+// Slot of particle i: its cell's start plus its rank; val_out records where it came from.
+struct KCellScatter {
+    static constexpr int kThreads = kBlock, kWaves = 0;
+    struct Args {
+        const uint32_t *key;
+        const uint32_t *rank;
+        const uint32_t *cell_start;
+        int64_t n;
+        uint32_t *key_out;
+        uint32_t *val_out;
+    };
+    static __device__ void run(const Args &a, uint32_t blk, uint32_t)
+    {
+        const int64_t i = (int64_t)blk * kThreads + threadIdx.x;
+        if (i >= a.n) return;
+        const uint32_t k = a.key[i];
+        const uint32_t p = a.cell_start[k] + a.rank[i];
+        a.key_out[p] = k;
+        a.val_out[p] = (uint32_t)i;
+    }
+};
 
 // Inside each storage cell, order slots by particle id (insertion sort; cells hold a few
 // particles). One thread per sorted slot: the first slot of a run of equal keys sorts the run.
@@ -453,11 +362,12 @@ inline unsigned grid1(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock);
 
 }  // namespace
 
-size_t sort_scratch_bytes(int64_t n, int64_t G)
+// Scratch of the cell sort: per-cell counts [K + 1], ranks [n], per-block counts and offsets.
+static int64_t scan_blocks(int64_t K) { return (K + 1 + kScanCells - 1) / kScanCells; }
+
+size_t sort_scratch_bytes(int64_t n, int64_t K)
 {
-    int64_t ntiles = (n + kTile - 1) / kTile;
-    int64_t nruns = G / kRangeBoxes + 1;              // runs covering boxes 0..G
-    return sizeof(uint32_t) * ((size_t)kDigits * (size_t)ntiles + kDigits + (size_t)nruns + 1);
+    return sizeof(uint32_t) * ((size_t)(K + 1) + (size_t)n + 2 * (size_t)scan_blocks(K));
 }
 
 void launch_wrap_key(const Grid &g, PSet s, int64_t n, uint32_t *key, uint32_t *val, hipStream_t st)
@@ -483,36 +393,26 @@ void launch_init_ids(PSet s, int64_t n, hipStream_t st)
     emit<KInitIds>({s, n}, grid1(n), st);
 }
 
-// Sorts (key, val) by key over the low `bits` bits. The result ends in (key, val): an odd
-// number of passes finishes with a copy back from the alternate buffers.
-bool launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key_alt, uint32_t *val_alt,
-                       void *scratch, int64_t n, int bits, hipStream_t st)
+void launch_cell_sort_init(void *scratch, int64_t n, int64_t K, hipStream_t st)
 {
-    int64_t ntiles = (n + kTile - 1) / kTile;
-    uint32_t *tile_counts = (uint32_t *)scratch;
-    uint32_t *digit_total = tile_counts + (size_t)kDigits * ntiles;
-    uint32_t *ki = key, *vi = val, *ko = key_alt, *vo = val_alt;
-    int passes = (bits + kRadixBits - 1) / kRadixBits;
-    for (int p = 0; p < passes; ++p) {
-        int shift = p * kRadixBits;
-        emit<KRadixCount>({ki, n, shift, tile_counts, ntiles}, (uint32_t)ntiles, st);
-        emit<KDigitScan>({tile_counts, ntiles, digit_total}, kDigits, st);
-        emit<KRadixScatter>({ki, vi, ko, vo, n, shift, tile_counts, ntiles, digit_total}, (uint32_t)ntiles, st);
-        uint32_t *t = ki; ki = ko; ko = t;
-        t = vi; vi = vo; vo = t;
-    }
-    // after an odd number of passes the sorted keys and values are in the alternate buffers
-    return ki != key;
+    uint32_t *cnt = (uint32_t *)scratch;
+    uint32_t *bsum = cnt + (K + 1) + n;
+    launch_fill_u32(cnt, 0u, K + 1, st);
+    launch_fill_u32(bsum, 0u, scan_blocks(K), st);
 }
 
-void launch_cell_ranges(const uint32_t *key_sorted, int64_t n, int64_t G, uint32_t *cell_start,
-                        void *scratch, hipStream_t st)
+void launch_cell_sort(const uint32_t *key, uint32_t *key_out, uint32_t *val_out, uint32_t *cell_start,
+                      void *scratch, int64_t n, int64_t K, hipStream_t st)
 {
-    const int64_t ntiles = (n + kTile - 1) / kTile;
-    uint32_t *run_start = (uint32_t *)scratch + (size_t)kDigits * (size_t)ntiles + kDigits;
-    const int64_t nruns = G / kRangeBoxes + 1;
-    emit<KRunStarts>({key_sorted, n, nruns, run_start}, grid1(n + 1), st);
-    emit<KCellRanges>({key_sorted, G, run_start, cell_start}, (uint32_t)nruns, st);
+    uint32_t *cnt = (uint32_t *)scratch;
+    uint32_t *rank = cnt + (K + 1);
+    uint32_t *bsum = rank + n;
+    const int64_t nb = scan_blocks(K);
+    uint32_t *boff = bsum + nb;
+    emit<KCellCount>({key, n, cnt, rank, bsum}, (uint32_t)((n + kBlock * kCountChunks - 1) / (kBlock * kCountChunks)), st);
+    emit<KCellBlockScan>({bsum, boff, nb}, 1, st);
+    emit<KCellScan>({cnt, cell_start, boff, K + 1}, (uint32_t)nb, st);
+    emit<KCellScatter>({key, rank, cell_start, n, key_out, val_out}, grid1(n), st);
 }
 
 void launch_cell_fixup(const uint32_t *key_sorted, int64_t n, uint32_t *val, const uint32_t *id_old,
