@@ -79,16 +79,23 @@ struct KCountFromRanges {
     static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
 };
 
+// Threads take the boxes in storage order (force row, then x, then the box's place in its row),
+// so that neighbouring threads read neighbouring cell starts; the image is written in box order.
 __device__ void KCountFromRanges::run(const Args &args_, uint32_t blk, uint32_t)
 {
-    Grid g = args_.g;
+    const Grid &g = args_.g;
     const uint32_t *cell_start = args_.cell_start;
-    uint32_t *out = args_.out;
-    int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
-    if (c >= g.G) return;
-    int64_t i, j, k;
-    coords(g, c, i, j, k);
-    out[c] = box_count(g, cell_start, (int32_t)i, (int32_t)j, (int32_t)k);
+    const int64_t t = (int64_t)blk * blockDim.x + threadIdx.x;
+    if (t >= g.G) return;
+    const int sub_bits = g.sy + g.sz;
+    const uint32_t sub = (uint32_t)t & ((1u << sub_bits) - 1u);
+    const uint32_t rest = (uint32_t)(t >> sub_bits);
+    const uint32_t a = rest % (uint32_t)g.n[0];
+    const uint32_t row = rest / (uint32_t)g.n[0];
+    const uint32_t rows_y = (uint32_t)g.n[1] >> g.sy;
+    const uint32_t b = ((row % rows_y) << g.sy) | (sub & ((1u << g.sy) - 1u));
+    const uint32_t c = ((row / rows_y) << g.sz) | (sub >> g.sy);
+    args_.out[((int64_t)c * g.n[1] + b) * g.n[0] + a] = box_count(g, cell_start, (int32_t)a, (int32_t)b, (int32_t)c);
 }
 
 // ---- histogram and two-means ----------------------------------------------------------
