@@ -313,7 +313,7 @@ void detect(dcm_system *s, hipStream_t st, bool with_cutoffs = true)
     stage_end(s, st);
     stage_begin(s, 3, st);
     launch_fill_u32((uint32_t *)w.stats, 0u, 16, st);
-    launch_two_means(g, w.g, w, w.stats, st);
+    launch_two_means(g, w.g, w, w.stats, true, st);
     stage_end(s, st);
     stage_begin(s, 4, st);
     MsParams ms = {s->p.ms_nu, std::max(s->p.box[0], std::max(s->p.box[1], s->p.box[2])), s->p.ms_iters};
@@ -470,6 +470,7 @@ dcm_status create_impl(const dcm_params *p, int64_t n, void *d_ws, size_t ws_byt
     launch_fill_u32(s->gw.flags, 0u, 1, st);
     launch_distance_flags_zero(s->grid, s->cap, s->gw, st);
     launch_cell_sort_init(s->sort_scratch, n, key_count(s->grid), st);
+    launch_fill_u32(s->gw.hist, 0u, kHistBins, st);
     launch_fill_u32((uint32_t *)s->nh, 0u, 8, st);
     launch_fill_u32(s->wave_time, 0u, s->nfb, st);
     launch_wave_order(s->wave_time, s->order, s->wave_hist, s->nfb, false, st);
@@ -904,7 +905,7 @@ dcm_status dcm_grid_two_means(const int32_t dims[3], const uint32_t *d_g, double
     hipStream_t st = (hipStream_t)stream;
     launch_fill_u32(w.flags, 0u, 1, st);
     w.km = d_km;
-    launch_two_means(g, d_g, w, (long long *)d_stats, st);
+    launch_two_means(g, d_g, w, (long long *)d_stats, false, st);
     return hip_status("dcm_grid_two_means");
 }
 

@@ -137,13 +137,14 @@ constexpr int kTmThreads = 1024;
 
 // Two-means on the histogram: the occupied range [min, max] is found by the whole block, copied
 // to LDS, and the Lloyd iterations then run in one wave with shuffle reductions only. All sums
-// are exact integers, so their order does not matter.
+// are exact integers, so their order does not matter. The histogram is left at zero for the
+// next detection.
 constexpr int kTmLds = 16384;
 
 struct KTwoMeans {
     static constexpr int kThreads = kTmThreads, kWaves = 0;
     struct Args {
-        const uint32_t *hist;
+        uint32_t *hist;
         double *km;
         long long *stats_iter;
     };
@@ -152,15 +153,21 @@ struct KTwoMeans {
 
 __device__ void KTwoMeans::run(const Args &args_, uint32_t, uint32_t)
 {
-    const uint32_t *hist = args_.hist;
+    uint32_t *hist = args_.hist;
     double *km = args_.km;
     long long *stats_iter = args_.stats_iter;
     __shared__ int lmn[16], lmx[16];
     __shared__ uint32_t lh[kTmLds];
     const int tid = threadIdx.x, w = tid >> 6;
     int mn = kHistBins, mx = -1;
-    for (int b = tid; b < kHistBins; b += kTmThreads)
-        if (hist[b]) { if (b < mn) mn = b; if (b > mx) mx = b; }
+    static_assert(kHistBins % (4 * kTmThreads) == 0, "whole uint4 loads");
+    for (int b0 = 4 * tid; b0 < kHistBins; b0 += 4 * kTmThreads) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(hist + b0);
+        const uint32_t h[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (h[q]) { mn = min(mn, b0 + q); mx = max(mx, b0 + q); }
+    }
     for (int off = 32; off > 0; off >>= 1) {
         mn = min(mn, __shfl_xor(mn, off, 64));
         mx = max(mx, __shfl_xor(mx, off, 64));
@@ -171,8 +178,12 @@ __device__ void KTwoMeans::run(const Args &args_, uint32_t, uint32_t)
     for (int q = 0; q < 16; ++q) { mn = min(mn, lmn[q]); mx = max(mx, lmx[q]); }
     if (mx < 0) mn = mx = 0;                    // empty histogram (cannot happen for G >= 27)
     const bool staged = mx - mn + 1 <= kTmLds;
-    if (staged)
-        for (int b = mn + tid; b <= mx; b += kTmThreads) lh[b - mn] = hist[b];
+    if (staged) {
+        for (int b = mn + tid; b <= mx; b += kTmThreads) {
+            lh[b - mn] = hist[b];
+            hist[b] = 0u;
+        }
+    }
     __syncthreads();
     if (w != 0) return;
     if (mn == mx) {
@@ -204,6 +215,8 @@ __device__ void KTwoMeans::run(const Args &args_, uint32_t, uint32_t)
         if (nl == prev) break;
         prev = nl;
     }
+    if (!staged)
+        for (int b = mn + tid; b <= mx; b += 64) hist[b] = 0u;
     if (tid == 0) {
         km[0] = cv; km[1] = cl; km[2] = 0.5 * (cv + cl);
         if (stats_iter) *stats_iter = it;
@@ -1159,9 +1172,9 @@ void launch_smooth(const Grid &g, int passes, const uint32_t *cell_start, const 
 }
 
 void launch_two_means(const Grid &g, const uint32_t *img, GridWork w, long long *stats_out,
-                      hipStream_t st)
+                      bool hist_zero, hipStream_t st)
 {
-    launch_fill_u32(w.hist, 0u, kHistBins, st);
+    if (!hist_zero) launch_fill_u32(w.hist, 0u, kHistBins, st);
     unsigned nb = (unsigned)std::min<int64_t>((g.G + kBlock - 1) / kBlock, 1024);
     emit<KHist>({img, g.G, w.hist, w.flags}, nb, st);
     emit<KTwoMeans>({w.hist, w.km, stats_out}, 1, st);

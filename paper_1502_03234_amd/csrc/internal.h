@@ -176,8 +176,10 @@ void launch_gather(PSet from, PSet to, const uint32_t *perm, int64_t n, hipStrea
 // detect.hip
 void launch_smooth(const Grid &g, int passes, const uint32_t *cell_start, const uint32_t *in,
                    uint32_t *out, uint32_t *tmp, hipStream_t st);
+// Two-means of the image's histogram (Eq. 14). The histogram is left at zero; hist_zero = true
+// says it is zero on entry (a previous call on this workspace, or a zeroed new one).
 void launch_two_means(const Grid &g, const uint32_t *img, GridWork w, long long *stats_out,
-                      hipStream_t st);
+                      bool hist_zero, hipStream_t st);
 // ms.nu > 0: Eq. 13's segmentation between the threshold and the component removal.
 void launch_segment(const Grid &g, const uint32_t *img, const double *km, int32_t min_component,
                     const MsParams &ms, GridWork w, hipStream_t st);
