@@ -754,6 +754,11 @@ __host__ __device__ inline int64_t distance_tile_count(const Grid &g)
     return (int64_t)((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY) * ((g.n[2] + TZ - 1) / TZ);
 }
 
+// Passes from kDistLatePass on run in one workgroup (KDistLate), which loops over them until a
+// pass changes nothing: by then the solve has converged on the interfaces measured, so they
+// cost one launch instead of one each.
+constexpr int kDistLatePass = 12;
+
 // The first kDistFullPasses passes launch one workgroup per tile. Later passes, where few tiles
 // are dirty or the solve has converged, launch fewer workgroups: each takes every nblk-th tile
 // (at most kDistListMax of them), reads their dirty flags at once and relaxes only the dirty
@@ -819,6 +824,52 @@ __device__ void KDistTiles::run(const Args &args_, uint32_t blk, uint32_t nblk)
     for (uint32_t q = 0; q < m; ++q) {
         __syncthreads();
         dist_tile(args_, list[q], ntiles);
+    }
+}
+
+// The passes from it0 to the budget in one workgroup: each pass lists its dirty tiles, 256 at a
+// time, and relaxes them one after the other. Every tile still reads the previous pass's state
+// (the two copies and their flags), so the result is the one separate launches would give; the
+// workgroup's barriers order its own writes before the next pass reads them.
+struct KDistLate {
+    static constexpr int kThreads = kTileThreads, kWaves = 0;
+    struct Args {
+        KDistTiles::Args t;
+        int it0;
+        int max_sweeps;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
+};
+
+__device__ void KDistLate::run(const Args &args_, uint32_t, uint32_t)
+{
+    KDistTiles::Args a = args_.t;
+    const int ntiles = (int)distance_tile_count(a.g);
+    __shared__ int list[kTileThreads];
+    __shared__ uint32_t count;
+    for (int it = args_.it0; it < args_.max_sweeps; ++it) {
+        __syncthreads();
+        if (it > 0 && a.changed[it - 1] == 0) break;
+        a.it = it;
+        const uint32_t *dflag = a.dirty + (it & 1) * ntiles;
+        const uint32_t *cprev = a.cur + (it & 1) * ntiles;
+        uint32_t *cnext = a.cur + ((it + 1) & 1) * ntiles;
+        for (int b0 = 0; b0 < ntiles; b0 += kTileThreads) {
+            if (threadIdx.x == 0) count = 0u;
+            __syncthreads();
+            const int b = b0 + (int)threadIdx.x;
+            if (b < ntiles) {
+                if (dflag[b]) list[atomicAdd(&count, 1u)] = b;
+                else cnext[b] = cprev[b];
+            }
+            __syncthreads();
+            const uint32_t m = count;
+            for (uint32_t q = 0; q < m; ++q) {
+                __syncthreads();
+                dist_tile(a, list[q], ntiles);
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -1225,9 +1276,12 @@ void launch_distance(const Grid &g, double cap, const uint8_t *label, uint8_t ze
         launch_fill_u32(w.tcur, 0u, 2 * (int64_t)ntiles, st);
     }
     emit<KDistInit>({g, label, dist, w.tdirty, zero}, grid1(g.G), st);
-    for (int it = 0; it < ms; ++it)
+    const int it0 = ms < kDistLatePass ? ms : kDistLatePass;
+    for (int it = 0; it < it0; ++it)
         emit<KDistTiles>({g, label, dist, w.dist2, cap, w.changed, w.tdirty, w.tcur, it, zero},
                          distance_groups(ntiles, it), st);
+    if (it0 < ms)
+        emit<KDistLate>({{g, label, dist, w.dist2, cap, w.changed, w.tdirty, w.tcur, it0, zero}, it0, ms}, 1, st);
     emit<KDistGather>({g, dist, (const double *)w.dist2, w.tcur, w.changed, ms, (int)ntiles}, grid1(g.G), st);
     const unsigned fb = grid1(2 * (int64_t)ntiles);
     emit<KDistFinish>({w.changed, ms, sweeps, w.flags, w.tdirty, w.tcur, (int64_t)ntiles}, fb < 256u ? fb : 256u, st);
