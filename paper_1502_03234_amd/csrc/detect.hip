@@ -336,6 +336,21 @@ __device__ __forceinline__ int64_t ct_tile(const Grid &g, int64_t i, int64_t j, 
     return ((k / CT) * nty + j / CT) * ntx + i / CT;
 }
 
+// Box q (0 .. CT^3 - 1, x fastest) of component tile t, if it lies inside the grid.
+__device__ __forceinline__ bool ct_box(const Grid &g, int64_t t, int q, int64_t &c)
+{
+    const int64_t ntx = (g.n[0] + CT - 1) / CT, nty = (g.n[1] + CT - 1) / CT;
+    const int64_t i = (t % ntx) * CT + q % CT, j = ((t / ntx) % nty) * CT + (q / CT) % CT;
+    const int64_t k = (t / (ntx * nty)) * CT + q / (CT * CT);
+    if (i >= g.n[0] || j >= g.n[1] || k >= g.n[2]) return false;
+    c = lin(g, i, j, k);
+    return true;
+}
+
+// The per-box kernels after the merge run one workgroup per component tile: only boxes of
+// kCtFull tiles hold union-find entries, so the other tiles' workgroups exit at once.
+constexpr int kCtPer = CT * CT * CT / kBlock;      // boxes per thread
+
 struct KCcLocal {
     static constexpr int kThreads = kCtBoxes, kWaves = 0;
     struct Args {
@@ -500,14 +515,13 @@ __device__ void KCcFlatten::run(const Args &args_, uint32_t blk, uint32_t)
 {
     const Grid &g = args_.g;
     uint32_t *parent = args_.parent;
-    int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
-    if (c >= g.G) return;
-    int64_t i, j, k;
-    coords(g, c, i, j, k);
-    if (args_.ctile[ct_tile(g, i, j, k)] != kCtFull) return;
-    uint32_t p = parent[c];
-    if (p == kInvalid) return;
-    parent[c] = find_root(parent, (uint32_t)c);
+    if (args_.ctile[blk] != kCtFull) return;
+    for (int h = 0; h < kCtPer; ++h) {
+        int64_t c;
+        if (!ct_box(g, blk, (int)threadIdx.x + h * kBlock, c)) continue;
+        if (parent[c] == kInvalid) continue;
+        parent[c] = find_root(parent, (uint32_t)c);
+    }
 }
 
 // Component sizes, counted only until they reach `limit` (only "size < limit" matters). Boxes
@@ -534,35 +548,33 @@ __device__ void KCcSize::run(const Args &args_, uint32_t blk, uint32_t)
     const uint32_t *psize = args_.psize;
     uint32_t *csize = args_.csize;
     uint32_t limit = args_.limit;
-    int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
-    bool full = false;
-    if (c < g.G) {
-        int64_t i, j, k;
-        coords(g, c, i, j, k);
-        full = args_.ctile[ct_tile(g, i, j, k)] == kCtFull;
-    }
-    uint32_t r = full ? parent[c] : kInvalid;
-    const uint32_t ps = r != kInvalid ? psize[c] : 0u;
-    const bool small = r != kInvalid && ps < limit;
-    const bool touched = r != kInvalid && ps == kTouched;
-    bool active = small || touched;
+    if (args_.ctile[blk] != kCtFull) return;
     const unsigned lane = __lane_id();
-    const unsigned long long smallmask = __ballot(small), touchedmask = __ballot(touched);
-    unsigned long long pending = __ballot(active);
-    while (pending) {
-        int leader = __ffsll((long long)pending) - 1;
-        uint32_t rl = __shfl(r, leader, 64);
-        unsigned long long peers = __ballot(active && r == rl);
-        if ((int)lane == leader) {
-            if (peers & touchedmask) {
-                atomicMax(csize + rl, limit);
-            } else {
-                uint32_t cur = __hip_atomic_load(csize + rl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (cur < limit) atomicAdd(csize + rl, (uint32_t)__popcll(peers & smallmask));
+    for (int h = 0; h < kCtPer; ++h) {
+        int64_t c = 0;
+        const bool in = ct_box(g, blk, (int)threadIdx.x + h * kBlock, c);
+        uint32_t r = in ? parent[c] : kInvalid;
+        const uint32_t ps = r != kInvalid ? psize[c] : 0u;
+        const bool small = r != kInvalid && ps < limit;
+        const bool touched = r != kInvalid && ps == kTouched;
+        bool active = small || touched;
+        const unsigned long long smallmask = __ballot(small), touchedmask = __ballot(touched);
+        unsigned long long pending = __ballot(active);
+        while (pending) {
+            int leader = __ffsll((long long)pending) - 1;
+            uint32_t rl = __shfl(r, leader, 64);
+            unsigned long long peers = __ballot(active && r == rl);
+            if ((int)lane == leader) {
+                if (peers & touchedmask) {
+                    atomicMax(csize + rl, limit);
+                } else {
+                    uint32_t cur = __hip_atomic_load(csize + rl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (cur < limit) atomicAdd(csize + rl, (uint32_t)__popcll(peers & smallmask));
+                }
             }
+            if (peers & (1ull << lane)) active = false;
+            pending &= ~peers;
         }
-        if (peers & (1ull << lane)) active = false;
-        pending &= ~peers;
     }
 }
 
@@ -595,24 +607,22 @@ __device__ void KCcFlip::run(const Args &args_, uint32_t blk, uint32_t)
     uint32_t limit = args_.limit;
     long long *stats = args_.stats;
     int slot = args_.slot;
-    int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
-    bool flip = false, root = false;
-    bool full = false;
-    if (c < g.G) {
-        int64_t i, j, k;
-        coords(g, c, i, j, k);
-        full = args_.ctile[ct_tile(g, i, j, k)] == kCtFull;
-    }
-    if (full && label[c] == phase && psize[c] < limit) {
-        uint32_t r = parent[c];
-        if (csize[r] < limit) {
-            flip = true;
-            root = r == (uint32_t)c;
-            label[c] = (uint8_t)(1 - phase);
+    if (args_.ctile[blk] != kCtFull) return;
+    unsigned long long nf = 0, nr = 0;
+    for (int h = 0; h < kCtPer; ++h) {
+        int64_t c = 0;
+        bool flip = false, root = false;
+        if (ct_box(g, blk, (int)threadIdx.x + h * kBlock, c) && label[c] == phase && psize[c] < limit) {
+            uint32_t r = parent[c];
+            if (csize[r] < limit) {
+                flip = true;
+                root = r == (uint32_t)c;
+                label[c] = (uint8_t)(1 - phase);
+            }
         }
+        nf += __popcll(__ballot(flip));
+        nr += __popcll(__ballot(root));
     }
-    unsigned long long nf = __popcll(__ballot(flip));
-    unsigned long long nr = __popcll(__ballot(root));
     if (__lane_id() == 0 && stats) {
         if (nr) atomicAdd((unsigned long long *)(stats + slot), nr);
         if (nf) atomicAdd((unsigned long long *)(stats + slot + 2), nf);
@@ -1243,10 +1253,10 @@ void launch_segment(const Grid &g, const uint32_t *img, const double *km, int32_
         const uint32_t limit = (uint32_t)min_component;
         emit<KCcLocal>({g, w.label, phase, w.parent, w.csize, w.gtmp, w.ctile, limit}, nct, st);
         emit<KCcMerge>({g, w.label, phase, w.parent, w.gtmp, limit, w.ctile}, grid1(g.G), st);
-        emit<KCcFlatten>({g, w.parent, w.ctile}, grid1(g.G), st);
-        emit<KCcSize>({g, w.parent, (const uint32_t *)w.gtmp, w.csize, limit, w.ctile}, grid1(g.G), st);
+        emit<KCcFlatten>({g, w.parent, w.ctile}, nct, st);
+        emit<KCcSize>({g, w.parent, (const uint32_t *)w.gtmp, w.csize, limit, w.ctile}, nct, st);
         emit<KCcFlip>({g, w.label, phase, w.parent, (const uint32_t *)w.gtmp, w.csize, limit, w.stats,
-                       1 + pass, w.ctile}, grid1(g.G), st);
+                       1 + pass, w.ctile}, nct, st);
     }
 }
 
