@@ -1059,13 +1059,16 @@ __device__ void KDistGather::run(const Args &args_, uint32_t blk, uint32_t)
     for (int q = 0; q < args_.max_sweeps; ++q)
         if (args_.changed[q] == 0) { last = q; break; }
     const uint32_t *cur_final = args_.cur + ((last + 1) & 1) * args_.ntiles;
-    int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
-    if (c >= g.G) return;
-    int64_t i, j, k;
-    coords(g, c, i, j, k);
+    // one workgroup per tile: only tiles that ended in the second copy move anything
+    if (!cur_final[blk]) return;
     const int ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY;
-    const int owner = (int)(((k / TZ) * nty + j / TY) * ntx + i / TX);
-    if (cur_final[owner]) d0[c] = d1[c];
+    const int x0 = (int)(blk % ntx) * TX, y0 = (int)((blk / ntx) % nty) * TY, z0 = (int)(blk / (ntx * nty)) * TZ;
+    for (int q = threadIdx.x; q < TX * TY * TZ; q += kBlock) {
+        const int gx = x0 + q % TX, gy = y0 + (q / TX) % TY, gz = z0 + q / (TX * TY);
+        if (gx >= g.n[0] || gy >= g.n[1] || gz >= g.n[2]) continue;
+        const int64_t c = lin(g, gx, gy, gz);
+        d0[c] = d1[c];
+    }
 }
 
 // Sweep count and the not-converged flag; then the per-pass change flags, tile dirty flags and
@@ -1292,7 +1295,7 @@ void launch_distance(const Grid &g, double cap, const uint8_t *label, uint8_t ze
                          distance_groups(ntiles, it), st);
     if (it0 < ms)
         emit<KDistLate>({{g, label, dist, w.dist2, cap, w.changed, w.tdirty, w.tcur, it0, zero}, it0, ms}, 1, st);
-    emit<KDistGather>({g, dist, (const double *)w.dist2, w.tcur, w.changed, ms, (int)ntiles}, grid1(g.G), st);
+    emit<KDistGather>({g, dist, (const double *)w.dist2, w.tcur, w.changed, ms, (int)ntiles}, ntiles, st);
     const unsigned fb = grid1(2 * (int64_t)ntiles);
     emit<KDistFinish>({w.changed, ms, sweeps, w.flags, w.tdirty, w.tcur, (int64_t)ntiles}, fb < 256u ? fb : 256u, st);
 }
