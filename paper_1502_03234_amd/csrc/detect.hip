@@ -40,33 +40,57 @@ __device__ __forceinline__ void coords(const Grid &g, int64_t c, int64_t &i, int
 }
 
 // ---- smoothing ------------------------------------------------------------------------
-struct KSmoothAxis {
+// One smoothing pass, [1, 2, 1] along x, then y, then z, periodic, on a 32 x 8 x 4 block of boxes
+// staged in LDS with a one-box halo. The sums are integers, so doing the three axes per block
+// gives the same values as three whole-grid passes.
+constexpr int SX = 32, SY = 8, SZ = 4;
+
+struct KSmooth3 {
     static constexpr int kThreads = kBlock, kWaves = 0;
     struct Args {
         Grid g;
         const uint32_t *in;
         uint32_t *out;
-        int axis;
     };
     static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
 };
 
-__device__ void KSmoothAxis::run(const Args &args_, uint32_t blk, uint32_t)
+__device__ __forceinline__ int wrap_index(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+__device__ void KSmooth3::run(const Args &args_, uint32_t blk, uint32_t)
 {
-    Grid g = args_.g;
+    const Grid &g = args_.g;
     const uint32_t *in = args_.in;
-    uint32_t *out = args_.out;
-    int axis = args_.axis;
-    int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
-    if (c >= g.G) return;
-    int64_t i, j, k;
-    coords(g, c, i, j, k);
-    int64_t q[3] = {i, j, k};
-    int64_t lo[3] = {i, j, k}, hi[3] = {i, j, k};
-    lo[axis] = q[axis] == 0 ? g.n[axis] - 1 : q[axis] - 1;
-    hi[axis] = q[axis] == g.n[axis] - 1 ? 0 : q[axis] + 1;
-    int64_t cl = lin(g, lo[0], lo[1], lo[2]), ch = lin(g, hi[0], hi[1], hi[2]);
-    out[c] = in[cl] + 2u * in[c] + in[ch];
+    __shared__ uint32_t A[SZ + 2][SY + 2][SX + 2];
+    __shared__ uint32_t B[SZ + 2][SY + 2][SX];
+    __shared__ uint32_t C[SZ + 2][SY][SX];
+    const int ntx = (g.n[0] + SX - 1) / SX, nty = (g.n[1] + SY - 1) / SY;
+    const int x0 = (int)(blk % ntx) * SX, y0 = (int)((blk / ntx) % nty) * SY, z0 = (int)(blk / (ntx * nty)) * SZ;
+    // positions past the grid's far edge hold wrapped values too; only in-grid boxes are written
+    for (int q = threadIdx.x; q < (SZ + 2) * (SY + 2) * (SX + 2); q += kBlock) {
+        const int hx = q % (SX + 2), hy = (q / (SX + 2)) % (SY + 2), hz = q / ((SX + 2) * (SY + 2));
+        const int gx = wrap_index((x0 + hx - 1) % g.n[0], g.n[0]);
+        const int gy = wrap_index((y0 + hy - 1) % g.n[1], g.n[1]);
+        const int gz = wrap_index((z0 + hz - 1) % g.n[2], g.n[2]);
+        A[hz][hy][hx] = in[lin(g, gx, gy, gz)];
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < (SZ + 2) * (SY + 2) * SX; q += kBlock) {
+        const int x = q % SX, y = (q / SX) % (SY + 2), z = q / (SX * (SY + 2));
+        B[z][y][x] = A[z][y][x] + 2u * A[z][y][x + 1] + A[z][y][x + 2];
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < (SZ + 2) * SY * SX; q += kBlock) {
+        const int x = q % SX, y = (q / SX) % SY, z = q / (SX * SY);
+        C[z][y][x] = B[z][y][x] + 2u * B[z][y + 1][x] + B[z][y + 2][x];
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < SZ * SY * SX; q += kBlock) {
+        const int x = q % SX, y = (q / SX) % SY, z = q / (SX * SY);
+        const int gx = x0 + x, gy = y0 + y, gz = z0 + z;
+        if (gx >= g.n[0] || gy >= g.n[1] || gz >= g.n[2]) continue;
+        args_.out[lin(g, gx, gy, gz)] = C[z][y][x] + 2u * C[z + 1][y][x] + C[z + 2][y][x];
+    }
 }
 
 struct KCountFromRanges {
@@ -1220,7 +1244,8 @@ void launch_smooth(const Grid &g, int passes, const uint32_t *cell_start, const 
         else launch_copy_bytes(out, in, sizeof(uint32_t) * (size_t)g.G, st);
         return;
     }
-    int total = 3 * passes;
+    const int total = passes;
+    const unsigned blocks = (unsigned)(((g.n[0] + SX - 1) / SX) * ((g.n[1] + SY - 1) / SY) * ((g.n[2] + SZ - 1) / SZ));
     const uint32_t *src = in;
     if (cell_start) {
         // the box counts (Eq. 9) as an image first, in the buffer the first pass does not write
@@ -1230,7 +1255,7 @@ void launch_smooth(const Grid &g, int passes, const uint32_t *cell_start, const 
     }
     for (int s = 0; s < total; ++s) {
         uint32_t *dst = ((total - 1 - s) % 2 == 0) ? out : tmp;
-        emit<KSmoothAxis>({g, src, dst, s % 3}, grid1(g.G), st);
+        emit<KSmooth3>({g, src, dst}, blocks, st);
         src = dst;
     }
 }
