@@ -46,7 +46,8 @@ def stage_bandwidth(breakdown: dict, n: int, G: int, detect_every: int) -> dict:
     (count: key read, rank written, 8 B; scatter: key, rank and cell start read, key and source
     slot written, 20 B; in-cell order 4 B; gather 120 B) plus 24 B per box (its two storage
     cells' counts read, starts written and counts cleared). Per box and
-    detection: smoothing 24 B (three axis passes of 8 B), two-means 4 B (histogram read),
+    detection: smoothing 20 B (the count image: two cell starts read, the count written, 12 B; one
+    fused [1,2,1]^3 pass, 8 B), two-means 4 B (histogram read),
     labels and components 66 B (threshold 6 B, two component passes of about 30 B). Per particle
     and detection: cutoffs 96 B (eight 8-byte box values, the 32-byte position record read).
     Detection stages count once per detect_every steps. The distance solve's floor is reading
@@ -57,7 +58,7 @@ def stage_bandwidth(breakdown: dict, n: int, G: int, detect_every: int) -> dict:
     bytes_per_step = {
         "kick_drift_key": 144.0 * n,
         "sort": 152.0 * n + 24.0 * G,
-        "smooth": 24.0 * G * per_det,
+        "smooth": 20.0 * G * per_det,
         "two_means": 4.0 * G * per_det,
         "segment": 66.0 * G * per_det,
         "distance": 9.0 * G * per_det,
