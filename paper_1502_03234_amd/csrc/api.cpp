@@ -285,10 +285,20 @@ void stage_end(dcm_system *s, hipStream_t st)
 
 // Re-bin the current set after its keys were written: sort, box ranges, in-box id order, and
 // gather into the other set.
-void rebin_sorted(dcm_system *s, hipStream_t st)
+// The count step of the counting sort inside the kick/drift kernel, on steps that re-bin
+// (without neighbour lists every step re-bins; with them only a list rebuild does, from keys of
+// its own).
+CellCounts step_counts(const dcm_system *s)
+{
+    if (s->p.neighbor_list) return {nullptr, nullptr, nullptr};
+    return cell_sort_counts(s->sort_scratch, s->n, key_count(s->grid));
+}
+
+void rebin_sorted(dcm_system *s, hipStream_t st, bool counted = false)
 {
     PSet from = s->set[s->cur], to = s->set[1 - s->cur];
-    launch_cell_sort(s->key, s->key_alt, s->val_alt, s->gw.cell_start, s->sort_scratch, s->n, key_count(s->grid), st);
+    launch_cell_sort(s->key, s->key_alt, s->val_alt, s->gw.cell_start, s->sort_scratch, s->n, key_count(s->grid),
+                     counted, st);
     std::swap(s->key, s->key_alt);
     std::swap(s->val, s->val_alt);
     launch_cell_fixup(s->key, s->n, s->val, from.id, st);
@@ -526,11 +536,11 @@ dcm_status step_nose_hoover(dcm_system *s, int32_t nsteps, hipStream_t st, dcm_t
         stage_end(s, st);
         stage_begin(s, 0, st);
         launch_kick_drift_key(s->grid, s->set[s->cur], s->fx, s->fy, s->fz, s->n, s->hdt, s->p.dt, 0,
-                              s->nh + 2, s->key, s->val, s->kparts, st);
+                              s->nh + 2, s->key, step_counts(s), s->kparts, st);
         stage_end(s, st);
         if (!s->p.neighbor_list) {
             stage_begin(s, 1, st);
-            rebin_sorted(s, st);
+            rebin_sorted(s, st, true);
             stage_end(s, st);
         }
         if (s->p.detect_every > 0 && s->k % s->p.detect_every == 0) detect(s, st);
@@ -683,7 +693,7 @@ dcm_status dcm_step(dcm_system *s, int32_t nsteps, dcm_stream_t stream, dcm_ther
         s->k += 1;
         stage_begin(s, 0, st);
         launch_kick_drift_key(s->grid, s->set[s->cur], s->fx, s->fy, s->fz, s->n, s->hdt, s->p.dt,
-                              q > 1 ? 1 : 0, nullptr, s->key, s->val, s->kparts, st);
+                              q > 1 ? 1 : 0, nullptr, s->key, step_counts(s), s->kparts, st);
         stage_end(s, st);
         if (q > 1 && d_th) {
             stage_begin(s, 8, st);
@@ -693,7 +703,7 @@ dcm_status dcm_step(dcm_system *s, int32_t nsteps, dcm_stream_t stream, dcm_ther
         }
         if (!s->p.neighbor_list) {
             stage_begin(s, 1, st);
-            rebin_sorted(s, st);
+            rebin_sorted(s, st, true);
             stage_end(s, st);
         }
         if (s->p.detect_every > 0 && s->k % s->p.detect_every == 0) detect(s, st);

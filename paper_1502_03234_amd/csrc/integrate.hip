@@ -74,7 +74,8 @@ struct KKickDriftKey {
         double hdt, dt;
         int second_kick;
         const double *scale;
-        uint32_t *key, *val;
+        uint32_t *key;
+        CellCounts counts;      // counts.cnt == nullptr: the keys are not counted here
         Partial *ke_partials;
     };
     static __device__ void run(const Args &a, uint32_t blk, uint32_t);
@@ -91,6 +92,7 @@ __device__ void KKickDriftKey::run(const Args &a, uint32_t blk, uint32_t)
     const double *scale = a.scale;
     int64_t i = (int64_t)blk * kThreads + threadIdx.x;
     double ke = 0.0;
+    uint32_t key = 0u;
     if (i < n) {
         double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
         const double f0 = fx[i], f1 = fy[i], f2 = fz[i];
@@ -117,8 +119,15 @@ __device__ void KKickDriftKey::run(const Args &a, uint32_t blk, uint32_t)
         s.vx[i] = vx;
         s.vy[i] = vy;
         s.vz[i] = vz;
-        a.key[i] = pos_key(g, p.x, p.y, p.z);
-        a.val[i] = (uint32_t)i;
+        key = pos_key(g, p.x, p.y, p.z);
+        a.key[i] = key;
+    }
+    if (a.counts.cnt) {
+        // the counting sort's count step, on the keys just computed
+        const bool valid[1] = {i < n};
+        const uint32_t k[1] = {key};
+        const int64_t idx[1] = {i};
+        count_cells<1>(valid, k, idx, a.counts.cnt, a.counts.rank, a.counts.bsum);
     }
     if (second_kick) {
         double t = block_sum(ke);
@@ -393,10 +402,10 @@ void launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t st)
 
 void launch_kick_drift_key(const Grid &g, PSet s, const double *fx, const double *fy,
                            const double *fz, int64_t n, double hdt, double dt, int second_kick,
-                           const double *scale, uint32_t *key, uint32_t *val, Partial *ke_partials,
+                           const double *scale, uint32_t *key, CellCounts counts, Partial *ke_partials,
                            hipStream_t st)
 {
-    emit<KKickDriftKey>({g, s, fx, fy, fz, n, hdt, dt, second_kick, scale, key, val, ke_partials}, grid1(n), st);
+    emit<KKickDriftKey>({g, s, fx, fy, fz, n, hdt, dt, second_kick, scale, key, counts, ke_partials}, grid1(n), st);
 }
 
 void launch_kick(PSet s, const double *fx, const double *fy, const double *fz, int64_t n,

@@ -91,6 +91,55 @@ __host__ __device__ inline uint32_t pos_key(const Grid &g, double x, double y, d
     return cell_key(g, (a << g.sx) + q, b, c);
 }
 
+// Cells per block of the cell-start scan (the counting sort's per-block counts are over these).
+constexpr int kCellScanBlock = 4096;
+
+// Counting step of the counting sort, for C chunks of consecutive particles held one per lane
+// (i[u], key k[u], valid[u]; valid lanes are a prefix of the wave): cnt[k] counts the cell's
+// particles, rank[i] gets the particle's place among them, bsum[k / kCellScanBlock] the
+// block's count. Particles arrive nearly in cell order, so a run of neighbouring lanes with one
+// key takes its ranks with one atomic of its first lane, and the lanes of a wave that fall in
+// one block add to its count together. The C chunks' atomics are issued before any result is
+// used. Every lane of the wave must call it.
+template <int C>
+__device__ __forceinline__ void count_cells(const bool (&valid)[C], const uint32_t (&k)[C], const int64_t (&i)[C],
+                                            uint32_t *cnt, uint32_t *rank, uint32_t *bsum)
+{
+    const unsigned lane = __lane_id();
+    uint32_t base[C];
+    int leader[C];
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+        const uint32_t prev = __shfl_up(k[u], 1, 64);
+        const unsigned long long vmask = __ballot(valid[u]);
+        const unsigned long long starts = __ballot(valid[u] && (lane == 0 || prev != k[u]));
+        // this lane's run starts at the highest start at or below it, and ends at the next
+        // start or the first invalid lane above that
+        const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+        const unsigned long long mine = starts & upto;
+        leader[u] = mine ? 63 - __clzll((long long)mine) : (int)lane;
+        const unsigned long long later = leader[u] == 63 ? 0ull : ~((2ull << leader[u]) - 1ull);
+        const unsigned long long ends = (starts | ~vmask) & later;
+        const int next = ends ? __ffsll((long long)ends) - 1 : 64;
+        base[u] = 0u;
+        if (valid[u] && lane == (unsigned)leader[u]) base[u] = atomicAdd(&cnt[k[u]], (uint32_t)(next - leader[u]));
+    }
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+        const uint32_t b = __shfl(base[u], valid[u] ? leader[u] : (int)lane, 64);
+        if (valid[u]) rank[i[u]] = b + (lane - (unsigned)leader[u]);
+        const uint32_t sb = k[u] / (uint32_t)kCellScanBlock;
+        unsigned long long todo = __ballot(valid[u]);
+        while (todo) {
+            const int first = __ffsll((long long)todo) - 1;
+            const uint32_t lb = __shfl(sb, first, 64);
+            const unsigned long long peers = __ballot(valid[u] && sb == lb) & todo;
+            if (lane == (unsigned)first) atomicAdd(&bsum[lb], (uint32_t)__popcll(peers));
+            todo &= ~peers;
+        }
+    }
+}
+
 // One copy of the per-particle state in cell-sorted order.
 struct PSet {
     double4 *pos;       // x, y, z, r_c
@@ -167,8 +216,16 @@ void launch_list_check(const Grid &g, const double4 *pos, const double4 *pos_bui
 // every cell. The sort's scratch holds per-cell counts that must be zero on entry: the sort
 // leaves them zero, and launch_cell_sort_init zeroes them once for a new workspace.
 void launch_cell_sort_init(void *scratch, int64_t n, int64_t K, hipStream_t st);
+// counted = true: the keys' kernel has already counted them (cell_sort_counts) and the count
+// step is skipped.
 void launch_cell_sort(const uint32_t *key, uint32_t *key_out, uint32_t *val_out, uint32_t *cell_start,
-                      void *scratch, int64_t n, int64_t K, hipStream_t st);
+                      void *scratch, int64_t n, int64_t K, bool counted, hipStream_t st);
+// The count, rank and block-count arrays inside the sort scratch, for a kernel that counts its
+// keys as it writes them.
+struct CellCounts {
+    uint32_t *cnt, *rank, *bsum;
+};
+CellCounts cell_sort_counts(void *scratch, int64_t n, int64_t K);
 void launch_cell_fixup(const uint32_t *key_sorted, int64_t n, uint32_t *val, const uint32_t *id_old,
                        hipStream_t st);
 void launch_gather(PSet from, PSet to, const uint32_t *perm, int64_t n, hipStream_t st);
@@ -279,9 +336,11 @@ void launch_forces_images(const Grid &g, PSet s, const uint32_t *cell_start, int
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t st);
 void launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t st);
 int stream_blocks(int64_t n);
+// counts.cnt != nullptr: the kernel also takes the counting sort's count step on the keys it
+// writes (the sort that follows is then launched with counted = true).
 void launch_kick_drift_key(const Grid &g, PSet s, const double *fx, const double *fy,
                            const double *fz, int64_t n, double hdt, double dt, int second_kick,
-                           const double *scale, uint32_t *key, uint32_t *val, Partial *ke_partials,
+                           const double *scale, uint32_t *key, CellCounts counts, Partial *ke_partials,
                            hipStream_t st);
 void launch_kick(PSet s, const double *fx, const double *fy, const double *fz, int64_t n,
                  double hdt, Partial *ke_partials, hipStream_t st);

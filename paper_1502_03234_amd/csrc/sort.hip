@@ -15,8 +15,8 @@ namespace dcm {
 namespace {
 
 constexpr int kBlockWaves = kBlock / 64;
-constexpr int kScanPer = 16;                        // cells per thread of the cell scan
-constexpr int kScanCells = kBlock * kScanPer;       // cells per scan block
+constexpr int kScanPer = kCellScanBlock / kBlock;   // cells per thread of the cell scan
+constexpr int kScanCells = kCellScanBlock;          // cells per scan block
 
 __device__ __forceinline__ double wrap1(double x, double L)
 {
@@ -151,50 +151,17 @@ struct KCellCount {
     };
     static __device__ void run(const Args &a, uint32_t blk, uint32_t)
     {
-        const unsigned lane = lane_id();
         const int64_t i0 = (int64_t)blk * (kThreads * kCountChunks) + threadIdx.x;
-        uint32_t k[kCountChunks], base[kCountChunks];
-        int leader[kCountChunks];
+        uint32_t k[kCountChunks];
+        int64_t i[kCountChunks];
         bool valid[kCountChunks];
 #pragma unroll
         for (int u = 0; u < kCountChunks; ++u) {
-            const int64_t i = i0 + (int64_t)u * kThreads;
-            valid[u] = i < a.n;
-            k[u] = valid[u] ? a.key[i] : 0u;
+            i[u] = i0 + (int64_t)u * kThreads;
+            valid[u] = i[u] < a.n;
+            k[u] = valid[u] ? a.key[i[u]] : 0u;
         }
-#pragma unroll
-        for (int u = 0; u < kCountChunks; ++u) {
-            // particles arrive nearly in cell order: a run of neighbouring lanes with one key
-            // takes its ranks with one atomic of its first lane (valid lanes are a prefix)
-            const uint32_t prev = __shfl_up(k[u], 1, 64);
-            const unsigned long long vmask = __ballot(valid[u]);
-            const unsigned long long starts = __ballot(valid[u] && (lane == 0 || prev != k[u]));
-            // this lane's run starts at the highest start at or below it, and ends at the next
-            // start or the first invalid lane above that
-            const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-            const unsigned long long mine = starts & upto;
-            leader[u] = mine ? 63 - __clzll((long long)mine) : (int)lane;
-            const unsigned long long later = leader[u] == 63 ? 0ull : ~((2ull << leader[u]) - 1ull);
-            const unsigned long long ends = (starts | ~vmask) & later;
-            const int next = ends ? __ffsll((long long)ends) - 1 : 64;
-            base[u] = 0u;
-            if (valid[u] && lane == (unsigned)leader[u]) base[u] = atomicAdd(&a.cnt[k[u]], (uint32_t)(next - leader[u]));
-        }
-#pragma unroll
-        for (int u = 0; u < kCountChunks; ++u) {
-            const uint32_t b = __shfl(base[u], valid[u] ? leader[u] : (int)lane, 64);
-            const int64_t i = i0 + (int64_t)u * kThreads;
-            if (valid[u]) a.rank[i] = b + (lane - (unsigned)leader[u]);
-            const uint32_t sb = k[u] / (uint32_t)kScanCells;
-            unsigned long long todo = __ballot(valid[u]);
-            while (todo) {
-                const int first = __ffsll((long long)todo) - 1;
-                const uint32_t lb = __shfl(sb, first, 64);
-                const unsigned long long peers = __ballot(valid[u] && sb == lb) & todo;
-                if (lane == (unsigned)first) atomicAdd(&a.bsum[lb], (uint32_t)__popcll(peers));
-                todo &= ~peers;
-            }
-        }
+        count_cells<kCountChunks>(valid, k, i, a.cnt, a.rank, a.bsum);
     }
 };
 
@@ -401,15 +368,22 @@ void launch_cell_sort_init(void *scratch, int64_t n, int64_t K, hipStream_t st)
     launch_fill_u32(bsum, 0u, scan_blocks(K), st);
 }
 
+CellCounts cell_sort_counts(void *scratch, int64_t n, int64_t K)
+{
+    uint32_t *cnt = (uint32_t *)scratch;
+    return {cnt, cnt + (K + 1), cnt + (K + 1) + n};
+}
+
 void launch_cell_sort(const uint32_t *key, uint32_t *key_out, uint32_t *val_out, uint32_t *cell_start,
-                      void *scratch, int64_t n, int64_t K, hipStream_t st)
+                      void *scratch, int64_t n, int64_t K, bool counted, hipStream_t st)
 {
     uint32_t *cnt = (uint32_t *)scratch;
     uint32_t *rank = cnt + (K + 1);
     uint32_t *bsum = rank + n;
     const int64_t nb = scan_blocks(K);
     uint32_t *boff = bsum + nb;
-    emit<KCellCount>({key, n, cnt, rank, bsum}, (uint32_t)((n + kBlock * kCountChunks - 1) / (kBlock * kCountChunks)), st);
+    if (!counted)
+        emit<KCellCount>({key, n, cnt, rank, bsum}, (uint32_t)((n + kBlock * kCountChunks - 1) / (kBlock * kCountChunks)), st);
     emit<KCellBlockScan>({bsum, boff, nb}, 1, st);
     emit<KCellScan>({cnt, cell_start, boff, K + 1}, (uint32_t)nb, st);
     emit<KCellScatter>({key, rank, cell_start, n, key_out, val_out}, grid1(n), st);
