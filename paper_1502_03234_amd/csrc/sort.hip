@@ -222,7 +222,12 @@ struct KCellScan {
         for (int q = 0; q < kScanPer; ++q) {
             const int e = q * kBlock + threadIdx.x;
             const int64_t c = base + e;
-            tile[(e / kScanPer) * (kScanPer + 1) + e % kScanPer] = c < a.ncells ? a.cnt[c] : 0u;
+            uint32_t v = 0u;
+            if (c < a.ncells) {
+                v = a.cnt[c];
+                if (v) a.cnt[c] = 0u;       // cleared for the next step (most cells stay empty)
+            }
+            tile[(e / kScanPer) * (kScanPer + 1) + e % kScanPer] = v;
         }
         __syncthreads();
         uint32_t *row = tile + threadIdx.x * (kScanPer + 1);
@@ -243,10 +248,7 @@ struct KCellScan {
         for (int q = 0; q < kScanPer; ++q) {
             const int e = q * kBlock + threadIdx.x;
             const int64_t c = base + e;
-            if (c < a.ncells) {
-                a.cell_start[c] = tile[(e / kScanPer) * (kScanPer + 1) + e % kScanPer];
-                a.cnt[c] = 0u;
-            }
+            if (c < a.ncells) a.cell_start[c] = tile[(e / kScanPer) * (kScanPer + 1) + e % kScanPer];
         }
     }
 };
