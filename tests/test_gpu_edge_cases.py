@@ -1,6 +1,7 @@
 """Degenerate and edge inputs of the HIP path against the CPU oracle (through the C ABI): a
-density image without an interface, a gas with no liquid, two particles, positions outside the
-box, other detection schedules, other smoothing and removal settings."""
+density image without an interface, a gas with no liquid, many particles in one storage cell,
+two particles, positions outside the box, other detection schedules, other smoothing and
+removal settings."""
 import numpy as np
 import pytest
 
@@ -35,6 +36,31 @@ def test_dilute_gas():
     st = synth.gas(500, (20.0, 20.0, 20.0), seed=6)
     p, po = make(st)
     check_system(st, p, po, "gas 500", planar=False).close()
+
+
+def test_crowded_storage_cell():
+    """64 particles inside one half-box storage cell (a 4 x 4 x 4 lattice of spacing 0.1 x 0.2 x
+    0.2) among 1,901 gas particles, a count that fills no whole workgroup: the counting sort's
+    runs of one key span a whole wave and its ranks come from atomics in no fixed order. Counts,
+    labels, distances, cutoffs, forces and pair counts match the oracle, and a second system made
+    from the same state gives the same force bits (the in-cell id order fixes the storage order)."""
+    box = (16.0, 16.0, 24.0)
+    gas = synth.gas(1901, box, seed=78)
+    g = np.arange(4, dtype=np.float64)
+    Z, Y, X = np.meshgrid(12.15 + 0.2 * g, 8.15 + 0.2 * g, 8.07 + 0.1 * g, indexing="ij")
+    crowd = np.stack([X.ravel(), Y.ravel(), Z.ravel()])
+    m = crowd.shape[1]
+    st = synth.State(x=np.ascontiguousarray(np.concatenate([gas.x, crowd], axis=1)),
+                     v=np.ascontiguousarray(np.concatenate([gas.v, np.zeros((3, m))], axis=1)),
+                     box=box, n_liquid=0, n_vapor=gas.n_vapor + m, temperature=0.7)
+    p, po = make(st)
+    s = check_system(st, p, po, "crowded cell", planar=False)
+    t = dcm.System(p, st.x, st.v)
+    fa, fb = s.forces()["f"], t.forces()["f"]
+    torch.cuda.synchronize()
+    assert torch.equal(fa, fb)
+    s.close()
+    t.close()
 
 
 def test_two_particles_closed_form():
