@@ -57,11 +57,14 @@ int orc_grid(const orc_params *p, int32_t dims[3], double h[3])
 }
 
 /* ---- periodic wrap into [0, L) --------------------------------------------------------- */
+/* x mod L. When |x| is so large that the remainder has no significant digits left, the result
+ * can land outside [0, L) after rounding; it is then taken as 0, so every wrapped position lies
+ * in the box. */
 static double wrap1(double x, double L)
 {
     double t = x - L * floor(x / L);
     if (t < 0.0) t += L;
-    if (t >= L) t = 0.0;
+    if (t < 0.0 || t >= L) t = 0.0;
     return t;
 }
 

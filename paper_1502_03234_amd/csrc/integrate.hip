@@ -21,14 +21,6 @@ namespace {
 
 inline unsigned grid1(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-__device__ __forceinline__ double wrap1(double x, double L)
-{
-    double t = x - L * floor(x / L);
-    if (t < 0.0) t += L;
-    if (t >= L) t = 0.0;
-    return t;
-}
-
 __device__ double block_sum(double v)
 {
     __shared__ double lds[kBlock / 64];
@@ -112,9 +104,9 @@ __device__ void KKickDriftKey::run(const Args &a, uint32_t blk, uint32_t)
         vy = vy + hdt * f1;
         vz = vz + hdt * f2;
         double4 p = s.pos[i];
-        p.x = wrap1(p.x + dt * vx, g.L[0]);
-        p.y = wrap1(p.y + dt * vy, g.L[1]);
-        p.z = wrap1(p.z + dt * vz, g.L[2]);
+        p.x = wrap_periodic(p.x + dt * vx, g.L[0]);
+        p.y = wrap_periodic(p.y + dt * vy, g.L[1]);
+        p.z = wrap_periodic(p.z + dt * vz, g.L[2]);
         s.pos[i] = p;
         s.vx[i] = vx;
         s.vy[i] = vy;

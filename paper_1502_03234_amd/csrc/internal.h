@@ -140,6 +140,17 @@ __device__ __forceinline__ void count_cells(const bool (&valid)[C], const uint32
     }
 }
 
+// A coordinate wrapped into the periodic box [0, L). Where rounding would leave the result
+// outside (|x| so large that x - L floor(x / L) loses the fraction), it becomes 0, so that every
+// position the kernels index cells with lies inside the box; NaN stays NaN.
+__device__ __forceinline__ double wrap_periodic(double x, double L)
+{
+    double t = x - L * floor(x / L);
+    if (t < 0.0) t += L;
+    if (t < 0.0 || t >= L) t = 0.0;
+    return t;
+}
+
 // One copy of the per-particle state in cell-sorted order.
 struct PSet {
     double4 *pos;       // x, y, z, r_c

@@ -18,14 +18,6 @@ constexpr int kBlockWaves = kBlock / 64;
 constexpr int kScanPer = kCellScanBlock / kBlock;   // cells per thread of the cell scan
 constexpr int kScanCells = kCellScanBlock;          // cells per scan block
 
-__device__ __forceinline__ double wrap1(double x, double L)
-{
-    double t = x - L * floor(x / L);
-    if (t < 0.0) t += L;
-    if (t >= L) t = 0.0;
-    return t;
-}
-
 struct KWrapKey {
     static constexpr int kThreads = kBlock, kWaves = 0;
     struct Args { Grid g; PSet s; int64_t n; uint32_t *key, *val; };
@@ -39,9 +31,9 @@ __device__ void KWrapKey::run(const Args &args, uint32_t blk, uint32_t)
     int64_t i = (int64_t)blk * kThreads + threadIdx.x;
     if (i >= args.n) return;
     double4 p = s.pos[i];
-    p.x = wrap1(p.x, g.L[0]);
-    p.y = wrap1(p.y, g.L[1]);
-    p.z = wrap1(p.z, g.L[2]);
+    p.x = wrap_periodic(p.x, g.L[0]);
+    p.y = wrap_periodic(p.y, g.L[1]);
+    p.z = wrap_periodic(p.z, g.L[2]);
     s.pos[i] = p;
     args.key[i] = pos_key(g, p.x, p.y, p.z);
     args.val[i] = (uint32_t)i;

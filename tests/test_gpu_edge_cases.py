@@ -91,6 +91,48 @@ def test_positions_outside_the_box_are_wrapped(slab16k):
     check_system(st, p, po, "slab16k shifted by whole boxes").close()
 
 
+def test_positions_far_outside_the_box_land_inside():
+    """Coordinates of size 1e16 to 1e22, where x - L floor(x / L) keeps no digit of the remainder
+    (for -7.3e22 on edges 14 and 28 and 7.3e22 on edge 24 the rounded remainder stays below 0
+    even after adding L), still wrap into [0, L) exactly as the oracle wraps them, so the
+    binning, the cell starts and the force kernel's cell windows index only cells of the box.
+    The moved particles are ones whose wrapped place is at least 1.0 from every other one."""
+    box = (14.0, 28.0, 24.0)
+    gas = synth.gas(2000, box, seed=91)
+    far = [(0, -7.3e22), (1, -7.3e22), (2, 7.3e22), (0, 1e16), (1, -1e16), (2, 3e17),
+           (0, -1e20), (1, 1e20), (2, -2.701e22)]
+    x = gas.x.copy()
+    po = O.params(box)
+    L = np.asarray(box)[:, None]
+    wrapped = O.wrap(po, x)
+    moved = []
+    for i in range(gas.n):
+        if len(moved) == len(far):
+            break
+        ax, val = far[len(moved)]
+        y = x[:, i].copy()
+        y[ax] = val
+        yw = O.wrap(po, np.ascontiguousarray(y[:, None]))
+        d = wrapped - yw
+        d -= L * np.round(d / L)
+        r = np.sqrt(np.sum(d * d, axis=0))
+        r[i] = np.inf
+        if np.all(r >= 1.0):
+            x[:, i] = y
+            wrapped[:, i] = yw[:, 0]
+            moved.append(i)
+    assert len(moved) == len(far)
+    st = synth.State(x=np.ascontiguousarray(x), v=gas.v, box=box, n_liquid=0,
+                     n_vapor=gas.n_vapor, temperature=gas.temperature)
+    p, po = make(st)
+    s = check_system(st, p, po, "gas with coordinates up to 7.3e22", planar=False)
+    xw = s.state()[0].cpu().numpy()
+    assert np.all((xw >= 0.0) & (xw < L))
+    s.step(4)
+    s.check()
+    s.close()
+
+
 @pytest.mark.parametrize("de,detections", [(0, 0), (1, 6), (3, 2)])
 def test_other_detection_schedules(slab16k, de, detections):
     p, po = make(slab16k, detect_every=de)

@@ -239,6 +239,24 @@ def test_wrap(orc):
     assert w[0, 1] == 0.0 and w[0, 2] == 5.5 and w[0, 3] == 6.75
 
 
+def test_wrap_far_outside_the_box_stays_inside(orc):
+    """Coordinates so large that x - L floor(x / L) keeps no digits of the remainder still land
+    in [0, L), and coordinates within a few thousand boxes keep their exact remainder."""
+    p = orc.params((10.0, 28.0, 60.0))
+    big = np.array([1e16, -1e16, 3e17, -3e17, 1e20, -1e20, -7.3e22, 1e300, -1e300,
+                    -2.5e15 - 0.5, 9.007199254740993e15])
+    x = np.stack([big, big * 0.37, -big])
+    w = orc.wrap(p, x)
+    for ax, L in enumerate((10.0, 28.0, 60.0)):
+        assert np.all((w[ax] >= 0.0) & (w[ax] < L)), (ax, w[ax])
+    rng = np.random.default_rng(3)
+    k = rng.integers(-4000, 4000, size=64)
+    r = rng.integers(0, 40, size=64) * 0.25          # remainders exact in binary
+    x = np.stack([k * 10.0 + r * 0.25, k * 28.0 + r, k * 60.0 + r])
+    w = orc.wrap(p, x)
+    assert np.array_equal(w, np.stack([r * 0.25, r, r]))
+
+
 # ---------------------------------------------------------------- smoothing
 @pytest.mark.parametrize("passes", [1, 2])
 def test_smoothing_is_periodic_binomial_convolution(orc, passes):
