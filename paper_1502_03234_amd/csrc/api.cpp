@@ -353,6 +353,11 @@ ForceArgs force_args(const dcm_system *s, double *e_out, double *w_out, uint32_t
     a.eps24 = 24.0 * s->p.epsilon;
     a.eps4 = 4.0 * s->p.epsilon;
     a.sigma2 = s->p.sigma * s->p.sigma;
+    {
+        const double s6 = a.sigma2 * a.sigma2 * a.sigma2;
+        a.sigma6x2 = 2.0 * s6;
+        a.eps24s6 = a.eps24 * s6;
+    }
     a.eps24f = (float)a.eps24;
     a.sigma2f = (float)a.sigma2;
     a.rc_max = s->p.rc_max;

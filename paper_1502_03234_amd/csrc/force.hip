@@ -49,11 +49,11 @@ __device__ __forceinline__ int floor_mul(double v, double inv_h) { return (int)f
 // Conservative square root for box bounds: the hardware estimate, enlarged well past its error.
 __device__ __forceinline__ double sqrt_up(double v) { return __builtin_amdgcn_sqrt(v) * (1.0 + 1e-6) + 1e-9; }
 
-// FP64 form. The pair loop accumulates the force and the virial in units of 24 eps (the factor
-// is applied once per particle) and, in place of the energy, the sum of (sigma/r)^6: with
-// u = (sigma/r)^6 (2 (sigma/r)^6 - 1) the force scalar is 24 eps u / r^2, so the trace of the
-// virial sum is sum u (up to rounding), and sum ((sigma/r)^12 - (sigma/r)^6) = (sum u - sum
-// (sigma/r)^6) / 2 gives the energy without a per-pair term of its own.
+// FP64 form. The pair loop accumulates the force and the virial in units of 24 eps sigma^6 (the
+// factor is applied once per particle) and, in place of the energy, the sum of r^-6: with
+// s = (sigma/r)^6 the force scalar is 24 eps s (2 s - 1) / r^2, so the trace of the virial sum is
+// sum (2 s^2 - s) / sigma^6 (up to rounding), and sum (s^2 - s) = sigma^6 (trace - sum r^-6) / 2
+// gives the energy without a per-pair term of its own. For sigma = 1 every scaling is exact.
 struct Acc {
     double fx, fy, fz, e, wxx, wyy, wzz, wxy, wxz, wyz, eshift;
     uint32_t pairs;
@@ -101,15 +101,16 @@ __device__ __forceinline__ void interact(const ForceArgs &a, const double4 pj, b
         lim2 = rcp * rcp;
     }
     if (valid && r2 < lim2) {
+        // in units of sigma^6: u = r^-6, so (sigma / r)^6 = sigma^6 u and the force scalar
+        // 24 eps (sigma / r)^6 (2 (sigma / r)^6 - 1) / r^2 is 24 eps sigma^6 times fr
         double inv = rcp_refined(r2);
-        double sr2 = a.sigma2 * inv;
-        double sr6 = sr2 * sr2 * sr2;
-        double fr = sr6 * fma(2.0, sr6, -1.0) * inv;     // force scalar / (24 eps)
+        double u = inv * inv * inv;
+        double fr = u * fma(a.sigma6x2, u, -1.0) * inv;
         double fxp = fr * dx, fyp = fr * dy, fzp = fr * dz;
         c.fx += fxp;
         c.fy += fyp;
         c.fz += fzp;
-        c.e += sr6;
+        c.e += u;
         c.wxx = fma(dx, fxp, c.wxx);
         c.wyy = fma(dy, fyp, c.wyy);
         c.wzz = fma(dz, fzp, c.wzz);
@@ -552,12 +553,12 @@ __device__ void KForces<PAIR, SHIFT, U, PREC, LIST>::run(const Args &args_, uint
     if (PREC == DCM_FP64) {
         if (LIST) list_scan<SHIFT, U, AccT>(a, live, q, c);
         else traverse<PAIR, SHIFT, U, AccT>(a, live, q, rc_max, c, stage);
-        // the pair loop's units (see Acc): forces and virial times 24 eps; sum ((sigma/r)^12 -
-        // (sigma/r)^6) from the virial trace and the sum of (sigma/r)^6
-        const double esum = 0.5 * ((c.wxx + c.wyy + c.wzz) - c.e);
-        c.fx *= a.eps24; c.fy *= a.eps24; c.fz *= a.eps24;
-        c.wxx *= a.eps24; c.wyy *= a.eps24; c.wzz *= a.eps24;
-        c.wxy *= a.eps24; c.wxz *= a.eps24; c.wyz *= a.eps24;
+        // the pair loop's units (see Acc): forces and virial times 24 eps sigma^6; sum
+        // ((sigma/r)^12 - (sigma/r)^6) from the virial trace and the sum of r^-6
+        const double esum = 0.5 * (0.5 * a.sigma6x2) * ((c.wxx + c.wyy + c.wzz) - c.e);
+        c.fx *= a.eps24s6; c.fy *= a.eps24s6; c.fz *= a.eps24s6;
+        c.wxx *= a.eps24s6; c.wyy *= a.eps24s6; c.wzz *= a.eps24s6;
+        c.wxy *= a.eps24s6; c.wxz *= a.eps24s6; c.wyz *= a.eps24s6;
         c.e = esum;
     } else {
         Acc32 c32 = {};

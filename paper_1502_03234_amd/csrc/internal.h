@@ -279,6 +279,8 @@ struct ForceArgs {
     const uint32_t *id;
     int64_t n;
     double eps24, eps4, sigma2;
+    double sigma6x2;        // 2 sigma^6 (the FP64 pair loop works in units of sigma^6)
+    double eps24s6;         // 24 eps sigma^6
     float eps24f, sigma2f;  // the same constants for the FP32 precision form
     double rc_max;          // largest cutoff (search radius of the symmetric rule)
     int pair_rule;

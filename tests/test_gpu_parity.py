@@ -158,6 +158,20 @@ def test_static_limit_and_symmetric_rule(slab16k):
         s.close()
 
 
+@pytest.mark.parametrize("kw", [dict(sigma=0.93, epsilon=1.7), dict(sigma=1.05, epsilon=0.6, energy_shift=1),
+                                dict(sigma=0.97, epsilon=1.2, pair_rule=dcm.DCM_PAIR_MAX, energy_shift=1),
+                                dict(sigma=1.03, epsilon=0.9, neighbor_list=1)])
+def test_sigma_and_epsilon_other_than_one(slab16k, kw):
+    """The FP64 pair loop works in units of sigma^6 and scales by 24 eps sigma^6 once per
+    particle: with sigma and eps away from 1 the forces, energies, virials and pair counts still
+    match the oracle (Eq. 4), for both pair rules, the shifted energy and the list variant."""
+    p, po = make(slab16k, **kw)
+    s = check_system(slab16k, p, po, f"slab16k {kw}")
+    s.step(3)
+    s.check()
+    s.close()
+
+
 def test_one_step_matches_oracle(slab16k):
     p, po = make(slab16k)
     s = dcm.System(p, slab16k.x, slab16k.v)
