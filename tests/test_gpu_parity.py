@@ -119,6 +119,13 @@ def check_system(state, p, po, name, planar=True):
     for c in range(6):
         assert sum_close(th["virial"][c], ref.w[c])
     assert sum_close(th["ke"], 0.5 * state.v ** 2)
+    # without per-atom outputs the FP64 form counts pairs per wave: the same forces to the bit,
+    # the same thermo sums and the same pair total
+    f2 = s.forces(per_atom=False)
+    th2 = dcm.thermo_records(f2["thermo"])[0]
+    assert torch.equal(f2["f"], fo["f"])
+    assert th2["pairs"] == th["pairs"] and th2["pe"] == th["pe"]
+    assert np.array_equal(th2["virial"], th["virial"])
     return s
 
 
