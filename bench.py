@@ -29,7 +29,7 @@ WORKLOAD = "slab2m"
 # Valid only for the kernel source it was taken on: reported as null once csrc/force.hip no longer
 # hashes to this value.
 FORCE_TRAFFIC_BYTES = 3.09e9
-FORCE_TRAFFIC_SRC = "83a2adb96acc3d5a"
+FORCE_TRAFFIC_SRC = "3b49024c01c4fbcf"
 
 
 def force_traffic():
@@ -42,10 +42,11 @@ def force_traffic():
 
 def stage_bandwidth(breakdown: dict, n: int, G: int, detect_every: int) -> dict:
     """Achieved bandwidth of the HBM-bound stages: algorithmic bytes per step / stage time.
-    Per particle: kick/drift/key 144 B (read x, v, F; write x, v, key, value); binning 152 B
-    (count: key read, rank written, 8 B; scatter: key, rank and cell start read, key and source
-    slot written, 20 B; in-cell order 4 B; gather 120 B) plus 24 B per box (its two storage
-    cells' counts read, starts written and counts cleared). Per box and
+    Per particle: kick/drift/key 144 B (read x, v, F; write x, v, key and the rank in its cell,
+    which the counting sort's count takes here); binning 144 B (scatter: key, rank and cell
+    start read, key and source slot written, 20 B; in-cell order 4 B; gather 120 B) plus 16 B
+    per box (its two storage cells' counts read and starts written; clearing the occupied
+    cells' counts is not counted). Per box and
     detection: smoothing 20 B (the count image: two cell starts read, the count written, 12 B; one
     fused [1,2,1]^3 pass, 8 B), two-means 4 B (histogram read),
     labels and components 66 B (threshold 6 B, two component passes of about 30 B). Per particle
@@ -57,7 +58,7 @@ def stage_bandwidth(breakdown: dict, n: int, G: int, detect_every: int) -> dict:
     per_det = 1.0 / detect_every if detect_every > 0 else 0.0
     bytes_per_step = {
         "kick_drift_key": 144.0 * n,
-        "sort": 152.0 * n + 24.0 * G,
+        "sort": 144.0 * n + 16.0 * G,
         "smooth": 20.0 * G * per_det,
         "two_means": 4.0 * G * per_det,
         "segment": 66.0 * G * per_det,
