@@ -157,69 +157,49 @@ struct KCellCount {
     }
 };
 
-// One workgroup: boff = exclusive scan of the block counts, which go back to zero.
-struct KCellBlockScan {
-    static constexpr int kThreads = kBlock, kWaves = 0;
-    struct Args {
-        uint32_t *bsum;
-        uint32_t *boff;
-        int64_t nb;
-    };
-    static __device__ void run(const Args &a, uint32_t, uint32_t)
-    {
-        __shared__ uint32_t lds[kBlockWaves];
-        uint32_t carry = 0;
-        for (int64_t start = 0; start < a.nb; start += kBlock * 4) {
-            uint32_t v[4], s = 0;
-            for (int q = 0; q < 4; ++q) {
-                const int64_t t = start + (int64_t)threadIdx.x * 4 + q;
-                v[q] = t < a.nb ? a.bsum[t] : 0u;
-                s += v[q];
-            }
-            uint32_t excl;
-            const uint32_t total = block_exclusive_scan(s, &excl, lds);
-            uint32_t run = carry + excl;
-            for (int q = 0; q < 4; ++q) {
-                const int64_t t = start + (int64_t)threadIdx.x * 4 + q;
-                if (t < a.nb) {
-                    a.boff[t] = run;
-                    a.bsum[t] = 0u;
-                }
-                run += v[q];
-            }
-            carry += total;
-        }
-    }
-};
-
 // cell_start[c] = particles in cells below c: each block scans its kScanCells counts and adds
 // the particles of the blocks before it; the counts go back to zero. The block's counts pass
-// through LDS so that global reads and writes are coalesced while each thread scans a run of
-// kScanPer consecutive cells (rows padded by one word against bank conflicts).
+// through LDS so that global reads and writes are coalesced 16-byte accesses (four cells each)
+// while each thread scans a run of kScanPer consecutive cells (rows padded by one word against
+// bank conflicts). Both arrays start 256-byte aligned and blocks start at multiples of
+// kScanCells, so every full group of four cells is one aligned 16-byte word.
 struct KCellScan {
     static constexpr int kThreads = kBlock, kWaves = 0;
     struct Args {
         uint32_t *cnt;
         uint32_t *cell_start;
-        const uint32_t *boff;
+        const uint32_t *bsum;   // particles per block of kScanCells cells
         int64_t ncells;     // key_count + 1 (the last start is the particle count)
     };
     static __device__ void run(const Args &a, uint32_t blk, uint32_t)
     {
+        static_assert(kScanPer % 4 == 0, "rows of whole 16-byte groups");
+        constexpr int kQuads = kScanCells / 4 / kBlock;     // 16-byte groups per thread
         __shared__ uint32_t lds[kBlockWaves];
         __shared__ uint32_t tile[kBlock * (kScanPer + 1)];
         const int64_t base = (int64_t)blk * kScanCells;
-        // coalesced load: element e of the block goes to row e / kScanPer, column e % kScanPer
+        // coalesced load: group g (cells 4g .. 4g + 3 of the block) goes to row 4g / kScanPer
 #pragma unroll
-        for (int q = 0; q < kScanPer; ++q) {
-            const int e = q * kBlock + threadIdx.x;
-            const int64_t c = base + e;
-            uint32_t v = 0u;
-            if (c < a.ncells) {
-                v = a.cnt[c];
-                if (v) a.cnt[c] = 0u;       // cleared for the next step (most cells stay empty)
+        for (int q = 0; q < kQuads; ++q) {
+            const int gq = q * kBlock + threadIdx.x;
+            const int64_t c = base + 4 * (int64_t)gq;
+            uint32_t v[4] = {0u, 0u, 0u, 0u};
+            if (c + 3 < a.ncells) {
+                uint4 *w = (uint4 *)(a.cnt + c);
+                const uint4 x = *w;
+                v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+                // cleared for the next step (most groups of cells are empty)
+                if (x.x | x.y | x.z | x.w) *w = make_uint4(0u, 0u, 0u, 0u);
+            } else {
+                for (int j = 0; j < 4; ++j)
+                    if (c + j < a.ncells) {
+                        v[j] = a.cnt[c + j];
+                        if (v[j]) a.cnt[c + j] = 0u;
+                    }
             }
-            tile[(e / kScanPer) * (kScanPer + 1) + e % kScanPer] = v;
+            const int e = 4 * gq;
+            uint32_t *t = tile + (e / kScanPer) * (kScanPer + 1) + e % kScanPer;
+            t[0] = v[0]; t[1] = v[1]; t[2] = v[2]; t[3] = v[3];
         }
         __syncthreads();
         uint32_t *row = tile + threadIdx.x * (kScanPer + 1);
@@ -228,7 +208,12 @@ struct KCellScan {
         for (int q = 0; q < kScanPer; ++q) s += row[q];
         uint32_t excl;
         block_exclusive_scan(s, &excl, lds);
-        uint32_t run = a.boff[blk] + excl;
+        // the particles of the blocks before this one: the block counts are complete before
+        // the scan starts, and a few thousand of them sit in L2
+        uint32_t before = 0, ignored;
+        for (uint32_t j = threadIdx.x; j < blk; j += kBlock) before += a.bsum[j];
+        before = block_exclusive_scan(before, &ignored, lds);
+        uint32_t run = before + excl;
 #pragma unroll
         for (int q = 0; q < kScanPer; ++q) {
             const uint32_t v = row[q];
@@ -237,10 +222,17 @@ struct KCellScan {
         }
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < kScanPer; ++q) {
-            const int e = q * kBlock + threadIdx.x;
-            const int64_t c = base + e;
-            if (c < a.ncells) a.cell_start[c] = tile[(e / kScanPer) * (kScanPer + 1) + e % kScanPer];
+        for (int q = 0; q < kQuads; ++q) {
+            const int gq = q * kBlock + threadIdx.x;
+            const int64_t c = base + 4 * (int64_t)gq;
+            const int e = 4 * gq;
+            const uint32_t *t = tile + (e / kScanPer) * (kScanPer + 1) + e % kScanPer;
+            if (c + 3 < a.ncells) {
+                *(uint4 *)(a.cell_start + c) = make_uint4(t[0], t[1], t[2], t[3]);
+            } else {
+                for (int j = 0; j < 4; ++j)
+                    if (c + j < a.ncells) a.cell_start[c + j] = t[j];
+            }
         }
     }
 };
@@ -255,10 +247,13 @@ struct KCellScatter {
         int64_t n;
         uint32_t *key_out;
         uint32_t *val_out;
+        uint32_t *bsum;     // cleared here for the next count (the scan has read it)
+        int64_t nb;
     };
     static __device__ void run(const Args &a, uint32_t blk, uint32_t)
     {
         const int64_t i = (int64_t)blk * kThreads + threadIdx.x;
+        if (i < a.nb) a.bsum[i] = 0u;
         if (i >= a.n) return;
         const uint32_t k = a.key[i];
         const uint32_t p = a.cell_start[k] + a.rank[i];
@@ -323,12 +318,12 @@ inline unsigned grid1(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock);
 
 }  // namespace
 
-// Scratch of the cell sort: per-cell counts [K + 1], ranks [n], per-block counts and offsets.
+// Scratch of the cell sort: per-cell counts [K + 1], ranks [n], per-block counts.
 static int64_t scan_blocks(int64_t K) { return (K + 1 + kScanCells - 1) / kScanCells; }
 
 size_t sort_scratch_bytes(int64_t n, int64_t K)
 {
-    return sizeof(uint32_t) * ((size_t)(K + 1) + (size_t)n + 2 * (size_t)scan_blocks(K));
+    return sizeof(uint32_t) * ((size_t)(K + 1) + (size_t)n + (size_t)scan_blocks(K));
 }
 
 void launch_wrap_key(const Grid &g, PSet s, int64_t n, uint32_t *key, uint32_t *val, hipStream_t st)
@@ -375,12 +370,11 @@ void launch_cell_sort(const uint32_t *key, uint32_t *key_out, uint32_t *val_out,
     uint32_t *rank = cnt + (K + 1);
     uint32_t *bsum = rank + n;
     const int64_t nb = scan_blocks(K);
-    uint32_t *boff = bsum + nb;
     if (!counted)
         emit<KCellCount>({key, n, cnt, rank, bsum}, (uint32_t)((n + kBlock * kCountChunks - 1) / (kBlock * kCountChunks)), st);
-    emit<KCellBlockScan>({bsum, boff, nb}, 1, st);
-    emit<KCellScan>({cnt, cell_start, boff, K + 1}, (uint32_t)nb, st);
-    emit<KCellScatter>({key, rank, cell_start, n, key_out, val_out}, grid1(n), st);
+    emit<KCellScan>({cnt, cell_start, bsum, K + 1}, (uint32_t)nb, st);
+    const int64_t m = n > nb ? n : nb;
+    emit<KCellScatter>({key, rank, cell_start, n, key_out, val_out, bsum, nb}, grid1(m), st);
 }
 
 void launch_cell_fixup(const uint32_t *key_sorted, int64_t n, uint32_t *val, const uint32_t *id_old,
