@@ -132,6 +132,7 @@ struct KHist {
         int64_t G;
         uint32_t *hist;
         uint32_t *flags;
+        int aligned;        // img is 16-byte aligned (a caller's image need not be)
     };
     static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
 };
@@ -145,13 +146,28 @@ __device__ void KHist::run(const Args &args_, uint32_t blk, uint32_t nblk)
     __shared__ uint32_t lh[kLdsBins];
     for (int b = threadIdx.x; b < kLdsBins; b += kBlock) lh[b] = 0;
     __syncthreads();
-    for (int64_t c = (int64_t)blk * blockDim.x + threadIdx.x; c < G;
-         c += (int64_t)nblk * blockDim.x) {
-        uint32_t v = img[c];
-        if (v < (uint32_t)kLdsBins) atomicAdd(&lh[v], 1u);
+    // empty boxes (most of the vapor) are counted in a register: the zero bin would otherwise
+    // take most of the LDS atomics, all on one address
+    uint32_t zeros = 0;
+    auto add = [&](uint32_t v) {
+        if (v == 0u) ++zeros;
+        else if (v < (uint32_t)kLdsBins) atomicAdd(&lh[v], 1u);
         else if (v < (uint32_t)kHistBins) atomicAdd(&hist[v], 1u);
         else atomicOr(flags, kFlagHistOverflow);
+    };
+    // four boxes per 16-byte load where the image is aligned, then the last G % 4
+    const int64_t G4 = args_.aligned ? G / 4 : 0;
+    const int64_t t0 = (int64_t)blk * blockDim.x + threadIdx.x, stride = (int64_t)nblk * blockDim.x;
+    for (int64_t q = t0; q < G4; q += stride) {
+        const uint4 w = ((const uint4 *)img)[q];
+        add(w.x);
+        add(w.y);
+        add(w.z);
+        add(w.w);
     }
+    for (int64_t c = 4 * G4 + t0; c < G; c += stride) add(img[c]);
+    for (int off = 32; off > 0; off >>= 1) zeros += __shfl_xor(zeros, off, 64);
+    if ((threadIdx.x & 63) == 0 && zeros) atomicAdd(&lh[0], zeros);
     __syncthreads();
     for (int b = threadIdx.x; b < kLdsBins; b += kBlock)
         if (lh[b]) atomicAdd(&hist[b], lh[b]);
@@ -1265,7 +1281,7 @@ void launch_two_means(const Grid &g, const uint32_t *img, GridWork w, long long 
 {
     if (!hist_zero) launch_fill_u32(w.hist, 0u, kHistBins, st);
     unsigned nb = (unsigned)std::min<int64_t>((g.G + kBlock - 1) / kBlock, 1024);
-    emit<KHist>({img, g.G, w.hist, w.flags}, nb, st);
+    emit<KHist>({img, g.G, w.hist, w.flags, ((uintptr_t)img & 15u) == 0}, nb, st);
     emit<KTwoMeans>({w.hist, w.km, stats_out}, 1, st);
 }
 

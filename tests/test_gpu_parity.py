@@ -302,12 +302,20 @@ def test_grid_two_means_and_segment():
     for trial in range(6):
         dims = tuple(int(v) for v in rng.integers(4, 20, size=3))
         G = int(np.prod(dims))
-        img = np.where(rng.random(G) < 0.4, rng.poisson(3, G), rng.poisson(40, G)).astype(np.uint32)
+        # odd trials: a low cluster of mostly empty boxes (the vapor of a slab)
+        low = rng.poisson(0.3 if trial % 2 else 3, G)
+        img = np.where(rng.random(G) < 0.4 + 0.2 * (trial % 2), low, rng.poisson(40, G)).astype(np.uint32)
         ws = _grid_ws(dims)
         km = torch.empty(3, dtype=torch.float64, device="cuda")
         it = torch.empty(1, dtype=torch.int64, device="cuda")
         g = torch.from_numpy(img.view(np.int32)).cuda()
         dcm.dcm_grid_two_means(dims, g, km, it, ws)
+        # the same image 4 bytes past a 16-byte boundary (the histogram's 4-byte load path)
+        g_off = torch.zeros(G + 1, dtype=torch.int32, device="cuda")
+        g_off[1:] = g
+        km_off = torch.empty_like(km)
+        it_off = torch.empty_like(it)
+        dcm.dcm_grid_two_means(dims, g_off[1:], km_off, it_off, ws)
         raw = torch.empty(G, dtype=torch.uint8, device="cuda")
         lab = torch.empty(G, dtype=torch.uint8, device="cuda")
         stats = torch.empty(4, dtype=torch.int64, device="cuda")
@@ -316,6 +324,7 @@ def test_grid_two_means_and_segment():
         torch.cuda.synchronize()
         okm, oit = O.two_means(img)
         assert np.array_equal(km.cpu().numpy(), okm) and it.item() == oit
+        assert np.array_equal(km_off.cpu().numpy(), okm) and it_off.item() == oit
         oraw, olab, ost = O.segment(dims, img, okm[2], mc)
         assert np.array_equal(raw.cpu().numpy(), oraw)
         assert np.array_equal(lab.cpu().numpy(), olab), (dims, mc)
