@@ -294,11 +294,20 @@ CellCounts step_counts(const dcm_system *s)
     return cell_sort_counts(s->sort_scratch, s->n, key_count(s->grid));
 }
 
-void rebin_sorted(dcm_system *s, hipStream_t st, bool counted = false)
+// The buffer in which the smoothing passes expect the box-count image (launch_smooth puts it
+// where the first pass does not write).
+uint32_t *count_image_target(const dcm_system *s)
+{
+    const int passes = s->p.smooth_passes;
+    return (passes > 0 && passes % 2 == 1) ? s->gw.gtmp : s->gw.g;
+}
+
+// image (optional): the sort also writes the box-count image there (a detection follows).
+void rebin_sorted(dcm_system *s, hipStream_t st, bool counted = false, uint32_t *image = nullptr)
 {
     PSet from = s->set[s->cur], to = s->set[1 - s->cur];
-    launch_cell_sort(s->key, s->key_alt, s->val_alt, s->gw.cell_start, s->sort_scratch, s->n, key_count(s->grid),
-                     counted, st);
+    launch_cell_sort(s->grid, s->key, s->key_alt, s->val_alt, s->gw.cell_start, s->sort_scratch, s->n, counted,
+                     image, st);
     std::swap(s->key, s->key_alt);
     std::swap(s->val, s->val_alt);
     launch_cell_fixup(s->key, s->n, s->val, from.id, st);
@@ -308,7 +317,8 @@ void rebin_sorted(dcm_system *s, hipStream_t st, bool counted = false)
 
 // The detection stages; with_cutoffs = false leaves the cutoffs as they are (the tail
 // correction of a state resumed between detections needs only the distance fields).
-void detect(dcm_system *s, hipStream_t st, bool with_cutoffs = true)
+// counted = true: the sort just before wrote the box-count image (count_image_target).
+void detect(dcm_system *s, hipStream_t st, bool with_cutoffs = true, bool counted = false)
 {
     const Grid &g = s->grid;
     GridWork w = s->gw;
@@ -317,6 +327,8 @@ void detect(dcm_system *s, hipStream_t st, bool with_cutoffs = true)
         // particles keep their storage order between list builds: count the current positions
         launch_count_boxes(g, s->set[s->cur].pos, s->n, s->box_count, st);
         launch_smooth(g, s->p.smooth_passes, nullptr, s->box_count, w.g, w.gtmp, st);
+    } else if (counted) {
+        launch_smooth(g, s->p.smooth_passes, nullptr, count_image_target(s), w.g, w.gtmp, st);
     } else {
         launch_smooth(g, s->p.smooth_passes, w.cell_start, nullptr, w.g, w.gtmp, st);
     }
@@ -543,12 +555,13 @@ dcm_status step_nose_hoover(dcm_system *s, int32_t nsteps, hipStream_t st, dcm_t
         launch_kick_drift_key(s->grid, s->set[s->cur], s->fx, s->fy, s->fz, s->n, s->hdt, s->p.dt, 0,
                               s->nh + 2, s->key, step_counts(s), s->kparts, st);
         stage_end(s, st);
+        const bool det = s->p.detect_every > 0 && s->k % s->p.detect_every == 0;
         if (!s->p.neighbor_list) {
             stage_begin(s, 1, st);
-            rebin_sorted(s, st, true);
+            rebin_sorted(s, st, true, det ? count_image_target(s) : nullptr);
             stage_end(s, st);
         }
-        if (s->p.detect_every > 0 && s->k % s->p.detect_every == 0) detect(s, st);
+        if (det) detect(s, st, true, !s->p.neighbor_list);
         if (s->p.neighbor_list) {
             dcm_status lr = list_update(s, st, false);
             if (lr != DCM_OK) return lr;
@@ -706,12 +719,13 @@ dcm_status dcm_step(dcm_system *s, int32_t nsteps, dcm_stream_t stream, dcm_ther
                                  s->rparts, s->nh, kNhNone, s->nhc, st);
             stage_end(s, st);
         }
+        const bool det = s->p.detect_every > 0 && s->k % s->p.detect_every == 0;
         if (!s->p.neighbor_list) {
             stage_begin(s, 1, st);
-            rebin_sorted(s, st, true);
+            rebin_sorted(s, st, true, det ? count_image_target(s) : nullptr);
             stage_end(s, st);
         }
-        if (s->p.detect_every > 0 && s->k % s->p.detect_every == 0) detect(s, st);
+        if (det) detect(s, st, true, !s->p.neighbor_list);
         if (s->p.neighbor_list) {
             dcm_status lr = list_update(s, st, false);
             if (lr != DCM_OK) return lr;

@@ -1257,7 +1257,7 @@ void launch_smooth(const Grid &g, int passes, const uint32_t *cell_start, const 
 {
     if (passes == 0) {
         if (cell_start) launch_count_from_ranges(g, cell_start, out, st);
-        else launch_copy_bytes(out, in, sizeof(uint32_t) * (size_t)g.G, st);
+        else if (in != out) launch_copy_bytes(out, in, sizeof(uint32_t) * (size_t)g.G, st);
         return;
     }
     const int total = passes;
@@ -1280,7 +1280,7 @@ void launch_two_means(const Grid &g, const uint32_t *img, GridWork w, long long 
                       bool hist_zero, hipStream_t st)
 {
     if (!hist_zero) launch_fill_u32(w.hist, 0u, kHistBins, st);
-    unsigned nb = (unsigned)std::min<int64_t>((g.G + kBlock - 1) / kBlock, 1024);
+    unsigned nb = (unsigned)std::min<int64_t>((g.G + kBlock - 1) / kBlock, 512);
     emit<KHist>({img, g.G, w.hist, w.flags, ((uintptr_t)img & 15u) == 0}, nb, st);
     emit<KTwoMeans>({w.hist, w.km, stats_out}, 1, st);
 }

@@ -228,9 +228,11 @@ void launch_list_check(const Grid &g, const double4 *pos, const double4 *pos_bui
 // leaves them zero, and launch_cell_sort_init zeroes them once for a new workspace.
 void launch_cell_sort_init(void *scratch, int64_t n, int64_t K, hipStream_t st);
 // counted = true: the keys' kernel has already counted them (cell_sort_counts) and the count
-// step is skipped.
-void launch_cell_sort(const uint32_t *key, uint32_t *key_out, uint32_t *val_out, uint32_t *cell_start,
-                      void *scratch, int64_t n, int64_t K, bool counted, hipStream_t st);
+// step is skipped. image (optional, G words): also write the box counts of Eq. 9 there, in box
+// order, as launch_count_from_ranges would from the cell starts.
+void launch_cell_sort(const Grid &g, const uint32_t *key, uint32_t *key_out, uint32_t *val_out,
+                      uint32_t *cell_start, void *scratch, int64_t n, bool counted, uint32_t *image,
+                      hipStream_t st);
 // The count, rank and block-count arrays inside the sort scratch, for a kernel that counts its
 // keys as it writes them.
 struct CellCounts {

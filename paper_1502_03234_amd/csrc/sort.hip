@@ -170,6 +170,8 @@ struct KCellScan {
         uint32_t *cell_start;
         const uint32_t *bsum;   // particles per block of kScanCells cells
         int64_t ncells;     // key_count + 1 (the last start is the particle count)
+        Grid g;
+        uint32_t *image;    // optional: the box counts of Eq. 9 as an image in box order
     };
     static __device__ void run(const Args &a, uint32_t blk, uint32_t)
     {
@@ -202,6 +204,31 @@ struct KCellScan {
             t[0] = v[0]; t[1] = v[1]; t[2] = v[2]; t[3] = v[3];
         }
         __syncthreads();
+        // The box counts (Eq. 9), when asked for: a box's 2^sx cells are keys 2^(sy + sz) apart
+        // inside one aligned group of 2^(sx + sy + sz) keys, so every box lies in one block. The
+        // reads of the counts here come before the scan below overwrites them (its first barrier
+        // separates the two).
+        if (a.image) {
+            const Grid &g = a.g;
+            const int gs = g.sy + g.sz;
+            const uint32_t ncx = (uint32_t)g.n[0] << g.sx, rows_y = (uint32_t)g.n[1] >> g.sy;
+            for (int t = threadIdx.x; t < (kScanCells >> g.sx); t += kBlock) {
+                const int place = t & ((1 << gs) - 1);
+                const int e0 = ((t >> gs) << (g.sx + gs)) + place;
+                const int64_t k0 = base + e0;
+                if (k0 + 1 >= a.ncells) continue;   // past the last cell
+                uint32_t cb = 0;
+                for (int j = 0; j < (1 << g.sx); ++j) {
+                    const int e = e0 + (j << gs);
+                    cb += tile[(e / kScanPer) * (kScanPer + 1) + e % kScanPer];
+                }
+                const uint32_t rest = (uint32_t)(k0 >> gs);
+                const uint32_t xa = (rest % ncx) >> g.sx, rw = rest / ncx;
+                const uint32_t yb = ((rw % rows_y) << g.sy) | ((uint32_t)place & ((1u << g.sy) - 1u));
+                const uint32_t zc = ((rw / rows_y) << g.sz) | ((uint32_t)place >> g.sy);
+                a.image[((int64_t)zc * g.n[1] + yb) * g.n[0] + xa] = cb;
+            }
+        }
         uint32_t *row = tile + threadIdx.x * (kScanPer + 1);
         uint32_t s = 0;
 #pragma unroll
@@ -363,16 +390,17 @@ CellCounts cell_sort_counts(void *scratch, int64_t n, int64_t K)
     return {cnt, cnt + (K + 1), cnt + (K + 1) + n};
 }
 
-void launch_cell_sort(const uint32_t *key, uint32_t *key_out, uint32_t *val_out, uint32_t *cell_start,
-                      void *scratch, int64_t n, int64_t K, bool counted, hipStream_t st)
+void launch_cell_sort(const Grid &g, const uint32_t *key, uint32_t *key_out, uint32_t *val_out,
+                      uint32_t *cell_start, void *scratch, int64_t n, bool counted, uint32_t *image, hipStream_t st)
 {
+    const int64_t K = key_count(g);
     uint32_t *cnt = (uint32_t *)scratch;
     uint32_t *rank = cnt + (K + 1);
     uint32_t *bsum = rank + n;
     const int64_t nb = scan_blocks(K);
     if (!counted)
         emit<KCellCount>({key, n, cnt, rank, bsum}, (uint32_t)((n + kBlock * kCountChunks - 1) / (kBlock * kCountChunks)), st);
-    emit<KCellScan>({cnt, cell_start, bsum, K + 1}, (uint32_t)nb, st);
+    emit<KCellScan>({cnt, cell_start, bsum, K + 1, g, image}, (uint32_t)nb, st);
     const int64_t m = n > nb ? n : nb;
     emit<KCellScatter>({key, rank, cell_start, n, key_out, val_out, bsum, nb}, grid1(m), st);
 }
