@@ -46,10 +46,9 @@ def stage_bandwidth(breakdown: dict, n: int, G: int, detect_every: int) -> dict:
     which the counting sort's count takes here); binning 144 B (scatter: key, rank and cell
     start read, key and source slot written, 20 B; in-cell order 4 B; gather 120 B) plus 16 B
     per box (its two storage cells' counts read and starts written; clearing the occupied
-    cells' counts is not counted). Per box and
-    detection: smoothing 20 B (the count image: two cell starts read, the count written, 12 B; one
-    fused [1,2,1]^3 pass, 8 B), two-means 4 B (histogram read),
-    labels and components 66 B (threshold 6 B, two component passes of about 30 B). Per particle
+    cells' counts is not counted) plus, per box and detection, the box-count image the cell
+    scan writes (4 B). Per box and detection: smoothing 8 B (one fused [1,2,1]^3 pass),
+    two-means 4 B (histogram read), labels and components 66 B (threshold 6 B, two component passes of about 30 B). Per particle
     and detection: cutoffs 96 B (eight 8-byte box values, the 32-byte position record read).
     Detection stages count once per detect_every steps. The distance solve's floor is reading
     the labels and writing the distances once, 9 B per box and detection; it runs far above that
@@ -58,8 +57,8 @@ def stage_bandwidth(breakdown: dict, n: int, G: int, detect_every: int) -> dict:
     per_det = 1.0 / detect_every if detect_every > 0 else 0.0
     bytes_per_step = {
         "kick_drift_key": 144.0 * n,
-        "sort": 144.0 * n + 16.0 * G,
-        "smooth": 20.0 * G * per_det,
+        "sort": 144.0 * n + 16.0 * G + 4.0 * G * per_det,
+        "smooth": 8.0 * G * per_det,
         "two_means": 4.0 * G * per_det,
         "segment": 66.0 * G * per_det,
         "distance": 9.0 * G * per_det,
