@@ -55,7 +55,14 @@ struct KSmooth3 {
     static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
 };
 
-__device__ __forceinline__ int wrap_index(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+// v in [-1, 2n): periodic index; axes shorter than a block (v past 2n - 1) take the remainder.
+__device__ __forceinline__ int wrap_halo(int v, int n)
+{
+    if (v < 0) return v + n;
+    if (v < n) return v;
+    v -= n;
+    return v < n ? v : v % n;
+}
 
 __device__ void KSmooth3::run(const Args &args_, uint32_t blk, uint32_t)
 {
@@ -69,10 +76,11 @@ __device__ void KSmooth3::run(const Args &args_, uint32_t blk, uint32_t)
     // positions past the grid's far edge hold wrapped values too; only in-grid boxes are written
     for (int q = threadIdx.x; q < (SZ + 2) * (SY + 2) * (SX + 2); q += kBlock) {
         const int hx = q % (SX + 2), hy = (q / (SX + 2)) % (SY + 2), hz = q / ((SX + 2) * (SY + 2));
-        const int gx = wrap_index((x0 + hx - 1) % g.n[0], g.n[0]);
-        const int gy = wrap_index((y0 + hy - 1) % g.n[1], g.n[1]);
-        const int gz = wrap_index((z0 + hz - 1) % g.n[2], g.n[2]);
-        A[hz][hy][hx] = in[lin(g, gx, gy, gz)];
+        // periodic neighbours without a division (block origins lie inside the grid)
+        const int gx = wrap_halo(x0 + hx - 1, g.n[0]);
+        const int gy = wrap_halo(y0 + hy - 1, g.n[1]);
+        const int gz = wrap_halo(z0 + hz - 1, g.n[2]);
+        A[hz][hy][hx] = in[((int64_t)gz * g.n[1] + gy) * g.n[0] + gx];
     }
     __syncthreads();
     for (int q = threadIdx.x; q < (SZ + 2) * (SY + 2) * SX; q += kBlock) {
