@@ -746,6 +746,31 @@ __device__ double godunov_uniform(double a0, double a1, double a2, double h, dou
     return d;
 }
 
+// The same root for unit box edges (h = w = 1), as godunov_uniform computes it: every
+// multiplication by w or w^2 there is exact and is left out, and the division by 2 is a
+// multiplication by 1/2 (exact), so the result is the same to the bit with fewer operations.
+__device__ double godunov_unit(double a0, double a1, double a2)
+{
+    const double lo = fmin(a0, a1), hi = fmax(a0, a1);
+    const double b0 = fmin(lo, a2), mid = fmax(lo, a2);
+    const double b1 = fmin(mid, hi), b2 = fmax(mid, hi);
+    if (isinf(b0)) return INFINITY;
+    double d = b0 + 1.0;
+    if (d > b1) {
+        const double dd = b0 - b1;
+        double disc = 2.0 - dd * dd;
+        if (disc < 0.0) disc = 0.0;
+        d = ((b0 + b1) + sqrt(disc)) * 0.5;
+        if (d > b2) {
+            const double d01 = b0 - b1, d02 = b0 - b2, d12 = b1 - b2;
+            disc = 3.0 - ((d01 * d01 + d02 * d02) + d12 * d12);
+            if (disc < 0.0) disc = 0.0;
+            d = (((b0 + b1) + b2) + sqrt(disc)) / 3.0;
+        }
+    }
+    return d;
+}
+
 // One global relaxation pass over LDS tiles. Two copies of the distance grid alternate;
 // cur[t] says which copy holds tile t's values as of the end of the previous pass. A tile
 // marked dirty loads its boxes and a one-box halo (each from the copy current for the tile that
@@ -1002,6 +1027,7 @@ __device__ __forceinline__ void dist_tile(const KDistTiles::Args &args_, int b, 
         }
     const double wx = 1.0 / (g.h[0] * g.h[0]), wy = 1.0 / (g.h[1] * g.h[1]), wz = 1.0 / (g.h[2] * g.h[2]);
     const bool uniform = g.h[0] == g.h[1] && g.h[1] == g.h[2];
+    const bool unit = uniform && g.h[0] == 1.0;
     __syncthreads();
     // the loaded values of this thread's boxes (the tile's own copy), to detect changes
     double init[2][2];
@@ -1027,8 +1053,9 @@ __device__ __forceinline__ void dist_tile(const KDistTiles::Args &args_, int b, 
                 seen[p][m][0] = ax; seen[p][m][1] = ay; seen[p][m][2] = az;
                 if (isinf(ax) && isinf(ay) && isinf(az)) continue;
                 const double old = t[hz][hy][hx];
-                const double db = uniform ? godunov_uniform(ax, ay, az, g.h[0], wx)
-                                          : godunov(ax, ay, az, g.h[0], g.h[1], g.h[2], wx, wy, wz);
+                const double db = unit ? godunov_unit(ax, ay, az)
+                                       : uniform ? godunov_uniform(ax, ay, az, g.h[0], wx)
+                                                 : godunov(ax, ay, az, g.h[0], g.h[1], g.h[2], wx, wy, wz);
                 if (db <= cap && db < old) { t[hz][hy][hx] = db; ch = true; }
             }
             if (p == 0) __syncthreads();
