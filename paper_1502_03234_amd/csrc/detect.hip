@@ -73,14 +73,26 @@ __device__ void KSmooth3::run(const Args &args_, uint32_t blk, uint32_t)
     __shared__ uint32_t C[SZ + 2][SY][SX];
     const int ntx = (g.n[0] + SX - 1) / SX, nty = (g.n[1] + SY - 1) / SY;
     const int x0 = (int)(blk % ntx) * SX, y0 = (int)((blk / ntx) % nty) * SY, z0 = (int)(blk / (ntx * nty)) * SZ;
-    // positions past the grid's far edge hold wrapped values too; only in-grid boxes are written
-    for (int q = threadIdx.x; q < (SZ + 2) * (SY + 2) * (SX + 2); q += kBlock) {
-        const int hx = q % (SX + 2), hy = (q / (SX + 2)) % (SY + 2), hz = q / ((SX + 2) * (SY + 2));
+    // positions past the grid's far edge hold wrapped values too; only in-grid boxes are written.
+    // A thread's loads are all in flight at once (one round trip, not one per load).
+    constexpr int kHalo = (SZ + 2) * (SY + 2) * (SX + 2);
+    constexpr int kHaloPer = (kHalo + kBlock - 1) / kBlock;
+    uint32_t hv[kHaloPer];
+#pragma unroll
+    for (int it = 0; it < kHaloPer; ++it) {
+        const int q = (int)threadIdx.x + it * kBlock;
+        const int qq = q < kHalo ? q : 0;
+        const int hx = qq % (SX + 2), hy = (qq / (SX + 2)) % (SY + 2), hz = qq / ((SX + 2) * (SY + 2));
         // periodic neighbours without a division (block origins lie inside the grid)
         const int gx = wrap_halo(x0 + hx - 1, g.n[0]);
         const int gy = wrap_halo(y0 + hy - 1, g.n[1]);
         const int gz = wrap_halo(z0 + hz - 1, g.n[2]);
-        A[hz][hy][hx] = in[((int64_t)gz * g.n[1] + gy) * g.n[0] + gx];
+        hv[it] = in[((int64_t)gz * g.n[1] + gy) * g.n[0] + gx];
+    }
+#pragma unroll
+    for (int it = 0; it < kHaloPer; ++it) {
+        const int q = (int)threadIdx.x + it * kBlock;
+        if (q < kHalo) A[q / ((SX + 2) * (SY + 2))][(q / (SX + 2)) % (SY + 2)][q % (SX + 2)] = hv[it];
     }
     __syncthreads();
     for (int q = threadIdx.x; q < (SZ + 2) * (SY + 2) * SX; q += kBlock) {
@@ -166,12 +178,22 @@ __device__ void KHist::run(const Args &args_, uint32_t blk, uint32_t nblk)
     // four boxes per 16-byte load where the image is aligned, then the last G % 4
     const int64_t G4 = args_.aligned ? G / 4 : 0;
     const int64_t t0 = (int64_t)blk * blockDim.x + threadIdx.x, stride = (int64_t)nblk * blockDim.x;
-    for (int64_t q = t0; q < G4; q += stride) {
-        const uint4 w = ((const uint4 *)img)[q];
-        add(w.x);
-        add(w.y);
-        add(w.z);
-        add(w.w);
+    // four 16-byte loads in flight per thread and round
+    for (int64_t q = t0; q < G4; q += 4 * stride) {
+        uint4 w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t qu = q + u * stride;
+            w[u] = ((const uint4 *)img)[qu < G4 ? qu : q];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (q + u * stride < G4) {
+                add(w[u].x);
+                add(w[u].y);
+                add(w[u].z);
+                add(w[u].w);
+            }
     }
     for (int64_t c = 4 * G4 + t0; c < G; c += stride) add(img[c]);
     for (int off = 32; off > 0; off >>= 1) zeros += __shfl_xor(zeros, off, 64);
@@ -209,7 +231,11 @@ __device__ void KTwoMeans::run(const Args &args_, uint32_t, uint32_t)
     const int tid = threadIdx.x, w = tid >> 6;
     int mn = kHistBins, mx = -1;
     static_assert(kHistBins % (4 * kTmThreads) == 0, "whole uint4 loads");
-    for (int b0 = 4 * tid; b0 < kHistBins; b0 += 4 * kTmThreads) {
+    // a fixed count, unrolled, so that a thread's 16 loads are in flight together rather than
+    // one at a time
+#pragma unroll
+    for (int qq = 0; qq < kHistBins / (4 * kTmThreads); ++qq) {
+        const int b0 = 4 * tid + qq * 4 * kTmThreads;
         const uint4 v = *reinterpret_cast<const uint4 *>(hist + b0);
         const uint32_t h[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
@@ -826,9 +852,11 @@ __device__ void KDistInit::run(const Args &args_, uint32_t blk, uint32_t)
     const int64_t xm = i == 0 ? g.n[0] - 1 : i - 1, xp = i == g.n[0] - 1 ? 0 : i + 1;
     const int64_t ym = j == 0 ? g.n[1] - 1 : j - 1, yp = j == g.n[1] - 1 ? 0 : j + 1;
     const int64_t zm = k == 0 ? g.n[2] - 1 : k - 1, zp = k == g.n[2] - 1 ? 0 : k + 1;
-    const bool front = label[lin(g, xm, j, k)] == zero || label[lin(g, xp, j, k)] == zero ||
-                       label[lin(g, i, ym, k)] == zero || label[lin(g, i, yp, k)] == zero ||
-                       label[lin(g, i, j, zm)] == zero || label[lin(g, i, j, zp)] == zero;
+    // the six neighbours' labels loaded together (no short circuit: one round trip, not six)
+    const uint8_t n0 = label[lin(g, xm, j, k)], n1 = label[lin(g, xp, j, k)];
+    const uint8_t n2 = label[lin(g, i, ym, k)], n3 = label[lin(g, i, yp, k)];
+    const uint8_t n4 = label[lin(g, i, j, zm)], n5 = label[lin(g, i, j, zp)];
+    const bool front = (n0 == zero) | (n1 == zero) | (n2 == zero) | (n3 == zero) | (n4 == zero) | (n5 == zero);
     if (front) dirty[tile_of(g, i, j, k)] = 1u;
 }
 
@@ -992,30 +1020,48 @@ __device__ __forceinline__ void dist_tile(const KDistTiles::Args &args_, int b, 
     }
     __syncthreads();
     // positions one box outside the grid hold the periodic neighbour (the only outside
-    // positions a grid box reads); positions further out (partial tiles) hold infinity
-    for (int q = threadIdx.x; q < HX * HY * HZ; q += kTileThreads) {
-        int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
-        int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
-        double v = INFINITY;
-        if (gx <= g.n[0] && gy <= g.n[1] && gz <= g.n[2]) {
-            int cx = gx < 0 ? gx + g.n[0] : (gx == g.n[0] ? 0 : gx);
-            int cy = gy < 0 ? gy + g.n[1] : (gy == g.n[1] ? 0 : gy);
-            int cz = gz < 0 ? gz + g.n[2] : (gz == g.n[2] ? 0 : gz);
+    // positions a grid box reads); positions further out (partial tiles) hold infinity. The
+    // loads of a thread's halo positions and labels are issued together, with no branch around
+    // them, so that a tile waits for one round trip to memory instead of one per load.
+    constexpr int kHalo = HX * HY * HZ;
+    constexpr int kHaloPer = (kHalo + kTileThreads - 1) / kTileThreads;
+    constexpr int kHaloBatch = 4;      // loads in flight per thread (registers: 2 per load)
+    static_assert(kHaloPer % kHaloBatch == 0, "whole batches");
+#pragma unroll 1
+    for (int it0 = 0; it0 < kHaloPer; it0 += kHaloBatch) {
+        double hv[kHaloBatch];
+#pragma unroll
+        for (int u = 0; u < kHaloBatch; ++u) {
+            const int q = (int)threadIdx.x + (it0 + u) * kTileThreads;
+            const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
+            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+            const bool ok = q < kHalo && gx <= g.n[0] && gy <= g.n[1] && gz <= g.n[2];
+            const int cx = gx < 0 ? gx + g.n[0] : (gx == g.n[0] ? 0 : gx);
+            const int cy = gy < 0 ? gy + g.n[1] : (gy == g.n[1] ? 0 : gy);
+            const int cz = gz < 0 ? gz + g.n[2] : (gz == g.n[2] ? 0 : gz);
             // owner tile relative to this one, -1, 0 or +1 per axis after the periodic wrap
             int ox = cx / TX - bx, oy = cy / TY - by, oz = cz / TZ - bz;
             ox = ox > 1 ? ox - ntx : (ox < -1 ? ox + ntx : ox);
             oy = oy > 1 ? oy - nty : (oy < -1 ? oy + nty : oy);
             oz = oz > 1 ? oz - ntz : (oz < -1 ? oz + ntz : oz);
-            const double *src = ncur[(oz + 1) * 9 + (oy + 1) * 3 + (ox + 1)] ? d1 : d0;
-            v = src[lin(g, cx, cy, cz)];
+            const int nq = ok ? (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1) : 13;
+            const double *src = ncur[nq] ? d1 : d0;
+            const double v = src[ok ? lin(g, cx, cy, cz) : 0];
+            hv[u] = ok ? v : INFINITY;
         }
-        t[hz][hy][hx] = v;
+#pragma unroll
+        for (int u = 0; u < kHaloBatch; ++u) {
+            const int q = (int)threadIdx.x + (it0 + u) * kTileThreads;
+            if (q < kHalo) t[q / (HX * HY)][(q / HX) % HY][q % HX] = hv[u];
+        }
     }
     // this thread's boxes: the m-th (m = 0, 1) box of parity p, counting along x-rows, which
     // hold TX / 2 boxes of each parity
     int bxs[2][2], bys[2][2], bzs[2][2];
     bool liq[2][2];
+#pragma unroll
     for (int p = 0; p < 2; ++p)
+#pragma unroll
         for (int m = 0; m < 2; ++m) {
             const int kk = threadIdx.x + m * kTileThreads;
             const int row = kk / (TX / 2), pos = kk % (TX / 2);
@@ -1023,7 +1069,8 @@ __device__ __forceinline__ void dist_tile(const KDistTiles::Args &args_, int b, 
             const int lx = 2 * pos + ((ly + lz + p) & 1);
             bxs[p][m] = lx + 1; bys[p][m] = ly + 1; bzs[p][m] = lz + 1;
             const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-            liq[p][m] = gx < g.n[0] && gy < g.n[1] && gz < g.n[2] && label[lin(g, gx, gy, gz)] != zero;
+            const bool in = gx < g.n[0] && gy < g.n[1] && gz < g.n[2];
+            liq[p][m] = in && label[in ? lin(g, gx, gy, gz) : 0] != zero;
         }
     const double wx = 1.0 / (g.h[0] * g.h[0]), wy = 1.0 / (g.h[1] * g.h[1]), wz = 1.0 / (g.h[2] * g.h[2]);
     const bool uniform = g.h[0] == g.h[1] && g.h[1] == g.h[2];

@@ -238,7 +238,13 @@ struct KCellScan {
         // the particles of the blocks before this one: the block counts are complete before
         // the scan starts, and a few thousand of them sit in L2
         uint32_t before = 0, ignored;
-        for (uint32_t j = threadIdx.x; j < blk; j += kBlock) before += a.bsum[j];
+        for (uint32_t j = threadIdx.x; j < blk; j += 4 * kBlock) {
+            // four loads in flight per round
+            uint32_t v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = j + u * kBlock < blk ? a.bsum[j + u * kBlock] : 0u;
+            before += (v[0] + v[1]) + (v[2] + v[3]);
+        }
         before = block_exclusive_scan(before, &ignored, lds);
         uint32_t run = before + excl;
 #pragma unroll
@@ -303,8 +309,9 @@ __device__ void KCellFixup::run(const Args &a, uint32_t blk, uint32_t)
     uint32_t *val = a.val;
     const int64_t s = (int64_t)blk * kThreads + threadIdx.x;
     if (s + 1 >= a.n) return;
-    const uint32_t k = key[s];
-    if ((s > 0 && key[s - 1] == k) || key[s + 1] != k) return;
+    // the three keys loaded together (no short circuit between the loads)
+    const uint32_t k = key[s], kn = key[s + 1], kp = key[s > 0 ? s - 1 : s + 1];
+    if ((s > 0 && kp == k) || kn != k) return;
     int64_t e = s + 2;
     while (e < a.n && key[e] == k) ++e;
     for (int64_t q = s + 1; q < e; ++q) {
