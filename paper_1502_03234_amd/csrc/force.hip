@@ -322,12 +322,23 @@ __device__ __forceinline__ void scan_row(const ForceArgs &a, __amdgpu_buffer_rsr
         return;
     }
     const uint32_t lane = threadIdx.x & 63u;
-    for (uint32_t k = lane; k < hi - lo; k += 64u) {
-        const double4 p = load_pos<PAIR>(rs, lo + k);
-        sg.x[k] = p.x;
-        sg.y[k] = p.y;
-        sg.z[k] = p.z;
-        if (PAIR == DCM_PAIR_MAX) sg.w[k] = p.w;
+    // the window's loads issued together (at most kStageSlots / 64 per lane), then stored
+    constexpr int kStagePer = kStageSlots / 64;
+    double4 pv[kStagePer];
+#pragma unroll
+    for (int u = 0; u < kStagePer; ++u) {
+        const uint32_t k = lane + 64u * u;
+        pv[u] = load_pos<PAIR>(rs, lo + (k < hi - lo ? k : 0u));
+    }
+#pragma unroll
+    for (int u = 0; u < kStagePer; ++u) {
+        const uint32_t k = lane + 64u * u;
+        if (k < hi - lo) {
+            sg.x[k] = pv[u].x;
+            sg.y[k] = pv[u].y;
+            sg.z[k] = pv[u].z;
+            if (PAIR == DCM_PAIR_MAX) sg.w[k] = pv[u].w;
+        }
     }
     __syncthreads();
     const bool image = has && (sx != 0.0 || sy != 0.0 || sz != 0.0);
