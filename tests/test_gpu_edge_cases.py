@@ -160,6 +160,38 @@ def test_other_detection_schedules(slab16k, de, detections):
     s.close()
 
 
+@pytest.mark.parametrize("n,box,seed,passes", [
+    (3000, (16.0, 16.0, 28.0), 1, 1),      # force rows 1 x 2 boxes (y too short)
+    (5617, (14.0, 14.0, 60.0), 2, 0),      # no smoothing: the count image is the smoothed image
+    (2800, (20.0, 20.0, 17.0), 5, 2),      # force rows 2 x 1 (z odd), two smoothing passes
+    (30000, (41.0, 37.0, 52.0), 3, 1),      # odd x and y
+])
+def test_steps_with_detection_on_ragged_grids(n, box, seed, passes):
+    """Steps that re-detect take the box-count image from the cell scan of the same step (a
+    box's storage cells lie in one scan block). On grids whose force rows are 1 box high in y
+    or z, with 0, 1 or 2 smoothing passes (the image lands in either smoothing buffer), two
+    steps that both re-detect match the oracle: positions, velocities and the new cutoffs."""
+    st = synth.small_slab(n, box, seed)
+    p, po = make(st, detect_every=1, smooth_passes=passes)
+    s = dcm.System(p, st.x, st.v)
+    x0, v0, rc0, _ = s.state()
+    f0 = s.forces()["f"]
+    torch.cuda.synchronize()
+    s.step(2)
+    x2, v2, rc2, k = s.state()
+    torch.cuda.synchronize()
+    assert k == 2
+    rs = O.RunState(x0.cpu().numpy(), v0.cpu().numpy(), rc0.cpu().numpy(), f0.cpu().numpy(), 0)
+    O.run(po, rs, 2)
+    say(f"ragged steps n={n} box={box} passes={passes}: max |dx| "
+        f"{np.max(np.abs(x2.cpu().numpy() - rs.x)):.2e}")
+    assert np.max(np.abs(x2.cpu().numpy() - rs.x)) < 1e-12
+    assert np.max(np.abs(v2.cpu().numpy() - rs.v)) < 1e-10
+    assert rc_close(rc2.cpu().numpy(), rs.rc)
+    s.check()
+    s.close()
+
+
 @pytest.mark.parametrize("kw", [dict(smooth_passes=2, min_component=0),
                                 dict(smooth_passes=0, min_component=100)])
 def test_smoothing_and_removal_settings(slab16k, kw):
