@@ -262,7 +262,13 @@ struct Stage {
 };
 
 // SELF: some lane's own slot lies in its interval (only then is j != i tested).
-template <int PAIR, bool SHIFT, bool IMAGE, bool SELF, int U, typename A>
+// OVER: every lane's interval lies in one force row of the wave's window, so a lane may test the
+// up to U - 1 slots after its interval's end in its last group of candidates: they hold
+// particles of the same row beyond the lane's x-interval, hence out of range (the pair test
+// decides them as it would anywhere), or, past the window's end, the stage's far sentinels. A lane
+// past its interval reads only the sentinels at kStageSlots. No per-candidate window test is
+// then needed.
+template <int PAIR, bool SHIFT, bool IMAGE, bool SELF, bool OVER, int U, typename A>
 __device__ __forceinline__ void scan_staged(const ForceArgs &a, const Stage &sg, uint32_t lo, const Particle &q,
                                             uint32_t jb, uint32_t je, double sx, double sy, double sz, A &c)
 {
@@ -271,8 +277,8 @@ __device__ __forceinline__ void scan_staged(const ForceArgs &a, const Stage &sg,
     // the particle's own slot as an offset into the interval (past its end if not in it)
     const uint32_t self = (uint32_t)q.i - jb;
     for (uint32_t t = 0; __any(t < len); t += U) {
-        // one clamped index per iteration; the stage has U - 1 slots of padding
-        const uint32_t k = min(o + t, kStageSlots);
+        // one index per iteration; the stage has U - 1 slots of padding
+        const uint32_t k = OVER ? (t < len ? o + t : kStageSlots) : min(o + t, kStageSlots);
         double4 p[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -283,8 +289,8 @@ __device__ __forceinline__ void scan_staged(const ForceArgs &a, const Stage &sg,
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            interact<PAIR, SHIFT, IMAGE>(a, p[u], t + u < len && (!SELF || t + u != self), q.x, q.y, q.z, q.rc,
-                                         q.rc2, sx, sy, sz, c, jb + t + u);
+            interact<PAIR, SHIFT, IMAGE>(a, p[u], (OVER || t + u < len) && (!SELF || t + u != self), q.x, q.y,
+                                         q.z, q.rc, q.rc2, sx, sy, sz, c, jb + t + u);
     }
 }
 
@@ -309,10 +315,12 @@ __device__ __forceinline__ uint32_t wave_max_u(uint32_t v) { return wave_reduce_
 
 // Slot range [jb, je) of every lane, from LDS when the lanes' ranges lie in one window of at
 // most kStageSlots slots (the usual case: the wave's lanes share a force row), else directly.
-template <int PAIR, bool SHIFT, int U, typename A>
+// OVER as in scan_staged: the caller's lanes all scan one force row.
+template <int PAIR, bool SHIFT, bool OVER, int U, typename A>
 __device__ __forceinline__ void scan_row(const ForceArgs &a, __amdgpu_buffer_rsrc_t rs, Stage &sg, const Particle &q,
                                          uint32_t jb, uint32_t je, double sx, double sy, double sz, A &c)
 {
+    static_assert(U <= (int)kStagePad, "the candidate groups read up to U - 1 slots past the window");
     const bool has = jb < je;
     const uint32_t lo = wave_min_u(has ? jb : 0xFFFFFFFFu);
     const uint32_t hi = wave_max_u(has ? je : 0u);
@@ -340,15 +348,17 @@ __device__ __forceinline__ void scan_row(const ForceArgs &a, __amdgpu_buffer_rsr
             if (PAIR == DCM_PAIR_MAX) sg.w[k] = pv[u].w;
         }
     }
+    // far sentinels for the slots a lane's last group reads past the window's end
+    if (OVER && lane < U - 1) sg.x[hi - lo + lane] = __builtin_inf();
     __syncthreads();
     const bool image = has && (sx != 0.0 || sy != 0.0 || sz != 0.0);
     const bool self = (uint32_t)q.i - jb < je - jb;
     if (__any(image))
-        scan_staged<PAIR, SHIFT, true, true, U, A>(a, sg, lo, q, jb, je, sx, sy, sz, c);
+        scan_staged<PAIR, SHIFT, true, true, OVER, U, A>(a, sg, lo, q, jb, je, sx, sy, sz, c);
     else if (__any(self))
-        scan_staged<PAIR, SHIFT, false, true, U, A>(a, sg, lo, q, jb, je, sx, sy, sz, c);
+        scan_staged<PAIR, SHIFT, false, true, OVER, U, A>(a, sg, lo, q, jb, je, sx, sy, sz, c);
     else
-        scan_staged<PAIR, SHIFT, false, false, U, A>(a, sg, lo, q, jb, je, sx, sy, sz, c);
+        scan_staged<PAIR, SHIFT, false, false, OVER, U, A>(a, sg, lo, q, jb, je, sx, sy, sz, c);
     __syncthreads();
 }
 
@@ -438,7 +448,7 @@ __device__ __forceinline__ void traverse_rows(const ForceArgs &a, bool live, con
                     e1 = a.cell_start[(row + (uint32_t)hi1 + 1u) << gs];
                 }
             }
-            if (sg) scan_row<PAIR, SHIFT, U, A>(a, pb, *sg, q, b0, e0, sx0, sy, sz, c);
+            if (sg) scan_row<PAIR, SHIFT, UNI, U, A>(a, pb, *sg, q, b0, e0, sx0, sy, sz, c);
             else scan_interval<PAIR, SHIFT, U, A>(a, pb, q, b0, e0, sx0, sy, sz, c);
             if (!UNI && __any(b1 < e1)) scan_interval<PAIR, SHIFT, U, A>(a, pb, q, b1, e1, sx1, sy, sz, c);
         }
@@ -560,6 +570,8 @@ __device__ void KForces<PAIR, SHIFT, U, PREC, LIST>::run(const Args &args_, uint
     if constexpr (!LIST) {
         __shared__ Stage st;
         stage = &st;
+        // the padding slots stay far sentinels (x = +inf: never in range) for the whole launch
+        if (threadIdx.x < kStagePad) st.x[kStageSlots + threadIdx.x] = __builtin_inf();
     }
     if (PREC == DCM_FP64) {
         if (LIST) list_scan<SHIFT, U, AccT>(a, live, q, c);
