@@ -257,8 +257,11 @@ __device__ __forceinline__ void scan_interval(const ForceArgs &a, __amdgpu_buffe
 constexpr uint32_t kStageSlots = 192;
 constexpr uint32_t kStagePad = 4;          // the candidate unroll reads up to U - 1 slots past
 struct Stage {
-    double x[kStageSlots + kStagePad], y[kStageSlots + kStagePad], z[kStageSlots + kStagePad],
-        w[kStageSlots + kStagePad];
+    // z first: every array is then in reach of the LDS reads' immediate offsets from the
+    // candidate's index scaled once per array
+    double z[kStageSlots + kStagePad];
+    double2 xy[kStageSlots + kStagePad];      // one 16-byte read per candidate
+    double w[kStageSlots + kStagePad];
 };
 
 // SELF: some lane's own slot lies in its interval (only then is j != i tested).
@@ -279,13 +282,23 @@ __device__ __forceinline__ void scan_staged(const ForceArgs &a, const Stage &sg,
     for (uint32_t t = 0; __any(t < len); t += U) {
         // one index per iteration; the stage has U - 1 slots of padding
         const uint32_t k = OVER ? (t < len ? o + t : kStageSlots) : min(o + t, kStageSlots);
+        // byte offsets of slot k in the 8- and 16-byte arrays, each formed once (the opaque copy
+        // keeps the compiler from deriving one from the other with extra instructions)
+        uint32_t b8 = k * 8u;
+        asm volatile("" : "+v"(b8));
+        const uint32_t b16 = b8 + b8;
+        const char *sb = reinterpret_cast<const char *>(&sg);
+        const double *zs = reinterpret_cast<const double *>(sb + b8);
+        const double2 *xys = reinterpret_cast<const double2 *>(sb + offsetof(Stage, xy) + b16);
+        const double *ws = reinterpret_cast<const double *>(sb + offsetof(Stage, w) + b8);
         double4 p[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            p[u].x = sg.x[k + u];
-            p[u].y = sg.y[k + u];
-            p[u].z = sg.z[k + u];
-            p[u].w = PAIR == DCM_PAIR_MAX ? sg.w[k + u] : 0.0;
+            const double2 xy = xys[u];
+            p[u].x = xy.x;
+            p[u].y = xy.y;
+            p[u].z = zs[u];
+            p[u].w = PAIR == DCM_PAIR_MAX ? ws[u] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -342,16 +355,17 @@ __device__ __forceinline__ void scan_row(const ForceArgs &a, __amdgpu_buffer_rsr
     for (int u = 0; u < kStagePer; ++u) {
         const uint32_t k = lane + 64u * u;
         if (k < hi - lo) {
-            sg.x[k] = pv[u].x;
-            sg.y[k] = pv[u].y;
-            sg.z[k] = pv[u].z;
+            sg.xy[k] = make_double2(pv[u].x, pv[u].y + (OVER ? sy : 0.0));
+            sg.z[k] = pv[u].z + (OVER ? sz : 0.0);
             if (PAIR == DCM_PAIR_MAX) sg.w[k] = pv[u].w;
         }
     }
     // far sentinels for the slots a lane's last group reads past the window's end
-    if (OVER && lane < U - 1) sg.x[hi - lo + lane] = __builtin_inf();
+    if (OVER && lane < U - 1) sg.xy[hi - lo + lane].x = __builtin_inf();
     __syncthreads();
-    const bool image = has && (sx != 0.0 || sy != 0.0 || sz != 0.0);
+    // a single-row wave's image shift (uniform, none in x) is already in the staged coordinates:
+    // the same sums the image form takes per candidate
+    const bool image = !OVER && has && (sx != 0.0 || sy != 0.0 || sz != 0.0);
     const bool self = (uint32_t)q.i - jb < je - jb;
     if (__any(image))
         scan_staged<PAIR, SHIFT, true, true, OVER, U, A>(a, sg, lo, q, jb, je, sx, sy, sz, c);
@@ -571,7 +585,7 @@ __device__ void KForces<PAIR, SHIFT, U, PREC, LIST>::run(const Args &args_, uint
         __shared__ Stage st;
         stage = &st;
         // the padding slots stay far sentinels (x = +inf: never in range) for the whole launch
-        if (threadIdx.x < kStagePad) st.x[kStageSlots + threadIdx.x] = __builtin_inf();
+        if (threadIdx.x < kStagePad) st.xy[kStageSlots + threadIdx.x].x = __builtin_inf();
     }
     if (PREC == DCM_FP64) {
         if (LIST) list_scan<SHIFT, U, AccT>(a, live, q, c);
