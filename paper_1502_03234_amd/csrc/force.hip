@@ -49,6 +49,10 @@ __device__ __forceinline__ int floor_mul(double v, double inv_h) { return (int)f
 // Conservative square root for box bounds: the hardware estimate, enlarged well past its error.
 __device__ __forceinline__ double sqrt_up(double v) { return __builtin_amdgcn_sqrt(v) * (1.0 + 1e-6) + 1e-9; }
 
+// An upper bound of sqrt_up(v) for every v <= rs * rs: the largest half-width of a row's x-interval
+// for search radius rs.
+__device__ __forceinline__ double x_reach(double rs) { return rs * (1.0 + 1e-5) + 1e-8; }
+
 // FP64 form. The pair loop accumulates the force and the virial in units of 24 eps sigma^6 (the
 // factor is applied once per particle) and, in place of the energy, the sum of r^-6: with
 // s = (sigma/r)^6 the force scalar is 24 eps s (2 s - 1) / r^2, so the trace of the virial sum is
@@ -483,7 +487,9 @@ __device__ __forceinline__ void traverse(const ForceArgs &a, bool live, const Pa
     // one force row for every live lane, and every x-interval inside [0, L_x)
     const int ylo = wave_min(live ? Yi : INT_MAX), yhi = wave_max(live ? Yi : INT_MIN);
     const int zlo = wave_min(live ? Zi : INT_MAX), zhi = wave_max(live ? Zi : INT_MIN);
-    const bool inside = !live || (q.x - rs >= 0.0 && q.x + rs < g.L[0]);
+    // (with the largest x reach a row's interval can take, so that no interval leaves [0, L_x))
+    const double rsx = x_reach(rs);
+    const bool inside = !live || (q.x - rsx >= 0.0 && q.x + rsx <= g.L[0] * (1.0 - 1e-9));
     if (ylo == yhi && zlo == zhi && __all(inside))
         traverse_rows<PAIR, SHIFT, U, A, true>(a, live, q, rs, ylo, zlo, c, sg);
     else
