@@ -28,8 +28,8 @@ WORKLOAD = "slab2m"
 # lattice start (--forces-only), scaled by a plain 1 GiB copy (profiles/KForces_slab2m_traffic.md).
 # Valid only for the kernel source it was taken on: reported as null once csrc/force.hip no longer
 # hashes to this value.
-FORCE_TRAFFIC_BYTES = 3.12e9
-FORCE_TRAFFIC_SRC = "ed70cc60c04999db"
+FORCE_TRAFFIC_BYTES = 3.13e9
+FORCE_TRAFFIC_SRC = "89513ad104e69f27"
 
 
 def force_traffic():
