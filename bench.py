@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 FP64_VALU_PEAK_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 FLOPS_PER_PAIR = 41              # algorithmic FP64 flops per in-range ordered pair
 WORKLOAD = "slab2m"
-# HBM-side bytes per force-kernel launch from FETCH_SIZE/WRITE_SIZE counter runs on the slab's
+# HBM-side bytes per launch of the FP64 traversal force kernel from FETCH_SIZE/WRITE_SIZE counter runs on the slab's
 # lattice start (--forces-only), scaled by a plain 1 GiB copy (profiles/KForces_slab2m_traffic.md).
 # Valid only for the kernel source it was taken on: reported as null once csrc/force.hip no longer
 # hashes to this value.
@@ -1174,9 +1174,14 @@ def main():
                    "n_particles": state.n, "grid": list(sysm.dims), "detect_every": args.detect_every,
                    "thermo_every_step": True, "equilibrated_steps": int(ek),
                    "pairs_per_particle": round(pairs / state.n, 2)},
-        "roofline": {"bound": "alu", "kernel": "KForces (FP64 pair forces, energy, virial; rows staged in LDS)",
+        "roofline": {"bound": "alu",
+                     "kernel": ("KForces (FP64 pair forces, energy, virial; " if prec == dcm.DCM_FP64 else
+                                "KForces (FP32 pair arithmetic, compensated FP32 sums, FP64 pair test; ")
+                               + ("Verlet lists)" if args.skin > 0 else "rows staged in LDS)"),
                      "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": force_traffic(),
+                     "frac": achieved / FP64_VALU_PEAK_TFLOPS,
+                     # the HBM counters were taken on the FP64 traversal kernel only
+                     "traffic": force_traffic() if prec == dcm.DCM_FP64 and args.skin == 0 else None,
                      "avg_launch_ms": f_avg_s * 1e3, "pairs_per_launch": pairs,
                      "flops_per_pair": FLOPS_PER_PAIR},
         "cpu_baseline": cpu and dict({k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
