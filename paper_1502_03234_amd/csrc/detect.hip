@@ -425,6 +425,72 @@ __device__ __forceinline__ bool ct_box(const Grid &g, int64_t t, int q, int64_t 
 // kCtFull tiles hold union-find entries, so the other tiles' workgroups exit at once.
 constexpr int kCtPer = CT * CT * CT / kBlock;      // boxes per thread
 
+// Tile kinds first, one wave per tile: each lane counts the in-grid boxes and the boxes of the
+// phase in one x-row of 8 boxes (one 8-byte load where the row is whole and aligned).
+struct KCcClassify {
+    static constexpr int kThreads = 64, kWaves = 0;
+    struct Args {
+        Grid g;
+        const uint8_t *label;
+        uint8_t phase;
+        uint8_t *ctile;
+        uint32_t limit;
+    };
+    static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
+};
+
+static_assert(CT == 8 && CT * CT == 64, "one lane per x-row of a component tile");
+
+__device__ void KCcClassify::run(const Args &args_, uint32_t blk, uint32_t)
+{
+    const Grid &g = args_.g;
+    const uint8_t *label = args_.label;
+    const uint8_t phase = args_.phase;
+    const int ntx = (g.n[0] + CT - 1) / CT, nty = (g.n[1] + CT - 1) / CT;
+    const int b = blk;
+    const int x0 = (b % ntx) * CT, y0 = ((b / ntx) % nty) * CT, z0 = (b / (ntx * nty)) * CT;
+    const int l = threadIdx.x;
+    const int gy = y0 + l % CT, gz = z0 + l / CT;
+    int nin = 0, nmine = 0;
+    if (gy < g.n[1] && gz < g.n[2]) {
+        const int64_t c0 = lin(g, x0, gy, gz);
+        const int nx = min(CT, (int)g.n[0] - x0);
+        if (nx == CT && (c0 & 7) == 0) {
+            // labels are 0 or 1: the byte sum of the row counts the liquid boxes
+            const uint64_t w = *reinterpret_cast<const uint64_t *>(label + c0);
+            const int ones = __popcll(w & 0x0101010101010101ull);
+            nin = CT;
+            nmine = phase ? ones : CT - ones;
+        } else {
+            nin = nx;
+            for (int x = 0; x < nx; ++x) nmine += label[c0 + x] == phase;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        nin += __shfl_xor(nin, off, 64);
+        nmine += __shfl_xor(nmine, off, 64);
+    }
+    if (l == 0) {
+        uint8_t kind = kCtFull;
+        if (nmine == 0) kind = kCtNone;
+        else if (nmine == nin && (uint32_t)nmine >= args_.limit) kind = kCtLarge;
+        args_.ctile[b] = kind;
+    }
+}
+
+// The union-find runs on the tiles of kind kCtFull only: each of at least kCcLocalGroups
+// workgroups reads the kinds of every nblk-th tile (at most one per thread), lists its kCtFull
+// tiles in LDS and labels them one after the other. The list's order is that of the LDS atomics;
+// each tile is labelled on its own, so the results do not depend on it.
+constexpr int64_t kCcLocalGroups = 1024;
+
+inline unsigned cc_local_groups(int64_t ntiles)
+{
+    const int64_t need = (ntiles + kCtBoxes - 1) / kCtBoxes;
+    const int64_t gr = ntiles < kCcLocalGroups ? ntiles : kCcLocalGroups;
+    return (unsigned)(gr > need ? gr : need);
+}
+
 struct KCcLocal {
     static constexpr int kThreads = kCtBoxes, kWaves = 0;
     struct Args {
@@ -434,13 +500,12 @@ struct KCcLocal {
         uint32_t *parent;
         uint32_t *csize;
         uint32_t *psize;
-        uint8_t *ctile;
-        uint32_t limit;
+        const uint8_t *ctile;
     };
     static __device__ void run(const Args &args_, uint32_t blk, uint32_t nblk);
 };
 
-__device__ void KCcLocal::run(const Args &args_, uint32_t blk, uint32_t)
+__device__ void KCcLocal::run(const Args &args_, uint32_t blk, uint32_t nblk)
 {
     Grid g = args_.g;
     const uint8_t *label = args_.label;
@@ -448,59 +513,60 @@ __device__ void KCcLocal::run(const Args &args_, uint32_t blk, uint32_t)
     uint32_t *parent = args_.parent;
     uint32_t *csize = args_.csize;
     uint32_t *psize = args_.psize;
-    uint8_t *ctile = args_.ctile;
-    const uint32_t limit = args_.limit;
     __shared__ uint32_t lp[kCtBoxes];
     __shared__ uint32_t lc[kCtBoxes];
     const int ntx = (g.n[0] + CT - 1) / CT, nty = (g.n[1] + CT - 1) / CT;
-    const int b = blk;
-    const int x0 = (b % ntx) * CT, y0 = ((b / ntx) % nty) * CT, z0 = (b / (ntx * nty)) * CT;
     const int l = threadIdx.x;
     const int lx = l % CT, ly = (l / CT) % CT, lz = l / (CT * CT);
-    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-    const bool in = gx < g.n[0] && gy < g.n[1] && gz < g.n[2];
-    const int64_t c = in ? lin(g, gx, gy, gz) : 0;
-    const bool mine = in && label[c] == phase;
-    // a tile whose boxes all have the phase (or none does) needs no union-find: its in-grid
-    // boxes form one box-shaped piece whose smallest member is the tile's first box
-    const int nmine = __syncthreads_count(mine), nin = __syncthreads_count(in);
-    if (nmine == 0 || (nmine == nin && (uint32_t)nmine >= limit)) {
-        if (l == 0) ctile[b] = nmine == 0 ? kCtNone : kCtLarge;
-        return;
-    }
-    if (l == 0) ctile[b] = kCtFull;
-    if (nmine == nin) {
-        if (in) {
-            if (mine) {
+    const int64_t ntiles = (int64_t)ntx * nty * ((g.n[2] + CT - 1) / CT);
+    __shared__ int list[kCtBoxes];
+    __shared__ uint32_t count;
+    if (l == 0) count = 0u;
+    __syncthreads();
+    const int64_t t = blk + (int64_t)l * nblk;
+    if (t < ntiles && args_.ctile[t] == kCtFull) list[atomicAdd(&count, 1u)] = (int)t;
+    __syncthreads();
+    const uint32_t m = count;
+    for (uint32_t q = 0; q < m; ++q) {
+        const int b = list[q];
+        const int x0 = (b % ntx) * CT, y0 = ((b / ntx) % nty) * CT, z0 = (b / (ntx * nty)) * CT;
+        const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+        const bool in = gx < g.n[0] && gy < g.n[1] && gz < g.n[2];
+        const int64_t c = in ? lin(g, gx, gy, gz) : 0;
+        const bool mine = in && label[c] == phase;
+        // the previous tile's LDS reads are done (and the counts below are uniform)
+        const int nmine = __syncthreads_count(mine), nin = __syncthreads_count(in);
+        if (nmine == nin) {
+            // every in-grid box has the phase (fewer than `limit`): one box-shaped piece whose
+            // smallest member is the tile's first box
+            if (in) {
                 csize[c] = 0;
                 parent[c] = (uint32_t)lin(g, x0, y0, z0);
                 psize[c] = (uint32_t)nmine;
+            }
+            continue;
+        }
+        lp[l] = mine ? (uint32_t)l : kInvalid;
+        lc[l] = 0;
+        __syncthreads();
+        if (mine) {
+            if (lx + 1 < CT && gx + 1 < g.n[0] && lp[l + 1] != kInvalid) lunite(lp, l, l + 1);
+            if (ly + 1 < CT && gy + 1 < g.n[1] && lp[l + CT] != kInvalid) lunite(lp, l, l + CT);
+            if (lz + 1 < CT && gz + 1 < g.n[2] && lp[l + CT * CT] != kInvalid) lunite(lp, l, l + CT * CT);
+        }
+        __syncthreads();
+        uint32_t r = mine ? lfind(lp, l) : 0u;
+        if (mine) atomicAdd(lc + r, 1u);
+        __syncthreads();
+        if (in) {
+            if (mine) {
+                csize[c] = 0;
+                int rx = r % CT, ry = (r / CT) % CT, rz = r / (CT * CT);
+                parent[c] = (uint32_t)lin(g, x0 + rx, y0 + ry, z0 + rz);
+                psize[c] = lc[r];
             } else {
                 parent[c] = kInvalid;
             }
-        }
-        return;
-    }
-    lp[l] = mine ? (uint32_t)l : kInvalid;
-    lc[l] = 0;
-    __syncthreads();
-    if (mine) {
-        if (lx + 1 < CT && gx + 1 < g.n[0] && lp[l + 1] != kInvalid) lunite(lp, l, l + 1);
-        if (ly + 1 < CT && gy + 1 < g.n[1] && lp[l + CT] != kInvalid) lunite(lp, l, l + CT);
-        if (lz + 1 < CT && gz + 1 < g.n[2] && lp[l + CT * CT] != kInvalid) lunite(lp, l, l + CT * CT);
-    }
-    __syncthreads();
-    uint32_t r = mine ? lfind(lp, l) : 0u;
-    if (mine) atomicAdd(lc + r, 1u);
-    __syncthreads();
-    if (in) {
-        if (mine) {
-            csize[c] = 0;
-            int rx = r % CT, ry = (r / CT) % CT, rz = r / (CT * CT);
-            parent[c] = (uint32_t)lin(g, x0 + rx, y0 + ry, z0 + rz);
-            psize[c] = lc[r];
-        } else {
-            parent[c] = kInvalid;
         }
     }
 }
@@ -1377,7 +1443,8 @@ void launch_segment(const Grid &g, const uint32_t *img, const double *km, int32_
         uint8_t phase = pass == 0 ? 1 : 0;
         unsigned nct = (unsigned)(((g.n[0] + CT - 1) / CT) * ((g.n[1] + CT - 1) / CT) * ((g.n[2] + CT - 1) / CT));
         const uint32_t limit = (uint32_t)min_component;
-        emit<KCcLocal>({g, w.label, phase, w.parent, w.csize, w.gtmp, w.ctile, limit}, nct, st);
+        emit<KCcClassify>({g, w.label, phase, w.ctile, limit}, nct, st);
+        emit<KCcLocal>({g, w.label, phase, w.parent, w.csize, w.gtmp, w.ctile}, cc_local_groups(nct), st);
         emit<KCcMerge>({g, w.label, phase, w.parent, w.gtmp, limit, w.ctile}, grid1(g.G), st);
         emit<KCcFlatten>({g, w.parent, w.ctile}, nct, st);
         emit<KCcSize>({g, w.parent, (const uint32_t *)w.gtmp, w.csize, limit, w.ctile}, nct, st);
