@@ -160,6 +160,34 @@ def test_other_detection_schedules(slab16k, de, detections):
     s.close()
 
 
+def test_single_row_wave_at_the_x_faces():
+    """A wave whose particles all lie in force row 0, with one particle just past x = r_s and
+    one just short of L_x - r_s (r_s the search radius): the x-interval a row gives them reaches
+    a little beyond r_s (the enlarged square root of the bounds), so they must leave the
+    single-row form, whose intervals may not wrap. Forces and pair counts match the oracle."""
+    from test_gpu_parity import force_err
+    st = synth.lattice(16, 16.0, seed=17)           # one particle per box: 64 in force row 0
+    rc0 = 2.5
+    rs = rc0 * (1.0 + 1e-12) + 1e-9
+    x = st.x.copy()
+    x[0, 2] = rs + 7.5e-7                           # box (2, 0, 0)
+    x[0, (1 * 16 + 1) * 16 + 13] = 16.0 - rs - 7.5e-7   # box (13, 1, 1)
+    p, po = make(st)
+    s = dcm.System(p, x, st.v)
+    rc = np.full(st.n, rc0)
+    s.set_cutoffs(rc)
+    fo = s.forces()
+    xg, _, _, _ = s.state()
+    torch.cuda.synchronize()
+    s.check()
+    xw = xg.cpu().numpy()
+    assert np.array_equal(xw, O.wrap(po, x))
+    ref = O.forces(po, xw, rc)
+    assert force_err(fo["f"].cpu().numpy(), ref.f).max() <= FORCE_TOL
+    assert np.array_equal(fo["pairs"].cpu().numpy().astype(np.int64), ref.pairs)
+    s.close()
+
+
 @pytest.mark.parametrize("n,box,seed,passes", [
     (3000, (16.0, 16.0, 28.0), 1, 1),      # force rows 1 x 2 boxes (y too short)
     (5617, (14.0, 14.0, 60.0), 2, 0),      # no smoothing: the count image is the smoothed image
