@@ -581,7 +581,8 @@ __device__ void KCcLocal::run(const Args &args_, uint32_t blk, uint32_t nblk)
 constexpr uint32_t kTouched = 0xffffffffu;
 
 struct KCcMerge {
-    static constexpr int kThreads = kBlock, kWaves = 0;
+    // one workgroup per component tile, a lane per box of its three upper faces (x, y, z)
+    static constexpr int kThreads = 3 * CT * CT, kWaves = 0;
     struct Args {
         Grid g;
         const uint8_t *label;
@@ -596,49 +597,56 @@ struct KCcMerge {
 
 __device__ void KCcMerge::run(const Args &args_, uint32_t blk, uint32_t)
 {
-    Grid g = args_.g;
+    const Grid &g = args_.g;
     const uint8_t *label = args_.label;
-    uint8_t phase = args_.phase;
+    const uint8_t phase = args_.phase;
     uint32_t *parent = args_.parent;
     uint32_t *psize = args_.psize;
-    uint32_t limit = args_.limit;
+    const uint32_t limit = args_.limit;
     const uint8_t *ctile = args_.ctile;
-    int64_t c = (int64_t)blk * blockDim.x + threadIdx.x;
-    if (c >= g.G || label[c] != phase) return;
-    int64_t i, j, k;
-    coords(g, c, i, j, k);
-    const bool fx = (i % CT) == CT - 1 || i + 1 == g.n[0];
-    const bool fy = (j % CT) == CT - 1 || j + 1 == g.n[1];
-    const bool fz = (k % CT) == CT - 1 || k + 1 == g.n[2];
-    if (!(fx || fy || fz)) return;
-    const int64_t ip = i + 1 == g.n[0] ? 0 : i + 1, jp = j + 1 == g.n[1] ? 0 : j + 1,
-                  kp = k + 1 == g.n[2] ? 0 : k + 1;
-    const int64_t nb[3] = {fx ? lin(g, ip, j, k) : -1, fy ? lin(g, i, jp, k) : -1, fz ? lin(g, i, j, kp) : -1};
-    const int64_t nt[3] = {ct_tile(g, ip, j, k), ct_tile(g, i, jp, k), ct_tile(g, i, j, kp)};
+    const uint8_t kind = ctile[blk];
+    if (kind == kCtNone) return;                    // no box of the phase here
+    const int ntx = (g.n[0] + CT - 1) / CT, nty = (g.n[1] + CT - 1) / CT;
+    const int b = blk;
+    const int x0 = (b % ntx) * CT, y0 = ((b / ntx) % nty) * CT, z0 = (b / (ntx * nty)) * CT;
+    // a tile's upper face in an axis is its last in-grid layer (the grid's last layer joins the
+    // first one across the periodic face)
+    const int nx = min(CT, (int)g.n[0] - x0), ny = min(CT, (int)g.n[1] - y0), nz = min(CT, (int)g.n[2] - z0);
+    const int q = threadIdx.x / (CT * CT);
+    const int u = threadIdx.x % CT, v = (threadIdx.x / CT) % CT;
+    const int lx = q == 0 ? nx - 1 : u, ly = q == 1 ? ny - 1 : (q == 0 ? u : v), lz = q == 2 ? nz - 1 : v;
+    if (lx >= nx || ly >= ny || lz >= nz) return;
+    const int i = x0 + lx, j = y0 + ly, k = z0 + lz;
+    const int64_t c = lin(g, i, j, k);
+    if (label[c] != phase) return;
+    const int ip = q == 0 ? (i + 1 == g.n[0] ? 0 : i + 1) : i;
+    const int jp = q == 1 ? (j + 1 == g.n[1] ? 0 : j + 1) : j;
+    const int kp = q == 2 ? (k + 1 == g.n[2] ? 0 : k + 1) : k;
+    const int64_t nb = lin(g, ip, jp, kp);
+    if (label[nb] != phase) return;
     // A box of a kCtLarge tile belongs to a large piece without union-find entries: a small
     // piece touching it is tagged (psize = kTouched, which the size count reads as "large")
     // instead of joined. Otherwise piece sizes only move to kTouched (>= limit) while this
-    // runs, and a face is joined when at least one of its two pieces can still be small.
-    const bool large_tile = ctile[ct_tile(g, i, j, k)] != kCtFull;
-    const bool small = !large_tile && psize[c] < limit;
-    for (int q = 0; q < 3; ++q) {
-        if (nb[q] < 0 || label[nb[q]] != phase) continue;
-        const bool nlarge_tile = ctile[nt[q]] != kCtFull;
-        if (large_tile && nlarge_tile) continue;
-        if (large_tile) {
-            if (psize[nb[q]] < limit) psize[nb[q]] = kTouched;
-            continue;
-        }
-        if (nlarge_tile) {
-            if (small) psize[c] = kTouched;
-            continue;
-        }
-        const bool nsmall = psize[nb[q]] < limit;
-        if (!small && !nsmall) continue;
-        unite(parent, (uint32_t)c, (uint32_t)nb[q]);
-        if (!small) psize[c] = kTouched;
-        if (!nsmall) psize[nb[q]] = kTouched;
+    // runs, and a face is joined when at least one of its two pieces can still be small (a box
+    // on several faces takes each face in its own lane; the outcome does not depend on their
+    // timing).
+    const bool large_tile = kind != kCtFull;
+    const bool nlarge_tile = ctile[ct_tile(g, ip, jp, kp)] != kCtFull;
+    if (large_tile && nlarge_tile) return;
+    if (large_tile) {
+        if (psize[nb] < limit) psize[nb] = kTouched;
+        return;
     }
+    const bool small = psize[c] < limit;
+    if (nlarge_tile) {
+        if (small) psize[c] = kTouched;
+        return;
+    }
+    const bool nsmall = psize[nb] < limit;
+    if (!small && !nsmall) return;
+    unite(parent, (uint32_t)c, (uint32_t)nb);
+    if (!small) psize[c] = kTouched;
+    if (!nsmall) psize[nb] = kTouched;
 }
 
 struct KCcFlatten {
@@ -1445,7 +1453,7 @@ void launch_segment(const Grid &g, const uint32_t *img, const double *km, int32_
         const uint32_t limit = (uint32_t)min_component;
         emit<KCcClassify>({g, w.label, phase, w.ctile, limit}, nct, st);
         emit<KCcLocal>({g, w.label, phase, w.parent, w.csize, w.gtmp, w.ctile}, cc_local_groups(nct), st);
-        emit<KCcMerge>({g, w.label, phase, w.parent, w.gtmp, limit, w.ctile}, grid1(g.G), st);
+        emit<KCcMerge>({g, w.label, phase, w.parent, w.gtmp, limit, w.ctile}, nct, st);
         emit<KCcFlatten>({g, w.parent, w.ctile}, nct, st);
         emit<KCcSize>({g, w.parent, (const uint32_t *)w.gtmp, w.csize, limit, w.ctile}, nct, st);
         emit<KCcFlip>({g, w.label, phase, w.parent, (const uint32_t *)w.gtmp, w.csize, limit, w.stats,
