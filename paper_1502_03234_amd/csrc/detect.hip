@@ -455,7 +455,8 @@ __device__ void KCcClassify::run(const Args &args_, uint32_t blk, uint32_t)
     if (gy < g.n[1] && gz < g.n[2]) {
         const int64_t c0 = lin(g, x0, gy, gz);
         const int nx = min(CT, (int)g.n[0] - x0);
-        if (nx == CT && (c0 & 7) == 0) {
+        // (labels may be a caller's buffer at any byte offset: the address itself is checked)
+        if (nx == CT && ((uintptr_t)(label + c0) & 7u) == 0) {
             // labels are 0 or 1: the byte sum of the row counts the liquid boxes
             const uint64_t w = *reinterpret_cast<const uint64_t *>(label + c0);
             const int ones = __popcll(w & 0x0101010101010101ull);

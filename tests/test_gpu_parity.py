@@ -299,8 +299,9 @@ def test_grid_smooth(dims, passes):
 
 def test_grid_two_means_and_segment():
     rng = np.random.default_rng(4)
-    for trial in range(6):
-        dims = tuple(int(v) for v in rng.integers(4, 20, size=3))
+    for trial in range(8):
+        # the last two trials have x-rows of whole 8-box tiles (the tile kinds' 8-byte label loads)
+        dims = tuple(int(v) for v in rng.integers(4, 20, size=3)) if trial < 6 else (16, 9 + trial, 10)
         G = int(np.prod(dims))
         # odd trials: a low cluster of mostly empty boxes (the vapor of a slab)
         low = rng.poisson(0.3 if trial % 2 else 3, G)
@@ -329,6 +330,15 @@ def test_grid_two_means_and_segment():
         assert np.array_equal(raw.cpu().numpy(), oraw)
         assert np.array_equal(lab.cpu().numpy(), olab), (dims, mc)
         assert np.array_equal(stats.cpu().numpy(), ost)
+        # label buffers at byte offsets 3 and 8 from an allocation's start
+        for off in (3, 8):
+            lab_b = torch.zeros(G + off, dtype=torch.uint8, device="cuda")
+            raw_b = torch.zeros(G + off, dtype=torch.uint8, device="cuda")
+            dcm.dcm_grid_segment(dims, g, km, mc, raw_b[off:], lab_b[off:], stats, ws)
+            torch.cuda.synchronize()
+            assert np.array_equal(raw_b[off:].cpu().numpy(), oraw)
+            assert np.array_equal(lab_b[off:].cpu().numpy(), olab), (dims, mc, off)
+            assert np.array_equal(stats.cpu().numpy(), ost)
 
 
 def test_grid_distance_half_space_sphere_and_random():
