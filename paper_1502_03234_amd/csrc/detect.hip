@@ -479,9 +479,10 @@ __device__ void KCcClassify::run(const Args &args_, uint32_t blk, uint32_t)
     }
 }
 
-// The union-find runs on the tiles of kind kCtFull only: each of at least kCcLocalGroups
-// workgroups reads the kinds of every nblk-th tile (at most one per thread), lists its kCtFull
-// tiles in LDS and labels them one after the other. The list's order is that of the LDS atomics;
+// The union-find runs on the tiles of kind kCtFull only: each of nblk workgroups (kCcLocalGroups,
+// fewer on grids with fewer tiles, more where a thread per tile would not cover them) reads the
+// kinds of every nblk-th tile (at most one per thread), lists its kCtFull tiles in LDS and labels
+// them one after the other. The list's order is that of the LDS atomics;
 // each tile is labelled on its own, so the results do not depend on it.
 constexpr int64_t kCcLocalGroups = 1024;
 
